@@ -1,0 +1,437 @@
+"""Plain FP64 CPU oracle of repeated-pattern FETI.  TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this module.  It shares no code with the GPU library: it reads the
+problem statement produced by ``workloads`` and follows the paper (Gosselet,
+Rixen, Rey, "A domain decomposition strategy to efficiently solve structures
+containing repeated patterns") step by step, with NumPy/SciPy primitives
+(sparse LU, dense eigendecomposition, dense inverse, matrix products).
+
+Every function names the passage it follows.  Readings where the paper is
+silent are marked READING.
+
+Parity status of each function (what pins it, see tests/test_oracle_*.py):
+* pattern condensation, kernel, pseudo-inverse: pinned (dense Schur, pinv,
+  analytic rigid modes, S S+ S = S);
+* assembly operators, F, G, Q, lambda_0: pinned (continuity of rigid motions,
+  antisymmetry, dense F, projector identities);
+* classical and block solvers, recovery: pinned against a brute-force global
+  solve assembled from the global node numbering, and the closed-form 1-D
+  solution of the heat row;
+* iteration counts against the paper's tables: parity unpinned (the paper's
+  matrices and preconditioner are not reproduced).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+KERNEL_TAU = 1e-10      # READING: eigenvalues below tau * lambda_max(S) span the kernel
+ETA_DROP = 1e-12        # READING: eigenvalues of eta below this * max are dropped (section 4.3)
+
+
+# =========================================================================== pattern level
+
+class PatternOracle:
+    """One pattern: S, its kernel Z, the pseudo-inverse S+ (section 2, definitions after eq. 3).
+
+    S = K_bb - K_bi K_ii^{-1} K_ib is the local Schur complement.  For a floating
+    pattern S is singular; Z is an orthonormal basis of its kernel and
+    S+ = (S + Z Z^T)^{-1} - Z Z^T is the Moore-Penrose pseudo-inverse (READING:
+    the paper only asks K K+ y = y on range K; this choice is canonical because
+    Z Z^T does not depend on the basis).
+    """
+
+    def __init__(self, K: sp.csr_matrix, bdofs: np.ndarray, expected_kernel: int | None = None,
+                 tau: float = KERNEL_TAU):
+        n = K.shape[0]
+        self.n = n
+        self.b = np.asarray(bdofs, np.int64)
+        mask = np.ones(n, bool)
+        mask[self.b] = False
+        self.i = np.nonzero(mask)[0]
+        K = K.tocsc()
+        self.K = K
+        self.Kii = K[self.i][:, self.i].tocsc()
+        self.Kib = K[self.i][:, self.b].toarray()
+        self.Kbb = K[self.b][:, self.b].toarray()
+        self.lu = spla.splu(self.Kii)
+        self.X = self.lu.solve(self.Kib)                 # K_ii^{-1} K_ib
+        S = self.Kbb - self.Kib.T @ self.X
+        self.S = 0.5 * (S + S.T)
+        self.Z = kernel_basis(self.S, tau)
+        if expected_kernel is not None and self.Z.shape[1] != expected_kernel:
+            raise ValueError(f"kernel dimension {self.Z.shape[1]} != {expected_kernel}")
+        self.Splus = pseudo_inverse(self.S, self.Z)
+        # N = [-K_ii^{-1} K_ib Z ; Z] in the pattern's dof order (kernel of K, section 2)
+        N = np.zeros((n, self.Z.shape[1]))
+        N[self.i] = -self.X @ self.Z
+        N[self.b] = self.Z
+        self.N = N
+
+    @property
+    def k(self) -> int:
+        return self.Z.shape[1]
+
+    @property
+    def n_b(self) -> int:
+        return len(self.b)
+
+    def condensed_load(self, f: np.ndarray) -> np.ndarray:
+        """g = f_b - K_bi K_ii^{-1} f_i (the load seen by the boundary, section 2)."""
+        return f[self.b] - self.Kib.T @ self.lu.solve(np.ascontiguousarray(f[self.i]))
+
+    def interior(self, f: np.ndarray, u_b: np.ndarray) -> np.ndarray:
+        """u_i = K_ii^{-1} (f_i - K_ib u_b): the interior rows of K u = f - t^T lambda_b."""
+        return self.lu.solve(np.ascontiguousarray(f[self.i] - self.Kib @ u_b))
+
+
+def kernel_basis(S: np.ndarray, tau: float = KERNEL_TAU) -> np.ndarray:
+    """Orthonormal basis of the numerical kernel of a symmetric PSD matrix (section 2: N)."""
+    w, V = np.linalg.eigh(S)
+    lmax = max(abs(w[-1]), abs(w[0]))
+    keep = np.abs(w) < tau * lmax
+    return np.ascontiguousarray(V[:, keep])
+
+
+def pseudo_inverse(S: np.ndarray, Z: np.ndarray) -> np.ndarray:
+    """S+ = (S + Z Z^T)^{-1} - Z Z^T (Moore-Penrose when Z spans ker S)."""
+    P = Z @ Z.T
+    Sp = np.linalg.inv(S + P) - P
+    return 0.5 * (Sp + Sp.T)
+
+
+# =========================================================================== interface level
+
+class FetiOracle:
+    """The dual interface problem (eq. 3) of a Problem, with identity preconditioner.
+
+    F = sum_s A^(s) S+ A^(s)T, G = [.. A^(s) t N^(s) ..], d = sum_s A^(s) t K+ f^(s),
+    e^T = [.. f^(s)T N^(s) ..] (section 2).  With the preconditioner taken as the
+    identity (READING), Q = I - G (G^T G)^{-1} G^T and lambda_0 = G (G^T G)^{-1} e
+    (section 2, projector and initialisation).  For elasticity A^(s) carries the
+    occurrence rotation O^(s) (section 5.2): A^(s)T takes global-frame interface
+    values to the pattern frame.
+    """
+
+    def __init__(self, problem, patterns: list | None = None):
+        pb = problem
+        self.pb = pb
+        self.dpn = dpn = pb.dpn
+        if patterns is None:
+            patterns = [PatternOracle(p.K, p.bdofs, p.kernel_dim) for p in pb.patterns]
+        self.pats = patterns
+        self.n_lambda = pb.n_lambda
+        # boundary position of every local node, per pattern
+        self.bpos = []
+        for p in pb.patterns:
+            pos = np.full(p.n_nodes, -1, np.int64)
+            pos[p.bnodes] = np.arange(len(p.bnodes))
+            self.bpos.append(pos)
+        self.A = [self._assembly(s) for s in range(pb.n_occ)]
+        cols = []
+        self.coarse_off = np.zeros(pb.n_occ + 1, np.int64)
+        for s in range(pb.n_occ):
+            Zs = self.pats[pb.occ_pattern[s]].Z
+            cols.append(sp.csr_matrix(self.A[s] @ Zs))
+            self.coarse_off[s + 1] = self.coarse_off[s] + Zs.shape[1]
+        self.G = sp.hstack(cols).tocsr() if cols else sp.csr_matrix((self.n_lambda, 0))
+        self.GtG = (self.G.T @ self.G).toarray()
+        self._GtG_cho = None
+
+    # -- signed Boolean assembly (eq. 2) ------------------------------------------------
+    def _assembly(self, s: int) -> sp.csr_matrix:
+        """A^(s): N_lambda x n_b(s); (A v)[l] = sign * O^(s) v[node] at every endpoint on s."""
+        pb, dpn = self.pb, self.dpn
+        p = pb.occ_pattern[s]
+        nb = self.pats[p].n_b
+        O = pb.occ_rot[s][:dpn, :dpn] if dpn > 1 else np.ones((1, 1))
+        rows, cols, vals = [], [], []
+        for e in range(2):
+            sel = np.nonzero(pb.mult_occ[:, e] == s)[0]
+            if len(sel) == 0:
+                continue
+            bp = self.bpos[p][pb.mult_node[sel, e]]
+            assert np.all(bp >= 0)
+            sg = pb.mult_sign[sel, e].astype(float)
+            for c in range(dpn):
+                for c2 in range(dpn):
+                    if O[c, c2] == 0.0:
+                        continue
+                    rows.append(sel * dpn + c)
+                    cols.append(bp * dpn + c2)
+                    vals.append(sg * O[c, c2])
+        if not rows:
+            return sp.csr_matrix((self.n_lambda, nb))
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(self.n_lambda, nb))
+
+    # -- operators ----------------------------------------------------------------------
+    def F(self, X: np.ndarray) -> np.ndarray:
+        """F X = sum_s A^(s) S+ A^(s)T X (section 2; section 4.2 computes all occurrences as S+ W)."""
+        X = np.asarray(X, float)
+        vec = X.ndim == 1
+        X2 = X[:, None] if vec else X
+        Y = np.zeros_like(X2)
+        for s in range(self.pb.n_occ):
+            Sp = self.pats[self.pb.occ_pattern[s]].Splus
+            Y += self.A[s] @ (Sp @ (self.A[s].T @ X2))
+        return Y[:, 0] if vec else Y
+
+    def Gt(self, X):
+        return self.G.T @ X
+
+    def coarse_solve(self, c):
+        """(G^T G)^{-1} c by a Cholesky factor computed on first use (G^T G is singular for a
+        structure with no Dirichlet condition at all; such structures never reach this)."""
+        if self.GtG.size == 0:
+            return c
+        if self._GtG_cho is None:
+            self._GtG_cho = sla.cho_factor(self.GtG)
+        return sla.cho_solve(self._GtG_cho, c)
+
+    def Q(self, X: np.ndarray) -> np.ndarray:
+        """Q X = X - G (G^T G)^{-1} G^T X (identity preconditioner; Q = Q^T)."""
+        if self.G.shape[1] == 0:
+            return np.array(X, float)
+        return X - self.G @ self.coarse_solve(self.G.T @ X)
+
+    # -- right-hand sides ---------------------------------------------------------------
+    def loads(self, f_local=None):
+        """Condensed loads g^(s), d = sum A S+ g, e = [Z^T g^(s)] (eq. 3 right-hand side)."""
+        pb = self.pb
+        f_local = pb.f_local if f_local is None else f_local
+        g = []
+        for s in range(pb.n_occ):
+            P = self.pats[pb.occ_pattern[s]]
+            g.append(P.condensed_load(f_local[s]))
+        nr = g[0].shape[1]
+        d = np.zeros((self.n_lambda, nr))
+        e = np.zeros((self.G.shape[1], nr))
+        for s in range(pb.n_occ):
+            P = self.pats[pb.occ_pattern[s]]
+            d += self.A[s] @ (P.Splus @ g[s])
+            e[self.coarse_off[s]:self.coarse_off[s + 1]] = P.Z.T @ g[s]
+        return g, d, e
+
+    def lambda0(self, e, lam00=None):
+        """lambda_0 = G (G^T G)^{-1} e + Q lambda_00 (Table 1, line 2)."""
+        l0 = self.G @ self.coarse_solve(e) if self.G.shape[1] else np.zeros((self.n_lambda, e.shape[1]))
+        if lam00 is not None:
+            l0 = l0 + self.Q(lam00)
+        return l0
+
+    def residual(self, lam, d):
+        """r = Q^T (d - F lambda) (Table 1, line 3)."""
+        return self.Q(d - self.F(lam))
+
+    def permute(self, z: np.ndarray) -> np.ndarray:
+        """Multivector [Pi_0 z, .., Pi_{np-1} z] for every column of z (section 3.1, eq. for w~).
+
+        Columns are ordered (load case, permutation): column l*np + k = Pi_k z_l.
+        """
+        P = self.pb.perm_dof()
+        nr = z.shape[1]
+        out = np.empty((z.shape[0], nr * P.shape[0]))
+        for l in range(nr):
+            for k in range(P.shape[0]):
+                out[:, l * P.shape[0] + k] = z[P[k], l]
+        return out
+
+    # -- solvers (Table 1) ----------------------------------------------------------------
+    def solve_classical(self, d, e, tol, max_it=2000, lam00=None, record=None):
+        """Projected CG, Table 1 left column, one load case at a time (FETI-mrhs, section 4.4).
+
+        record: optional list receiving lambda after every iteration (first load case).
+        """
+        nr = d.shape[1]
+        lam = self.lambda0(e, lam00)
+        its = []
+        hist = []
+        for c in range(nr):
+            l = lam[:, c].copy()
+            r = self.Q(d[:, c] - self.F(l))
+            r0 = np.linalg.norm(r)
+            z = self.Q(r)
+            w = z.copy()
+            h = [1.0]
+            j = 0
+            while r0 > 0 and np.linalg.norm(r) > tol * r0 and j < max_it:
+                p = self.Q(self.F(w))
+                wp = w @ p
+                alpha = (w @ r) / wp
+                l += alpha * w
+                r -= alpha * p
+                z = self.Q(r)
+                beta = -(p @ z) / wp
+                w = z + beta * w
+                j += 1
+                h.append(np.linalg.norm(r) / r0)
+                if record is not None and c == 0:
+                    record.append(l.copy())
+            lam[:, c] = l
+            its.append(j)
+            hist.append(h)
+        return lam, dict(iterations=its, history=hist)
+
+    def solve_block(self, d, e, tol, max_it=2000, lam00=None, full_reorth=True, record=None):
+        """Multivector projected CG, Table 1 right column.
+
+        full_reorth=True: every new block is F-orthogonalised against all stored blocks and
+        F-normalised, W <- W eta^{-1/2}, P <- P eta^{-1/2} with eta = P^T W (section 4.3);
+        eigenvalues of eta below ETA_DROP * max are dropped (pseudo-inverse, section 4.3).
+        full_reorth=False: the short recurrence of Table 1 (beta against the previous block),
+        with a pseudo-inverse of W^T P.
+        Stopping (READING): max over load cases of ||r_c|| / ||r0_c|| <= tol.
+        """
+        lam = self.lambda0(e, lam00)
+        r = self.Q(d - self.F(lam))
+        r0 = np.linalg.norm(r, axis=0)
+        r0[r0 == 0] = 1.0
+        z = self.Q(r)
+        Zb = self.Q(self.permute(z))          # READING: re-project permuted directions
+        Ws, Ps = [], []
+        W_prev = P_prev = None
+        hist = [1.0]
+        drops = 0
+        j = 0
+        while np.max(np.linalg.norm(r, axis=0) / r0) > tol and j < max_it:
+            if full_reorth:
+                for Wi, Pi in zip(Ws, Ps):
+                    Zb = Zb - Wi @ (Pi.T @ Zb)
+                Pb = self.Q(self.F(Zb))
+                eta = Zb.T @ Pb
+                eta = 0.5 * (eta + eta.T)
+                ev, V = np.linalg.eigh(eta)
+                keep = ev > ETA_DROP * max(ev.max(), 0.0)
+                drops += int((~keep).sum())
+                if not keep.any():
+                    break
+                T = V[:, keep] / np.sqrt(ev[keep])[None, :]
+                W = Zb @ T
+                P = Pb @ T
+                alpha = W.T @ r
+                lam = lam + W @ alpha
+                r = r - P @ alpha
+                Ws.append(W)
+                Ps.append(P)
+            else:
+                if W_prev is None:
+                    W = Zb
+                else:
+                    beta = -np.linalg.pinv(WtP) @ (P_prev.T @ Zb)
+                    W = Zb + W_prev @ beta
+                P = self.Q(self.F(W))
+                WtP = W.T @ P
+                WtP = 0.5 * (WtP + WtP.T)
+                alpha = np.linalg.pinv(WtP) @ (W.T @ r)
+                lam = lam + W @ alpha
+                r = r - P @ alpha
+                W_prev, P_prev = W, P
+            j += 1
+            hist.append(float(np.max(np.linalg.norm(r, axis=0) / r0)))
+            if record is not None:
+                record.append(lam.copy())
+            z = self.Q(r)
+            Zb = self.Q(self.permute(z))
+        return lam, dict(iterations=j, history=hist, rank_drops=drops)
+
+    # -- recovery -------------------------------------------------------------------------
+    def recover(self, lam, d, g, f_local=None):
+        """Local displacements from lambda (eq. 2 with the kernel term).
+
+        READING of the coarse unknown's sign: eq. 2 gives u^(s) = K+(f - t^T A^T lambda) + N alpha_s
+        with F lambda - G alpha = d, so alpha = (G^T G)^{-1} G^T (F lambda - d) and the paper's
+        g = -alpha.  Boundary: u_b = S+ (g^(s) - A^(s)T lambda) + Z alpha_s; interior:
+        u_i = K_ii^{-1} (f_i - K_ib u_b).
+        """
+        pb = self.pb
+        f_local = pb.f_local if f_local is None else f_local
+        alpha = self.coarse_solve(self.G.T @ (self.F(lam) - d)) if self.G.shape[1] else None
+        u = []
+        for s in range(pb.n_occ):
+            P = self.pats[pb.occ_pattern[s]]
+            ub = P.Splus @ (g[s] - self.A[s].T @ lam)
+            if alpha is not None and P.k:
+                ub = ub + P.Z @ alpha[self.coarse_off[s]:self.coarse_off[s + 1]]
+            us = np.zeros((P.n, lam.shape[1]))
+            us[P.b] = ub
+            us[P.i] = P.interior(f_local[s], ub)
+            u.append(us)
+        return u
+
+    def solve(self, method="block", tol=None, max_it=2000, full_reorth=True):
+        tol = self.pb.tol if tol is None else tol
+        g, d, e = self.loads()
+        if method == "classical":
+            lam, st = self.solve_classical(d, e, tol, max_it)
+        else:
+            lam, st = self.solve_block(d, e, tol, max_it, full_reorth=full_reorth)
+        u = self.recover(lam, d, g)
+        return lam, u, st
+
+
+# =========================================================================== brute force
+
+def global_solve(problem):
+    """Assembled global problem K u = f (eq. 1) with u = 0 on the Dirichlet nodes.
+
+    The global matrix is assembled from the global node numbering (occurrence
+    stiffness rotated to the global frame), independently of the multipliers.
+    Returns u per occurrence (pattern frame) and the global vector.
+    """
+    pb = problem
+    dpn = pb.dpn
+    n = pb.n_gnodes * dpn
+    rows, cols, vals = [], [], []
+    f = np.zeros((n, pb.n_rhs))
+    for s in range(pb.n_occ):
+        pat = pb.patterns[pb.occ_pattern[s]]
+        O = pb.occ_rot[s][:dpn, :dpn] if dpn > 1 else np.ones((1, 1))
+        R = sp.kron(sp.identity(pat.n_nodes), sp.csr_matrix(O)).tocsr()
+        Kg = (R @ pat.K @ R.T).tocoo()
+        gd = (pb.occ_gnode[s][:, None] * dpn + np.arange(dpn)[None, :]).ravel()
+        rows.append(gd[Kg.row])
+        cols.append(gd[Kg.col])
+        vals.append(Kg.data)
+        np.add.at(f, gd, R @ pb.f_local[s])
+    K = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    fixed = np.zeros(n, bool)
+    for c in range(dpn):
+        fixed[pb.dirichlet_gnodes * dpn + c] = True
+    free = np.nonzero(~fixed)[0]
+    Kf = K[free][:, free].tocsc()
+    ug = np.zeros((n, pb.n_rhs))
+    if len(free) <= 3000:
+        ug[free] = sla.cho_solve(sla.cho_factor(Kf.toarray()), f[free])
+    else:
+        ug[free] = spla.splu(Kf).solve(f[free])
+    u = []
+    for s in range(pb.n_occ):
+        pat = pb.patterns[pb.occ_pattern[s]]
+        O = pb.occ_rot[s][:dpn, :dpn] if dpn > 1 else np.ones((1, 1))
+        R = sp.kron(sp.identity(pat.n_nodes), sp.csr_matrix(O)).tocsr()
+        gd = (pb.occ_gnode[s][:, None] * dpn + np.arange(dpn)[None, :]).ravel()
+        u.append(R.T @ ug[gd])
+    return u, ug, K, f
+
+
+def multipliers_from_displacements(oracle: FetiOracle, u):
+    """lambda solving B^T lambda = f - K u occurrence by occurrence (rows of eq. 2).
+
+    With non-redundant multipliers B = [A^(s) t^(s)] has full row rank, so lambda is the
+    unique least-squares solution.
+    """
+    pb = oracle.pb
+    blocks_B, blocks_r = [], []
+    for s in range(pb.n_occ):
+        P = oracle.pats[pb.occ_pattern[s]]
+        res = pb.f_local[s] - pb.patterns[pb.occ_pattern[s]].K @ u[s]
+        blocks_B.append(oracle.A[s])
+        blocks_r.append(res[P.b])
+    B = sp.hstack(blocks_B).tocsr()          # N_lambda x sum n_b
+    r = np.vstack(blocks_r)
+    BBt = (B @ B.T).tocsc()
+    return spla.splu(BBt).solve(np.asarray(B @ r))

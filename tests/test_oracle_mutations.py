@@ -1,0 +1,106 @@
+"""Plant plausible mistakes in the CPU oracle and check that its pins notice them.
+
+Every mutant lives here, on the CPU, and is applied by monkeypatching; the
+oracle itself is never modified.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import feti as OF
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def prob():
+    return W.small_elast((2, 2, 2), (2, 2, 2), n_rhs=1, n_perm=2, seed=11)
+
+
+@pytest.fixture(scope="module")
+def brute(prob):
+    ub, _, _, _ = O.global_solve(prob)
+    return ub
+
+
+def _err(u, ub):
+    return max(np.abs(a - b).max() for a, b in zip(u, ub)) / max(np.abs(b).max() for b in ub)
+
+
+def test_reference_passes(prob, brute):
+    _, u, _ = O.FetiOracle(prob).solve("block", tol=1e-11)
+    assert _err(u, brute) < 1e-9
+
+
+def test_dropped_kernel_term_in_pseudo_inverse_is_caught(prob, monkeypatch):
+    monkeypatch.setattr(OF, "pseudo_inverse", lambda S, Z: np.linalg.inv(S + Z @ Z.T))
+    P = OF.PatternOracle(prob.patterns[0].K, prob.patterns[0].bdofs, 6)
+    # the Moore-Penrose pin fails (the solution itself would not notice: Q removes G G^T)
+    assert np.abs(P.Splus - np.linalg.pinv(P.S, rcond=1e-10)).max() > 1e-3 * np.abs(P.Splus).max()
+
+
+def test_wrong_sign_of_kernel_term_in_recovery_is_caught(prob, brute, monkeypatch):
+    o = O.FetiOracle(prob)
+    orig = o.coarse_solve
+    g, d, e = o.loads()
+    lam, _ = o.solve_block(d, e, 1e-11)
+    monkeypatch.setattr(o, "coarse_solve", lambda c: -orig(c))
+    u = o.recover(lam, d, g)
+    assert _err(u, brute) > 1e-3
+
+
+def test_wrong_sign_in_condensed_load_is_caught(prob, brute, monkeypatch):
+    def bad(self, f):
+        return f[self.b] + self.Kib.T @ self.lu.solve(np.ascontiguousarray(f[self.i]))
+    monkeypatch.setattr(OF.PatternOracle, "condensed_load", bad)
+    _, u, _ = O.FetiOracle(prob).solve("block", tol=1e-11)
+    assert _err(u, brute) > 1e-3
+
+
+def test_unsigned_assembly_is_caught(prob):
+    bad = prob.mult_sign.copy()
+    bad[:] = np.abs(bad)
+    p2 = W.small_elast((2, 2, 2), (2, 2, 2), n_rhs=1, n_perm=2, seed=11)
+    p2.mult_sign = bad
+    o = O.FetiOracle(p2)
+    rng = np.random.default_rng(3)
+    ug = rng.standard_normal((p2.n_gnodes, 3))
+    total = sum(o.A[s] @ ug[p2.occ_gnode[s]].ravel()[o.pats[0].b] for s in range(p2.n_occ))
+    nd = p2.n_dirichlet_mult() * 3
+    assert np.abs(total[:p2.n_lambda - nd]).max() > 0.1      # continuity pin fails
+
+
+def test_reversed_permutation_is_caught():
+    p = W.ring_heat(3, (2, 2), n_perm=3)
+    p.perm_node = p.perm_node[[0, 2, 1]]        # Pi_k -> Pi_{-k}
+    o = O.FetiOracle(p)
+    nn = 3
+    w = np.zeros((p.n_lambda, 1))
+    for s in range(3):
+        w[nn * s:nn * (s + 1), 0] = s + 1
+    Wt = o.permute(w)
+    # paper: second column starts with w23
+    assert not np.array_equal(Wt[:nn, 1], w[nn:2 * nn, 0])
+
+
+def test_projector_with_wrong_sign_is_caught(prob, monkeypatch):
+    o = O.FetiOracle(prob)
+    monkeypatch.setattr(o, "Q", lambda X: X + o.G @ o.coarse_solve(o.G.T @ X))
+    X = np.random.default_rng(0).standard_normal((prob.n_lambda, 2))
+    QX = o.Q(X)
+    assert np.abs(o.G.T @ QX).max() > 1e-3
+
+
+def test_operator_drift_inside_block_solver_is_caught(prob, brute, monkeypatch):
+    """An F that changes between iterations (e.g. a stale or mis-scaled operand) is noticed."""
+    o = O.FetiOracle(prob)
+    g, d, e = o.loads()
+    orig_F = o.F
+    calls = {"n": 0}
+
+    def F_scaled(X):
+        calls["n"] += 1
+        return orig_F(X) * (1.0 if calls["n"] < 3 else 1.0 + 1e-3)   # operator drift mid-solve
+    monkeypatch.setattr(o, "F", F_scaled)
+    lam, st = o.solve_block(d, e, 1e-11, max_it=300)
+    u = o.recover(lam, d, g)
+    assert _err(u, brute) > 1e-6

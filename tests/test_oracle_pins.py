@@ -1,0 +1,338 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test names the passage it checks.  A plausible mistake in the oracle (a
+dropped term, a wrong sign, a transposed operand) must fail at least one of
+them; tests/test_oracle_mutations.py plants such mistakes and checks that.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+from workloads import mesh as M
+
+
+# ----------------------------------------------------------------------------- elements
+
+def test_quad_element_closed_form():
+    Ke = M.quad_laplace(0.3, 0.3)
+    ref = np.array([[4, -1, -2, -1], [-1, 4, -1, -2], [-2, -1, 4, -1], [-1, -2, -1, 4]]) / 6.0
+    assert np.abs(Ke - ref).max() < 1e-15
+
+
+def _rigid_modes(coords):
+    n = coords.shape[0]
+    R = np.zeros((n, 3, 6))
+    for c in range(3):
+        R[:, c, c] = 1.0
+    x, y, z = coords[:, 0], coords[:, 1], coords[:, 2]
+    R[:, 0, 3], R[:, 1, 3] = -y, x          # about z
+    R[:, 1, 4], R[:, 2, 4] = -z, y          # about x
+    R[:, 0, 5], R[:, 2, 5] = z, -x          # about y
+    return R.reshape(3 * n, 6)
+
+
+def test_hex_element_rank_kernel_and_patch():
+    Ke = M.hex_elasticity(0.1, 0.2, 0.15)
+    assert np.abs(Ke - Ke.T).max() < 1e-14
+    w = np.linalg.eigvalsh(Ke)
+    assert (np.abs(w) < 1e-12 * w.max()).sum() == 6
+    X = ((M.HEX_NODES + 1) / 2) * np.array([0.1, 0.2, 0.15])
+    assert np.abs(Ke @ _rigid_modes(X)).max() < 1e-13 * np.abs(Ke).max()
+    # patch test: a linear field on a 2x2x2 patch leaves no force on the centre node
+    mesh = M.GridMesh((2, 2, 2), (1.0, 1.3, 0.7))
+    K = M.assemble(mesh, M.hex_elasticity(*mesh.h), 3)
+    Aff = np.array([[0.3, -0.2, 0.5], [0.1, 0.7, -0.4], [0.6, 0.2, 0.9]])
+    u = (mesh.coords @ Aff.T).ravel()
+    centre = mesh.node_id([1, 1, 1])
+    assert np.abs((K @ u)[3 * centre:3 * centre + 3]).max() < 1e-13
+
+
+def test_general_hex_matches_box():
+    X = ((M.HEX_NODES + 1) / 2) * np.array([0.1, 0.2, 0.15])
+    assert np.abs(M.hex_elasticity_general(X) - M.hex_elasticity(0.1, 0.2, 0.15)).max() < 1e-13
+
+
+# ----------------------------------------------------------------------------- generator
+
+def test_grid_structure_matches_directly_meshed_global_grid():
+    """Occurrences placed on the grid assemble to the stiffness of the directly meshed domain."""
+    p = W.small_elast((2, 3, 2), (2, 2, 1))
+    _, _, Kocc, _ = O.global_solve(p)
+    gm = M.GridMesh((4, 6, 2), (1.0, 1.0, 0.5))
+    Kdir = M.assemble(gm, M.hex_elasticity(*gm.h), 3)
+    assert abs(Kocc - Kdir).max() < 1e-14
+
+
+def test_multiplier_counts_config1():
+    p = W.config(1)
+    pat = p.patterns[0]
+    assert pat.n == 6591 and pat.n_b == 2598
+    assert p.n_lambda == 76080 and p.n_dirichlet_mult() * 3 == 7203
+
+
+# ----------------------------------------------------------------------------- pattern level
+
+@pytest.fixture(scope="module")
+def elast_small():
+    p = W.small_elast((3, 3, 3), (3, 2, 2), n_rhs=2, n_perm=4)
+    return p, O.FetiOracle(p)
+
+
+def test_schur_equals_dense(elast_small):
+    p, o = elast_small
+    P = o.pats[0]
+    K = p.patterns[0].K.toarray()
+    b, i = P.b, P.i
+    S = K[np.ix_(b, b)] - K[np.ix_(b, i)] @ np.linalg.solve(K[np.ix_(i, i)], K[np.ix_(i, b)])
+    assert np.abs(S - P.S).max() < 1e-12 * np.abs(S).max()
+
+
+def test_kernel_is_rigid_body_motion(elast_small):
+    p, o = elast_small
+    P = o.pats[0]
+    pat = p.patterns[0]
+    R = _rigid_modes(pat.coords)
+    assert np.abs(pat.K @ R).max() < 1e-13 * abs(pat.K).max()
+    assert P.k == 6
+    Qr, _ = np.linalg.qr(R[P.b])
+    assert np.linalg.norm(P.Z - Qr @ (Qr.T @ P.Z)) < 1e-10
+    assert np.abs(P.Z.T @ P.Z - np.eye(6)).max() < 1e-13
+    # N spans the kernel of K
+    assert np.abs(pat.K @ P.N).max() < 1e-11
+
+
+def test_heat_kernel_is_constant():
+    p = W.config(0)
+    P = O.PatternOracle(p.patterns[0].K, p.patterns[0].bdofs, 1)
+    z = P.Z[:, 0] * np.sign(P.Z[0, 0])
+    assert np.abs(z - 1 / np.sqrt(len(z))).max() < 1e-12
+
+
+def test_pseudo_inverse_is_moore_penrose(elast_small):
+    p, o = elast_small
+    P = o.pats[0]
+    assert np.abs(P.Splus - np.linalg.pinv(P.S, rcond=1e-10)).max() < 1e-9 * np.abs(P.Splus).max()
+    assert np.abs(P.S @ P.Splus @ P.S - P.S).max() < 1e-10 * np.abs(P.S).max()
+
+
+def test_generalized_inverse_identity(elast_small):
+    """Section 2: S+ = t K+ t^T, read as S (t K^g t^T) S = S for a generalized inverse K^g."""
+    p, o = elast_small
+    P = o.pats[0]
+    K = p.patterns[0].K.toarray()
+    Kg = np.linalg.pinv(K, rcond=1e-12)
+    T = Kg[np.ix_(P.b, P.b)]
+    assert np.abs(P.S @ T @ P.S - P.S).max() < 1e-9 * np.abs(P.S).max()
+
+
+def test_condensed_load(elast_small):
+    p, o = elast_small
+    P = o.pats[0]
+    K = p.patterns[0].K.toarray()
+    f = p.f_local[3]
+    b, i = P.b, P.i
+    g = f[b] - K[np.ix_(b, i)] @ np.linalg.solve(K[np.ix_(i, i)], f[i])
+    assert np.abs(P.condensed_load(f) - g).max() < 1e-12 * np.abs(g).max()
+
+
+# ----------------------------------------------------------------------------- interface level
+
+def test_continuity_of_a_global_field(elast_small):
+    """Eq. 2, second row: sum_s A^(s) t u^(s) = 0 for a globally continuous field."""
+    p, o = elast_small
+    rng = np.random.default_rng(3)
+    ug = rng.standard_normal((p.n_gnodes, 3))
+    total = np.zeros(p.n_lambda)
+    for s in range(p.n_occ):
+        us = ug[p.occ_gnode[s]].ravel()
+        total += o.A[s] @ us[o.pats[0].b]
+    # Dirichlet rows see u itself; zero it on Dirichlet nodes to test interfaces only
+    nd = p.n_dirichlet_mult() * 3
+    assert np.abs(total[:p.n_lambda - nd]).max() < 1e-14
+    assert np.abs(total[p.n_lambda - nd:]).max() > 0.1
+
+
+def test_ring_w_format_antisymmetry(golden_dir):
+    """Section 3.2: the W format stores w^(s,s+1) and w^(s,s-1) = -w^(s-1,s) per occurrence."""
+    gold = json.load(open(os.path.join(golden_dir, "ring_w_format.json")))
+    p = W.ring_heat(3, (1, 1), n_perm=3)
+    o = O.FetiOracle(p)
+    # multipliers per node pair: interface (s,s+1) holds nodes 2*s, 2*s+1
+    lam = np.zeros(p.n_lambda)
+    names = gold["w"]
+    vals = {names[s]: 10.0 * (s + 1) for s in range(3)}
+    for s in range(3):
+        lam[2 * s:2 * s + 2] = vals[names[s]]
+    pat = p.patterns[0]
+    for s in range(3):
+        local = o.A[s].T @ lam
+        right = [np.nonzero(pat.bnodes == n)[0][0] for n in (1, 3)]   # ix = 1 edge
+        left = [np.nonzero(pat.bnodes == n)[0][0] for n in (0, 2)]    # ix = 0 edge
+        top, bot = gold["W"][0][s], gold["W"][1][s]
+        assert np.allclose(local[right], float(top[0] + "1") * vals[top[1:]])
+        assert np.allclose(local[left], float(bot[0] + "1") * vals[bot[1:]])
+
+
+def test_ring_multivector_is_circulant(golden_dir):
+    gold = json.load(open(os.path.join(golden_dir, "ring_multivector.json")))
+    p = W.ring_heat(3, (2, 2), n_perm=3)
+    o = O.FetiOracle(p)
+    nn = 3                      # nodes per interface edge (ny + 1)
+    w = np.zeros((p.n_lambda, 1))
+    names = gold["w"]
+    for s in range(3):
+        w[nn * s:nn * (s + 1), 0] = (s + 1) * 100 + np.arange(nn)
+    Wt = o.permute(w)
+    for row in range(3):
+        for col in range(3):
+            src = names.index(gold["w_tilde"][row][col])
+            assert np.array_equal(Wt[nn * row:nn * (row + 1), col], w[nn * src:nn * (src + 1), 0])
+
+
+def test_stand_interface_replicated(golden_dir):
+    gold = json.load(open(os.path.join(golden_dir, "stand_multivector.json")))
+    p = W.ring_heat(3, (2, 2), stand=True, n_perm=3)
+    o = O.FetiOracle(p)
+    w = np.arange(p.n_lambda, dtype=float)[:, None] + 1
+    Wt = o.permute(w)
+    ring = p.mult_occ[:, 1] < 3
+    ring &= p.mult_occ[:, 0] < 3
+    stand = ~ring
+    # every stand multiplier (interface (3,4) and its corner links) keeps its own value
+    assert stand.any()
+    for col in range(3):
+        assert np.array_equal(Wt[stand, col], w[stand, 0])
+    # the ring interior-edge multipliers rotate as in the three-occurrence ring
+    assert not np.array_equal(Wt[ring, 1], w[ring, 0])
+    assert gold["w_tilde"][3] == ["34", "34", "34"]
+
+
+def test_ring_coarse_G_structure(golden_dir):
+    """Section 5.3: block structure and signs of G on a three-occurrence ring."""
+    gold = json.load(open(os.path.join(golden_dir, "ring_coarse_G.json")))
+    p = W.ring_heat(3, (2, 2), n_perm=3, dirichlet_bottom=False)
+    o = O.FetiOracle(p)
+    G = o.G.toarray()
+    nn = 3
+    z = o.pats[0].Z[0, 0]
+    for row in range(3):
+        for col in range(3):
+            blk = G[nn * row:nn * (row + 1), col]
+            want = gold["blocks"][row][col]
+            if want == "0":
+                assert np.all(blk == 0)
+            else:
+                sign = 1.0 if want[0] == "+" else -1.0
+                assert np.allclose(blk, sign * z, atol=1e-14)
+
+
+def test_F_symmetric_psd_and_dense(elast_small):
+    p, o = elast_small
+    F = o.F(np.eye(p.n_lambda))
+    assert np.abs(F - F.T).max() < 1e-12 * np.abs(F).max()
+    assert np.linalg.eigvalsh(F).min() > -1e-10 * np.abs(F).max()
+    Fd = sum(o.A[s].toarray() @ o.pats[0].Splus @ o.A[s].toarray().T for s in range(p.n_occ))
+    assert np.abs(F - Fd).max() < 1e-12 * np.abs(F).max()
+
+
+def test_projector_identities(elast_small):
+    """Section 2: Q^2 = Q, G^T Q = 0, G^T lambda_0 = e."""
+    p, o = elast_small
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((p.n_lambda, 3))
+    QX = o.Q(X)
+    assert np.abs(o.Q(QX) - QX).max() < 1e-12 * np.abs(X).max()
+    assert np.abs(o.G.T @ QX).max() < 1e-11
+    g, d, e = o.loads()
+    l0 = o.lambda0(e)
+    assert np.abs(o.G.T @ l0 - e).max() < 1e-11 * np.abs(e).max()
+
+
+def test_periodic_ring_commutation():
+    """Section 3.1: on a truly periodic ring F and the permutations commute."""
+    p = W.ring_heat(5, (3, 3), n_perm=5)
+    o = O.FetiOracle(p)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((p.n_lambda, 1))
+    Pk = p.perm_dof()
+    for k in range(1, 5):
+        lhs = o.F(x[Pk[k]])
+        rhs = o.F(x)[Pk[k]]
+        assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+
+
+# ----------------------------------------------------------------------------- solvers
+
+def test_heat_row_closed_form(golden_dir):
+    gold = json.load(open(os.path.join(golden_dir, "heat_row_closed_form.json")))
+    p = W.config(0)
+    o = O.FetiOracle(p)
+    for method in ("classical", "block"):
+        lam, u, st = o.solve(method)
+        x = p.patterns[0].coords[:, 0]
+        for s in range(4):
+            xs = x + s
+            assert np.abs(u[s][:, 0] - xs * (8 - xs) / 2).max() < 1e-9
+    assert max(u[3][:, 0]) == pytest.approx(gold["u_max"], abs=1e-9)
+
+
+def test_brute_force_elasticity(elast_small):
+    p, o = elast_small
+    ub, _, _, _ = O.global_solve(p)
+    scale = max(np.abs(x).max() for x in ub)
+    for method, fr in (("classical", True), ("block", True), ("block", False)):
+        lam, u, st = o.solve(method, tol=1e-11, full_reorth=fr)
+        err = max(np.abs(ub[s] - u[s]).max() for s in range(p.n_occ)) / scale
+        assert err < 1e-9, (method, fr, err)
+    lb = O.multipliers_from_displacements(o, ub)
+    assert np.abs(lb - lam).max() < 1e-8 * np.abs(lam).max()
+
+
+def test_equilibrium_and_continuity_of_solution(elast_small):
+    p, o = elast_small
+    lam, u, st = o.solve("block", tol=1e-11)
+    g, d, e = o.loads()
+    assert np.abs(o.G.T @ lam - e).max() < 1e-10 * np.abs(e).max()
+    cont = sum(o.A[s] @ u[s][o.pats[0].b] for s in range(p.n_occ))
+    assert np.abs(cont).max() < 1e-9 * max(np.abs(x).max() for x in u)
+    # each floating occurrence is in equilibrium against its rigid modes
+    for s in range(p.n_occ):
+        P = o.pats[0]
+        lb = o.A[s].T @ lam
+        res = P.N.T @ p.f_local[s] - P.Z.T @ lb
+        assert np.abs(res).max() < 1e-9 * np.abs(p.f_local[s]).max()
+
+
+def test_block_single_direction_equals_classical():
+    """Table 1: with one direction per iteration the multivector column reduces to the classical one."""
+    p = W.small_elast((2, 2, 2), (2, 2, 1), n_rhs=1, n_perm=1)
+    o = O.FetiOracle(p)
+    g, d, e = o.loads()
+    rc, rb = [], []
+    o.solve_classical(d, e, 1e-10, record=rc)
+    o.solve_block(d, e, 1e-10, full_reorth=True, record=rb)
+    n = min(20, len(rc), len(rb))
+    for j in range(n):
+        assert np.abs(rc[j] - rb[j][:, 0]).max() < 1e-10 * np.abs(rc[j]).max()
+
+
+def test_classical_converges_within_rank():
+    p = W.small_heat((2, 2), (3, 1), n_rhs=1)
+    o = O.FetiOracle(p)
+    g, d, e = o.loads()
+    lam, st = o.solve_classical(d, e, 1e-12)
+    assert st["iterations"][0] <= p.n_lambda - o.G.shape[1] + 1
+
+
+def test_block_not_slower_than_classical():
+    """Sections 3.1 and 6: the multivector method needs no more iterations (soft check)."""
+    p = W.config(0)
+    o = O.FetiOracle(p)
+    _, _, sc = o.solve("classical")
+    _, _, sb = o.solve("block")
+    assert sb["iterations"] <= max(sc["iterations"])

@@ -1,0 +1,352 @@
+"""Seeded synthetic structures made of repeated patterns.
+
+A ``Problem`` is the statement of the method's input (the dual split of
+section 2, eq. 2): for every pattern its Neumann stiffness K (CSR) and the set
+of boundary nodes, for every occurrence the pattern it instantiates, its
+rotation O (pattern frame -> global frame, section 5.2) and its loads f, and
+the signed Boolean assembly A as a list of multipliers, each joining one node of
+one occurrence (sign +1) to one node of another (sign -1), or, for a Dirichlet
+condition imposed by a multiplier (Total FETI reading of section 5.1.3), to a
+single node.  It also carries the permutation maps used to build multivectors
+(section 4.1): index structure, not arithmetic.
+
+Readings taken here (the paper does not define them for 3-D grids):
+
+* multipliers at nodes shared by q > 2 occurrences form a non-redundant chain
+  of q-1 links in ascending occurrence id; each Dirichlet node gets one
+  multiplier on the lowest-id occurrence that holds it;
+* the pattern boundary is the union of the local nodes that carry a multiplier
+  in any occurrence of the pattern;
+* permutation classes group multipliers with the same (pattern, local node)
+  pair at both ends; Pi_k shifts every class cyclically by k positions in
+  ascending occurrence order; a multiplier in a class of size one is kept.
+
+Everything random is drawn from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import mesh as M
+
+BASE_SEED = 12086387
+
+
+@dataclass
+class Pattern:
+    name: str
+    dpn: int
+    coords: np.ndarray            # (n_nodes, dim) pattern frame
+    K: sp.csr_matrix              # (n, n) full symmetric, Neumann (floating)
+    kernel_dim: int               # rigid modes of the free pattern
+    bnodes: np.ndarray = None     # sorted local boundary nodes
+
+    @property
+    def n_nodes(self) -> int:
+        return self.coords.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.n_nodes * self.dpn
+
+    @property
+    def bdofs(self) -> np.ndarray:
+        return (self.bnodes[:, None] * self.dpn + np.arange(self.dpn)[None, :]).ravel().astype(np.int32)
+
+    @property
+    def n_b(self) -> int:
+        return len(self.bnodes) * self.dpn
+
+
+@dataclass
+class Problem:
+    name: str
+    dpn: int
+    patterns: List[Pattern]
+    occ_pattern: np.ndarray       # (n_occ,) int32
+    occ_rot: np.ndarray           # (n_occ, 3, 3) pattern frame -> global frame
+    occ_gnode: List[np.ndarray]   # per occurrence: local node -> global node
+    n_gnodes: int
+    dirichlet_gnodes: np.ndarray  # global nodes with u = 0
+    mult_occ: np.ndarray          # (N_mn, 2) int32, -1 = no second endpoint
+    mult_node: np.ndarray         # (N_mn, 2) int32 local node at each endpoint
+    mult_sign: np.ndarray         # (N_mn, 2) int8
+    n_rhs: int
+    f_local: List[np.ndarray]     # per occurrence (n_p, n_rhs), pattern frame
+    perm_node: np.ndarray         # (n_perm, N_mn) int32: (Pi_k z)[mn] = z[perm_node[k, mn]]
+    tol: float = 1e-8
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_occ(self) -> int:
+        return len(self.occ_pattern)
+
+    @property
+    def n_mult_nodes(self) -> int:
+        return self.mult_occ.shape[0]
+
+    @property
+    def n_lambda(self) -> int:
+        return self.n_mult_nodes * self.dpn
+
+    @property
+    def n_perm(self) -> int:
+        return self.perm_node.shape[0]
+
+    @property
+    def has_rotation(self) -> bool:
+        return not np.allclose(self.occ_rot, np.eye(3)[None], atol=0.0, rtol=0.0)
+
+    def perm_dof(self) -> np.ndarray:
+        """(n_perm, N_lambda) dof-level permutation source index."""
+        d = self.dpn
+        return (self.perm_node[:, :, None] * d + np.arange(d)[None, None, :]).reshape(self.n_perm, -1).astype(np.int32)
+
+    def n_dirichlet_mult(self) -> int:
+        return int((self.mult_occ[:, 1] < 0).sum())
+
+
+# --------------------------------------------------------------------------- multipliers
+
+def chain_multipliers(occ, lnode, gnode, is_dirichlet_g, swap_rule=None):
+    """Non-redundant signed Boolean multipliers for copies (occ, lnode) of global nodes.
+
+    Returns (mult_occ, mult_node, mult_sign) at node level, interface links first,
+    ordered by (occ_A, occ_B, node_A), then Dirichlet multipliers ordered by (occ, node).
+    """
+    occ = np.asarray(occ, np.int64)
+    lnode = np.asarray(lnode, np.int64)
+    gnode = np.asarray(gnode, np.int64)
+    order = np.lexsort((occ, gnode))
+    o, l, g = occ[order], lnode[order], gnode[order]
+    same = g[1:] == g[:-1]
+    a = np.nonzero(same)[0]
+    oa, la, ob, lb = o[a], l[a], o[a + 1], l[a + 1]
+    if swap_rule is not None:
+        sw = swap_rule(oa, la, ob, lb)
+        oa, ob = np.where(sw, ob, oa), np.where(sw, oa, ob)
+        la, lb = np.where(sw, lb, la), np.where(sw, la, lb)
+    lo = np.lexsort((la, ob, oa))
+    oa, la, ob, lb = oa[lo], la[lo], ob[lo], lb[lo]
+    first = np.ones(len(g), bool)
+    first[1:] = ~same
+    dpos = np.nonzero(first & is_dirichlet_g[g])[0]
+    do, dl = o[dpos], l[dpos]
+    lo = np.lexsort((dl, do))
+    do, dl = do[lo], dl[lo]
+    n_i, n_d = len(oa), len(do)
+    mult_occ = np.full((n_i + n_d, 2), -1, np.int32)
+    mult_node = np.full((n_i + n_d, 2), -1, np.int32)
+    mult_sign = np.zeros((n_i + n_d, 2), np.int8)
+    mult_occ[:n_i, 0], mult_occ[:n_i, 1] = oa, ob
+    mult_node[:n_i, 0], mult_node[:n_i, 1] = la, lb
+    mult_sign[:n_i, 0], mult_sign[:n_i, 1] = 1, -1
+    mult_occ[n_i:, 0], mult_node[n_i:, 0], mult_sign[n_i:, 0] = do, dl, 1
+    return mult_occ, mult_node, mult_sign
+
+
+def pattern_boundaries(patterns, occ_pattern, mult_occ, mult_node):
+    for p, pat in enumerate(patterns):
+        sel = []
+        for e in range(2):
+            ok = mult_occ[:, e] >= 0
+            occs = mult_occ[ok, e]
+            sel.append(mult_node[ok, e][occ_pattern[occs] == p])
+        pat.bnodes = np.unique(np.concatenate(sel)).astype(np.int32)
+
+
+def permutation_maps(occ_pattern, mult_occ, mult_node, n_perm):
+    """Cyclic shifts within classes of equivalent multipliers (section 4.1 and 5.1 examples)."""
+    n = mult_occ.shape[0]
+    pa = occ_pattern[mult_occ[:, 0]]
+    pb = np.where(mult_occ[:, 1] >= 0, occ_pattern[np.maximum(mult_occ[:, 1], 0)], -1)
+    nb = np.where(mult_occ[:, 1] >= 0, mult_node[:, 1], -1)
+    keys = np.stack([pa, pb, mult_node[:, 0], nb], axis=1)
+    _, cls = np.unique(keys, axis=0, return_inverse=True)
+    cls = cls.ravel()
+    # members of a class in ascending (occ_A, occ_B) order, multipliers are already sorted so
+    order = np.lexsort((np.arange(n), mult_occ[:, 1], mult_occ[:, 0], cls))
+    sizes = np.bincount(cls)
+    start = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    pos = np.empty(n, np.int64)
+    pos[order] = np.arange(n) - start[cls[order]]
+    perm = np.empty((n_perm, n), np.int32)
+    for k in range(n_perm):
+        src_pos = (pos + k) % sizes[cls]
+        perm[k] = order[start[cls] + src_pos]
+    return perm
+
+
+# --------------------------------------------------------------------------- builders
+
+def _finish(name, dpn, patterns, occ_pattern, occ_rot, occ_gnode, n_gnodes, dirichlet_g,
+            f_local, n_rhs, n_perm, tol, meta, swap_rule=None):
+    occ_pattern = np.asarray(occ_pattern, np.int32)
+    occ = np.concatenate([np.full(len(g), s) for s, g in enumerate(occ_gnode)])
+    ln = np.concatenate([np.arange(len(g)) for g in occ_gnode])
+    gn = np.concatenate(occ_gnode)
+    isd = np.zeros(n_gnodes, bool)
+    isd[dirichlet_g] = True
+    mo, mn, ms = chain_multipliers(occ, ln, gn, isd, swap_rule)
+    pattern_boundaries(patterns, occ_pattern, mo, mn)
+    perm = permutation_maps(occ_pattern, mo, mn, n_perm)
+    return Problem(name=name, dpn=dpn, patterns=patterns, occ_pattern=occ_pattern,
+                   occ_rot=np.asarray(occ_rot, float), occ_gnode=[np.asarray(g, np.int64) for g in occ_gnode],
+                   n_gnodes=int(n_gnodes), dirichlet_gnodes=np.asarray(dirichlet_g, np.int64),
+                   mult_occ=mo, mult_node=mn, mult_sign=ms, n_rhs=n_rhs, f_local=f_local,
+                   perm_node=perm, tol=tol, meta=meta)
+
+
+def grid_structure(name, kind, pat_shape, pat_size, grid, n_rhs=1, n_perm=1, load="normal",
+                   dirichlet=(0, 0), traction=None, seed=0, tol=1e-8):
+    """Axis-aligned grid of identical box patterns (no rotation).
+
+    kind: 'heat' (2-D quads, 1 dof/node) or 'elast' (3-D bricks, 3 dofs/node).
+    dirichlet: (axis, side) of the global face with u = 0, or None.
+    load: 'unit_source' (consistent loads of f = 1) or 'normal' (i.i.d. N(0,1) nodal forces
+          drawn per occurrence, load case, node, component).
+    traction: optional (axis, side, t) uniform traction on a global face, added to every case.
+    """
+    dim = len(pat_shape)
+    mesh = M.GridMesh(pat_shape, pat_size)
+    if kind == "heat":
+        assert dim == 2
+        dpn, kdim = 1, 1
+        K = M.assemble(mesh, M.quad_laplace(*mesh.h), 1)
+    elif kind == "elast":
+        assert dim == 3
+        dpn, kdim = 3, 6
+        K = M.assemble(mesh, M.hex_elasticity(*mesh.h), 3)
+    else:
+        raise ValueError(kind)
+    pat = Pattern(name=f"{name}-pattern", dpn=dpn, coords=mesh.coords, K=K, kernel_dim=kdim)
+    grid = tuple(grid)
+    gidx = np.indices(grid[::-1]).reshape(dim, -1)[::-1].T  # occurrence grid index, x fastest
+    n_occ = len(gidx)
+    gshape = [grid[d] * pat_shape[d] for d in range(dim)]
+    gnpa = [s + 1 for s in gshape]
+    occ_gnode = []
+    for s in range(n_occ):
+        lat = mesh.lattice + gidx[s] * np.asarray(pat_shape)
+        if dim == 2:
+            gid = lat[:, 0] + gnpa[0] * lat[:, 1]
+        else:
+            gid = lat[:, 0] + gnpa[0] * (lat[:, 1] + gnpa[1] * lat[:, 2])
+        occ_gnode.append(gid)
+    n_g = int(np.prod(gnpa))
+    glat = np.indices(gnpa[::-1]).reshape(dim, -1)[::-1].T
+    if dirichlet is not None:
+        ax, side = dirichlet
+        target = 0 if side == 0 else gshape[ax]
+        dir_g = np.nonzero(glat[:, ax] == target)[0]
+    else:
+        dir_g = np.zeros(0, np.int64)
+    n = mesh.n_nodes * dpn
+    if load == "unit_source":
+        fe = M.quad_unit_source(*mesh.h)
+        fp = M.assemble_vector(mesh, fe, dpn)
+        f_local = [np.repeat(fp[:, None], n_rhs, axis=1) for _ in range(n_occ)]
+    elif load == "normal":
+        rng = np.random.Generator(np.random.PCG64(seed))
+        draws = rng.standard_normal((n_occ, n_rhs, mesh.n_nodes, dpn))
+        f_local = [np.ascontiguousarray(draws[s].reshape(n_rhs, n).T) for s in range(n_occ)]
+    else:
+        raise ValueError(load)
+    if traction is not None:
+        ax, side, t = traction
+        ft = M.face_traction_load(mesh, ax, side, t)
+        for s in range(n_occ):
+            if gidx[s, ax] == (grid[ax] - 1 if side == 1 else 0):
+                f_local[s] = f_local[s] + ft[:, None]
+    rot = np.repeat(np.eye(3)[None], n_occ, axis=0)
+    meta = dict(kind=kind, pat_shape=tuple(pat_shape), pat_size=tuple(pat_size), grid=grid,
+                grid_index=gidx, global_shape=tuple(gshape), load=load, seed=seed)
+    return _finish(name, dpn, [pat], np.zeros(n_occ, np.int32), rot, occ_gnode, n_g, dir_g,
+                   f_local, n_rhs, n_perm, tol, meta)
+
+
+def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed=1, dirichlet_bottom=False):
+    """Periodic ring of unit-square heat patterns (section 3's toy problem, cut open as a strip
+    whose last right edge is glued to the first left edge).  Interface (s, s+1) has the right edge
+    of s as its '+' side.  stand=True adds one stand pattern (a 1 x 1/2 rectangle) on top of
+    occurrence n_occ-1 (section 5.1.1).  dirichlet_bottom fixes the bottom edge of occurrence 0.
+    """
+    nx, ny = pat_shape
+    mesh = M.GridMesh(pat_shape, (1.0, 1.0))
+    K = M.assemble(mesh, M.quad_laplace(*mesh.h), 1)
+    pats = [Pattern("ring-pattern", 1, mesh.coords, K, 1)]
+    W = n_occ * nx
+    occ_gnode = []
+    for s in range(n_occ):
+        gx = (mesh.lattice[:, 0] + s * nx) % W
+        occ_gnode.append(gx + W * mesh.lattice[:, 1])
+    occ_pattern = [0] * n_occ
+    n_g = W * (ny + 1)
+    if stand:
+        smesh = M.GridMesh((nx, max(ny // 2, 1)), (1.0, 0.5))
+        Ks = M.assemble(smesh, M.quad_laplace(*smesh.h), 1)
+        pats.append(Pattern("stand-pattern", 1, smesh.coords, Ks, 1))
+        s_last = n_occ - 1
+        gx = (smesh.lattice[:, 0] + s_last * nx) % W
+        iy = smesh.lattice[:, 1]
+        gid = np.where(iy == 0, gx + W * ny, n_g + gx + W * (iy - 1))
+        occ_gnode.append(gid)
+        occ_pattern.append(1)
+        n_g = n_g + W * smesh.shape[1]
+    dir_g = np.nonzero((np.arange(n_g) < W) & (np.arange(n_g) < nx + 1))[0] if dirichlet_bottom else np.zeros(0, np.int64)
+    n_total = len(occ_gnode)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f_local = [rng.standard_normal((len(g), n_rhs)) for g in occ_gnode]
+    rot = np.repeat(np.eye(3)[None], n_total, axis=0)
+
+    def swap(oa, la, ob, lb):
+        # make the right edge of the ring occurrence the '+' side of a ring interface
+        ring = (oa < n_occ) & (ob < n_occ)
+        return ring & (la % (nx + 1) == 0) & (lb % (nx + 1) == nx)
+
+    meta = dict(kind="heat", ring=n_occ, stand=stand, grid=(n_occ,), pat_shape=pat_shape)
+    return _finish(f"ring{n_occ}{'-stand' if stand else ''}", 1, pats, occ_pattern, rot, occ_gnode,
+                   n_g, dir_g, f_local, n_rhs, n_perm if n_perm is not None else n_occ, 1e-10, meta,
+                   swap_rule=swap)
+
+
+# --------------------------------------------------------------------------- named configurations
+
+def config(i: int, small: bool = False) -> Problem:
+    """The five benchmark configurations, 0-based (seed 12086387 + i).
+
+    0: 2-D heat, 16x16 Q1 square pattern, 1x4 row, f = 1, u = 0 on the left edge.
+    1: 3-D elasticity, 12^3 brick pattern, 4x4x4 grid, clamped x = 0, N(0,1) nodal forces.
+    2: same with 8 load cases.
+    3: uneven three-pattern batch (not built here yet).
+    4: 20^3 brick pattern, 8x8x8 grid, 16 load cases plus traction (1,0,0) on x = 1.
+    """
+    seed = BASE_SEED + i
+    if i == 0:
+        return grid_structure("heat-row-16x16x4", "heat", (16, 16), (1.0, 1.0), (4, 1), n_rhs=1, n_perm=3,
+                              load="unit_source", dirichlet=(0, 0), seed=seed, tol=1e-10)
+    if i == 1:
+        return grid_structure("elast-12cube-4x4x4", "elast", (12, 12, 12), (0.25,) * 3, (4, 4, 4), n_rhs=1,
+                              n_perm=8, dirichlet=(0, 0), seed=seed)
+    if i == 2:
+        return grid_structure("elast-12cube-4x4x4-8rhs", "elast", (12, 12, 12), (0.25,) * 3, (4, 4, 4), n_rhs=8,
+                              n_perm=1, dirichlet=(0, 0), seed=seed)
+    if i == 4:
+        return grid_structure("elast-20cube-8x8x8-16rhs", "elast", (20, 20, 20), (0.125,) * 3, (8, 8, 8),
+                              n_rhs=16, n_perm=1, dirichlet=(0, 0), traction=(0, 1, (1.0, 0.0, 0.0)), seed=seed)
+    raise NotImplementedError(f"configuration {i}")
+
+
+def small_elast(pat=(3, 3, 3), grid=(2, 2, 2), n_rhs=1, n_perm=1, seed=7, traction=None):
+    side = 1.0 / max(grid)
+    return grid_structure(f"elast-{pat[0]}cube-{'x'.join(map(str, grid))}", "elast", pat, (side,) * 3, grid,
+                          n_rhs=n_rhs, n_perm=n_perm, dirichlet=(0, 0), traction=traction, seed=seed)
+
+
+def small_heat(pat=(4, 4), grid=(3, 2), n_rhs=1, n_perm=1, seed=5, load="normal"):
+    return grid_structure(f"heat-{pat[0]}sq-{'x'.join(map(str, grid))}", "heat", pat, (1.0, 1.0), grid,
+                          n_rhs=n_rhs, n_perm=n_perm, load=load, dirichlet=(0, 0), seed=seed, tol=1e-10)
