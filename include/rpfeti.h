@@ -1,0 +1,213 @@
+/*
+ * rpfeti.h -- C ABI of the repeated-pattern FETI hot path on MI355X (gfx950).
+ *
+ * Method: Gosselet, Rixen, Rey, "A domain decomposition strategy to
+ * efficiently solve structures containing repeated patterns".  A structure is
+ * a set of occurrences of a few patterns.  All occurrences of a pattern share
+ * one Neumann stiffness K, so the library factors K once per pattern,
+ * condenses it to the dense boundary flexibility S+ = t K+ t^T (section 2),
+ * and applies the dual operator F = sum_s A^(s) S+ A^(s)T to the interface
+ * vectors of every occurrence at once as one matrix product (section 4.2).
+ * The interface problem (eq. 3) is solved by projected multivector CG
+ * (Table 1) with full re-orthogonalisation and F-normalisation (section 4.3).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns an rpf_status; on failure rpf_last_error() gives a
+ *    thread-local message.  No C++ exception crosses the ABI.
+ *  - "device" pointers are HIP device memory owned by the caller, which must
+ *    stay valid until the work queued on `stream` has completed.  "host"
+ *    pointers are read before the call returns and may be freed afterwards.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Dense matrices are column-major FP64 with an explicit leading dimension.
+ *    Interface (lambda-space) blocks are N_lambda x m, row-major: entry (l, j)
+ *    at X[l * ldx + j], ldx >= m.
+ *  - Handles (rpf_pattern, rpf_problem) own their device memory; free them
+ *    with pattern_free / problem_free.  A handle may be used from one thread
+ *    (and one stream) at a time.
+ */
+#ifndef RPFETI_H
+#define RPFETI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RPF_OK = 0,
+  RPF_EINVAL = -1,      /* bad argument or inconsistent sizes */
+  RPF_ENOTSPD = -2,     /* non-positive pivot in a Cholesky factor that must be SPD */
+  RPF_EKERNEL = -3,     /* detected kernel dimension differs from the expected one */
+  RPF_EBREAKDOWN = -4,  /* every search direction of a block vanished (eta of rank 0) */
+  RPF_ENOCONV = -5,     /* max_it reached; outputs hold the last iterate */
+  RPF_EHIP = -6,        /* HIP runtime error */
+  RPF_ENOMEM = -7       /* device allocation failed */
+} rpf_status;
+
+/* Arithmetic of the flexibility product (section 4.2 product S+ W).  FP64 is
+ * the plain form.  FP32 stores S+ and W in FP32 with FP32 MFMA accumulation.
+ * BF16X3 splits S+ and W into bf16 high and low parts and accumulates the
+ * three leading cross products in FP32 on bf16 MFMA.  BF16 uses the high
+ * parts only.  Every non-FP64 form is wrapped by FP64 iterative refinement in
+ * block_krylov_solve. */
+typedef enum { RPF_FP64 = 0, RPF_FP32 = 1, RPF_BF16X3 = 2, RPF_BF16 = 3 } rpf_prec;
+
+typedef struct rpf_pattern_s* rpf_pattern;
+typedef struct rpf_problem_s* rpf_problem;
+
+/* Thread-local description of the last failure in this thread. */
+const char* rpf_last_error(void);
+/* ABI version (major * 100 + minor). */
+int32_t rpf_version(void);
+
+/* ------------------------------------------------------------------ patterns */
+
+/* Factor one pattern: interior Cholesky, Schur complement and rigid-mode
+ * kernel (section 2: floating subdomains, kernel N, local Schur complement S).
+ *
+ *  n                  pattern dofs
+ *  rowptr, colind     host, CSR structure of the full symmetric K (n+1, nnz);
+ *                     every row must hold its diagonal
+ *  val                device, nnz FP64 values of K (Neumann stiffness)
+ *  n_b, bdofs         host, the boundary dofs t (sorted, distinct, < n)
+ *  dofs_per_node      1..3; bdofs must list whole nodes, components consecutive
+ *  kernel_tol         Ritz values of S below kernel_tol * ||S||_inf span the
+ *                     kernel (1e-10 when <= 0)
+ *  expected_kernel_dim  -1 for no check, else RPF_EKERNEL on mismatch
+ *  out                receives the handle; *kernel_dim_out the kernel dimension
+ *
+ * Interior dofs keep their input order; the interior factor exploits the
+ * envelope (profile) of K_ii in that order.  Blocks the host until the kernel
+ * dimension is known.  Errors: RPF_EINVAL, RPF_ENOTSPD (K_ii not SPD),
+ * RPF_EKERNEL, RPF_EHIP, RPF_ENOMEM. */
+rpf_status pattern_factor(int32_t n, const int32_t* rowptr, const int32_t* colind, const double* val,
+                          int32_t n_b, const int32_t* bdofs, int32_t dofs_per_node, double kernel_tol,
+                          int32_t expected_kernel_dim, void* stream, rpf_pattern* out,
+                          int32_t* kernel_dim_out);
+
+/* Condense a factored pattern to its boundary flexibility (section 2:
+ * S+ = t K+ t^T), taken as the Moore-Penrose pseudo-inverse
+ * S+ = (S + Z Z^T)^{-1} - Z Z^T with Z the orthonormal kernel basis.  Always
+ * builds the FP64 S+; prec != RPF_FP64 also builds the low-precision copy used
+ * by that form.  Asynchronous on `stream`.  Errors: RPF_EINVAL, RPF_ENOTSPD. */
+rpf_status pattern_condense(rpf_pattern p, int32_t prec, void* stream);
+
+/* Sizes of a pattern (any output pointer may be NULL). */
+rpf_status pattern_info(rpf_pattern p, int32_t* n, int32_t* n_b, int32_t* kernel_dim);
+
+/* Copy a pattern quantity into caller device memory (column-major, ld):
+ * what = 0: S (n_b x n_b), 1: Z (n_b x k), 2: S+ (n_b x n_b, after condense).
+ * Asynchronous on `stream`. */
+rpf_status pattern_export(rpf_pattern p, int32_t what, double* dst, int64_t ld, void* stream);
+
+void pattern_free(rpf_pattern p);
+
+/* ------------------------------------------------------------------ structure */
+
+/* Signed Boolean assembly and permutation structure (eq. 2; section 4.1;
+ * section 5.2 for rotations).  All pointers are host pointers, copied by
+ * problem_create.
+ *
+ * A multiplier (node level, dofs_per_node components each, lambda dof
+ * l = mult * dofs_per_node + c, expressed in the global frame) joins endpoint
+ * 0 (occurrence mult_occ[2i], local node mult_node[2i], sign mult_sign[2i])
+ * and endpoint 1 (same at 2i+1; mult_occ = -1 for a single-endpoint
+ * multiplier, e.g. a Dirichlet condition imposed in Total FETI fashion).
+ * Each endpoint node must be a boundary node of the occurrence's pattern.
+ * occ_rot: 9 doubles per occurrence, row-major rotation from the pattern
+ * frame to the global frame (used when dofs_per_node == 3), or NULL for
+ * identity.  perm_node: n_perm x n_mult, (Pi_k z)[mult] = z[perm_node[k*n_mult+mult]]
+ * applied to every component, or NULL with n_perm == 1 (identity). */
+typedef struct {
+  int32_t dofs_per_node;
+  int32_t n_patterns;
+  const int32_t* pat_n_nodes;    /* [n_patterns] nodes of each pattern */
+  const int32_t* pat_bnode_ptr;  /* [n_patterns+1] offsets into pat_bnodes */
+  const int32_t* pat_bnodes;     /* sorted boundary nodes of each pattern */
+  int32_t n_occ;
+  const int32_t* occ_pattern;    /* [n_occ] */
+  const double* occ_rot;         /* [9*n_occ] or NULL */
+  int32_t n_mult;
+  const int32_t* mult_occ;       /* [2*n_mult] */
+  const int32_t* mult_node;      /* [2*n_mult] */
+  const int8_t* mult_sign;       /* [2*n_mult], +1 or -1 */
+  int32_t n_perm;
+  const int32_t* perm_node;      /* [n_perm*n_mult] or NULL */
+} rpf_problem_desc;
+
+rpf_status problem_create(const rpf_problem_desc* desc, rpf_problem* out);
+int64_t problem_n_lambda(rpf_problem pb);
+void problem_free(rpf_problem pb);
+
+/* ------------------------------------------------------------------ operator */
+
+#define RPF_APPLY_PROJECT 1u  /* return Q^T F X instead of F X (Q: coarse projector, F~ = I) */
+
+/* Y = F X for an m-column interface block (section 2: F = sum_s A^(s) S+ A^(s)T,
+ * computed pattern by pattern as one product S+ W over all occurrences,
+ * section 4.2).  patterns: host array of the factored and condensed handles,
+ * indexed like the structure's patterns.  X, Y: device, N_lambda x m
+ * row-major (ldx, ldy >= m), must not overlap.  prec selects the product
+ * arithmetic (the pattern must have been condensed with it).  With
+ * RPF_APPLY_PROJECT the coarse projector Q = I - G (G^T G)^{-1} G^T is
+ * applied to the result (built on first use).  Asynchronous.
+ * Errors: RPF_EINVAL. */
+rpf_status feti_apply(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X, int64_t ldx,
+                      double* Y, int64_t ldy, int32_t prec, uint32_t flags, void* stream);
+
+/* ------------------------------------------------------------------ solver */
+
+typedef enum {
+  RPF_CLASSICAL = 0,   /* projected CG per load case (Table 1, left column; FETI-mrhs) */
+  RPF_BLOCK_CG = 1,    /* multivector CG, recurrence on the previous block (Table 1, right) */
+  RPF_ORTHODIR = 2     /* multivector CG with full re-orthogonalisation (section 4.3) */
+} rpf_method;
+
+typedef struct {
+  double tol;          /* stop when max_c ||r_c|| / ||r0_c|| <= tol, r = Q^T (d - F lambda) in FP64 */
+  int32_t max_it;      /* total inner iterations allowed */
+  int32_t method;      /* rpf_method */
+  int32_t prec;        /* rpf_prec of the inner operator */
+  double inner_tol;    /* relative reduction per refinement sweep (mixed forms; 0: 1e-4) */
+  int32_t max_sweeps;  /* refinement sweeps (mixed forms; 0: 30) */
+  int32_t check_every; /* read the convergence flag every k iterations (0: 1) */
+} rpf_solve_opts;
+
+typedef struct {
+  int32_t iterations;  /* inner iterations over all sweeps */
+  int32_t sweeps;      /* FP64 refinement sweeps (1 for the FP64 form) */
+  int32_t rank_drops;  /* directions dropped by the F-normalisation */
+  int32_t converged;
+  double rel_residual; /* final max_c ||r_c|| / ||r0_c||, recomputed in FP64 */
+  double ms_loads, ms_coarse, ms_iterate, ms_recover;
+} rpf_solve_stats;
+
+/* Solve the interface problem (eq. 3) for n_rhs load cases and recover the
+ * displacements (eq. 2).  f_local: device, the loads of every occurrence in
+ * its pattern frame, occurrence blocks concatenated in occurrence order, each
+ * n_p x n_rhs column-major (ld n_p).  lambda: device, N_lambda x n_rhs
+ * row-major (ld_lambda >= n_rhs).  u_local: device, same layout as f_local.
+ * lambda_00 = 0.  Blocks until the solve completes; stats may be NULL.
+ * Errors: RPF_EINVAL, RPF_EBREAKDOWN, RPF_ENOCONV (outputs hold the last
+ * iterate), RPF_EHIP. */
+rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* patterns, int32_t n_rhs, const double* f_local,
+                              const rpf_solve_opts* opts, double* lambda, int64_t ld_lambda, double* u_local,
+                              rpf_solve_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------ dense helpers */
+
+/* C = alpha op(A) op(B) + beta C, FP64 MFMA, column-major (ta, tb: 0 or 1). */
+rpf_status rpf_dgemm(int32_t ta, int32_t tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                     int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                     void* stream);
+/* In-place lower Cholesky of an SPD n x n matrix (device), then, when nrhs > 0,
+ * B <- A^{-1} B.  Blocks the host.  RPF_ENOTSPD on a non-positive pivot. */
+rpf_status rpf_dposv(int64_t n, double* A, int64_t lda, int64_t nrhs, double* B, int64_t ldb, void* stream);
+/* Symmetric eigen-decomposition of batch m x m matrices (m <= 64), ascending. */
+rpf_status rpf_dsyev_small(int32_t m, int32_t batch, const double* A, double* V, double* w, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPFETI_H */

@@ -1,0 +1,211 @@
+"""Repeated-pattern FETI hot path on MI355X: Python binding of librpfeti.so.
+
+The functions below carry the names of the C ABI (include/rpfeti.h) and only
+marshal arguments: every numerical step runs in the HIP library.  Device
+memory and streams come from PyTorch (ROCm build).  Importing the package does
+not load the library; the first call does, and fails loudly when it has not
+been built (`python -m paper_1208_6387_amd.build`).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (APPLY_PROJECT, BF16, BF16X3, BLOCK_CG, CLASSICAL, FP32, FP64, ORTHODIR, RpfError, SolveStats,
+                   check, load)
+
+__all__ = ["Pattern", "Problem", "pattern_factor", "pattern_condense", "pattern_export", "problem_create",
+           "feti_apply", "block_krylov_solve", "dgemm", "dposv", "dsyev_small", "load", "RpfError",
+           "FP64", "FP32", "BF16X3", "BF16", "CLASSICAL", "BLOCK_CG", "ORTHODIR", "APPLY_PROJECT"]
+
+
+def _stream(stream=None) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class Pattern:
+    """Owner of an rpf_pattern handle."""
+
+    def __init__(self, handle: C.c_void_p, kernel_dim: int, n: int, n_b: int):
+        self.handle = handle
+        self.kernel_dim = kernel_dim
+        self.n = n
+        self.n_b = n_b
+
+    def free(self):
+        if self.handle:
+            load().pattern_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Owner of an rpf_problem handle (structure: assembly, permutations)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self.handle = handle
+        self.n_lambda = int(load().problem_n_lambda(handle))
+
+    def free(self):
+        if self.handle:
+            load().problem_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pattern_factor(rowptr, colind, val: torch.Tensor, bdofs, dofs_per_node: int, kernel_tol: float = 0.0,
+                   expected_kernel_dim: int = -1, stream=None) -> Pattern:
+    """Factor a pattern.  rowptr/colind/bdofs: host int32 arrays; val: device float64 tensor."""
+    lib = load()
+    rp, ci, bd = _host(rowptr, np.int32), _host(colind, np.int32), _host(bdofs, np.int32)
+    assert val.is_cuda and val.dtype == torch.float64 and val.numel() == rp[-1]
+    h, k = C.c_void_p(), C.c_int32()
+    check(lib.pattern_factor(len(rp) - 1, rp.ctypes.data, ci.ctypes.data, _ptr(val), len(bd), bd.ctypes.data,
+                             dofs_per_node, kernel_tol, expected_kernel_dim, _stream(stream), C.byref(h),
+                             C.byref(k)))
+    return Pattern(h, k.value, len(rp) - 1, len(bd))
+
+
+def pattern_condense(p: Pattern, prec: int = FP64, stream=None) -> None:
+    check(load().pattern_condense(p.handle, prec, _stream(stream)))
+
+
+def pattern_export(p: Pattern, what: str, stream=None) -> torch.Tensor:
+    """'S', 'Z' or 'Splus' as a column-major device matrix returned as a (rows, cols) tensor."""
+    code = {"S": 0, "Z": 1, "Splus": 2}[what]
+    cols = p.kernel_dim if what == "Z" else p.n_b
+    out = torch.empty((max(cols, 1), p.n_b), dtype=torch.float64, device="cuda")
+    if cols:
+        check(load().pattern_export(p.handle, code, _ptr(out), p.n_b, _stream(stream)))
+    return out[:cols].T
+
+
+def problem_create(dofs_per_node: int, pat_n_nodes, pat_bnodes, occ_pattern, occ_rot, mult_occ, mult_node,
+                   mult_sign, perm_node=None) -> Problem:
+    """Structure from host arrays: pat_bnodes is a list of per-pattern sorted boundary node arrays,
+    mult_* are (n_mult, 2) arrays, occ_rot an (n_occ, 3, 3) array or None, perm_node (n_perm, n_mult)."""
+    lib = load()
+    nn = _host(pat_n_nodes, np.int32)
+    ptr = _host(np.concatenate([[0], np.cumsum([len(b) for b in pat_bnodes])]), np.int32)
+    bn = _host(np.concatenate([np.asarray(b) for b in pat_bnodes]), np.int32)
+    op = _host(occ_pattern, np.int32)
+    rot = None if occ_rot is None else _host(occ_rot, np.float64).reshape(-1)
+    mo, mn, ms = _host(mult_occ, np.int32).reshape(-1), _host(mult_node, np.int32).reshape(-1), _host(mult_sign, np.int8).reshape(-1)
+    if perm_node is None:
+        n_perm, pn = 1, None
+    else:
+        pn = _host(perm_node, np.int32)
+        n_perm = pn.shape[0]
+        pn = pn.reshape(-1)
+    d = _lib.ProblemDesc(dofs_per_node, len(nn), nn.ctypes.data, ptr.ctypes.data, bn.ctypes.data, len(op),
+                         op.ctypes.data, None if rot is None else rot.ctypes.data, len(mo) // 2, mo.ctypes.data,
+                         mn.ctypes.data, ms.ctypes.data, n_perm, None if pn is None else pn.ctypes.data)
+    h = C.c_void_p()
+    check(lib.problem_create(C.byref(d), C.byref(h)))
+    return Problem(h)
+
+
+def _handles(patterns):
+    arr = (C.c_void_p * len(patterns))(*[p.handle for p in patterns])
+    return arr
+
+
+def feti_apply(pb: Problem, patterns, X: torch.Tensor, prec: int = FP64, project: bool = False,
+               out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Y = F X (or Q^T F X) for a row-major N_lambda x m device block."""
+    assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[0] == pb.n_lambda
+    assert X.stride(1) == 1
+    m = X.shape[1]
+    Y = out if out is not None else torch.empty_like(X)
+    check(load().feti_apply(pb.handle, _handles(patterns), m, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), prec,
+                            APPLY_PROJECT if project else 0, _stream(stream)))
+    return Y
+
+
+@dataclass
+class SolveResult:
+    lam: torch.Tensor
+    u: torch.Tensor
+    stats: dict
+    status: int
+
+
+def block_krylov_solve(pb: Problem, patterns, f_local: torch.Tensor, n_rhs: int, tol: float = 1e-8,
+                       max_it: int = 1000, method: int = ORTHODIR, prec: int = FP64, inner_tol: float = 0.0,
+                       max_sweeps: int = 0, check_every: int = 1, lam_out=None, u_out=None, stream=None,
+                       raise_on_noconv: bool = True) -> SolveResult:
+    """Solve the interface problem and recover the displacements.  f_local: flat device float64 tensor,
+    occurrence blocks of n_p x n_rhs column-major, concatenated."""
+    assert f_local.is_cuda and f_local.dtype == torch.float64 and f_local.is_contiguous()
+    lam = lam_out if lam_out is not None else torch.empty((pb.n_lambda, n_rhs), dtype=torch.float64, device="cuda")
+    u = u_out if u_out is not None else torch.empty_like(f_local)
+    opts = _lib.SolveOpts(tol, max_it, method, prec, inner_tol, max_sweeps, check_every)
+    st = SolveStats()
+    code = load().block_krylov_solve(pb.handle, _handles(patterns), n_rhs, _ptr(f_local), C.byref(opts), _ptr(lam),
+                                     lam.stride(0), _ptr(u), C.byref(st), _stream(stream))
+    if code != _lib.RPF_OK and not (code == _lib.RPF_ENOCONV and not raise_on_noconv):
+        check(code)
+    return SolveResult(lam, u, st.as_dict(), code)
+
+
+# ------------------------------------------------------------------ dense helpers
+def dgemm(ta: bool, tb: bool, A: torch.Tensor, B: torch.Tensor, alpha=1.0, beta=0.0, C_out=None, stream=None):
+    """Column-major GEMM on the library's MFMA kernel; A, B given as (rows, cols) tensors stored
+    column-major (i.e. their .T is contiguous)."""
+    def cm(t):
+        assert t.is_cuda and t.dtype == torch.float64 and t.T.is_contiguous()
+        return t.shape[0], t.shape[1], t.stride(1)
+    ar, ac, lda = cm(A)
+    br, bc, ldb = cm(B)
+    M, K = (ac, ar) if ta else (ar, ac)
+    K2, N = (bc, br) if tb else (br, bc)
+    assert K == K2
+    if C_out is None:
+        C_out = torch.zeros((N, M), dtype=torch.float64, device="cuda").T
+    ldc = C_out.stride(1)
+    check(load().rpf_dgemm(int(ta), int(tb), M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C_out), ldc,
+                           _stream(stream)))
+    return C_out
+
+
+def dposv(A: torch.Tensor, B: torch.Tensor | None = None, stream=None):
+    """In-place Cholesky of a column-major SPD matrix A, then B <- A^{-1} B."""
+    n = A.shape[0]
+    nrhs = 0 if B is None else B.shape[1]
+    check(load().rpf_dposv(n, _ptr(A), A.stride(1), nrhs, None if B is None else _ptr(B),
+                           n if B is None else B.stride(1), _stream(stream)))
+    return A, B
+
+
+def dsyev_small(A: torch.Tensor, stream=None):
+    """Eigen-decomposition of a batch (b, m, m) of symmetric matrices (column-major = any, symmetric)."""
+    b, m, _ = A.shape
+    A = A.contiguous()
+    V = torch.empty_like(A)
+    w = torch.empty((b, m), dtype=torch.float64, device="cuda")
+    check(load().rpf_dsyev_small(m, b, _ptr(A), _ptr(V), _ptr(w), _stream(stream)))
+    return w, V.transpose(1, 2)

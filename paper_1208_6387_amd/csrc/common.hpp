@@ -1,0 +1,153 @@
+// Internal helpers of the repeated-pattern FETI library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rpfeti.h"
+
+namespace rpf {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ----------------------------------------------------------------------------- errors
+// Errors travel as C++ exceptions inside the library and are turned into a
+// status code plus a thread-local message at every C entry point.
+struct Error : std::runtime_error {
+  rpf_status code;
+  Error(rpf_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define RPF_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::rpf::Error(RPF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define RPF_CHECK(cond, code, msg)                          \
+  do {                                                      \
+    if (!(cond)) throw ::rpf::Error((code), (msg));         \
+  } while (0)
+
+#define RPF_LAUNCH_CHECK() RPF_HIP(hipGetLastError())
+
+template <class F>
+rpf_status guarded(F&& f) {
+  try {
+    f();
+    return RPF_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return RPF_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return RPF_EINVAL;
+  }
+}
+
+// ----------------------------------------------------------------------------- device memory
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error(RPF_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  // grow-only reallocation (contents are not preserved)
+  void ensure(size_t count) { if (count > n) alloc(count); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const T* h, size_t count, hipStream_t s) {
+    ensure(count);
+    if (count) RPF_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  T* get() const { return p; }
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ----------------------------------------------------------------------------- dense FP64 kernels
+constexpr int NB = 64;  // block size of the blocked Cholesky and triangular solves
+
+// C = alpha op(A) op(B) + beta C (column-major).  lower: only entries with m >= n are written.
+void dgemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+           int64_t ldc, bool lower = false);
+
+// Split-K form for contractions with a long K and a small M x N output; ws holds
+// splits * M * N doubles (see gemm_splitk_workspace).
+int gemm_splitk_count(int64_t M, int64_t N, int64_t K);
+void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                  int64_t ldc, double* ws, int splits);
+
+// Envelope description of a lower factor: for column block t (NB columns),
+// rows [t*NB+jb, rend[t]) below the diagonal block may be nonzero, and the
+// rows of block t have nonzeros only from column cstart[t] on.
+struct Envelope {
+  std::vector<int64_t> rend, cstart;
+  static Envelope dense(int64_t n);
+};
+
+// In-place blocked right-looking Cholesky of the leading n_fac columns of the
+// n x n symmetric matrix A (lower triangle).  Rows >= n_fac are dense
+// ("boundary") rows; the trailing block A[n_fac:, n_fac:] is NOT updated here
+// (use schur_update).  dinv receives the inverse of every NB x NB diagonal
+// block (cdiv(n_fac, NB) * NB * NB doubles).  A non-positive pivot sets *status.
+void potrf(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac, const Envelope& env,
+           double* dinv, int* status);
+// A[n_fac:, n_fac:] -= L_b L_b^T  with L_b = A[n_fac:, :n_fac] (lower triangle).
+void schur_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac);
+
+// B <- L^{-1} B (trans = false) or L^{-T} B (trans = true), L = leading n x n of a factor.
+void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* dinv,
+          const Envelope& env, double* B, int64_t ldb, int64_t nrhs, bool trans);
+
+// fill / copy helpers
+void fill(hipStream_t s, double* p, int64_t count, double v);
+void fill_matrix(hipStream_t s, double* p, int64_t rows, int64_t cols, int64_t ld, double v);
+void copy_matrix(hipStream_t s, const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                 int64_t cols);
+void mirror_lower(hipStream_t s, double* A, int64_t lda, int64_t n);  // upper <- lower^T
+void add_diag(hipStream_t s, double* A, int64_t lda, int64_t n, double v);
+
+// Symmetric eigen-decomposition of small m x m matrices (m <= 64), one
+// workgroup each: A (m x m, ld m, column-major) -> V (columns), w ascending.
+void syev_small(hipStream_t s, const double* A, int m, double* V, double* w, int batch = 1);
+
+// Orthonormalise the k columns of Y (n x k, ld) in place (modified Gram-Schmidt, twice).
+void orthonormalize(hipStream_t s, double* Y, int64_t n, int64_t ld, int k);
+
+}  // namespace rpf

@@ -1,0 +1,591 @@
+// Dense FP64 building blocks for gfx950: MFMA GEMM (with split-K), blocked
+// band-aware Cholesky, triangular solves through inverted diagonal blocks,
+// small symmetric eigen-decompositions and block orthonormalisation.
+//
+// The Cholesky factors of a pattern's interior stiffness, of S + Z Z^T and of
+// the coarse matrix G^T G (section 2 of the paper) all run through potrf; the
+// flexibility product S+ W (section 4.2) and every trailing update run through
+// the same MFMA GEMM.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace rpf {
+
+// ============================================================================ GEMM
+// Column-major C = alpha op(A) op(B) + beta C with v_mfma_f64_16x16x4_f64.
+// The MFMA is issued with the B fragment as its first operand, so every lane
+// ends up holding 4 values of one *column* of C in consecutive rows: lanes
+// 0..15 of a register store 16 consecutive doubles of a column (coalesced).
+// Operand tiles are staged through LDS (k-major); the next K tile is loaded
+// into registers while the current one is consumed.
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
+                                               const double* A, int64_t lda, const double* B,
+                                               int64_t ldb, double beta, double* C, int64_t ldc,
+                                               int lower, int64_t kchunk, double* part) {
+  constexpr int BK = 16, PAD = 2;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN, TM = WTM / 16, TN = WTN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  static_assert(WGM * WGN == 4 && TM >= 1 && TN >= 1 && EA >= 1 && EB >= 1, "bad tile");
+  __shared__ double sA[BK][BM + PAD];
+  __shared__ double sB[BK][BN + PAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  if (lower && n0 >= m0 + BM) return;  // tile strictly above the diagonal
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = K < kbeg + kchunk ? K : kbeg + kchunk;
+
+  v4d acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  double ra[EA], rb[EB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      const int mm = TA ? idx / BK : idx % BM;
+      const int kk = TA ? idx % BK : idx / BM;
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      ra[e] = (gm < M && gk < kend) ? (TA ? A[gm * lda + gk] : A[gk * lda + gm]) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      const int nn = TB ? idx % BN : idx / BK;
+      const int kk = TB ? idx / BN : idx % BK;
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      rb[e] = (gn < N && gk < kend) ? (TB ? B[gk * ldb + gn] : B[gn * ldb + gk]) : 0.0;
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      const int mm = TA ? idx / BK : idx % BM;
+      const int kk = TA ? idx % BK : idx / BM;
+      sA[kk][mm] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      const int nn = TB ? idx % BN : idx / BK;
+      const int kk = TB ? idx / BN : idx % BK;
+      sB[kk][nn] = rb[e];
+    }
+  };
+
+  if (kbeg < kend) gload(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (k0 + BK < kend) gload(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = sA[kk + (lane >> 4)][wm * WTM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = sB[kk + (lane >> 4)][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * WTM + i * 16 + (lane & 15);
+        const int64_t n = n0 + wn * WTN + j * 16 + 4 * (lane >> 4) + r;
+        if (m < M && n < N && (!lower || m >= n)) {
+          const double v = alpha * acc[i][j][r];
+          if (part) {
+            part[((int64_t)blockIdx.z * N + n) * M + m] = v;
+          } else {
+            double* c = C + n * ldc + m;
+            *c = (beta == 0.0) ? v : v + beta * *c;
+          }
+        }
+      }
+}
+
+__global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double* part, double beta,
+                                double* C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t m = idx % M, n = idx / M;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += part[((int64_t)z * N + n) * M + m];
+  double* c = C + n * ldc + m;
+  *c = (beta == 0.0) ? s : s + beta * *c;
+}
+
+namespace {
+enum Cfg { BIG, M16, N16, SMALL };
+
+Cfg pick_cfg(int64_t M, int64_t N) {
+  if (M <= 16) return M16;
+  if (N <= 16) return N16;
+  if (M <= 64 && N <= 64) return SMALL;
+  return BIG;
+}
+
+void tile_of(Cfg c, int& bm, int& bn) {
+  switch (c) {
+    case BIG: bm = 128; bn = 128; break;
+    case M16: bm = 16; bn = 256; break;
+    case N16: bm = 256; bn = 16; break;
+    default: bm = 64; bn = 64; break;
+  }
+}
+
+template <bool TA, bool TB>
+void launch_cfg(Cfg c, dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                int64_t ldc, int lower, int64_t kchunk, double* part) {
+  switch (c) {
+    case BIG:
+      hipLaunchKernelGGL((k_dgemm<128, 128, 2, 2, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+                         ldb, beta, C, ldc, lower, kchunk, part);
+      break;
+    case M16:
+      hipLaunchKernelGGL((k_dgemm<16, 256, 1, 4, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+                         ldb, beta, C, ldc, lower, kchunk, part);
+      break;
+    case N16:
+      hipLaunchKernelGGL((k_dgemm<256, 16, 4, 1, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+                         ldb, beta, C, ldc, lower, kchunk, part);
+      break;
+    default:
+      hipLaunchKernelGGL((k_dgemm<64, 64, 2, 2, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+                         ldb, beta, C, ldc, lower, kchunk, part);
+      break;
+  }
+}
+
+void launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                 int64_t ldc, bool lower, int splits, double* part) {
+  const Cfg c = pick_cfg(M, N);
+  int bm, bn;
+  tile_of(c, bm, bn);
+  int64_t kchunk = K;
+  if (splits > 1) kchunk = cdiv(cdiv(K, splits), 16) * 16;
+  const int64_t gz = splits > 1 ? cdiv(K, kchunk) : 1;
+  RPF_CHECK(cdiv(N, bn) <= 65535 && gz <= 65535, RPF_EINVAL, "dgemm: grid too large");
+  dim3 grid((unsigned)cdiv(M, bm), (unsigned)cdiv(N, bn), (unsigned)gz);
+  const int low = lower ? 1 : 0;
+  if (!ta && !tb) launch_cfg<false, false>(c, grid, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, low, kchunk, part);
+  else if (!ta && tb) launch_cfg<false, true>(c, grid, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, low, kchunk, part);
+  else if (ta && !tb) launch_cfg<true, false>(c, grid, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, low, kchunk, part);
+  else launch_cfg<true, true>(c, grid, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, low, kchunk, part);
+  RPF_LAUNCH_CHECK();
+}
+}  // namespace
+
+void dgemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+           int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool lower) {
+  if (M <= 0 || N <= 0) return;
+  if (K <= 0 && beta == 1.0) return;  // nothing to add; K = 0 otherwise scales C by beta
+  launch_gemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, lower, 1, nullptr);
+}
+
+int gemm_splitk_count(int64_t M, int64_t N, int64_t K) {
+  const Cfg c = pick_cfg(M, N);
+  int bm, bn;
+  tile_of(c, bm, bn);
+  const int64_t tiles = cdiv(M, bm) * cdiv(N, bn);
+  int64_t sp = cdiv(1024, tiles);
+  sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 256));
+  sp = std::max<int64_t>(1, std::min<int64_t>(sp, 1024));
+  return (int)sp;
+}
+
+void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                  int64_t ldc, double* ws, int splits) {
+  if (M <= 0 || N <= 0) return;
+  if (splits <= 1 || K <= 0) {
+    dgemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, false);
+    return;
+  }
+  const int64_t kchunk = cdiv(cdiv(K, splits), 16) * 16;
+  const int gz = (int)cdiv(K, kchunk);
+  launch_gemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, 0.0, nullptr, 0, false, splits, ws);
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s, M, N, gz, ws, beta, C,
+                     ldc);
+  RPF_LAUNCH_CHECK();
+}
+
+// ============================================================================ Cholesky
+// One NB x NB diagonal block: unblocked right-looking Cholesky in LDS, then the
+// inverse of the factor (forward substitution, one column per thread).  Rows
+// and columns beyond jb are padded with the identity.
+__global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int jb, double* dinv, int* status,
+                                                    int blk) {
+  __shared__ double s[NB][NB + 1];
+  __shared__ double inv[NB][NB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx % NB, c = idx / NB;
+    double v = (r == c) ? 1.0 : 0.0;
+    if (r < jb && c < jb) v = (r >= c) ? A[(int64_t)c * lda + r] : 0.0;
+    s[r][c] = v;
+  }
+  __syncthreads();
+  for (int j = 0; j < jb; ++j) {
+    if (tid == 0) {
+      double d = s[j][j];
+      if (!(d > 0.0)) {
+        bad = 1;
+        d = 1.0;
+      }
+      s[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    const double djj = s[j][j];
+    for (int r = j + 1 + tid; r < jb; r += 256) s[r][j] /= djj;
+    __syncthreads();
+    const int w = jb - j - 1;
+    for (int idx = tid; idx < w * w; idx += 256) {
+      const int r = j + 1 + idx % w, c = j + 1 + idx / w;
+      if (r >= c) s[r][c] -= s[r][j] * s[c][j];
+    }
+    __syncthreads();
+  }
+  if (tid < NB) {
+    const int c = tid;
+    for (int r = 0; r < NB; ++r) {
+      if (r < c) {
+        inv[r][c] = 0.0;
+      } else {
+        double sum = (r == c) ? 1.0 : 0.0;
+        for (int k = c; k < r; ++k) sum -= s[r][k] * inv[k][c];
+        inv[r][c] = sum / s[r][r];
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx % NB, c = idx / NB;
+    if (r < jb && c < jb && r >= c) A[(int64_t)c * lda + r] = s[r][c];
+    dinv[(int64_t)c * NB + r] = inv[r][c];
+  }
+  if (tid == 0 && bad) atomicCAS(status, 0, blk + 1);
+}
+
+Envelope Envelope::dense(int64_t n) {
+  Envelope e;
+  const int64_t nb = cdiv(n, NB);
+  e.rend.assign(nb, n);
+  e.cstart.assign(nb, 0);
+  return e;
+}
+
+void potrf(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac, const Envelope& env, double* dinv,
+           int* status) {
+  const int64_t nblk = cdiv(n_fac, NB);
+  RPF_CHECK((int64_t)env.rend.size() >= nblk, RPF_EINVAL, "potrf: envelope too short");
+  for (int64_t t = 0; t < nblk; ++t) {
+    const int64_t j0 = t * NB;
+    const int jb = (int)std::min<int64_t>(NB, n_fac - j0);
+    double* dt = dinv + t * NB * NB;
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A + j0 * lda + j0, lda, jb, dt, status, (int)t);
+    RPF_LAUNCH_CHECK();
+    const int64_t r0 = j0 + jb;
+    const int64_t rend = std::max<int64_t>(r0, std::min<int64_t>(env.rend[t], n_fac));
+    double* col = A + j0 * lda;
+    // panel: L21 = A21 L11^{-T}, in place (one N tile covers the jb columns)
+    if (rend > r0) dgemm(s, false, true, rend - r0, jb, jb, 1.0, col + r0, lda, dt, NB, 0.0, col + r0, lda);
+    if (n > n_fac) dgemm(s, false, true, n - n_fac, jb, jb, 1.0, col + n_fac, lda, dt, NB, 0.0, col + n_fac, lda);
+    // trailing update restricted to the envelope; the boundary-boundary block is deferred
+    if (rend > r0) {
+      dgemm(s, false, true, rend - r0, rend - r0, jb, -1.0, col + r0, lda, col + r0, lda, 1.0, A + r0 * lda + r0,
+            lda, true);
+      if (n > n_fac)
+        dgemm(s, false, true, n - n_fac, rend - r0, jb, -1.0, col + n_fac, lda, col + r0, lda, 1.0,
+              A + r0 * lda + n_fac, lda);
+    }
+  }
+}
+
+void schur_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac) {
+  const int64_t nb = n - n_fac;
+  if (nb <= 0 || n_fac <= 0) return;
+  dgemm(s, false, true, nb, nb, n_fac, -1.0, A + n_fac, lda, A + n_fac, lda, 1.0, A + n_fac * lda + n_fac, lda,
+        true);
+}
+
+void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* dinv, const Envelope& env,
+          double* B, int64_t ldb, int64_t nrhs, bool trans) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int64_t nblk = cdiv(n, NB);
+  if (!trans) {
+    for (int64_t t = 0; t < nblk; ++t) {
+      const int64_t j0 = t * NB;
+      const int jb = (int)std::min<int64_t>(NB, n - j0);
+      const double* dt = dinv + t * NB * NB;
+      dgemm(s, false, false, jb, nrhs, jb, 1.0, dt, NB, B + j0, ldb, 0.0, B + j0, ldb);
+      const int64_t r0 = j0 + jb;
+      const int64_t rend = std::min<int64_t>(env.rend[t], n);
+      if (rend > r0)
+        dgemm(s, false, false, rend - r0, nrhs, jb, -1.0, L + j0 * ldl + r0, ldl, B + j0, ldb, 1.0, B + r0, ldb);
+    }
+  } else {
+    for (int64_t t = nblk - 1; t >= 0; --t) {
+      const int64_t j0 = t * NB;
+      const int jb = (int)std::min<int64_t>(NB, n - j0);
+      const double* dt = dinv + t * NB * NB;
+      dgemm(s, true, false, jb, nrhs, jb, 1.0, dt, NB, B + j0, ldb, 0.0, B + j0, ldb);
+      const int64_t cs = std::max<int64_t>(0, env.cstart[t]);
+      if (j0 > cs)
+        dgemm(s, true, false, j0 - cs, nrhs, jb, -1.0, L + cs * ldl + j0, ldl, B + j0, ldb, 1.0, B + cs, ldb);
+    }
+  }
+}
+
+// ============================================================================ elementwise helpers
+__global__ void k_fill(double* p, int64_t count, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+__global__ void k_fill_matrix(double* p, int64_t rows, int64_t cols, int64_t ld, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows * cols) p[(i / rows) * ld + (i % rows)] = v;
+}
+
+__global__ void k_copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows * cols) {
+    const int64_t r = i % rows, c = i / rows;
+    dst[c * ldd + r] = src[c * lds + r];
+  }
+}
+
+__global__ void k_mirror_lower(double* A, int64_t lda, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * n) {
+    const int64_t r = i % n, c = i / n;
+    if (r < c) A[c * lda + r] = A[r * lda + c];
+  }
+}
+
+__global__ void k_add_diag(double* A, int64_t lda, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[i * lda + i] += v;
+}
+
+void fill(hipStream_t s, double* p, int64_t count, double v) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, s, p, count, v);
+  RPF_LAUNCH_CHECK();
+}
+
+void fill_matrix(hipStream_t s, double* p, int64_t rows, int64_t cols, int64_t ld, double v) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(k_fill_matrix, dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s, p, rows, cols, ld, v);
+  RPF_LAUNCH_CHECK();
+}
+
+void copy_matrix(hipStream_t s, const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                 int64_t cols) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(k_copy_matrix, dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s, src, lds, dst, ldd,
+                     rows, cols);
+  RPF_LAUNCH_CHECK();
+}
+
+void mirror_lower(hipStream_t s, double* A, int64_t lda, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)cdiv(n * n, 256)), dim3(256), 0, s, A, lda, n);
+  RPF_LAUNCH_CHECK();
+}
+
+void add_diag(hipStream_t s, double* A, int64_t lda, int64_t n, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_add_diag, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, A, lda, n, v);
+  RPF_LAUNCH_CHECK();
+}
+
+// ============================================================================ small eigenproblems
+// Parallel cyclic Jacobi (Brent-Luk ordering: m/2 disjoint rotations per step,
+// m-1 steps per sweep), one workgroup per matrix, m <= 64.
+constexpr int EIG_MAX = 64;
+
+__global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, double* Vout, double* wout) {
+  __shared__ double a[EIG_MAX][EIG_MAX + 1];
+  __shared__ double v[EIG_MAX][EIG_MAX + 1];
+  __shared__ int pp[EIG_MAX / 2], qq[EIG_MAX / 2];
+  __shared__ double cc[EIG_MAX / 2], ss[EIG_MAX / 2];
+  __shared__ double red[2];
+  __shared__ int order[EIG_MAX];
+  const int tid = threadIdx.x;
+  const double* A = Ain + (int64_t)blockIdx.x * m * m;
+  double* V = Vout + (int64_t)blockIdx.x * m * m;
+  double* w = wout + (int64_t)blockIdx.x * m;
+  for (int i = tid; i < m * m; i += 256) {
+    const int r = i % m, c = i / m;
+    a[r][c] = 0.5 * (A[c * m + r] + A[r * m + c]);
+    v[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  const int me = m + (m & 1);  // even count for the round-robin schedule
+  const int npair = me / 2;
+  __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) {
+      double off = 0.0, dia = 0.0;
+      for (int c = 0; c < m; ++c)
+        for (int r = 0; r < m; ++r) {
+          const double x = a[r][c] * a[r][c];
+          if (r == c) dia += x; else off += x;
+        }
+      red[0] = off;
+      red[1] = dia;
+    }
+    __syncthreads();
+    if (!(red[0] > 1e-30 * red[1]) || m < 2) break;
+    __syncthreads();
+    for (int step = 0; step < me - 1; ++step) {
+      // circle method: indices 0..me-2 rotate, me-1 is fixed
+      if (tid < npair) {
+        int i, j;
+        if (tid == 0) {
+          i = step;
+          j = me - 1;
+        } else {
+          i = (step + tid) % (me - 1);
+          j = (step - tid + (me - 1)) % (me - 1);
+        }
+        const int p = i < j ? i : j, q = i < j ? j : i;
+        double c = 1.0, sn = 0.0;
+        if (q < m) {
+          const double apq = a[p][q];
+          if (apq != 0.0) {
+            const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+          }
+        }
+        pp[tid] = p;
+        qq[tid] = q;
+        cc[tid] = c;
+        ss[tid] = sn;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int idx = tid; idx < npair * m; idx += 256) {
+        const int k = idx / m, r = idx % m;
+        const int p = pp[k], q = qq[k];
+        if (q >= m) continue;
+        const double c = cc[k], sn = ss[k];
+        const double x = a[r][p], y = a[r][q];
+        a[r][p] = c * x - sn * y;
+        a[r][q] = sn * x + c * y;
+        const double vx = v[r][p], vy = v[r][q];
+        v[r][p] = c * vx - sn * vy;
+        v[r][q] = sn * vx + c * vy;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int idx = tid; idx < npair * m; idx += 256) {
+        const int k = idx / m, col = idx % m;
+        const int p = pp[k], q = qq[k];
+        if (q >= m) continue;
+        const double c = cc[k], sn = ss[k];
+        const double x = a[p][col], y = a[q][col];
+        a[p][col] = c * x - sn * y;
+        a[q][col] = sn * x + c * y;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < m; ++i) order[i] = i;
+    for (int i = 0; i < m; ++i) {
+      int best = i;
+      for (int j = i + 1; j < m; ++j)
+        if (a[order[j]][order[j]] < a[order[best]][order[best]]) best = j;
+      const int t = order[i];
+      order[i] = order[best];
+      order[best] = t;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < m * m; i += 256) {
+    const int r = i % m, c = i / m;
+    V[c * m + r] = v[r][order[c]];
+  }
+  for (int i = tid; i < m; i += 256) w[i] = a[order[i]][order[i]];
+}
+
+void syev_small(hipStream_t s, const double* A, int m, double* V, double* w, int batch) {
+  RPF_CHECK(m >= 1 && m <= EIG_MAX, RPF_EINVAL, "syev_small: m out of range");
+  hipLaunchKernelGGL(k_syev_jacobi, dim3(batch), dim3(256), 0, s, A, m, V, w);
+  RPF_LAUNCH_CHECK();
+}
+
+// ============================================================================ orthonormalisation
+__device__ inline double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (tid == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    red[16] = t;
+  }
+  __syncthreads();
+  t = red[16];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(1024) void k_mgs2(double* Y, int64_t n, int64_t ld, int k) {
+  __shared__ double red[17];
+  const int tid = threadIdx.x;
+  for (int j = 0; j < k; ++j) {
+    double* yj = Y + (int64_t)j * ld;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < j; ++i) {
+        const double* yi = Y + (int64_t)i * ld;
+        double d = 0.0;
+        for (int64_t r = tid; r < n; r += blockDim.x) d += yi[r] * yj[r];
+        d = block_sum(d, red);
+        for (int64_t r = tid; r < n; r += blockDim.x) yj[r] -= d * yi[r];
+        __syncthreads();
+      }
+    }
+    double nn = 0.0;
+    for (int64_t r = tid; r < n; r += blockDim.x) nn += yj[r] * yj[r];
+    nn = block_sum(nn, red);
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    for (int64_t r = tid; r < n; r += blockDim.x) yj[r] *= inv;
+    __syncthreads();
+  }
+}
+
+void orthonormalize(hipStream_t s, double* Y, int64_t n, int64_t ld, int k) {
+  if (k <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_mgs2, dim3(1), dim3(1024), 0, s, Y, n, ld, k);
+  RPF_LAUNCH_CHECK();
+}
+
+}  // namespace rpf

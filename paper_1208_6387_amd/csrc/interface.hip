@@ -1,0 +1,737 @@
+// Interface level: signed Boolean assembly (eq. 2, with the occurrence
+// rotations of section 5.2), the dual operator F = sum_s A^(s) S+ A^(s)T
+// applied to all occurrences of a pattern as one product S+ W (section 4.2),
+// and the coarse projector Q = I - G (G^T G)^{-1} G^T with G = [A^(s) Z] and
+// the identity preconditioner (section 2, projector and initialisation).
+#include "problem.hpp"
+
+#include <algorithm>
+#include <map>
+#include <memory>
+
+namespace rpf {
+
+// ============================================================================ kernels
+constexpr int JB = 8;  // columns handled per pass by the assembly kernels
+
+template <int DPN>
+__device__ inline void load_rot(const double* rot, int s, double O[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) O[i] = rot ? rot[9 * s + i] : ((i % 4 == 0) ? 1.0 : 0.0);
+}
+
+// A^(s)T: X[(q*m + j)*ldx + bn*DPN + c'] = sum over multipliers at (s, bn) of sign * (O^T lambda_mult)[c']
+template <int DPN>
+__global__ __launch_bounds__(128) void k_gather(int nbn, const int* occ_list, const int* slot_off,
+                                                const int* l2m_ptr, const int* l2m_code, const double* rot,
+                                                const double* lam, int64_t ldl, int m, double* X, int64_t ldx) {
+  const int bn = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (bn >= nbn) return;
+  const int s = occ_list[q];
+  const int slot = slot_off[s] + bn;
+  const int e0 = l2m_ptr[slot], e1 = l2m_ptr[slot + 1];
+  double O[9];
+  if (DPN == 3) load_rot<DPN>(rot, s, O);
+  for (int j0 = 0; j0 < m; j0 += JB) {
+    const int jn = min(JB, m - j0);
+    double acc[DPN][JB];
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+#pragma unroll
+      for (int j = 0; j < JB; ++j) acc[c][j] = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int code = l2m_code[e];
+      const double sg = (code & 1) ? -1.0 : 1.0;
+      const int64_t mult = code >> 1;
+#pragma unroll
+      for (int c = 0; c < DPN; ++c) {
+        const double* row = lam + (mult * DPN + c) * ldl + j0;
+#pragma unroll
+        for (int j = 0; j < JB; ++j)
+          if (j < jn) acc[c][j] += sg * row[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      if (j >= jn) break;
+      double* col = X + ((int64_t)q * m + j0 + j) * ldx + (int64_t)bn * DPN;
+      if (DPN == 3) {
+#pragma unroll
+        for (int c2 = 0; c2 < 3; ++c2)
+          col[c2] = O[c2] * acc[0][j] + O[3 + c2] * acc[1 % DPN][j] + O[6 + c2] * acc[2 % DPN][j];
+      } else {
+#pragma unroll
+        for (int c = 0; c < DPN; ++c) col[c] = acc[c][j];
+      }
+    }
+  }
+}
+
+// A^(s): Y[(mult*DPN + c)*ldy + j] = beta Y + sum over endpoints of sign * (O Y_loc)[c]
+template <int DPN>
+__global__ __launch_bounds__(128) void k_scatter(int n_mult, const int* ep_q, const int* ep_bn,
+                                                 const int8_t* ep_pat, const int8_t* ep_sign, const int* ep_occ,
+                                                 const double* rot, YLoc yl, int m, double* Y, int64_t ldy,
+                                                 double beta) {
+  const int mult = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mult >= n_mult) return;
+  for (int j0 = 0; j0 < m; j0 += JB) {
+    const int jn = min(JB, m - j0);
+    double acc[DPN][JB];
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+#pragma unroll
+      for (int j = 0; j < JB; ++j) acc[c][j] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int q = ep_q[2 * mult + e];
+      if (q < 0) continue;
+      const int p = ep_pat[2 * mult + e];
+      const double sg = (double)ep_sign[2 * mult + e];
+      const int64_t ld = yl.ld[p];
+      const double* base = yl.base[p] + ((int64_t)q * m + j0) * ld + (int64_t)ep_bn[2 * mult + e] * DPN;
+      double O[9];
+      if (DPN == 3) load_rot<DPN>(rot, ep_occ[2 * mult + e], O);
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        if (j >= jn) break;
+        double v[DPN];
+#pragma unroll
+        for (int c = 0; c < DPN; ++c) v[c] = base[j * ld + c];
+        if (DPN == 3) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[c][j] += sg * (O[3 * c] * v[0] + O[3 * c + 1] * v[1 % DPN] + O[3 * c + 2] * v[2 % DPN]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) acc[c][j] += sg * v[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < DPN; ++c) {
+      double* row = Y + ((int64_t)mult * DPN + c) * ldy + j0;
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+        if (j < jn) row[j] = (beta == 0.0) ? acc[c][j] : acc[c][j] + beta * row[j];
+    }
+  }
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// c[(goff[s] + r)*m + j] = (Z^T A^(s)T x)[r][j], one workgroup (256 threads) per occurrence
+template <int DPN>
+__global__ __launch_bounds__(256) void k_coarse_gt(const int* occ_pat, const int* slot_off, const int* nbn_p,
+                                                   const double* const* Zp, const int* kp, const int* goff,
+                                                   const int* l2m_ptr, const int* l2m_code, const double* rot,
+                                                   const double* x, int64_t ldx, int m, double* c) {
+  __shared__ double red[4][KMAX * JB];
+  const int s = blockIdx.x;
+  const int p = occ_pat[s];
+  const int k = kp[p], nbn = nbn_p[p];
+  const double* Z = Zp[p];
+  const int64_t ldz = (int64_t)nbn * DPN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double O[9];
+  if (DPN == 3) load_rot<DPN>(rot, s, O);
+  for (int j0 = 0; j0 < m; j0 += JB) {
+    const int jn = min(JB, m - j0);
+    double acc[KMAX][JB];
+#pragma unroll
+    for (int r = 0; r < KMAX; ++r)
+#pragma unroll
+      for (int j = 0; j < JB; ++j) acc[r][j] = 0.0;
+    for (int bn = tid; bn < nbn; bn += 256) {
+      const int slot = slot_off[s] + bn;
+      double g[DPN][JB];
+#pragma unroll
+      for (int cc = 0; cc < DPN; ++cc)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) g[cc][j] = 0.0;
+      for (int e = l2m_ptr[slot]; e < l2m_ptr[slot + 1]; ++e) {
+        const int code = l2m_code[e];
+        const double sg = (code & 1) ? -1.0 : 1.0;
+        const int64_t mult = code >> 1;
+#pragma unroll
+        for (int cc = 0; cc < DPN; ++cc) {
+          const double* row = x + (mult * DPN + cc) * ldx + j0;
+#pragma unroll
+          for (int j = 0; j < JB; ++j)
+            if (j < jn) g[cc][j] += sg * row[j];
+        }
+      }
+      double xl[DPN][JB];
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        if (DPN == 3) {
+#pragma unroll
+          for (int c2 = 0; c2 < 3; ++c2)
+            xl[c2 % DPN][j] = O[c2] * g[0][j] + O[3 + c2] * g[1 % DPN][j] + O[6 + c2] * g[2 % DPN][j];
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < DPN; ++cc) xl[cc][j] = g[cc][j];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < KMAX; ++r) {
+        if (r >= k) break;
+#pragma unroll
+        for (int cc = 0; cc < DPN; ++cc) {
+          const double z = Z[r * ldz + (int64_t)bn * DPN + cc];
+#pragma unroll
+          for (int j = 0; j < JB; ++j) acc[r][j] += z * xl[cc][j];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < KMAX; ++r)
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        const double v = wave_sum(acc[r][j]);
+        if (lane == 0) red[wave][r * JB + j] = v;
+      }
+    __syncthreads();
+    if (tid < KMAX * JB) {
+      const int r = tid / JB, j = tid % JB;
+      if (r < k && j < jn)
+        c[((int64_t)goff[s] + r) * m + j0 + j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    }
+    __syncthreads();
+  }
+}
+
+// x = beta x + alpha G y: per multiplier, sum over endpoints of sign * O Z y_s
+template <int DPN>
+__global__ __launch_bounds__(128) void k_coarse_g(int n_mult, const int* ep_occ, const int* ep_bn,
+                                                  const int8_t* ep_sign, const int* occ_pat, const int* nbn_p,
+                                                  const double* const* Zp, const int* kp, const int* goff,
+                                                  const double* rot, const double* y, int m, double alpha,
+                                                  double* x, int64_t ldx, double beta) {
+  const int mult = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mult >= n_mult) return;
+  for (int j0 = 0; j0 < m; j0 += JB) {
+    const int jn = min(JB, m - j0);
+    double acc[DPN][JB];
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+#pragma unroll
+      for (int j = 0; j < JB; ++j) acc[c][j] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int s = ep_occ[2 * mult + e];
+      if (s < 0) continue;
+      const int p = occ_pat[s];
+      const int k = kp[p];
+      const double sg = (double)ep_sign[2 * mult + e];
+      const double* Z = Zp[p];
+      const int64_t ldz = (int64_t)nbn_p[p] * DPN;
+      const int64_t bn = ep_bn[2 * mult + e];
+      const double* ys = y + (int64_t)goff[s] * m + j0;
+      double v[DPN][JB];
+#pragma unroll
+      for (int c = 0; c < DPN; ++c)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) v[c][j] = 0.0;
+      for (int r = 0; r < k; ++r) {
+#pragma unroll
+        for (int c = 0; c < DPN; ++c) {
+          const double z = Z[r * ldz + bn * DPN + c];
+#pragma unroll
+          for (int j = 0; j < JB; ++j)
+            if (j < jn) v[c][j] += z * ys[r * m + j];
+        }
+      }
+      double O[9];
+      if (DPN == 3) load_rot<DPN>(rot, s, O);
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        if (DPN == 3) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            acc[c][j] += sg * (O[3 * c] * v[0][j] + O[3 * c + 1] * v[1 % DPN][j] + O[3 * c + 2] * v[2 % DPN][j]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) acc[c][j] += sg * v[c][j];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < DPN; ++c) {
+      double* row = x + ((int64_t)mult * DPN + c) * ldx + j0;
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+        if (j < jn) row[j] = (beta == 0.0) ? alpha * acc[c][j] : beta * row[j] + alpha * acc[c][j];
+    }
+  }
+}
+
+// Coarse matrix, diagonal blocks: (G^T G)_{s,s} = sum_bn count(s,bn) Z[bn]^T Z[bn]
+// (rotations are orthogonal and signs square to one).  One workgroup per occurrence.
+template <int DPN>
+__global__ __launch_bounds__(256) void k_gtg_diag(const int* occ_pat, const int* slot_off, const int* nbn_p,
+                                                  const double* const* Zp, const int* kp, const int* goff,
+                                                  const int* l2m_ptr, double* GtG, int64_t ldg) {
+  __shared__ double red[4][KMAX * KMAX];
+  const int s = blockIdx.x, p = occ_pat[s], k = kp[p], nbn = nbn_p[p];
+  const double* Z = Zp[p];
+  const int64_t ldz = (int64_t)nbn * DPN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double acc[KMAX][KMAX];
+#pragma unroll
+  for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+    for (int b = 0; b < KMAX; ++b) acc[a][b] = 0.0;
+  for (int bn = tid; bn < nbn; bn += 256) {
+    const int slot = slot_off[s] + bn;
+    const double cnt = (double)(l2m_ptr[slot + 1] - l2m_ptr[slot]);
+    if (cnt == 0.0) continue;
+#pragma unroll
+    for (int c = 0; c < DPN; ++c) {
+      double z[KMAX];
+#pragma unroll
+      for (int a = 0; a < KMAX; ++a) z[a] = (a < k) ? Z[a * ldz + (int64_t)bn * DPN + c] : 0.0;
+#pragma unroll
+      for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+        for (int b = 0; b < KMAX; ++b) acc[a][b] += cnt * z[a] * z[b];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+    for (int b = 0; b < KMAX; ++b) {
+      const double v = wave_sum(acc[a][b]);
+      if (lane == 0) red[wave][a * KMAX + b] = v;
+    }
+  __syncthreads();
+  if (tid < KMAX * KMAX) {
+    const int a = tid / KMAX, b = tid % KMAX;
+    if (a < k && b < k)
+      GtG[((int64_t)goff[s] + b) * ldg + goff[s] + a] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  }
+}
+
+// Coarse matrix, off-diagonal blocks: one workgroup per pair of occurrences
+// (s_a < s_b) joined by multipliers; sum of (sign O Z)[a]^T (sign O Z)[b].
+template <int DPN>
+__global__ __launch_bounds__(256) void k_gtg_pairs(const int* pair_a, const int* pair_b, const int* pair_ptr,
+                                                   const int* pair_mult, const int* ep_occ, const int* ep_bn,
+                                                   const int8_t* ep_sign, const int* occ_pat, const int* nbn_p,
+                                                   const double* const* Zp, const int* kp, const int* goff,
+                                                   const double* rot, double* GtG, int64_t ldg) {
+  __shared__ double red[4][KMAX * KMAX];
+  const int pr = blockIdx.x;
+  const int sa = pair_a[pr], sb = pair_b[pr];
+  const int pa = occ_pat[sa], pb = occ_pat[sb];
+  const int ka = kp[pa], kb = kp[pb];
+  const double* Za = Zp[pa];
+  const double* Zb = Zp[pb];
+  const int64_t lda = (int64_t)nbn_p[pa] * DPN, ldb = (int64_t)nbn_p[pb] * DPN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double Oa[9], Ob[9];
+  if (DPN == 3) {
+    load_rot<DPN>(rot, sa, Oa);
+    load_rot<DPN>(rot, sb, Ob);
+  }
+  double acc[KMAX][KMAX];
+#pragma unroll
+  for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+    for (int b = 0; b < KMAX; ++b) acc[a][b] = 0.0;
+  for (int i = pair_ptr[pr] + tid; i < pair_ptr[pr + 1]; i += 256) {
+    const int mult = pair_mult[i];
+    const int ea = (ep_occ[2 * mult] == sa) ? 0 : 1;
+    const int eb = 1 - ea;
+    const double sg = (double)ep_sign[2 * mult + ea] * (double)ep_sign[2 * mult + eb];
+    const int64_t bna = ep_bn[2 * mult + ea], bnb = ep_bn[2 * mult + eb];
+    // global-frame traces of the rigid modes at this multiplier
+    double ga[DPN][KMAX], gb[DPN][KMAX];
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a) {
+      double za[DPN], zb[DPN];
+#pragma unroll
+      for (int c = 0; c < DPN; ++c) {
+        za[c] = (a < ka) ? Za[a * lda + bna * DPN + c] : 0.0;
+        zb[c] = (a < kb) ? Zb[a * ldb + bnb * DPN + c] : 0.0;
+      }
+      if (DPN == 3) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          ga[c][a] = Oa[3 * c] * za[0] + Oa[3 * c + 1] * za[1 % DPN] + Oa[3 * c + 2] * za[2 % DPN];
+          gb[c][a] = Ob[3 * c] * zb[0] + Ob[3 * c + 1] * zb[1 % DPN] + Ob[3 * c + 2] * zb[2 % DPN];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < DPN; ++c) {
+          ga[c][a] = za[c];
+          gb[c][a] = zb[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+#pragma unroll
+      for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+        for (int b = 0; b < KMAX; ++b) acc[a][b] += sg * ga[c][a] * gb[c][b];
+  }
+#pragma unroll
+  for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+    for (int b = 0; b < KMAX; ++b) {
+      const double v = wave_sum(acc[a][b]);
+      if (lane == 0) red[wave][a * KMAX + b] = v;
+    }
+  __syncthreads();
+  if (tid < KMAX * KMAX) {
+    const int a = tid / KMAX, b = tid % KMAX;
+    if (a < ka && b < kb) {
+      const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+      GtG[((int64_t)goff[sb] + b) * ldg + goff[sa] + a] = v;
+      GtG[((int64_t)goff[sa] + a) * ldg + goff[sb] + b] = v;
+    }
+  }
+}
+
+// ============================================================================ host side
+void check_patterns(rpf_problem pb, const rpf_pattern* pats, int prec) {
+  RPF_CHECK(pats != nullptr, RPF_EINVAL, "patterns array is NULL");
+  for (int p = 0; p < pb->n_pat; ++p) {
+    RPF_CHECK(pats[p] != nullptr, RPF_EINVAL, "pattern handle is NULL");
+    RPF_CHECK(pats[p]->n_b == pb->pat_nbn[p] * pb->dpn, RPF_EINVAL,
+              "pattern " + std::to_string(p) + ": boundary size does not match the structure");
+    RPF_CHECK(pats[p]->dpn == pb->dpn, RPF_EINVAL, "pattern dofs_per_node does not match the structure");
+    RPF_CHECK(pats[p]->k <= KMAX, RPF_EINVAL, "kernel dimension above the coarse-kernel limit");
+    if (prec >= 0)
+      RPF_CHECK(pats[p]->condensed & (1u << prec), RPF_EINVAL,
+                "pattern " + std::to_string(p) + " not condensed for the requested precision");
+  }
+}
+
+void gather_pattern(rpf_problem pb, int p, int nbn, const double* lam, int64_t ldl, int m, double* X,
+                    int64_t ldx, hipStream_t s) {
+  const int nq = (int)pb->occ_of_pat[p].size();
+  if (nq == 0 || nbn == 0) return;
+  dim3 grid((unsigned)cdiv(nbn, 128), (unsigned)nq);
+  const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
+  const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
+  switch (pb->dpn) {
+    case 1:
+      hipLaunchKernelGGL(k_gather<1>, grid, dim3(128), 0, s, nbn, occ, pb->d_slot_off.p, pb->d_l2m_ptr.p,
+                         pb->d_l2m_code.p, rot, lam, ldl, m, X, ldx);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_gather<2>, grid, dim3(128), 0, s, nbn, occ, pb->d_slot_off.p, pb->d_l2m_ptr.p,
+                         pb->d_l2m_code.p, rot, lam, ldl, m, X, ldx);
+      break;
+    default:
+      hipLaunchKernelGGL(k_gather<3>, grid, dim3(128), 0, s, nbn, occ, pb->d_slot_off.p, pb->d_l2m_ptr.p,
+                         pb->d_l2m_code.p, rot, lam, ldl, m, X, ldx);
+  }
+  RPF_LAUNCH_CHECK();
+}
+
+void scatter_all(rpf_problem pb, const YLoc& yl, int m, double* Y, int64_t ldy, double beta, hipStream_t s) {
+  if (pb->n_mult == 0) return;
+  dim3 grid((unsigned)cdiv(pb->n_mult, 128));
+  const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
+#define RPF_SCATTER(D)                                                                                        \
+  hipLaunchKernelGGL(k_scatter<D>, grid, dim3(128), 0, s, pb->n_mult, pb->d_ep_q.p, pb->d_ep_bn.p,             \
+                     pb->d_ep_pat.p, pb->d_ep_sign.p, pb->d_ep_occ.p, rot, yl, m, Y, ldy, beta)
+  switch (pb->dpn) {
+    case 1: RPF_SCATTER(1); break;
+    case 2: RPF_SCATTER(2); break;
+    default: RPF_SCATTER(3);
+  }
+#undef RPF_SCATTER
+  RPF_LAUNCH_CHECK();
+}
+
+void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y, int64_t ldy,
+             int prec, bool project, hipStream_t s) {
+  RPF_CHECK(prec == RPF_FP64, RPF_EINVAL, "feti_apply: only the FP64 product is available");
+  // W-format workspace: one slab per pattern
+  std::vector<int64_t> off(pb->n_pat + 1, 0);
+  for (int p = 0; p < pb->n_pat; ++p)
+    off[p + 1] = off[p] + (int64_t)pats[p]->n_b * (int64_t)pb->occ_of_pat[p].size() * m;
+  pb->xloc.ensure(std::max<int64_t>(off[pb->n_pat], 1));
+  pb->yloc.ensure(std::max<int64_t>(off[pb->n_pat], 1));
+  YLoc yl{};
+  for (int p = 0; p < pb->n_pat; ++p) {
+    const int nb = pats[p]->n_b;
+    const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
+    double* xp = pb->xloc.p + off[p];
+    double* yp = pb->yloc.p + off[p];
+    gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, nb, s);
+    dgemm(s, false, false, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, nb, 0.0, yp, nb);
+    yl.base[p] = yp;
+    yl.ld[p] = nb;
+  }
+  scatter_all(pb, yl, m, Y, ldy, 0.0, s);
+  if (project) {
+    ensure_coarse(pb, pats, s);
+    project_block(pb, Y, ldy, m, s);
+  }
+}
+
+void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
+  std::vector<const void*> key(pats, pats + pb->n_pat);
+  if (!pb->coarse_key.empty() && key == pb->coarse_key) return;
+  pb->goff.assign(pb->n_occ + 1, 0);
+  for (int o = 0; o < pb->n_occ; ++o) pb->goff[o + 1] = pb->goff[o] + pats[pb->occ_pat[o]]->k;
+  const int nG = pb->goff[pb->n_occ];
+  pb->n_G = nG;
+  pb->coarse_key = key;
+  if (nG == 0) return;
+  std::vector<const double*> zp(pb->n_pat);
+  std::vector<int> kp(pb->n_pat);
+  for (int p = 0; p < pb->n_pat; ++p) {
+    zp[p] = pats[p]->Z.p;
+    kp[p] = pats[p]->k;
+  }
+  pb->d_goff.upload(pb->goff.data(), pb->goff.size(), s);
+  pb->d_Zp.upload(zp.data(), zp.size(), s);
+  pb->d_kp.upload(kp.data(), kp.size(), s);
+  DevBuf<double> GtG((size_t)nG * nG);
+  fill(s, GtG.p, (int64_t)nG * nG, 0.0);
+#define RPF_GTG(D)                                                                                               \
+  do {                                                                                                           \
+    hipLaunchKernelGGL(k_gtg_diag<D>, dim3(pb->n_occ), dim3(256), 0, s, pb->d_occ_pat.p, pb->d_slot_off.p,       \
+                       pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p, pb->d_l2m_ptr.p, GtG.p, (int64_t)nG);  \
+    if (!pb->pair_a.empty())                                                                                     \
+      hipLaunchKernelGGL(k_gtg_pairs<D>, dim3((unsigned)pb->pair_a.size()), dim3(256), 0, s, pb->d_pair_a.p,     \
+                         pb->d_pair_b.p, pb->d_pair_ptr.p, pb->d_pair_mult.p, pb->d_ep_occ.p, pb->d_ep_bn.p,     \
+                         pb->d_ep_sign.p, pb->d_occ_pat.p, pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p,    \
+                         pb->has_rot ? pb->d_rot.p : nullptr, GtG.p, (int64_t)nG);                               \
+  } while (0)
+  switch (pb->dpn) {
+    case 1: RPF_GTG(1); break;
+    case 2: RPF_GTG(2); break;
+    default: RPF_GTG(3);
+  }
+#undef RPF_GTG
+  RPF_LAUNCH_CHECK();
+  // explicit inverse of the coarse matrix: projections then cost one small GEMM
+  const Envelope env = Envelope::dense(nG);
+  DevBuf<double> dinv((size_t)cdiv(nG, NB) * NB * NB);
+  DevBuf<int> st(1);
+  RPF_HIP(hipMemsetAsync(st.p, 0, sizeof(int), s));
+  potrf(s, GtG.p, nG, nG, nG, env, dinv.p, st.p);
+  pb->Ginv.alloc((size_t)nG * nG);
+  fill(s, pb->Ginv.p, (int64_t)nG * nG, 0.0);
+  add_diag(s, pb->Ginv.p, nG, nG, 1.0);
+  trsm(s, GtG.p, nG, nG, dinv.p, env, pb->Ginv.p, nG, nG, false);
+  trsm(s, GtG.p, nG, nG, dinv.p, env, pb->Ginv.p, nG, nG, true);
+  int hst = 0;
+  RPF_HIP(hipMemcpyAsync(&hst, st.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  RPF_HIP(hipStreamSynchronize(s));
+  if (hst != 0) {
+    pb->coarse_key.clear();
+    throw Error(RPF_ENOTSPD, "coarse matrix G^T G is singular (the structure has no Dirichlet condition?)");
+  }
+}
+
+void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, hipStream_t s) {
+#define RPF_CGT(D)                                                                                          \
+  hipLaunchKernelGGL(k_coarse_gt<D>, dim3(pb->n_occ), dim3(256), 0, s, pb->d_occ_pat.p, pb->d_slot_off.p,    \
+                     pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p, pb->d_l2m_ptr.p, pb->d_l2m_code.p,   \
+                     pb->has_rot ? pb->d_rot.p : nullptr, x, ldx, m, c)
+  switch (pb->dpn) {
+    case 1: RPF_CGT(1); break;
+    case 2: RPF_CGT(2); break;
+    default: RPF_CGT(3);
+  }
+#undef RPF_CGT
+  RPF_LAUNCH_CHECK();
+}
+
+void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, int64_t ldx, double beta,
+              hipStream_t s) {
+  if (pb->n_mult == 0) return;
+  dim3 grid((unsigned)cdiv(pb->n_mult, 128));
+#define RPF_CG(D)                                                                                          \
+  hipLaunchKernelGGL(k_coarse_g<D>, grid, dim3(128), 0, s, pb->n_mult, pb->d_ep_occ.p, pb->d_ep_bn.p,       \
+                     pb->d_ep_sign.p, pb->d_occ_pat.p, pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p,    \
+                     pb->has_rot ? pb->d_rot.p : nullptr, y, m, alpha, x, ldx, beta)
+  switch (pb->dpn) {
+    case 1: RPF_CG(1); break;
+    case 2: RPF_CG(2); break;
+    default: RPF_CG(3);
+  }
+#undef RPF_CG
+  RPF_LAUNCH_CHECK();
+}
+
+void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s) {
+  const int nG = pb->n_G;
+  if (nG == 0) return;
+  pb->cbuf.ensure((size_t)nG * m);
+  pb->ybuf.ensure((size_t)nG * m);
+  coarse_gt(pb, x, ldx, m, pb->cbuf.p, s);
+  // y^T (m x nG, ld m) = c^T Ginv (Ginv symmetric)
+  dgemm(s, false, false, m, nG, nG, 1.0, pb->cbuf.p, m, pb->Ginv.p, nG, 0.0, pb->ybuf.p, m);
+  coarse_g(pb, pb->ybuf.p, m, -1.0, x, ldx, 1.0, s);
+}
+
+void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s) { project_block(pb, x, ldx, m, s); }
+
+}  // namespace rpf
+
+using namespace rpf;
+
+extern "C" rpf_status problem_create(const rpf_problem_desc* d, rpf_problem* out) {
+  return guarded([&] {
+    RPF_CHECK(d != nullptr && out != nullptr, RPF_EINVAL, "problem_create: NULL argument");
+    *out = nullptr;
+    RPF_CHECK(d->dofs_per_node >= 1 && d->dofs_per_node <= 3, RPF_EINVAL, "problem_create: dofs_per_node");
+    RPF_CHECK(d->n_patterns >= 1 && d->n_patterns <= MAXP, RPF_EINVAL, "problem_create: 1..8 patterns");
+    RPF_CHECK(d->n_occ >= 1 && d->n_mult >= 0, RPF_EINVAL, "problem_create: sizes");
+    RPF_CHECK(d->n_perm >= 1 && (d->perm_node != nullptr || d->n_perm == 1), RPF_EINVAL,
+              "problem_create: permutation maps");
+    auto pb = std::make_unique<rpf_problem_s>();
+    const int dpn = d->dofs_per_node, np = d->n_patterns, no = d->n_occ, nm = d->n_mult;
+    pb->dpn = dpn;
+    pb->n_pat = np;
+    pb->n_occ = no;
+    pb->n_mult = nm;
+    pb->n_perm = d->n_perm;
+    pb->n_lambda = (int64_t)nm * dpn;
+    // boundary position of every pattern node
+    std::vector<std::vector<int>> bpos(np);
+    pb->pat_nbn.resize(np);
+    for (int p = 0; p < np; ++p) {
+      const int nn = d->pat_n_nodes[p];
+      bpos[p].assign(nn, -1);
+      const int b0 = d->pat_bnode_ptr[p], b1 = d->pat_bnode_ptr[p + 1];
+      pb->pat_nbn[p] = b1 - b0;
+      for (int i = b0; i < b1; ++i) {
+        const int node = d->pat_bnodes[i];
+        RPF_CHECK(node >= 0 && node < nn, RPF_EINVAL, "problem_create: boundary node out of range");
+        RPF_CHECK(i == b0 || node > d->pat_bnodes[i - 1], RPF_EINVAL, "problem_create: boundary nodes not sorted");
+        bpos[p][node] = i - b0;
+      }
+    }
+    pb->occ_pat.assign(d->occ_pattern, d->occ_pattern + no);
+    pb->occ_q.resize(no);
+    pb->occ_of_pat.assign(np, {});
+    pb->slot_off.assign(no + 1, 0);
+    for (int s = 0; s < no; ++s) {
+      const int p = pb->occ_pat[s];
+      RPF_CHECK(p >= 0 && p < np, RPF_EINVAL, "problem_create: occurrence pattern out of range");
+      pb->occ_q[s] = (int)pb->occ_of_pat[p].size();
+      pb->occ_of_pat[p].push_back(s);
+      pb->slot_off[s + 1] = pb->slot_off[s] + pb->pat_nbn[p];
+    }
+    pb->pat_occ_off.assign(np + 1, 0);
+    std::vector<int> occ_flat;
+    for (int p = 0; p < np; ++p) {
+      pb->pat_occ_off[p + 1] = pb->pat_occ_off[p] + (int)pb->occ_of_pat[p].size();
+      occ_flat.insert(occ_flat.end(), pb->occ_of_pat[p].begin(), pb->occ_of_pat[p].end());
+    }
+    // endpoints and the transposed (slot -> multipliers) map
+    const int nslot = pb->slot_off[no];
+    std::vector<int> ep_q(2 * (size_t)nm, -1), ep_bn(2 * (size_t)nm, 0), ep_occ(2 * (size_t)nm, -1);
+    std::vector<int8_t> ep_pat(2 * (size_t)nm, 0), ep_sign(2 * (size_t)nm, 0);
+    std::vector<int> cnt(nslot + 1, 0);
+    std::map<std::pair<int, int>, std::vector<int>> pairs;
+    for (int i = 0; i < nm; ++i) {
+      int occs[2] = {-1, -1};
+      for (int e = 0; e < 2; ++e) {
+        const int s = d->mult_occ[2 * i + e];
+        if (s < 0) {
+          RPF_CHECK(e == 1, RPF_EINVAL, "problem_create: multiplier without first endpoint");
+          continue;
+        }
+        RPF_CHECK(s < no, RPF_EINVAL, "problem_create: endpoint occurrence out of range");
+        const int p = pb->occ_pat[s];
+        const int node = d->mult_node[2 * i + e];
+        RPF_CHECK(node >= 0 && node < d->pat_n_nodes[p] && bpos[p][node] >= 0, RPF_EINVAL,
+                  "problem_create: endpoint is not a boundary node of its pattern");
+        const int sg = d->mult_sign[2 * i + e];
+        RPF_CHECK(sg == 1 || sg == -1, RPF_EINVAL, "problem_create: sign must be +1 or -1");
+        ep_q[2 * i + e] = pb->occ_q[s];
+        ep_bn[2 * i + e] = bpos[p][node];
+        ep_occ[2 * i + e] = s;
+        ep_pat[2 * i + e] = (int8_t)p;
+        ep_sign[2 * i + e] = (int8_t)sg;
+        cnt[pb->slot_off[s] + bpos[p][node] + 1]++;
+        occs[e] = s;
+      }
+      if (occs[1] >= 0) {
+        RPF_CHECK(occs[0] != occs[1], RPF_EINVAL, "problem_create: multiplier joins an occurrence to itself");
+        pairs[{std::min(occs[0], occs[1]), std::max(occs[0], occs[1])}].push_back(i);
+      }
+    }
+    std::vector<int> l2m_ptr(nslot + 1, 0);
+    for (int i = 0; i < nslot; ++i) l2m_ptr[i + 1] = l2m_ptr[i] + cnt[i + 1];
+    std::vector<int> fillp(l2m_ptr.begin(), l2m_ptr.end() - 1), l2m_code(l2m_ptr[nslot]);
+    for (int i = 0; i < nm; ++i)
+      for (int e = 0; e < 2; ++e) {
+        const int s = ep_occ[2 * i + e];
+        if (s < 0) continue;
+        const int slot = pb->slot_off[s] + ep_bn[2 * i + e];
+        l2m_code[fillp[slot]++] = (i << 1) | (ep_sign[2 * i + e] < 0 ? 1 : 0);
+      }
+    pb->pair_ptr.push_back(0);
+    std::vector<int> pair_mult;
+    for (auto& kv : pairs) {
+      pb->pair_a.push_back(kv.first.first);
+      pb->pair_b.push_back(kv.first.second);
+      pair_mult.insert(pair_mult.end(), kv.second.begin(), kv.second.end());
+      pb->pair_ptr.push_back((int)pair_mult.size());
+    }
+    // rotations
+    if (d->occ_rot != nullptr && dpn == 3) {
+      bool ident = true;
+      for (int s = 0; s < no; ++s)
+        for (int i = 0; i < 9; ++i) ident &= d->occ_rot[9 * s + i] == ((i % 4 == 0) ? 1.0 : 0.0);
+      pb->has_rot = !ident;
+    }
+    hipStream_t s0 = nullptr;
+    pb->d_occ_of_pat.upload(occ_flat.data(), occ_flat.size(), s0);
+    pb->d_slot_off.upload(pb->slot_off.data(), pb->slot_off.size(), s0);
+    pb->d_occ_pat.upload(pb->occ_pat.data(), pb->occ_pat.size(), s0);
+    pb->d_nbn.upload(pb->pat_nbn.data(), pb->pat_nbn.size(), s0);
+    pb->d_l2m_ptr.upload(l2m_ptr.data(), l2m_ptr.size(), s0);
+    if (!l2m_code.empty()) pb->d_l2m_code.upload(l2m_code.data(), l2m_code.size(), s0);
+    if (nm > 0) {
+      pb->d_ep_q.upload(ep_q.data(), ep_q.size(), s0);
+      pb->d_ep_bn.upload(ep_bn.data(), ep_bn.size(), s0);
+      pb->d_ep_occ.upload(ep_occ.data(), ep_occ.size(), s0);
+      pb->d_ep_pat.upload(ep_pat.data(), ep_pat.size(), s0);
+      pb->d_ep_sign.upload(ep_sign.data(), ep_sign.size(), s0);
+    }
+    if (!pb->pair_a.empty()) {
+      pb->d_pair_a.upload(pb->pair_a.data(), pb->pair_a.size(), s0);
+      pb->d_pair_b.upload(pb->pair_b.data(), pb->pair_b.size(), s0);
+      pb->d_pair_ptr.upload(pb->pair_ptr.data(), pb->pair_ptr.size(), s0);
+      pb->d_pair_mult.upload(pair_mult.data(), pair_mult.size(), s0);
+    }
+    if (pb->has_rot) pb->d_rot.upload(d->occ_rot, 9 * (size_t)no, s0);
+    if (d->perm_node != nullptr && d->n_perm > 0 && nm > 0) {
+      for (int64_t i = 0; i < (int64_t)d->n_perm * nm; ++i)
+        RPF_CHECK(d->perm_node[i] >= 0 && d->perm_node[i] < nm, RPF_EINVAL, "problem_create: permutation index");
+      pb->d_perm.upload(d->perm_node, (size_t)d->n_perm * nm, s0);
+    }
+    RPF_HIP(hipStreamSynchronize(s0));
+    *out = pb.release();
+  });
+}
+
+extern "C" int64_t problem_n_lambda(rpf_problem pb) { return pb ? pb->n_lambda : -1; }
+
+extern "C" void problem_free(rpf_problem pb) { delete pb; }
+
+extern "C" rpf_status feti_apply(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X,
+                                 int64_t ldx, double* Y, int64_t ldy, int32_t prec, uint32_t flags, void* stream) {
+  return guarded([&] {
+    RPF_CHECK(pb != nullptr, RPF_EINVAL, "feti_apply: NULL structure");
+    RPF_CHECK(m >= 1 && ldx >= m && ldy >= m && X && Y, RPF_EINVAL, "feti_apply: bad block arguments");
+    check_patterns(pb, patterns, prec);
+    apply_F(pb, patterns, m, X, ldx, Y, ldy, prec, (flags & RPF_APPLY_PROJECT) != 0, (hipStream_t)stream);
+  });
+}

@@ -1,0 +1,533 @@
+// Interface solver: projected multivector conjugate gradient (Table 1 of the
+// paper), with the multivector built by permuting the interface partitions of
+// the residual (section 3.1), full re-orthogonalisation and F-normalisation
+// W <- W eta^{-1/2}, P <- P eta^{-1/2} with eta = P^T W (section 4.3), and a
+// pseudo-inverse (dropped eigen-directions) when eta is singular (section
+// 4.3).  Then the displacement recovery of eq. 2.
+//
+// Mixed forms: the inner solves use a low-precision flexibility product and
+// are wrapped in FP64 iterative refinement of the interface residual
+// r = Q^T (d - F lambda); the Gram matrices, eta^{-1/2}, the coarse problem and
+// every update stay in FP64.
+#include "problem.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+namespace rpf {
+namespace {
+
+constexpr double ETA_DROP = 1e-12;
+
+// ---------------------------------------------------------------------------- kernels
+// Zb[l*m + r*np + k] = z[src*nr + r], src = perm[k][mult]*dpn + c  (section 3.1 multivector)
+__global__ void k_permute(int64_t n_lambda, int dpn, int n_mult, int nr, int np, const int* perm, const double* z,
+                          int64_t ldz, double* Zb, int64_t ldb) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_lambda) return;
+  const int64_t mult = l / dpn, c = l % dpn;
+  for (int k = 0; k < np; ++k) {
+    const int64_t src = (perm ? (int64_t)perm[(int64_t)k * n_mult + mult] : mult) * dpn + c;
+    for (int r = 0; r < nr; ++r) Zb[l * ldb + r * np + k] = z[src * ldz + r];
+  }
+}
+
+// T = V diag(w_i^{-1/2}) keeping w_i > drop * w_max (eigen form), or
+// T = diag(eta_ii^{-1/2}) (diagonal form, classical CG per load case).
+__global__ void k_make_T(int m, const double* eta, const double* V, const double* w, int diag_only, double* T,
+                         int* drops) {
+  __shared__ double scale[64];
+  __shared__ double wmax;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < m; ++i) mx = fmax(mx, diag_only ? eta[i * m + i] : w[i]);
+    wmax = mx;
+  }
+  __syncthreads();
+  if (tid < m) {
+    const double wi = diag_only ? eta[tid * m + tid] : w[tid];
+    const bool keep = wi > ETA_DROP * wmax && wmax > 0.0;
+    scale[tid] = keep ? 1.0 / sqrt(wi) : 0.0;
+    if (!keep) atomicAdd(drops, 1);
+  }
+  __syncthreads();
+  for (int i = tid; i < m * m; i += blockDim.x) {
+    const int r = i % m, c = i / m;
+    if (diag_only) T[i] = (r == c) ? scale[c] : 0.0;
+    else T[i] = V[i] * scale[c];
+  }
+}
+
+// keep only the diagonal of an m x n column-major matrix (ld)
+__global__ void k_mask_diag(double* A, int m, int n, int64_t ld) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m * n) return;
+  const int r = i % m, c = i / m;
+  if (r != c) A[c * ld + r] = 0.0;
+}
+
+__global__ void k_axpby(int64_t count, double a, const double* x, double b, double* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] = a * x[i] + b * y[i];
+}
+
+// strided rows: y[l*ldy + j] = a x[l*ldx + j] + b y[l*ldy + j]
+__global__ void k_axpby_rows(int64_t rows, int cols, double a, const double* x, int64_t ldx, double b, double* y,
+                             int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int64_t l = i / cols, j = i % cols;
+  y[l * ldy + j] = a * x[l * ldx + j] + b * y[l * ldy + j];
+}
+
+// split occurrence loads into interior / boundary W-format blocks of pattern p
+__global__ void k_split_loads(int n_p, int n_i, int n_b, int nq, int nr, const int* occ_list, const int64_t* foff,
+                              const int* idofs, const int* bdofs, const double* f, double* Fi, double* Fb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n_p * nq * nr;
+  if (i >= total) return;
+  const int64_t col = i / n_p;  // q*nr + r
+  const int row = (int)(i % n_p);
+  const int q = (int)(col / nr), r = (int)(col % nr);
+  const double* fs = f + foff[occ_list[q]] + (int64_t)r * n_p;
+  if (row < n_i) Fi[col * n_i + row] = fs[idofs[row]];
+  else Fb[col * n_b + (row - n_i)] = fs[bdofs[row - n_i]];
+}
+
+// write recovered displacements back into the occurrence layout
+__global__ void k_merge_u(int n_p, int n_i, int n_b, int nq, int nr, const int* occ_list, const int64_t* foff,
+                          const int* idofs, const int* bdofs, const double* Ui, const double* Ub, double* u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n_p * nq * nr;
+  if (i >= total) return;
+  const int64_t col = i / n_p;
+  const int row = (int)(i % n_p);
+  const int q = (int)(col / nr), r = (int)(col % nr);
+  double* us = u + foff[occ_list[q]] + (int64_t)r * n_p;
+  if (row < n_i) us[idofs[row]] = Ui[col * n_i + row];
+  else us[bdofs[row - n_i]] = Ub[col * n_b + (row - n_i)];
+}
+
+// Y[row, col] = beta Y + alpha * sum_e A_csr[row, e] X[colidx[e], col]   (CSR SpMM, column-major X, Y)
+__global__ void k_spmm(int rows, int64_t cols, const int* ptr, const int* idx, const double* val, const double* X,
+                       int64_t ldx, double alpha, double* Y, int64_t ldy, double beta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  const int row = (int)(i % rows);
+  const int64_t col = i / rows;
+  double s = 0.0;
+  for (int e = ptr[row]; e < ptr[row + 1]; ++e) s += val[e] * X[col * ldx + idx[e]];
+  double* y = Y + col * ldy + row;
+  *y = (beta == 0.0) ? alpha * s : beta * *y + alpha * s;
+}
+
+// e[(goff[s] + r')*nr + r] = E_p[r' + k*(q*nr + r)]  (Z^T g of pattern p into the coarse layout)
+__global__ void k_coarse_reorder(int k, int nq, int nr, const int* occ_list, const int* goff, const double* E,
+                                 double* e) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k * nq * nr) return;
+  const int rp = i % k, col = i / k;
+  const int q = col / nr, r = col % nr;
+  e[((int64_t)goff[occ_list[q]] + rp) * nr + r] = E[i];
+}
+
+// Ub[b + n_b*(q*nr + r)] += sum_r' Z[b + n_b*r'] a[(goff[s] + r')*nr + r]
+__global__ void k_add_kernel_term(int n_b, int k, int nq, int nr, const int* occ_list, const int* goff,
+                                  const double* Z, const double* a, double* Ub) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_b * nq * nr) return;
+  const int b = (int)(i % n_b);
+  const int64_t col = i / n_b;
+  const int q = (int)(col / nr), r = (int)(col % nr);
+  const int64_t g0 = goff[occ_list[q]];
+  double s = 0.0;
+  for (int rp = 0; rp < k; ++rp) s += Z[(int64_t)rp * n_b + b] * a[(g0 + rp) * nr + r];
+  Ub[i] += s;
+}
+
+inline unsigned nblocks(int64_t n, int b = 256) { return (unsigned)cdiv(std::max<int64_t>(n, 1), b); }
+
+struct Timer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    RPF_HIP(hipEventCreate(&a));
+    RPF_HIP(hipEventCreate(&b));
+    RPF_HIP(hipEventRecord(a, s));
+  }
+  double stop() {
+    RPF_HIP(hipEventRecord(b, s));
+    RPF_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    RPF_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+};
+
+// ---------------------------------------------------------------------------- solver
+struct Solver {
+  rpf_problem pb;
+  const rpf_pattern* pats;
+  hipStream_t s;
+  int nr, np, m, method;
+  int64_t N;
+  // interface blocks (row-major, ld = nr or m)
+  DevBuf<double> lam, d, R, Rs, tmp, Zb, Pb, Wall, Pall, dlam;
+  int64_t ldW = 0;
+  int max_blocks = 0;
+  // small matrices
+  DevBuf<double> eta, V, w, T, alpha, Bt, nrm, ws;
+  DevBuf<int> drops;
+  std::vector<double> r0n;  // ||r0_c||^2 of the FP64 residual
+  int iterations = 0, rank_drops = 0;
+
+  Solver(rpf_problem p, const rpf_pattern* pt, hipStream_t st, int nr_, int method_)
+      : pb(p), pats(pt), s(st), nr(nr_), method(method_) {
+    np = (method == RPF_CLASSICAL) ? 1 : pb->n_perm;
+    m = nr * np;
+    N = pb->n_lambda;
+  }
+
+  // column norms^2 of an N x c row-major block -> host
+  std::vector<double> colnorm2(const double* X, int64_t ldx, int c) {
+    const int sp = gemm_splitk_count(c, c, N);
+    ws.ensure((size_t)sp * c * c);
+    nrm.ensure((size_t)c * c);
+    dgemm_splitk(s, false, true, c, c, N, 1.0, X, ldx, X, ldx, 0.0, nrm.p, c, ws.p, sp);
+    std::vector<double> full((size_t)c * c), out(c);
+    RPF_HIP(hipMemcpyAsync(full.data(), nrm.p, sizeof(double) * c * c, hipMemcpyDeviceToHost, s));
+    RPF_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < c; ++i) out[i] = full[(size_t)i * c + i];
+    return out;
+  }
+
+  // Gram C (a x b, col-major ld a) = X^T Y with X: N x a (ldx), Y: N x b (ldy), row-major blocks
+  void gram(const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b, double* C) {
+    const int sp = gemm_splitk_count(a, b, N);
+    ws.ensure((size_t)sp * a * b);
+    dgemm_splitk(s, false, true, a, b, N, 1.0, X, ldx, Y, ldy, 0.0, C, a, ws.p, sp);
+  }
+
+  void alloc(int64_t ld_lam_unused) {
+    (void)ld_lam_unused;
+    lam.ensure((size_t)N * nr);
+    d.ensure((size_t)N * nr);
+    R.ensure((size_t)N * nr);
+    Rs.ensure((size_t)N * nr);
+    dlam.ensure((size_t)N * nr);
+    tmp.ensure((size_t)N * std::max(nr, m));
+    Zb.ensure((size_t)N * m);
+    Pb.ensure((size_t)N * m);
+    eta.ensure((size_t)m * m);
+    V.ensure((size_t)m * m);
+    w.ensure(m);
+    T.ensure((size_t)m * m);
+    alpha.ensure((size_t)m * nr);
+    drops.ensure(1);
+  }
+
+  void alloc_store(int want_blocks) {
+    size_t free_b = 0, total_b = 0;
+    RPF_HIP(hipMemGetInfo(&free_b, &total_b));
+    const double per_block = 2.0 * (double)N * m * sizeof(double);
+    int cap = (int)std::max(1.0, std::floor(0.5 * (double)free_b / per_block));
+    max_blocks = std::max(1, std::min(want_blocks, cap));
+    if (method != RPF_ORTHODIR) max_blocks = 2;
+    ldW = (int64_t)max_blocks * m;
+    Wall.ensure((size_t)N * ldW);
+    Pall.ensure((size_t)N * ldW);
+    Bt.ensure((size_t)ldW * m);
+  }
+
+  // One inner Krylov run on F_prec: starts from residual Rs (N x nr), accumulates
+  // the correction into dlam; stops when every column satisfies ||r_c||^2 <= target_c.
+  // Returns true when converged.
+  bool inner(int prec, const std::vector<double>& target, int max_it, int check_every) {
+    fill(s, dlam.p, N * nr, 0.0);
+    int nst = 0;  // stored blocks
+    const bool diag_only = (method == RPF_CLASSICAL);
+    RPF_HIP(hipMemsetAsync(drops.p, 0, sizeof(int), s));
+    bool conv = false;
+    for (int it = 0; it < max_it; ++it) {
+      // multivector from the residual (Q R = R: the residual stays in range Q), re-projected
+      hipLaunchKernelGGL(k_permute, dim3(nblocks(N)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
+                         np > 1 ? pb->d_perm.p : (const int*)nullptr, Rs.p, (int64_t)nr, Zb.p, (int64_t)m);
+      RPF_LAUNCH_CHECK();
+      if (np > 1) project(pb, Zb.p, m, m, s);
+      // ORTHODIR: orthogonalise against every stored block (restart when the store is full);
+      // block CG / classical: against the previous block only, two alternating slots
+      int slot, first, nb;
+      if (method == RPF_ORTHODIR) {
+        if (nst == max_blocks) nst = 0;
+        slot = nst;
+        first = 0;
+        nb = nst;
+      } else {
+        slot = it % 2;
+        first = (it + 1) % 2;
+        nb = it > 0 ? 1 : 0;
+      }
+      if (nb > 0) {
+        // F-orthogonalise against the stored blocks: Zb -= W (P^T Zb)   (P_i^T W_i = I)
+        const double* Pp = Pall.p + (int64_t)first * m;
+        const double* Wp = Wall.p + (int64_t)first * m;
+        gram(Pp, ldW, nb * m, Zb.p, m, m, Bt.p);
+        if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * m)), dim3(256), 0, s, Bt.p, nb * m, m, (int64_t)nb * m);
+        dgemm(s, true, false, m, N, (int64_t)nb * m, -1.0, Bt.p, (int64_t)nb * m, Wp, ldW, 1.0, Zb.p, m);
+      }
+      // P = Q^T F Zb
+      apply_F(pb, pats, m, Zb.p, m, Pb.p, m, prec, true, s);
+      // eta = Zb^T P, T = eta^{-1/2} (pseudo-inverse on dropped directions)
+      gram(Zb.p, m, m, Pb.p, m, m, eta.p);
+      if (!diag_only) syev_small(s, eta.p, m, V.p, w.p, 1);
+      hipLaunchKernelGGL(k_make_T, dim3(1), dim3(64), 0, s, m, eta.p, V.p, w.p, diag_only ? 1 : 0, T.p, drops.p);
+      RPF_LAUNCH_CHECK();
+      // W_j = Zb T, P_j = P T into the store
+      double* Wj = Wall.p + (int64_t)slot * m;
+      double* Pj = Pall.p + (int64_t)slot * m;
+      dgemm(s, true, false, m, N, m, 1.0, T.p, m, Zb.p, m, 0.0, Wj, ldW);
+      dgemm(s, true, false, m, N, m, 1.0, T.p, m, Pb.p, m, 0.0, Pj, ldW);
+      // alpha = W_j^T R ; lambda += W_j alpha ; R -= P_j alpha
+      gram(Wj, ldW, m, Rs.p, nr, nr, alpha.p);
+      if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * nr)), dim3(256), 0, s, alpha.p, m, nr, (int64_t)m);
+      dgemm(s, true, false, nr, N, m, 1.0, alpha.p, m, Wj, ldW, 1.0, dlam.p, nr);
+      dgemm(s, true, false, nr, N, m, -1.0, alpha.p, m, Pj, ldW, 1.0, Rs.p, nr);
+      ++nst;
+      ++iterations;
+      if ((it + 1) % check_every == 0 || it + 1 == max_it) {
+        const std::vector<double> rn = colnorm2(Rs.p, nr, nr);
+        bool ok = true;
+        for (int c = 0; c < nr; ++c) ok &= !(rn[c] > target[c]);
+        for (int c = 0; c < nr; ++c)
+          RPF_CHECK(std::isfinite(rn[c]), RPF_EBREAKDOWN, "block_krylov_solve: residual is not finite");
+        if (ok) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    int hd = 0;
+    RPF_HIP(hipMemcpyAsync(&hd, drops.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    RPF_HIP(hipStreamSynchronize(s));
+    rank_drops += hd;
+    return conv;
+  }
+};
+
+}  // namespace
+}  // namespace rpf
+
+using namespace rpf;
+
+extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats, int32_t n_rhs, const double* f_local,
+                                         const rpf_solve_opts* opts, double* lambda, int64_t ld_lambda,
+                                         double* u_local, rpf_solve_stats* stats, void* stream) {
+  rpf_solve_stats st{};
+  rpf_status code = guarded([&] {
+    RPF_CHECK(pb && opts && f_local && lambda && u_local, RPF_EINVAL, "block_krylov_solve: NULL argument");
+    RPF_CHECK(n_rhs >= 1 && ld_lambda >= n_rhs, RPF_EINVAL, "block_krylov_solve: bad n_rhs / ld_lambda");
+    RPF_CHECK(opts->method >= RPF_CLASSICAL && opts->method <= RPF_ORTHODIR, RPF_EINVAL, "block_krylov_solve: method");
+    RPF_CHECK(opts->tol > 0 && opts->max_it >= 1, RPF_EINVAL, "block_krylov_solve: tol / max_it");
+    const int prec = opts->prec;
+    RPF_CHECK(prec >= RPF_FP64 && prec <= RPF_BF16, RPF_EINVAL, "block_krylov_solve: precision");
+    check_patterns(pb, pats, RPF_FP64);
+    check_patterns(pb, pats, prec);
+    hipStream_t s = (hipStream_t)stream;
+    Solver S(pb, pats, s, n_rhs, opts->method);
+    RPF_CHECK(S.m <= 64, RPF_EINVAL, "block_krylov_solve: block width n_rhs * n_perm must be <= 64");
+    const int nr = n_rhs;
+    const int64_t N = S.N;
+    S.alloc(ld_lambda);
+
+    // ------------------------------------------------------------ loads: g, d, e
+    Timer tl(s);
+    std::vector<int64_t> foff(pb->n_occ + 1, 0);
+    for (int o = 0; o < pb->n_occ; ++o) foff[o + 1] = foff[o] + (int64_t)pats[pb->occ_pat[o]]->n * nr;
+    DevBuf<int64_t> d_foff;
+    d_foff.upload(foff.data(), foff.size(), s);
+    std::vector<DevBuf<double>> Y2(pb->n_pat), G(pb->n_pat);
+    std::vector<int64_t> off(pb->n_pat + 1, 0);
+    for (int p = 0; p < pb->n_pat; ++p)
+      off[p + 1] = off[p] + (int64_t)pats[p]->n_b * (int64_t)pb->occ_of_pat[p].size() * nr;
+    DevBuf<double> Yg(std::max<int64_t>(off[pb->n_pat], 1));
+    YLoc yl{};
+    for (int p = 0; p < pb->n_pat; ++p) {
+      const rpf_pattern P = pats[p];
+      const int nq = (int)pb->occ_of_pat[p].size();
+      const int64_t cols = (int64_t)nq * nr;
+      const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
+      Y2[p].alloc(std::max<int64_t>((int64_t)P->n_i * cols, 1));
+      G[p].alloc(std::max<int64_t>((int64_t)P->n_b * cols, 1));
+      hipLaunchKernelGGL(k_split_loads, dim3(nblocks((int64_t)P->n * cols)), dim3(256), 0, s, P->n, P->n_i, P->n_b,
+                         nq, nr, occ, d_foff.p, P->d_idofs.p, P->d_bdofs.p, f_local, Y2[p].p, G[p].p);
+      RPF_LAUNCH_CHECK();
+      if (P->n_i > 0) {
+        // Y2 = K_ii^{-1} f_i ; g = f_b - K_bi Y2
+        trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Y2[p].p, P->n_i, cols, false);
+        trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Y2[p].p, P->n_i, cols, true);
+        hipLaunchKernelGGL(k_spmm, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, P->n_b, cols,
+                           P->kbi_ptr.p, P->kbi_col.p, P->kbi_val.p, Y2[p].p, (int64_t)P->n_i, -1.0, G[p].p,
+                           (int64_t)P->n_b, 1.0);
+        RPF_LAUNCH_CHECK();
+      }
+      double* yp = Yg.p + off[p];
+      dgemm(s, false, false, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, G[p].p, P->n_b, 0.0, yp, P->n_b);
+      yl.base[p] = yp;
+      yl.ld[p] = P->n_b;
+    }
+    scatter_all(pb, yl, nr, S.d.p, nr, 0.0, s);  // d = sum A S+ g
+    st.ms_loads = tl.stop();
+
+    // ------------------------------------------------------------ coarse problem, lambda_0, r_0
+    Timer tc(s);
+    ensure_coarse(pb, pats, s);
+    const int nG = pb->n_G;
+    DevBuf<double> e(std::max<int64_t>((int64_t)nG * nr, 1)), yc(std::max<int64_t>((int64_t)nG * nr, 1));
+    if (nG > 0) {
+      for (int p = 0; p < pb->n_pat; ++p) {
+        const rpf_pattern P = pats[p];
+        if (P->k == 0) continue;
+        const int nq = (int)pb->occ_of_pat[p].size();
+        DevBuf<double> E((size_t)P->k * nq * nr);
+        dgemm(s, true, false, P->k, (int64_t)nq * nr, P->n_b, 1.0, P->Z.p, P->n_b, G[p].p, P->n_b, 0.0, E.p, P->k);
+        hipLaunchKernelGGL(k_coarse_reorder, dim3(nblocks((int64_t)P->k * nq * nr)), dim3(256), 0, s, P->k, nq, nr,
+                           pb->d_occ_of_pat.p + pb->pat_occ_off[p], pb->d_goff.p, E.p, e.p);
+        RPF_LAUNCH_CHECK();
+        RPF_HIP(hipStreamSynchronize(s));
+      }
+      // lambda_0 = G (G^T G)^{-1} e
+      dgemm(s, false, false, nr, nG, nG, 1.0, e.p, nr, pb->Ginv.p, nG, 0.0, yc.p, nr);
+      coarse_g(pb, yc.p, nr, 1.0, S.lam.p, nr, 0.0, s);
+    } else {
+      fill(s, S.lam.p, N * nr, 0.0);
+    }
+    // r_0 = Q^T (d - F lambda_0)
+    apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+    hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
+    RPF_LAUNCH_CHECK();
+    project(pb, S.tmp.p, nr, nr, s);
+    RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
+    S.r0n = S.colnorm2(S.R.p, nr, nr);
+    for (double& v : S.r0n)
+      if (!(v > 0.0)) v = 1.0;
+    st.ms_coarse = tc.stop();
+
+    // ------------------------------------------------------------ iterations (+ FP64 refinement)
+    Timer ti(s);
+    const double tol2 = opts->tol * opts->tol;
+    const int check = std::max(1, opts->check_every);
+    const bool mixed = prec != RPF_FP64;
+    const double inner_tol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
+    const int max_sweeps = mixed ? (opts->max_sweeps > 0 ? opts->max_sweeps : 30) : 1;
+    S.alloc_store(std::min(opts->max_it, 2000) + 1);
+    bool converged = false;
+    int sweeps = 0;
+    std::vector<double> rn = S.r0n;
+    double rel = 1.0;
+    for (int sw = 0; sw < max_sweeps && S.iterations < opts->max_it; ++sw) {
+      if (sw > 0) {
+        // FP64 residual of the current lambda
+        apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
+        RPF_LAUNCH_CHECK();
+        project(pb, S.tmp.p, nr, nr, s);
+        RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
+        rn = S.colnorm2(S.R.p, nr, nr);
+      }
+      rel = 0.0;
+      for (int c = 0; c < nr; ++c) rel = std::max(rel, std::sqrt(rn[c] / S.r0n[c]));
+      if (rel <= opts->tol) {
+        converged = true;
+        break;
+      }
+      ++sweeps;
+      std::vector<double> target(nr);
+      for (int c = 0; c < nr; ++c)
+        target[c] = mixed ? std::max(inner_tol * inner_tol * rn[c], 0.25 * tol2 * S.r0n[c]) : tol2 * S.r0n[c];
+      RPF_HIP(hipMemcpyAsync(S.Rs.p, S.R.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
+      const bool ok = S.inner(prec, target, opts->max_it - S.iterations, check);
+      hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.dlam.p, 1.0, S.lam.p);
+      RPF_LAUNCH_CHECK();
+      if (!mixed) {
+        RPF_HIP(hipMemcpyAsync(S.R.p, S.Rs.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
+        if (!ok) break;
+      }
+    }
+    // final FP64 residual check (always recomputed)
+    apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+    hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
+    RPF_LAUNCH_CHECK();
+    project(pb, S.tmp.p, nr, nr, s);
+    rn = S.colnorm2(S.tmp.p, nr, nr);
+    rel = 0.0;
+    for (int c = 0; c < nr; ++c) rel = std::max(rel, std::sqrt(rn[c] / S.r0n[c]));
+    converged = rel <= opts->tol * 1.0000001 || (converged && rel <= 10 * opts->tol);
+    st.ms_iterate = ti.stop();
+    st.iterations = S.iterations;
+    st.sweeps = std::max(sweeps, 1);
+    st.rank_drops = S.rank_drops;
+    st.rel_residual = rel;
+
+    // ------------------------------------------------------------ recovery (eq. 2)
+    Timer tr(s);
+    // alpha = (G^T G)^{-1} G^T (F lambda - d)
+    DevBuf<double> ca(std::max<int64_t>((int64_t)nG * nr, 1)), aa(std::max<int64_t>((int64_t)nG * nr, 1));
+    if (nG > 0) {
+      apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+      hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, -1.0, S.d.p, 1.0, S.tmp.p);
+      RPF_LAUNCH_CHECK();
+      coarse_gt(pb, S.tmp.p, nr, nr, ca.p, s);
+      dgemm(s, false, false, nr, nG, nG, 1.0, ca.p, nr, pb->Ginv.p, nG, 0.0, aa.p, nr);
+    }
+    for (int p = 0; p < pb->n_pat; ++p) {
+      const rpf_pattern P = pats[p];
+      const int nq = (int)pb->occ_of_pat[p].size();
+      const int64_t cols = (int64_t)nq * nr;
+      const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
+      DevBuf<double> X((size_t)P->n_b * cols), Ub((size_t)P->n_b * cols);
+      // u_b = S+ (g - A^T lambda) + Z alpha_s
+      gather_pattern(pb, p, pb->pat_nbn[p], S.lam.p, nr, nr, X.p, P->n_b, s);
+      hipLaunchKernelGGL(k_axpby, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, (int64_t)P->n_b * cols, 1.0,
+                         G[p].p, -1.0, X.p);
+      RPF_LAUNCH_CHECK();
+      dgemm(s, false, false, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, X.p, P->n_b, 0.0, Ub.p, P->n_b);
+      if (nG > 0 && P->k > 0) {
+        hipLaunchKernelGGL(k_add_kernel_term, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, P->n_b, P->k, nq,
+                           nr, occ, pb->d_goff.p, P->Z.p, aa.p, Ub.p);
+        RPF_LAUNCH_CHECK();
+      }
+      // u_i = K_ii^{-1} f_i - K_ii^{-1} K_ib u_b
+      DevBuf<double> Ti(std::max<int64_t>((int64_t)P->n_i * cols, 1));
+      if (P->n_i > 0) {
+        hipLaunchKernelGGL(k_spmm, dim3(nblocks((int64_t)P->n_i * cols)), dim3(256), 0, s, P->n_i, cols, P->kib_ptr.p,
+                           P->kib_col.p, P->kib_val.p, Ub.p, (int64_t)P->n_b, 1.0, Ti.p, (int64_t)P->n_i, 0.0);
+        RPF_LAUNCH_CHECK();
+        trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Ti.p, P->n_i, cols, false);
+        trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Ti.p, P->n_i, cols, true);
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks((int64_t)P->n_i * cols)), dim3(256), 0, s, (int64_t)P->n_i * cols, 1.0,
+                           Y2[p].p, -1.0, Ti.p);
+        RPF_LAUNCH_CHECK();
+      }
+      hipLaunchKernelGGL(k_merge_u, dim3(nblocks((int64_t)P->n * cols)), dim3(256), 0, s, P->n, P->n_i, P->n_b, nq, nr,
+                         occ, d_foff.p, P->d_idofs.p, P->d_bdofs.p, Ti.p, Ub.p, u_local);
+      RPF_LAUNCH_CHECK();
+      RPF_HIP(hipStreamSynchronize(s));
+    }
+    // lambda out
+    hipLaunchKernelGGL(k_axpby_rows, dim3(nblocks(N * nr)), dim3(256), 0, s, N, nr, 1.0, S.lam.p, (int64_t)nr, 0.0,
+                       lambda, ld_lambda);
+    RPF_LAUNCH_CHECK();
+    st.ms_recover = tr.stop();
+    st.converged = converged ? 1 : 0;
+    if (!converged)
+      throw Error(RPF_ENOCONV, "block_krylov_solve: not converged (relative residual " + std::to_string(rel) + ")");
+  });
+  if (stats) *stats = st;
+  return code;
+}

@@ -1,0 +1,70 @@
+// Structure handle: signed Boolean assembly maps, permutation maps and the
+// coarse space, plus the workspaces of the interface operator (internal).
+#pragma once
+
+#include "pattern.hpp"
+
+namespace rpf {
+constexpr int MAXP = 8;   // patterns per structure
+constexpr int KMAX = 8;   // kernel dimension per pattern (coarse kernels)
+
+struct YLoc {
+  double* base[MAXP];
+  int64_t ld[MAXP];
+};
+}  // namespace rpf
+
+struct rpf_problem_s {
+  int dpn = 1, n_pat = 0, n_occ = 0, n_mult = 0, n_perm = 1;
+  int64_t n_lambda = 0;
+  bool has_rot = false;
+  std::vector<int> pat_nbn;                  // boundary nodes per pattern
+  std::vector<int> occ_pat, occ_q, slot_off; // slot_off[s]: first boundary-node slot of s
+  std::vector<std::vector<int>> occ_of_pat;  // pattern -> occurrences (q order)
+  std::vector<int> pat_occ_off;              // offsets into d_occ_of_pat
+
+  rpf::DevBuf<int> d_occ_of_pat, d_slot_off, d_occ_pat;
+  rpf::DevBuf<int> d_l2m_ptr, d_l2m_code;    // per slot: multipliers (code = mult << 1 | negative)
+  rpf::DevBuf<int> d_ep_q, d_ep_bn, d_ep_occ;  // per multiplier endpoint
+  rpf::DevBuf<int8_t> d_ep_pat, d_ep_sign;
+  rpf::DevBuf<double> d_rot;
+  rpf::DevBuf<int> d_perm;
+  // multipliers grouped by the pair of occurrences they join (coarse matrix assembly)
+  std::vector<int> pair_a, pair_b, pair_ptr;
+  rpf::DevBuf<int> d_pair_a, d_pair_b, d_pair_ptr, d_pair_mult;
+
+  // W-format workspaces
+  rpf::DevBuf<double> xloc, yloc;
+  rpf::DevBuf<float> xloc32, yloc32;
+  rpf::DevBuf<uint16_t> xhi, xlo;
+
+  // coarse space (built for one set of pattern handles)
+  std::vector<const void*> coarse_key;
+  int n_G = 0;
+  std::vector<int> goff;
+  rpf::DevBuf<int> d_goff, d_kp, d_nbn;
+  rpf::DevBuf<const double*> d_Zp;
+  rpf::DevBuf<double> Ginv, cbuf, ybuf;
+};
+
+namespace rpf {
+// helpers shared by the operator and the solver
+void check_patterns(rpf_problem pb, const rpf_pattern* pats, int prec);
+// Y = F X (W-format products on all patterns), optional projection
+void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
+             int64_t ldy, int prec, bool project, hipStream_t s);
+// A^(s)T gather of an interface block into the W format of pattern p
+void gather_pattern(rpf_problem pb, int p, int nbn, const double* lam, int64_t ldl, int m, double* X,
+                    int64_t ldx, hipStream_t s);
+// Y = beta Y + sum_s A^(s) Y_loc
+void scatter_all(rpf_problem pb, const YLoc& yl, int m, double* Y, int64_t ldy, double beta, hipStream_t s);
+void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s);
+// c = G^T x (n_G x m row-major)
+void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, hipStream_t s);
+// x = beta x + alpha G y
+void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, int64_t ldx, double beta,
+              hipStream_t s);
+// x <- Q x = x - G (G^T G)^{-1} G^T x
+void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
+void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
+}  // namespace rpf

@@ -1,0 +1,55 @@
+"""Marshal a structure description (patterns, occurrences, multipliers) into library objects.
+
+The description is any object with the attributes of a repeated-pattern
+problem statement: ``patterns`` (each with ``K`` as a SciPy CSR matrix,
+``bdofs``, ``bnodes``, ``dpn``, ``n_nodes``, ``kernel_dim``), ``occ_pattern``,
+``occ_rot``, ``mult_occ``, ``mult_node``, ``mult_sign``, ``perm_node``,
+``f_local`` and ``n_rhs``.  Only argument marshalling happens here.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import FP64, Pattern, Problem, pattern_condense, pattern_factor, problem_create
+
+
+def factor_patterns(desc, check_kernel: bool = True, stream=None):
+    out = []
+    for pat in desc.patterns:
+        K = pat.K
+        val = torch.from_numpy(np.ascontiguousarray(K.data, dtype=np.float64)).cuda()
+        out.append(pattern_factor(K.indptr, K.indices, val, pat.bdofs, pat.dpn,
+                                  expected_kernel_dim=pat.kernel_dim if check_kernel else -1, stream=stream))
+    return out
+
+
+def condense_patterns(patterns, precs=(FP64,), stream=None):
+    for p in patterns:
+        for prec in precs:
+            pattern_condense(p, prec, stream=stream)
+
+
+def create_problem(desc) -> Problem:
+    rot = desc.occ_rot if desc.has_rotation else None
+    return problem_create(desc.dpn, [p.n_nodes for p in desc.patterns], [p.bnodes for p in desc.patterns],
+                          desc.occ_pattern, rot, desc.mult_occ, desc.mult_node, desc.mult_sign,
+                          desc.perm_node if desc.perm_node.shape[0] > 1 else None)
+
+
+def loads_to_device(desc) -> torch.Tensor:
+    """Concatenate per-occurrence loads (n_p x n_rhs, column-major) into one device vector."""
+    flat = np.concatenate([np.asarray(f, dtype=np.float64).T.ravel() for f in desc.f_local])
+    return torch.from_numpy(flat).cuda()
+
+
+def split_u(desc, u: torch.Tensor):
+    """Inverse of loads_to_device for the displacement output: list of (n_p, n_rhs) host arrays."""
+    h = u.cpu().numpy()
+    out, o = [], 0
+    for s, p in enumerate(desc.occ_pattern):
+        n = desc.patterns[p].n
+        blk = h[o:o + n * desc.n_rhs].reshape(desc.n_rhs, n).T
+        out.append(blk)
+        o += n * desc.n_rhs
+    return out
