@@ -15,9 +15,10 @@ namespace rpf {
 
 // ============================================================================ GEMM
 // Column-major C = alpha op(A) op(B) + beta C with v_mfma_f64_16x16x4_f64.
-// The MFMA is issued with the B fragment as its first operand, so every lane
-// ends up holding 4 values of one *column* of C in consecutive rows: lanes
-// 0..15 of a register store 16 consecutive doubles of a column (coalesced).
+// The MFMA is issued with the B fragment as its first operand, so the 16x16
+// accumulator holds a transposed C block: lane l, item r is C[l % 16][l / 16 + 4 r]
+// (the f64 accumulator layout strides its 4 items by 4 rows), and lanes 0..15
+// of one item store 16 consecutive doubles of a column of C (coalesced).
 // Operand tiles are staged through LDS (k-major); the next K tile is loaded
 // into registers while the current one is consumed.
 template <int BM, int BN, int WGM, int WGN, bool TA, bool TB>
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + wm * WTM + i * 16 + (lane & 15);
-        const int64_t n = n0 + wn * WTN + j * 16 + 4 * (lane >> 4) + r;
+        const int64_t n = n0 + wn * WTN + j * 16 + (lane >> 4) + 4 * r;
         if (m < M && n < N && (!lower || m >= n)) {
           const double v = alpha * acc[i][j][r];
           if (part) {
