@@ -195,6 +195,18 @@ rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* patterns, int32
                               const rpf_solve_opts* opts, double* lambda, int64_t ld_lambda, double* u_local,
                               rpf_solve_stats* stats, void* stream);
 
+/* ------------------------------------------------------------------ tracing */
+
+/* Kernel timing of the flexibility product (section 4.2: S+ W over all the
+ * occurrences of a pattern), the hot kernel of every iteration.  While enabled,
+ * every such product launched by feti_apply or block_krylov_solve is bracketed
+ * by HIP events on its own stream.  rpf_trace_read synchronises those events,
+ * returns the number of products, their summed duration in ms and their
+ * algorithmic flop count (2 n_b^2 columns each), then resets the counters.
+ * Process-wide; not meant for concurrent solves. */
+rpf_status rpf_trace_enable(int32_t on);
+rpf_status rpf_trace_read(int64_t* count, double* total_ms, double* flops);
+
 /* ------------------------------------------------------------------ dense helpers */
 
 /* C = alpha op(A) op(B) + beta C, FP64 MFMA, column-major (ta, tb: 0 or 1). */

@@ -209,3 +209,15 @@ def dsyev_small(A: torch.Tensor, stream=None):
     w = torch.empty((b, m), dtype=torch.float64, device="cuda")
     check(load().rpf_dsyev_small(m, b, _ptr(A), _ptr(V), _ptr(w), _stream(stream)))
     return w, V.transpose(1, 2)
+
+
+def trace_enable(on: bool = True) -> None:
+    """Bracket every flexibility product S+ W with HIP events (see rpf_trace_read)."""
+    check(load().rpf_trace_enable(1 if on else 0))
+
+
+def trace_read() -> dict:
+    """Products launched since the last read: count, summed kernel ms, algorithmic flops."""
+    n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
+    check(load().rpf_trace_read(C.byref(n), C.byref(ms), C.byref(fl)))
+    return {"count": n.value, "ms": ms.value, "flops": fl.value}

@@ -17,7 +17,7 @@ APPLY_PROJECT = 1
 # every symbol the header declares
 EXPORTS = ["rpf_last_error", "rpf_version", "pattern_factor", "pattern_condense", "pattern_info", "pattern_export",
            "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "feti_apply", "block_krylov_solve",
-           "rpf_dgemm", "rpf_dposv", "rpf_dsyev_small"]
+           "rpf_dgemm", "rpf_dposv", "rpf_dsyev_small", "rpf_trace_enable", "rpf_trace_read"]
 
 
 class ProblemDesc(C.Structure):
@@ -70,6 +70,8 @@ def load() -> C.CDLL:
         "rpf_dgemm": (i32, [i32, i32, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64, vp]),
         "rpf_dposv": (i32, [i64, vp, i64, i64, vp, i64, vp]),
         "rpf_dsyev_small": (i32, [i32, i32, vp, vp, vp, vp]),
+        "rpf_trace_enable": (i32, [i32]),
+        "rpf_trace_read": (i32, [C.POINTER(i64), C.POINTER(f64), C.POINTER(f64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <mutex>
 
 namespace rpf {
 
@@ -467,7 +468,9 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     double* xp = pb->xloc.p + off[p];
     double* yp = pb->yloc.p + off[p];
     gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, nb, s);
+    void* tok = trace_begin(s);
     dgemm(s, false, false, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, nb, 0.0, yp, nb);
+    trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
     yl.base[p] = yp;
     yl.ld[p] = nb;
   }
@@ -733,5 +736,83 @@ extern "C" rpf_status feti_apply(rpf_problem pb, const rpf_pattern* patterns, in
     RPF_CHECK(m >= 1 && ldx >= m && ldy >= m && X && Y, RPF_EINVAL, "feti_apply: bad block arguments");
     check_patterns(pb, patterns, prec);
     apply_F(pb, patterns, m, X, ldx, Y, ldy, prec, (flags & RPF_APPLY_PROJECT) != 0, (hipStream_t)stream);
+  });
+}
+
+// ---------------------------------------------------------------------------- tracing
+namespace rpf {
+namespace {
+struct TraceState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Rec { hipEvent_t a, b; double flops; };
+  std::vector<Rec> pending;
+};
+TraceState& tstate() {
+  static TraceState t;
+  return t;
+}
+hipEvent_t take_event(TraceState& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  RPF_HIP(hipEventCreate(&e));
+  return e;
+}
+}  // namespace
+
+bool trace_on() { return tstate().on; }
+
+void* trace_begin(hipStream_t s) {
+  TraceState& t = tstate();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (!t.on) return nullptr;
+  hipEvent_t a = take_event(t);
+  RPF_HIP(hipEventRecord(a, s));
+  return (void*)a;
+}
+
+void trace_end(void* tok, hipStream_t s, double flops) {
+  if (!tok) return;
+  TraceState& t = tstate();
+  std::lock_guard<std::mutex> g(t.mu);
+  hipEvent_t b = take_event(t);
+  RPF_HIP(hipEventRecord(b, s));
+  t.pending.push_back({(hipEvent_t)tok, b, flops});
+}
+}  // namespace rpf
+
+extern "C" rpf_status rpf_trace_enable(int32_t on) {
+  return guarded([&] {
+    TraceState& t = tstate();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.on = on != 0;
+  });
+}
+
+extern "C" rpf_status rpf_trace_read(int64_t* count, double* total_ms, double* flops) {
+  return guarded([&] {
+    TraceState& t = tstate();
+    std::lock_guard<std::mutex> g(t.mu);
+    int64_t n = 0;
+    double ms = 0.0, fl = 0.0;
+    for (auto& r : t.pending) {
+      RPF_HIP(hipEventSynchronize(r.b));
+      float e = 0.f;
+      RPF_HIP(hipEventElapsedTime(&e, r.a, r.b));
+      ms += e;
+      fl += r.flops;
+      ++n;
+      t.pool.push_back(r.a);
+      t.pool.push_back(r.b);
+    }
+    t.pending.clear();
+    if (count) *count = n;
+    if (total_ms) *total_ms = ms;
+    if (flops) *flops = fl;
   });
 }

@@ -67,4 +67,8 @@ void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, i
 // x <- Q x = x - G (G^T G)^{-1} G^T x
 void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
 void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
+// event tracing of the flexibility products
+bool trace_on();
+void* trace_begin(hipStream_t s);
+void trace_end(void* tok, hipStream_t s, double flops);
 }  // namespace rpf
