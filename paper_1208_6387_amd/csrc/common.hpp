@@ -113,6 +113,11 @@ void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t
                   const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                   int64_t ldc, double* ws, int splits);
 
+// Row-block product for tall interface blocks: Y (N x b, row-major ldy) = beta Y
+// + alpha X (N x a, row-major ldx) M (a x b, column-major, ld a).
+void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* M,
+               double beta, double* Y, int64_t ldy);
+
 // Envelope description of a lower factor: for column block t (NB columns),
 // rows [t*NB+jb, rend[t]) below the diagonal block may be nonzero, and the
 // rows of block t have nonzeros only from column cstart[t] on.

@@ -122,15 +122,26 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
       }
 }
 
-__global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double* part, double beta,
-                                double* C, int64_t ldc) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= M * N) return;
-  const int64_t m = idx % M, n = idx / M;
-  double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += part[((int64_t)z * N + n) * M + m];
-  double* c = C + n * ldc + m;
-  *c = (beta == 0.0) ? s : s + beta * *c;
+// Sum of the split-K partials: one wavefront per 8 outputs, lanes stride over
+// the splits (fixed order, so the result is deterministic).
+__global__ __launch_bounds__(256) void k_splitk_reduce(int64_t M, int64_t N, int splits, const double* part,
+                                                       double beta, double* C, int64_t ldc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 8;
+  const int64_t MN = M * N;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int64_t idx = base + o;
+    if (idx >= MN) break;
+    double s = 0.0;
+    for (int z = lane; z < splits; z += 64) s += part[(int64_t)z * MN + idx];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) {
+      const int64_t m = idx % M, n = idx / M;
+      double* c = C + n * ldc + m;
+      *c = (beta == 0.0) ? s : s + beta * *c;
+    }
+  }
 }
 
 namespace {
@@ -140,6 +151,8 @@ Cfg pick_cfg(int64_t M, int64_t N) {
   if (M <= 16) return M16;
   if (N <= 16) return N16;
   if (M <= 64 && N <= 64) return SMALL;
+  // 256 CUs: fall back to 64x64 tiles when 128x128 tiles cannot give two per CU
+  if (cdiv(M, 128) * cdiv(N, 128) < 512) return SMALL;
   return BIG;
 }
 
@@ -225,8 +238,58 @@ void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t
   const int64_t kchunk = cdiv(cdiv(K, splits), 16) * 16;
   const int gz = (int)cdiv(K, kchunk);
   launch_gemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, 0.0, nullptr, 0, false, splits, ws);
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s, M, N, gz, ws, beta, C,
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 32)), dim3(256), 0, s, M, N, gz, ws, beta, C,
                      ldc);
+  RPF_LAUNCH_CHECK();
+}
+
+// ============================================================================ row-block products
+// Y[l*ldy + j] = beta Y + alpha sum_i X[l*ldx + i] M[i + a*j] for N rows, a small
+// a x b matrix M (column-major) staged through LDS in slices of 64 rows.  One
+// thread per row, up to 16 outputs in registers per pass.  Used for the block
+// updates of the interface solver (rows = interface dofs, row-major blocks).
+__global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, double alpha, const double* X,
+                                                   int64_t ldx, const double* Mm, double beta, double* Y,
+                                                   int64_t ldy) {
+  __shared__ double sm[64][17];
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = l < N;
+  for (int j0 = 0; j0 < b; j0 += 16) {
+    const int jn = min(16, b - j0);
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (int i0 = 0; i0 < a; i0 += 64) {
+      const int in = min(64, a - i0);
+      __syncthreads();
+      for (int t = threadIdx.x; t < 64 * 16; t += blockDim.x) {
+        const int i = t % 64, j = t / 64;
+        sm[i][j] = (i < in && j < jn) ? Mm[(int64_t)(i0 + i) + (int64_t)a * (j0 + j)] : 0.0;
+      }
+      __syncthreads();
+      if (live) {
+        const double* xr = X + l * ldx + i0;
+        for (int i = 0; i < in; ++i) {
+          const double xv = xr[i];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[j] += xv * sm[i][j];
+        }
+      }
+    }
+    if (live) {
+      double* yr = Y + l * ldy + j0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j < jn) yr[j] = (beta == 0.0) ? alpha * acc[j] : beta * yr[j] + alpha * acc[j];
+    }
+  }
+}
+
+void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* Mm,
+               double beta, double* Y, int64_t ldy) {
+  if (N <= 0 || b <= 0) return;
+  hipLaunchKernelGGL(k_rows_gemm, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, beta, Y,
+                     ldy);
   RPF_LAUNCH_CHECK();
 }
 
@@ -258,8 +321,8 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int 
       s[j][j] = sqrt(d);
     }
     __syncthreads();
-    const double djj = s[j][j];
-    for (int r = j + 1 + tid; r < jb; r += 256) s[r][j] /= djj;
+    const double rdjj = 1.0 / s[j][j];
+    for (int r = j + 1 + tid; r < jb; r += 256) s[r][j] *= rdjj;
     __syncthreads();
     const int w = jb - j - 1;
     for (int idx = tid; idx < w * w; idx += 256) {
@@ -268,19 +331,22 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int 
     }
     __syncthreads();
   }
-  if (tid < NB) {
-    const int c = tid;
+  // inverse of the factor, row by row: inv[r][c] = (delta_rc - sum_{c<=k<r} L[r][k] inv[k][c]) / L[r][r];
+  // the 256 threads are 64 columns x 4 interleaved slices of the k sum
+  {
+    __shared__ double part[4][NB];
+    const int c = tid & (NB - 1), q = tid >> 6;
     for (int r = 0; r < NB; ++r) {
-      if (r < c) {
-        inv[r][c] = 0.0;
-      } else {
-        double sum = (r == c) ? 1.0 : 0.0;
-        for (int k = c; k < r; ++k) sum -= s[r][k] * inv[k][c];
-        inv[r][c] = sum / s[r][r];
-      }
+      double sum = 0.0;
+      if (r > c)
+        for (int k = c + q; k < r; k += 4) sum += s[r][k] * inv[k][c];
+      part[q][c] = sum;
+      __syncthreads();
+      if (q == 0)
+        inv[r][c] = (r < c) ? 0.0 : (((r == c) ? 1.0 : 0.0) - (part[0][c] + part[1][c] + part[2][c] + part[3][c])) / s[r][r];
+      __syncthreads();
     }
   }
-  __syncthreads();
   for (int idx = tid; idx < NB * NB; idx += 256) {
     const int r = idx % NB, c = idx / NB;
     if (r < jb && c < jb && r >= c) A[(int64_t)c * lda + r] = s[r][c];
@@ -433,7 +499,7 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
   __shared__ double v[EIG_MAX][EIG_MAX + 1];
   __shared__ int pp[EIG_MAX / 2], qq[EIG_MAX / 2];
   __shared__ double cc[EIG_MAX / 2], ss[EIG_MAX / 2];
-  __shared__ double red[2];
+
   __shared__ int order[EIG_MAX];
   const int tid = threadIdx.x;
   const double* A = Ain + (int64_t)blockIdx.x * m * m;
@@ -446,20 +512,12 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
   }
   const int me = m + (m & 1);  // even count for the round-robin schedule
   const int npair = me / 2;
+  __shared__ int nrot;
   __syncthreads();
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    if (tid == 0) {
-      double off = 0.0, dia = 0.0;
-      for (int c = 0; c < m; ++c)
-        for (int r = 0; r < m; ++r) {
-          const double x = a[r][c] * a[r][c];
-          if (r == c) dia += x; else off += x;
-        }
-      red[0] = off;
-      red[1] = dia;
-    }
-    __syncthreads();
-    if (!(red[0] > 1e-30 * red[1]) || m < 2) break;
+  // threshold Jacobi: a pair is rotated only while |a_pq| > 1e-15 sqrt(|a_pp a_qq|)
+  // (high relative accuracy); the sweeps stop once a whole sweep rotates nothing
+  for (int sweep = 0; sweep < 30 && m >= 2; ++sweep) {
+    if (tid == 0) nrot = 0;
     __syncthreads();
     for (int step = 0; step < me - 1; ++step) {
       // circle method: indices 0..me-2 rotate, me-1 is fixed
@@ -476,7 +534,8 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
         double c = 1.0, sn = 0.0;
         if (q < m) {
           const double apq = a[p][q];
-          if (apq != 0.0) {
+          if (fabs(apq) > 1e-15 * sqrt(fabs(a[p][p] * a[q][q])) && fabs(apq) > 1e-300) {
+            atomicAdd(&nrot, 1);
             const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
             const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -515,6 +574,8 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
       }
       __syncthreads();
     }
+    if (nrot == 0) break;  // uniform: read after the last barrier of the sweep
+    __syncthreads();
   }
   __syncthreads();
   if (tid == 0) {

@@ -124,18 +124,19 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// c[(goff[s] + r)*m + j] = (Z^T A^(s)T x)[r][j], one workgroup (256 threads) per occurrence
+// Partial sums of (Z^T A^(s)T x)[r][j]: workgroup (s, sp) covers the boundary
+// nodes [256 sp, 256 sp + 256) of occurrence s; part[((s*nsplit + sp)*KMAX + r)*m + j].
 template <int DPN>
 __global__ __launch_bounds__(256) void k_coarse_gt(const int* occ_pat, const int* slot_off, const int* nbn_p,
                                                    const double* const* Zp, const int* kp, const int* goff,
                                                    const int* l2m_ptr, const int* l2m_code, const double* rot,
-                                                   const double* x, int64_t ldx, int m, double* c) {
+                                                   const double* x, int64_t ldx, int m, int nsplit, double* part) {
   __shared__ double red[4][KMAX * JB];
-  const int s = blockIdx.x;
+  const int s = blockIdx.x, sp = blockIdx.y;
   const int p = occ_pat[s];
-  const int k = kp[p], nbn = nbn_p[p];
+  const int k = kp[p], nbn = min(nbn_p[p], 256 * (sp + 1));
   const double* Z = Zp[p];
-  const int64_t ldz = (int64_t)nbn * DPN;
+  const int64_t ldz = (int64_t)nbn_p[p] * DPN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double O[9];
   if (DPN == 3) load_rot<DPN>(rot, s, O);
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(256) void k_coarse_gt(const int* occ_pat, const int
     for (int r = 0; r < KMAX; ++r)
 #pragma unroll
       for (int j = 0; j < JB; ++j) acc[r][j] = 0.0;
-    for (int bn = tid; bn < nbn; bn += 256) {
+    for (int bn = 256 * sp + tid; bn < nbn; bn += 256) {
       const int slot = slot_off[s] + bn;
       double g[DPN][JB];
 #pragma unroll
@@ -199,74 +200,73 @@ __global__ __launch_bounds__(256) void k_coarse_gt(const int* occ_pat, const int
     if (tid < KMAX * JB) {
       const int r = tid / JB, j = tid % JB;
       if (r < k && j < jn)
-        c[((int64_t)goff[s] + r) * m + j0 + j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+        part[(((int64_t)s * nsplit + sp) * KMAX + r) * m + j0 + j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
     }
     __syncthreads();
   }
 }
 
+// c[(goff[s] + r)*m + j] = sum over the node slices of the partial sums (fixed order)
+__global__ void k_coarse_gt_reduce(int n_occ, int nsplit, const int* occ_pat, const int* kp, const int* goff, int m,
+                                   const double* part, double* c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_occ * KMAX * m) return;
+  const int j = (int)(i % m);
+  const int r = (int)((i / m) % KMAX);
+  const int s = (int)(i / ((int64_t)m * KMAX));
+  if (r >= kp[occ_pat[s]]) return;
+  double v = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) v += part[(((int64_t)s * nsplit + sp) * KMAX + r) * m + j];
+  c[((int64_t)goff[s] + r) * m + j] = v;
+}
+
 // x = beta x + alpha G y: per multiplier, sum over endpoints of sign * O Z y_s
 template <int DPN>
-__global__ __launch_bounds__(128) void k_coarse_g(int n_mult, const int* ep_occ, const int* ep_bn,
+__global__ __launch_bounds__(256) void k_coarse_g(int n_mult, const int* ep_occ, const int* ep_bn,
                                                   const int8_t* ep_sign, const int* occ_pat, const int* nbn_p,
                                                   const double* const* Zp, const int* kp, const int* goff,
                                                   const double* rot, const double* y, int m, double alpha,
                                                   double* x, int64_t ldx, double beta) {
-  const int mult = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mult >= n_mult) return;
-  for (int j0 = 0; j0 < m; j0 += JB) {
-    const int jn = min(JB, m - j0);
-    double acc[DPN][JB];
+  // one thread per (multiplier, column): consecutive threads share the multiplier's Z rows
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_mult * m) return;
+  const int mult = (int)(idx / m), j = (int)(idx % m);
+  double acc[DPN];
 #pragma unroll
-    for (int c = 0; c < DPN; ++c)
+  for (int c = 0; c < DPN; ++c) acc[c] = 0.0;
 #pragma unroll
-      for (int j = 0; j < JB; ++j) acc[c][j] = 0.0;
+  for (int e = 0; e < 2; ++e) {
+    const int s = ep_occ[2 * mult + e];
+    if (s < 0) continue;
+    const int p = occ_pat[s];
+    const int k = kp[p];
+    const double sg = (double)ep_sign[2 * mult + e];
+    const double* Z = Zp[p] + (int64_t)ep_bn[2 * mult + e] * DPN;
+    const int64_t ldz = (int64_t)nbn_p[p] * DPN;
+    const double* ys = y + (int64_t)goff[s] * m + j;
+    double v[DPN];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int s = ep_occ[2 * mult + e];
-      if (s < 0) continue;
-      const int p = occ_pat[s];
-      const int k = kp[p];
-      const double sg = (double)ep_sign[2 * mult + e];
-      const double* Z = Zp[p];
-      const int64_t ldz = (int64_t)nbn_p[p] * DPN;
-      const int64_t bn = ep_bn[2 * mult + e];
-      const double* ys = y + (int64_t)goff[s] * m + j0;
-      double v[DPN][JB];
+    for (int c = 0; c < DPN; ++c) v[c] = 0.0;
+    for (int r = 0; r < k; ++r) {
+      const double yr = ys[(int64_t)r * m];
 #pragma unroll
-      for (int c = 0; c < DPN; ++c)
-#pragma unroll
-        for (int j = 0; j < JB; ++j) v[c][j] = 0.0;
-      for (int r = 0; r < k; ++r) {
-#pragma unroll
-        for (int c = 0; c < DPN; ++c) {
-          const double z = Z[r * ldz + bn * DPN + c];
-#pragma unroll
-          for (int j = 0; j < JB; ++j)
-            if (j < jn) v[c][j] += z * ys[r * m + j];
-        }
-      }
+      for (int c = 0; c < DPN; ++c) v[c] += Z[r * ldz + c] * yr;
+    }
+    if (DPN == 3) {
       double O[9];
-      if (DPN == 3) load_rot<DPN>(rot, s, O);
+      load_rot<DPN>(rot, s, O);
 #pragma unroll
-      for (int j = 0; j < JB; ++j) {
-        if (DPN == 3) {
+      for (int c = 0; c < 3; ++c)
+        acc[c % DPN] += sg * (O[3 * c] * v[0] + O[3 * c + 1] * v[1 % DPN] + O[3 * c + 2] * v[2 % DPN]);
+    } else {
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            acc[c][j] += sg * (O[3 * c] * v[0][j] + O[3 * c + 1] * v[1 % DPN][j] + O[3 * c + 2] * v[2 % DPN][j]);
-        } else {
-#pragma unroll
-          for (int c = 0; c < DPN; ++c) acc[c][j] += sg * v[c][j];
-        }
-      }
+      for (int c = 0; c < DPN; ++c) acc[c] += sg * v[c];
     }
+  }
 #pragma unroll
-    for (int c = 0; c < DPN; ++c) {
-      double* row = x + ((int64_t)mult * DPN + c) * ldx + j0;
-#pragma unroll
-      for (int j = 0; j < JB; ++j)
-        if (j < jn) row[j] = (beta == 0.0) ? alpha * acc[c][j] : beta * row[j] + alpha * acc[c][j];
-    }
+  for (int c = 0; c < DPN; ++c) {
+    double* xv = x + ((int64_t)mult * DPN + c) * ldx + j;
+    *xv = (beta == 0.0) ? alpha * acc[c] : beta * *xv + alpha * acc[c];
   }
 }
 
@@ -454,7 +454,14 @@ void scatter_all(rpf_problem pb, const YLoc& yl, int m, double* Y, int64_t ldy, 
 
 void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y, int64_t ldy,
              int prec, bool project, hipStream_t s) {
-  RPF_CHECK(prec == RPF_FP64, RPF_EINVAL, "feti_apply: only the FP64 product is available");
+  if (prec != RPF_FP64) {
+    apply_F_lowprec(pb, pats, m, X, ldx, Y, ldy, prec, s);
+    if (project) {
+      ensure_coarse(pb, pats, s);
+      project_block(pb, Y, ldy, m, s);
+    }
+    return;
+  }
   // W-format workspace: one slab per pattern
   std::vector<int64_t> off(pb->n_pat + 1, 0);
   for (int p = 0; p < pb->n_pat; ++p)
@@ -482,7 +489,8 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
 }
 
 void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
-  std::vector<const void*> key(pats, pats + pb->n_pat);
+  std::vector<uint64_t> key(pb->n_pat);
+  for (int p = 0; p < pb->n_pat; ++p) key[p] = pats[p]->uid;
   if (!pb->coarse_key.empty() && key == pb->coarse_key) return;
   pb->goff.assign(pb->n_occ + 1, 0);
   for (int o = 0; o < pb->n_occ; ++o) pb->goff[o + 1] = pb->goff[o] + pats[pb->occ_pat[o]]->k;
@@ -539,10 +547,13 @@ void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
 }
 
 void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, hipStream_t s) {
-#define RPF_CGT(D)                                                                                          \
-  hipLaunchKernelGGL(k_coarse_gt<D>, dim3(pb->n_occ), dim3(256), 0, s, pb->d_occ_pat.p, pb->d_slot_off.p,    \
-                     pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p, pb->d_l2m_ptr.p, pb->d_l2m_code.p,   \
-                     pb->has_rot ? pb->d_rot.p : nullptr, x, ldx, m, c)
+  const int max_nbn = *std::max_element(pb->pat_nbn.begin(), pb->pat_nbn.end());
+  const int nsplit = (int)std::max<int64_t>(1, cdiv(max_nbn, 256));
+  pb->cpart.ensure((size_t)pb->n_occ * nsplit * KMAX * m);
+#define RPF_CGT(D)                                                                                             \
+  hipLaunchKernelGGL(k_coarse_gt<D>, dim3(pb->n_occ, nsplit), dim3(256), 0, s, pb->d_occ_pat.p, pb->d_slot_off.p, \
+                     pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p, pb->d_l2m_ptr.p, pb->d_l2m_code.p,      \
+                     pb->has_rot ? pb->d_rot.p : nullptr, x, ldx, m, nsplit, pb->cpart.p)
   switch (pb->dpn) {
     case 1: RPF_CGT(1); break;
     case 2: RPF_CGT(2); break;
@@ -550,14 +561,18 @@ void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, h
   }
 #undef RPF_CGT
   RPF_LAUNCH_CHECK();
+  const int64_t tot = (int64_t)pb->n_occ * KMAX * m;
+  hipLaunchKernelGGL(k_coarse_gt_reduce, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, pb->n_occ, nsplit,
+                     pb->d_occ_pat.p, pb->d_kp.p, pb->d_goff.p, m, pb->cpart.p, c);
+  RPF_LAUNCH_CHECK();
 }
 
 void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, int64_t ldx, double beta,
               hipStream_t s) {
   if (pb->n_mult == 0) return;
-  dim3 grid((unsigned)cdiv(pb->n_mult, 128));
+  dim3 grid((unsigned)cdiv((int64_t)pb->n_mult * m, 256));
 #define RPF_CG(D)                                                                                          \
-  hipLaunchKernelGGL(k_coarse_g<D>, grid, dim3(128), 0, s, pb->n_mult, pb->d_ep_occ.p, pb->d_ep_bn.p,       \
+  hipLaunchKernelGGL(k_coarse_g<D>, grid, dim3(256), 0, s, pb->n_mult, pb->d_ep_occ.p, pb->d_ep_bn.p,       \
                      pb->d_ep_sign.p, pb->d_occ_pat.p, pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p,    \
                      pb->has_rot ? pb->d_rot.p : nullptr, y, m, alpha, x, ldx, beta)
   switch (pb->dpn) {

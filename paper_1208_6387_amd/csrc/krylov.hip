@@ -279,7 +279,7 @@ struct Solver {
         const double* Wp = Wall.p + (int64_t)first * m;
         gram(Pp, ldW, nb * m, Zb.p, m, m, Bt.p);
         if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * m)), dim3(256), 0, s, Bt.p, nb * m, m, (int64_t)nb * m);
-        dgemm(s, true, false, m, N, (int64_t)nb * m, -1.0, Bt.p, (int64_t)nb * m, Wp, ldW, 1.0, Zb.p, m);
+        rows_gemm(s, N, nb * m, m, -1.0, Wp, ldW, Bt.p, 1.0, Zb.p, m);
       }
       // P = Q^T F Zb
       apply_F(pb, pats, m, Zb.p, m, Pb.p, m, prec, true, s);
@@ -291,13 +291,13 @@ struct Solver {
       // W_j = Zb T, P_j = P T into the store
       double* Wj = Wall.p + (int64_t)slot * m;
       double* Pj = Pall.p + (int64_t)slot * m;
-      dgemm(s, true, false, m, N, m, 1.0, T.p, m, Zb.p, m, 0.0, Wj, ldW);
-      dgemm(s, true, false, m, N, m, 1.0, T.p, m, Pb.p, m, 0.0, Pj, ldW);
+      rows_gemm(s, N, m, m, 1.0, Zb.p, m, T.p, 0.0, Wj, ldW);
+      rows_gemm(s, N, m, m, 1.0, Pb.p, m, T.p, 0.0, Pj, ldW);
       // alpha = W_j^T R ; lambda += W_j alpha ; R -= P_j alpha
       gram(Wj, ldW, m, Rs.p, nr, nr, alpha.p);
       if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * nr)), dim3(256), 0, s, alpha.p, m, nr, (int64_t)m);
-      dgemm(s, true, false, nr, N, m, 1.0, alpha.p, m, Wj, ldW, 1.0, dlam.p, nr);
-      dgemm(s, true, false, nr, N, m, -1.0, alpha.p, m, Pj, ldW, 1.0, Rs.p, nr);
+      rows_gemm(s, N, m, nr, 1.0, Wj, ldW, alpha.p, 1.0, dlam.p, nr);
+      rows_gemm(s, N, m, nr, -1.0, Pj, ldW, alpha.p, 1.0, Rs.p, nr);
       ++nst;
       ++iterations;
       if ((it + 1) % check_every == 0 || it + 1 == max_it) {

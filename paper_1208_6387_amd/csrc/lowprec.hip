@@ -1,0 +1,408 @@
+// Low-precision flexibility products for the mixed forms: Y_loc = S+ X_loc with
+// FP32 operands (v_mfma_f32_16x16x4_f32) or with bf16 high/low splits of both
+// operands (v_mfma_f32_16x16x32_bf16, three cross products hi*hi + hi*lo + lo*hi),
+// FP32 accumulation in both cases.  The gather writes the W format directly in
+// the low-precision layout and the scatter reads FP32 and assembles in FP64.
+#include "problem.hpp"
+
+namespace rpf {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_val(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ---------------------------------------------------------------------------- gather (low precision out)
+// mode 0: FP32 out (Xf); mode 1: bf16 split out (Xh, Xl)
+template <int DPN, int MODE>
+__global__ __launch_bounds__(128) void k_gather_lp(int nbn, const int* occ_list, const int* slot_off,
+                                                   const int* l2m_ptr, const int* l2m_code, const double* rot,
+                                                   const double* lam, int64_t ldl, int m, float* Xf, uint16_t* Xh,
+                                                   uint16_t* Xl, int64_t ldx) {
+  const int bn = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (bn >= nbn) return;
+  const int s = occ_list[q];
+  const int slot = slot_off[s] + bn;
+  const int e0 = l2m_ptr[slot], e1 = l2m_ptr[slot + 1];
+  double O[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) O[i] = rot ? rot[9 * s + i] : ((i % 4 == 0) ? 1.0 : 0.0);
+  for (int j0 = 0; j0 < m; j0 += 8) {
+    const int jn = min(8, m - j0);
+    double acc[DPN][8];
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[c][j] = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int code = l2m_code[e];
+      const double sg = (code & 1) ? -1.0 : 1.0;
+      const int64_t mult = code >> 1;
+#pragma unroll
+      for (int c = 0; c < DPN; ++c) {
+        const double* row = lam + (mult * DPN + c) * ldl + j0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < jn) acc[c][j] += sg * row[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j >= jn) break;
+      const int64_t base = ((int64_t)q * m + j0 + j) * ldx + (int64_t)bn * DPN;
+#pragma unroll
+      for (int c2 = 0; c2 < DPN; ++c2) {
+        double v;
+        if (DPN == 3) v = O[c2] * acc[0][j] + O[3 + c2] * acc[1 % DPN][j] + O[6 + c2] * acc[2 % DPN][j];
+        else v = acc[c2][j];
+        if (MODE == 0) {
+          Xf[base + c2] = (float)v;
+        } else {
+          const uint16_t h = bf16_bits((float)v);
+          Xh[base + c2] = h;
+          Xl[base + c2] = bf16_bits((float)(v - (double)bf16_val(h)));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- FP32 MFMA GEMM
+// C (M x N, FP32, col-major ldc) = A (M x K, symmetric S+ read as k-contiguous rows, lda) * B (K x N, col-major)
+// Tile 64x64, 4 waves of 32x32, BK = 16.  Like the FP64 kernel the B fragment is
+// the first MFMA operand so that lanes 0..15 of an accumulator item hold 16 rows
+// of one column of C.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_sgemm_sym(int M, int N, int K, const float* A, int64_t lda, const float* B,
+                                                   int64_t ldb, float* C, int64_t ldc) {
+  constexpr int BK = 16, PAD = 4;
+  constexpr int WTM = BM / 2, WTN = BN / 2, TM = WTM / 16, TN = WTN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  __shared__ float sA[BK][BM + PAD];
+  __shared__ float sB[BK][BN + PAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % 2, wn = wave / 2;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float ra[EA], rb[EB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % BK, mm = idx / BK;  // A symmetric: row m is k-contiguous
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[e] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % BK, nn = idx / BK;
+      const int gn = n0 + nn, gk = k0 + kk;
+      rb[e] = (gn < N && gk < K) ? B[(int64_t)gn * ldb + gk] : 0.f;
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      sA[idx % BK][idx / BK] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      sB[idx % BK][idx / BK] = rb[e];
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      float af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = sA[kk + (lane >> 4)][wm * WTM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = sB[kk + (lane >> 4)][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[j], af[i], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * WTM + i * 16 + (lane & 15);
+        const int n = n0 + wn * WTN + j * 16 + 4 * (lane >> 4) + r;
+        if (m < M && n < N) C[(int64_t)n * ldc + m] = acc[i][j][r];
+      }
+}
+
+// ---------------------------------------------------------------------------- bf16x3 MFMA GEMM
+// Same product with both operands split into bf16 hi + lo; 16x16x32 MFMA, BK = 32.
+// LDS holds rows of 32 k-values (64 bytes, padded) so a lane reads its 8
+// consecutive k of one row as one 16-byte access.
+template <int BM, int BN, bool X3>
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* Ah, const uint16_t* Al,
+                                                   int64_t lda, const uint16_t* Bh, const uint16_t* Bl, int64_t ldb,
+                                                   float* C, int64_t ldc) {
+  constexpr int BK = 32, RS = BK + 8;  // row stride in bf16 elements (80 bytes)
+  constexpr int WTM = BM / 2, WTN = BN / 2, TM = WTM / 16, TN = WTN / 16;
+  constexpr int NA = BM * BK / 8 / 256, NB = BN * BK / 8 / 256;  // 16-byte chunks per thread
+  static_assert(NA >= 1 && NB >= 1, "tile too small");
+  __shared__ __attribute__((aligned(16))) uint16_t sAh[BM * RS];
+  __shared__ __attribute__((aligned(16))) uint16_t sAl[BM * RS];
+  __shared__ __attribute__((aligned(16))) uint16_t sBh[BN * RS];
+  __shared__ __attribute__((aligned(16))) uint16_t sBl[BN * RS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % 2, wn = wave / 2;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
+  // a 16-byte chunk = 8 consecutive k of one row; chunk c of the tile: row c / 4, k offset 8 (c % 4)
+  auto load_chunk = [&](const uint16_t* P, int64_t ld, int row, int nrow, int k, int krem, uint4& out) {
+    if (row < nrow && krem >= 8) {
+      out = *reinterpret_cast<const uint4*>(P + (int64_t)row * ld + k);
+    } else {
+      uint16_t t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = (row < nrow && u < krem) ? P[(int64_t)row * ld + k + u] : (uint16_t)0;
+      out = *reinterpret_cast<uint4*>(t);
+    }
+  };
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int c = tid + e * 256, row = c / 4, kk = 8 * (c % 4);
+      load_chunk(Ah, lda, m0 + row, M, k0 + kk, K - (k0 + kk), rah[e]);
+      if (X3) load_chunk(Al, lda, m0 + row, M, k0 + kk, K - (k0 + kk), ral[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int c = tid + e * 256, row = c / 4, kk = 8 * (c % 4);
+      load_chunk(Bh, ldb, n0 + row, N, k0 + kk, K - (k0 + kk), rbh[e]);
+      if (X3) load_chunk(Bl, ldb, n0 + row, N, k0 + kk, K - (k0 + kk), rbl[e]);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int c = tid + e * 256, row = c / 4, kk = 8 * (c % 4);
+      *reinterpret_cast<uint4*>(&sAh[row * RS + kk]) = rah[e];
+      if (X3) *reinterpret_cast<uint4*>(&sAl[row * RS + kk]) = ral[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int c = tid + e * 256, row = c / 4, kk = 8 * (c % 4);
+      *reinterpret_cast<uint4*>(&sBh[row * RS + kk]) = rbh[e];
+      if (X3) *reinterpret_cast<uint4*>(&sBl[row * RS + kk]) = rbl[e];
+    }
+  };
+  // the 16-byte alignment of the vector loads needs lda, ldb, K multiples of 8: guaranteed by the host
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (k0 + BK < K) gload(k0 + BK);
+    const int ko = 8 * (lane >> 4);
+    bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int row = wm * WTM + i * 16 + (lane & 15);
+      ah[i] = *reinterpret_cast<const bf16x8*>(&sAh[row * RS + ko]);
+      if (X3) al[i] = *reinterpret_cast<const bf16x8*>(&sAl[row * RS + ko]);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int row = wn * WTN + j * 16 + (lane & 15);
+      bh[j] = *reinterpret_cast<const bf16x8*>(&sBh[row * RS + ko]);
+      if (X3) bl[j] = *reinterpret_cast<const bf16x8*>(&sBl[row * RS + ko]);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah[i], acc[i][j], 0, 0, 0);
+        if (X3) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah[i], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al[i], acc[i][j], 0, 0, 0);
+        }
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * WTM + i * 16 + (lane & 15);
+        const int n = n0 + wn * WTN + j * 16 + 4 * (lane >> 4) + r;
+        if (m < M && n < N) C[(int64_t)n * ldc + m] = acc[i][j][r];
+      }
+}
+
+// ---------------------------------------------------------------------------- scatter from FP32
+struct YLoc32 {
+  const float* base[MAXP];
+  int64_t ld[MAXP];
+};
+
+template <int DPN>
+__global__ __launch_bounds__(128) void k_scatter_f32(int n_mult, const int* ep_q, const int* ep_bn,
+                                                     const int8_t* ep_pat, const int8_t* ep_sign, const int* ep_occ,
+                                                     const double* rot, YLoc32 yl, int m, double* Y, int64_t ldy) {
+  const int mult = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mult >= n_mult) return;
+  for (int j0 = 0; j0 < m; j0 += 8) {
+    const int jn = min(8, m - j0);
+    double acc[DPN][8];
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[c][j] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int q = ep_q[2 * mult + e];
+      if (q < 0) continue;
+      const int p = ep_pat[2 * mult + e];
+      const double sg = (double)ep_sign[2 * mult + e];
+      const int64_t ld = yl.ld[p];
+      const float* base = yl.base[p] + ((int64_t)q * m + j0) * ld + (int64_t)ep_bn[2 * mult + e] * DPN;
+      double O[9];
+      const int s = ep_occ[2 * mult + e];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) O[i] = rot ? rot[9 * s + i] : ((i % 4 == 0) ? 1.0 : 0.0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j >= jn) break;
+        double v[DPN];
+#pragma unroll
+        for (int c = 0; c < DPN; ++c) v[c] = (double)base[j * ld + c];
+        if (DPN == 3) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            acc[c % DPN][j] += sg * (O[3 * c] * v[0] + O[3 * c + 1] * v[1 % DPN] + O[3 * c + 2] * v[2 % DPN]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) acc[c][j] += sg * v[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < DPN; ++c) {
+      double* row = Y + ((int64_t)mult * DPN + c) * ldy + j0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < jn) row[j] = acc[c][j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- host
+void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
+                     int64_t ldy, int prec, hipStream_t s) {
+  const bool split = (prec == RPF_BF16X3 || prec == RPF_BF16);
+  // W format with ld rounded up to a multiple of 8 (16-byte rows for the bf16 loads)
+  std::vector<int64_t> off(pb->n_pat + 1, 0), ld(pb->n_pat);
+  for (int p = 0; p < pb->n_pat; ++p) {
+    ld[p] = cdiv(pats[p]->n_b, 8) * 8;
+    off[p + 1] = off[p] + ld[p] * (int64_t)pb->occ_of_pat[p].size() * m;
+  }
+  const int64_t tot = std::max<int64_t>(off[pb->n_pat], 8);
+  pb->yloc32.ensure(tot);
+  if (split) {
+    pb->xhi.ensure(tot);
+    pb->xlo.ensure(tot);
+  } else {
+    pb->xloc32.ensure(tot);
+  }
+  YLoc32 yl{};
+  for (int p = 0; p < pb->n_pat; ++p) {
+    const rpf_pattern P = pats[p];
+    const int nb = P->n_b, nq = (int)pb->occ_of_pat[p].size(), nbn = pb->pat_nbn[p];
+    const int cols = nq * m;
+    const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
+    const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
+    float* yp = pb->yloc32.p + off[p];
+    yl.base[p] = yp;
+    yl.ld[p] = ld[p];
+    if (nq == 0) continue;
+    dim3 grid((unsigned)cdiv(nbn, 128), (unsigned)nq);
+#define RPF_GLP(D, MODE)                                                                                        \
+  hipLaunchKernelGGL((k_gather_lp<D, MODE>), grid, dim3(128), 0, s, nbn, occ, pb->d_slot_off.p, pb->d_l2m_ptr.p, \
+                     pb->d_l2m_code.p, rot, X, ldx, m, pb->xloc32.p + off[p], pb->xhi.p + off[p],                 \
+                     pb->xlo.p + off[p], ld[p])
+    if (split) {
+      // the padded rows between n_b and ld must hold zeros for the 16-byte loads
+      if (ld[p] != nb) RPF_HIP(hipMemsetAsync(pb->xhi.p + off[p], 0, sizeof(uint16_t) * ld[p] * cols, s));
+      if (ld[p] != nb) RPF_HIP(hipMemsetAsync(pb->xlo.p + off[p], 0, sizeof(uint16_t) * ld[p] * cols, s));
+      switch (pb->dpn) {
+        case 1: RPF_GLP(1, 1); break;
+        case 2: RPF_GLP(2, 1); break;
+        default: RPF_GLP(3, 1);
+      }
+    } else {
+      switch (pb->dpn) {
+        case 1: RPF_GLP(1, 0); break;
+        case 2: RPF_GLP(2, 0); break;
+        default: RPF_GLP(3, 0);
+      }
+    }
+#undef RPF_GLP
+    RPF_LAUNCH_CHECK();
+    void* tok = trace_begin(s);
+    if (split) {
+      RPF_CHECK(P->ldlp == ld[p], RPF_EINVAL, "low-precision S+ layout mismatch");
+      dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64));
+      if (prec == RPF_BF16X3)
+        hipLaunchKernelGGL((k_gemm_bf16<64, 64, true>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p,
+                           P->Sp_lo.p, ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p]);
+      else
+        hipLaunchKernelGGL((k_gemm_bf16<64, 64, false>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p,
+                           P->Sp_lo.p, ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p]);
+    } else {
+      dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64));
+      hipLaunchKernelGGL((k_sgemm_sym<64, 64>), g2, dim3(256), 0, s, nb, cols, nb, P->Splus32.p, (int64_t)nb,
+                         pb->xloc32.p + off[p], ld[p], yp, ld[p]);
+    }
+    RPF_LAUNCH_CHECK();
+    trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
+  }
+  if (pb->n_mult == 0) return;
+  dim3 grid((unsigned)cdiv(pb->n_mult, 128));
+  const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
+#define RPF_SF(D)                                                                                              \
+  hipLaunchKernelGGL(k_scatter_f32<D>, grid, dim3(128), 0, s, pb->n_mult, pb->d_ep_q.p, pb->d_ep_bn.p,          \
+                     pb->d_ep_pat.p, pb->d_ep_sign.p, pb->d_ep_occ.p, rot, yl, m, Y, ldy)
+  switch (pb->dpn) {
+    case 1: RPF_SF(1); break;
+    case 2: RPF_SF(2); break;
+    default: RPF_SF(3);
+  }
+#undef RPF_SF
+  RPF_LAUNCH_CHECK();
+}
+
+}  // namespace rpf

@@ -4,6 +4,7 @@
 #include "pattern.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <memory>
 #include <sstream>
@@ -84,16 +85,20 @@ __device__ inline uint16_t bf16_rne(float f) {
 }
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-__global__ void k_lowprec(const double* A, int64_t count, float* f32, uint16_t* hi, uint16_t* lo) {
+__global__ void k_to_f32(const double* A, int64_t count, float* f32) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const double x = A[i];
-  if (f32) f32[i] = (float)x;
-  if (hi) {
-    const uint16_t h = bf16_rne((float)x);
-    hi[i] = h;
-    if (lo) lo[i] = bf16_rne((float)(x - (double)bf16_to_f(h)));
-  }
+  if (i < count) f32[i] = (float)A[i];
+}
+
+// bf16 split of a symmetric n x n matrix into n rows of ldp (>= n) entries, zero padded
+__global__ void k_split_bf16(const double* A, int64_t n, int64_t ldp, uint16_t* hi, uint16_t* lo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * ldp) return;
+  const int64_t row = i / ldp, k = i % ldp;
+  const double x = (k < n) ? A[row * n + k] : 0.0;
+  const uint16_t h = bf16_rne((float)x);
+  hi[i] = h;
+  lo[i] = bf16_rne((float)(x - (double)bf16_to_f(h)));
 }
 
 void check_status(hipStream_t s, const int* d_status, const char* what) {
@@ -129,6 +134,8 @@ extern "C" rpf_status pattern_factor(int32_t n, const int32_t* rowptr, const int
     hipStream_t s = (hipStream_t)stream;
     if (ktol <= 0) ktol = 1e-10;
     auto P = std::make_unique<rpf_pattern_s>();
+    static std::atomic<uint64_t> next_uid{1};
+    P->uid = next_uid.fetch_add(1);
     P->n = n;
     P->n_b = n_b;
     P->n_i = n - n_b;
@@ -319,16 +326,17 @@ extern "C" rpf_status pattern_condense(rpf_pattern p, int32_t prec, void* stream
     const int64_t cnt = (int64_t)nb * nb;
     if (prec == RPF_FP32 && !(p->condensed & (1u << RPF_FP32))) {
       p->Splus32.alloc(cnt);
-      hipLaunchKernelGGL(k_lowprec, dim3((unsigned)cdiv(cnt, 256)), dim3(256), 0, s, p->Splus.p, cnt, p->Splus32.p,
-                         (uint16_t*)nullptr, (uint16_t*)nullptr);
+      hipLaunchKernelGGL(k_to_f32, dim3((unsigned)cdiv(cnt, 256)), dim3(256), 0, s, p->Splus.p, cnt, p->Splus32.p);
       RPF_LAUNCH_CHECK();
       p->condensed |= 1u << RPF_FP32;
     }
     if ((prec == RPF_BF16X3 || prec == RPF_BF16) && !(p->condensed & (1u << RPF_BF16X3))) {
-      p->Sp_hi.alloc(cnt);
-      p->Sp_lo.alloc(cnt);
-      hipLaunchKernelGGL(k_lowprec, dim3((unsigned)cdiv(cnt, 256)), dim3(256), 0, s, p->Splus.p, cnt,
-                         (float*)nullptr, p->Sp_hi.p, p->Sp_lo.p);
+      p->ldlp = cdiv(nb, 8) * 8;
+      const int64_t cntp = (int64_t)nb * p->ldlp;
+      p->Sp_hi.alloc(cntp);
+      p->Sp_lo.alloc(cntp);
+      hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)cdiv(cntp, 256)), dim3(256), 0, s, p->Splus.p, (int64_t)nb,
+                         p->ldlp, p->Sp_hi.p, p->Sp_lo.p);
       RPF_LAUNCH_CHECK();
       p->condensed |= (1u << RPF_BF16X3) | (1u << RPF_BF16);
     }

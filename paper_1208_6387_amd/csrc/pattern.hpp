@@ -4,6 +4,7 @@
 #include "common.hpp"
 
 struct rpf_pattern_s {
+  uint64_t uid = 0;  // unique per handle for the life of the process (cache keys)
   int n = 0, n_b = 0, n_i = 0, dpn = 1, k = 0;
   std::vector<int> bdofs, idofs;  // original dof ids of the boundary / interior rows
 
@@ -19,7 +20,8 @@ struct rpf_pattern_s {
   rpf::DevBuf<double> Z;       // n_b x k orthonormal kernel basis, ld n_b
   rpf::DevBuf<double> Splus;   // n_b x n_b FP64 pseudo-inverse, ld n_b
   rpf::DevBuf<float> Splus32;  // FP32 copy
-  rpf::DevBuf<uint16_t> Sp_hi, Sp_lo;  // bf16 split of S+ (bit patterns)
+  rpf::DevBuf<uint16_t> Sp_hi, Sp_lo;  // bf16 split of S+ (bit patterns), n_b rows of ldlp, zero padded
+  int64_t ldlp = 0;
   uint32_t condensed = 0;      // bit per rpf_prec built
 
   // K_bi (rows: boundary index, cols: interior index) and K_ib, CSR, for the

@@ -39,12 +39,12 @@ struct rpf_problem_s {
   rpf::DevBuf<uint16_t> xhi, xlo;
 
   // coarse space (built for one set of pattern handles)
-  std::vector<const void*> coarse_key;
+  std::vector<uint64_t> coarse_key;  // uids of the pattern handles the coarse space was built for
   int n_G = 0;
   std::vector<int> goff;
   rpf::DevBuf<int> d_goff, d_kp, d_nbn;
   rpf::DevBuf<const double*> d_Zp;
-  rpf::DevBuf<double> Ginv, cbuf, ybuf;
+  rpf::DevBuf<double> Ginv, cbuf, ybuf, cpart;
 };
 
 namespace rpf {
@@ -67,6 +67,9 @@ void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, i
 // x <- Q x = x - G (G^T G)^{-1} G^T x
 void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
 void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
+// F X with a low-precision flexibility product (FP32 or bf16 split), FP64 in and out
+void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
+                     int64_t ldy, int prec, hipStream_t s);
 // event tracing of the flexibility products
 bool trace_on();
 void* trace_begin(hipStream_t s);

@@ -119,6 +119,48 @@ def test_solve(case, R, method):
         assert abs(res.stats["iterations"] - max(sc["iterations"])) <= 2
 
 
+# Low-precision flexibility products: relative error bounds of the operator (max-norm, relative to
+# max |F X|).  FP32 and bf16x3 are limited by FP32 accumulation over n_b terms (~sqrt(n_b) 2^-24)
+# and, for bf16x3, by the 16-bit split (~2^-17); plain bf16 by its 8-bit significand.
+LOWPREC_TOL = {"fp32": 5e-5, "bf16x3": 5e-5, "bf16": 3e-2}
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("m", [1, 8, 11])
+def test_feti_apply_lowprec(case, R, form, m):
+    p, o, pats, pb = case
+    prec = {"fp32": R.FP32, "bf16x3": R.BF16X3, "bf16": R.BF16}[form]
+    for P in pats:
+        R.pattern_condense(P, prec)
+    rng = np.random.default_rng(100 + m)
+    X = rng.standard_normal((p.n_lambda, m))
+    Y = R.feti_apply(pb, pats, torch.from_numpy(X).cuda(), prec=prec).cpu().numpy()
+    ref = o.F(X)
+    err = np.abs(Y - ref).max() / np.abs(ref).max()
+    assert err <= LOWPREC_TOL[form], (form, err)
+    assert err > 0.0   # really computed in low precision
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x3"])
+def test_solve_mixed_refined(case, R, form):
+    """Mixed form: low-precision inner solves + FP64 refinement reach the FP64 tolerance, and u is
+    within 1e-6 of the oracle."""
+    from paper_1208_6387_amd import structure as ST
+    p, o, pats, pb = case
+    prec = {"fp32": R.FP32, "bf16x3": R.BF16X3}[form]
+    for P in pats:
+        R.pattern_condense(P, prec)
+    f = ST.loads_to_device(p)
+    res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=1e-8, max_it=3000, method=R.ORTHODIR, prec=prec,
+                               inner_tol=1e-3)
+    assert res.stats["rel_residual"] <= 1e-8
+    u = ST.split_u(p, res.u)
+    lam_o, u_o, st = o.solve("block", tol=1e-12)
+    scale = max(np.abs(x).max() for x in u_o)
+    err = max(np.abs(a - b).max() for a, b in zip(u, u_o)) / scale
+    assert err < 1e-6, (form, err, res.stats)
+
+
 def test_heat_row_closed_form(R):
     from paper_1208_6387_amd import structure as ST
     p = W.config(0)
@@ -132,6 +174,25 @@ def test_heat_row_closed_form(R):
         for s in range(4):
             xs = x + s
             assert np.abs(u[s][:, 0] - xs * (8 - xs) / 2).max() < 1e-8
+
+
+def test_structure_reused_with_new_pattern_handles(R):
+    """One structure, patterns factored, freed and factored again (handles may reuse addresses):
+    the coarse space must be rebuilt for the new handles and both solves agree."""
+    from paper_1208_6387_amd import structure as ST
+    p = W.small_elast((3, 3, 3), (2, 2, 1), n_rhs=2, n_perm=2, seed=4)
+    pb = ST.create_problem(p)
+    f = ST.loads_to_device(p)
+    outs = []
+    for rep in range(3):
+        pats = ST.factor_patterns(p)
+        ST.condense_patterns(pats)
+        res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=1e-10, max_it=500, method=R.ORTHODIR)
+        outs.append(res.u.cpu().numpy())
+        for P in pats:
+            P.free()
+    for u in outs[1:]:
+        assert np.abs(u - outs[0]).max() <= 1e-9 * np.abs(outs[0]).max()
 
 
 def test_kernel_dimension_mismatch_is_reported(R):
