@@ -106,12 +106,32 @@ void dgemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
            const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
            int64_t ldc, bool lower = false);
 
+// Output tiles of the configuration dgemm picks for an M x N product.
+int gemm_tiles(int64_t M, int64_t N);
+// NN product split over K into `splits` partial M x N slabs part[z*M*N + n*M + m]
+// (no reduction; the consumer sums the slabs).  The split boundaries are
+// multiples of 16, so at most cdiv(K, 16) slabs are non-empty; callers size part
+// for `splits` slabs and must read exactly splits_used(K, splits) of them.
+void dgemm_partials(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                    int64_t ldb, double* part, int splits);
+inline int splits_used(int64_t K, int splits) {
+  if (splits <= 1) return 1;
+  const int64_t kchunk = ((K + splits - 1) / splits + 15) / 16 * 16;
+  return (int)((K + kchunk - 1) / kchunk);
+}
+
 // Split-K form for contractions with a long K and a small M x N output; ws holds
 // splits * M * N doubles (see gemm_splitk_workspace).
 int gemm_splitk_count(int64_t M, int64_t N, int64_t K);
 void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                   const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                   int64_t ldc, double* ws, int splits);
+
+// Tall-skinny Gram C (a x b, column-major ld a) = X^T Y for row-major X (N x a, ldx)
+// and Y (N x b, ldy); ws must hold gram_chunks(N, a, b) * a * b doubles.
+int gram_chunks(int64_t N, int a, int b);
+void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy,
+          double* C, double* ws);
 
 // Row-block product for tall interface blocks: Y (N x b, row-major ldy) = beta Y
 // + alpha X (N x a, row-major ldx) M (a x b, column-major, ld a).

@@ -216,6 +216,19 @@ void dgemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
   launch_gemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, lower, 1, nullptr);
 }
 
+int gemm_tiles(int64_t M, int64_t N) {
+  const Cfg c = pick_cfg(M, N);
+  int bm, bn;
+  tile_of(c, bm, bn);
+  return (int)(cdiv(M, bm) * cdiv(N, bn));
+}
+
+void dgemm_partials(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                    int64_t ldb, double* part, int splits) {
+  if (M <= 0 || N <= 0) return;
+  launch_gemm(s, false, false, M, N, K, 1.0, A, lda, B, ldb, 0.0, nullptr, 0, false, splits, part);
+}
+
 int gemm_splitk_count(int64_t M, int64_t N, int64_t K) {
   const Cfg c = pick_cfg(M, N);
   int bm, bn;
@@ -243,44 +256,112 @@ void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t
   RPF_LAUNCH_CHECK();
 }
 
+// ============================================================================ tall-skinny Gram
+// Partial C (a x b) = X^T Y over a chunk of rows, X and Y row-major (N x a, N x b).
+// Workgroup (tile, chunk): tile = (ti, tj) 16 x 16 block of C; each wave takes 4
+// rows per v_mfma_f64_16x16x4_f64 (the k dimension of the MFMA runs over rows),
+// the 4 waves are summed in LDS and the partial goes to part[chunk][j][i].
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t N, int a, int b, const double* X, int64_t ldx,
+                                                      const double* Y, int64_t ldy, int64_t chunk, double* part) {
+  __shared__ double red[4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ta = (a + 15) / 16;
+  const int i0 = (blockIdx.x % ta) * 16, j0 = (blockIdx.x / ta) * 16;
+  const int64_t r_beg = (int64_t)blockIdx.y * chunk;
+  const int64_t r_end = min(N, r_beg + chunk);
+  const int i = i0 + (lane & 15), j = j0 + (lane & 15);
+  const bool iok = i < a, jok = j < b;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r0 = r_beg + 4 * wave; r0 < r_end; r0 += 16) {
+    const int64_t row = r0 + (lane >> 4);
+    const bool rok = row < r_end;
+    const double xa = (rok && iok) ? X[row * ldx + i] : 0.0;
+    const double yb = (rok && jok) ? Y[row * ldy + j] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, acc, 0, 0, 0);
+  }
+  // accumulator item r of lane l is C[i0 + l/16 + 4r][j0 + l%16]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave][((lane >> 4) + 4 * r) * 16 + (lane & 15)] = acc[r];
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int ci = i0 + t / 16, cj = j0 + t % 16;
+  if (ci < a && cj < b)
+    part[((int64_t)blockIdx.y * b + cj) * a + ci] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+int gram_chunks(int64_t N, int a, int b) {
+  const int64_t tiles = cdiv(a, 16) * cdiv(b, 16);
+  int64_t g = cdiv(1024, tiles);
+  g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(N, 64)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
+}
+
+void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy,
+          double* C, double* ws) {
+  if (a <= 0 || b <= 0) return;
+  const int g = gram_chunks(N, a, b);
+  const int64_t chunk = cdiv(N, g);
+  const int gz = (int)cdiv(N, chunk);
+  const int64_t tiles = cdiv(a, 16) * cdiv(b, 16);
+  RPF_CHECK(gz <= 65535, RPF_EINVAL, "gram: too many chunks");
+  hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)tiles, (unsigned)gz), dim3(256), 0, s, N, a, b, X, ldx, Y, ldy,
+                     chunk, ws);
+  RPF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * b, 32)), dim3(256), 0, s, (int64_t)a,
+                     (int64_t)b, gz, ws, 0.0, C, (int64_t)a);
+  RPF_LAUNCH_CHECK();
+}
+
 // ============================================================================ row-block products
-// Y[l*ldy + j] = beta Y + alpha sum_i X[l*ldx + i] M[i + a*j] for N rows, a small
-// a x b matrix M (column-major) staged through LDS in slices of 64 rows.  One
-// thread per row, up to 16 outputs in registers per pass.  Used for the block
-// updates of the interface solver (rows = interface dofs, row-major blocks).
+// Y[l*ldy + j] = beta Y + alpha sum_i X[l*ldx + i] M[i + a*j] for N rows and a
+// small a x b matrix M (column-major).  A workgroup owns 64 rows; slices of 32
+// columns of X are staged through LDS with coalesced loads (consecutive lanes
+// read consecutive columns of a row), M slices likewise; lane (r, q) then forms
+// outputs 4q..4q+3 of row r.  Used for the block updates of the interface
+// solver (rows = interface dofs, row-major blocks).
 __global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, double alpha, const double* X,
                                                    int64_t ldx, const double* Mm, double beta, double* Y,
                                                    int64_t ldy) {
-  __shared__ double sm[64][17];
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = l < N;
+  __shared__ double sx[64][33];
+  __shared__ double sm[32][16];
+  const int tid = threadIdx.x;
+  const int r = tid & 63, q = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int64_t row = row0 + r;
   for (int j0 = 0; j0 < b; j0 += 16) {
-    const int jn = min(16, b - j0);
-    double acc[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-    for (int i0 = 0; i0 < a; i0 += 64) {
-      const int in = min(64, a - i0);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < a; i0 += 32) {
       __syncthreads();
-      for (int t = threadIdx.x; t < 64 * 16; t += blockDim.x) {
-        const int i = t % 64, j = t / 64;
-        sm[i][j] = (i < in && j < jn) ? Mm[(int64_t)(i0 + i) + (int64_t)a * (j0 + j)] : 0.0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int idx = tid + 256 * e;
+        const int ii = idx & 31, rr = idx >> 5;
+        const int64_t gr = row0 + rr;
+        sx[rr][ii] = (gr < N && i0 + ii < a) ? X[gr * ldx + i0 + ii] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int idx = tid + 256 * e;
+        const int ii = idx & 31, jj = idx >> 5;
+        sm[ii][jj] = (i0 + ii < a && j0 + jj < b) ? Mm[(int64_t)(i0 + ii) + (int64_t)a * (j0 + jj)] : 0.0;
       }
       __syncthreads();
-      if (live) {
-        const double* xr = X + l * ldx + i0;
-        for (int i = 0; i < in; ++i) {
-          const double xv = xr[i];
+#pragma unroll 8
+      for (int ii = 0; ii < 32; ++ii) {
+        const double xv = sx[r][ii];
 #pragma unroll
-          for (int j = 0; j < 16; ++j) acc[j] += xv * sm[i][j];
-        }
+        for (int u = 0; u < 4; ++u) acc[u] += xv * sm[ii][4 * q + u];
       }
     }
-    if (live) {
-      double* yr = Y + l * ldy + j0;
+    if (row < N) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (j < jn) yr[j] = (beta == 0.0) ? alpha * acc[j] : beta * yr[j] + alpha * acc[j];
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 4 * q + u;
+        if (j < b) {
+          double* y = Y + row * ldy + j;
+          *y = (beta == 0.0) ? alpha * acc[u] : beta * *y + alpha * acc[u];
+        }
+      }
     }
   }
 }
@@ -288,71 +369,74 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, doub
 void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* Mm,
                double beta, double* Y, int64_t ldy) {
   if (N <= 0 || b <= 0) return;
-  hipLaunchKernelGGL(k_rows_gemm, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, beta, Y,
+  hipLaunchKernelGGL(k_rows_gemm, dim3((unsigned)cdiv(N, 64)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, beta, Y,
                      ldy);
   RPF_LAUNCH_CHECK();
 }
 
 // ============================================================================ Cholesky
-// One NB x NB diagonal block: unblocked right-looking Cholesky in LDS, then the
-// inverse of the factor (forward substitution, one column per thread).  Rows
+// One NB x NB diagonal block on a single wavefront: lane t keeps row t of the
+// block in registers and the factor is built column by column (right-looking),
+// each finished column broadcast through LDS; then lane c forms column c of the
+// inverse factor by forward substitution against the rows of L in LDS.  Rows
 // and columns beyond jb are padded with the identity.
-__global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int jb, double* dinv, int* status,
-                                                    int blk) {
-  __shared__ double s[NB][NB + 1];
-  __shared__ double inv[NB][NB + 1];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx % NB, c = idx / NB;
-    double v = (r == c) ? 1.0 : 0.0;
-    if (r < jb && c < jb) v = (r >= c) ? A[(int64_t)c * lda + r] : 0.0;
-    s[r][c] = v;
+__global__ __launch_bounds__(64) void k_potrf_diag(double* A, int64_t lda, int jb, double* dinv, int* status,
+                                                   int blk) {
+  __shared__ double Ls[NB][NB + 1];
+  const int t = threadIdx.x;
+  bool bad = false;
+  {
+    double a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double v = (c == t) ? 1.0 : 0.0;
+      if (t < jb && c < jb && c <= t) v = A[(int64_t)c * lda + t];
+      a[c] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (t == j) {
+        double d = a[j];
+        if (!(d > 0.0)) {
+          bad = true;
+          d = 1.0;
+        }
+        a[j] = sqrt(d);
+        Ls[j][j] = a[j];
+      }
+      __syncthreads();
+      if (t > j) {
+        a[j] *= 1.0 / Ls[j][j];
+        Ls[t][j] = a[j];
+      }
+      __syncthreads();
+      if (t > j) {
+        const double ltj = a[j];
+#pragma unroll
+        for (int c = j + 1; c < NB; ++c)
+          if (c <= t) a[c] -= ltj * Ls[c][j];
+      }
+    }
   }
   __syncthreads();
-  for (int j = 0; j < jb; ++j) {
-    if (tid == 0) {
-      double d = s[j][j];
-      if (!(d > 0.0)) {
-        bad = 1;
-        d = 1.0;
-      }
-      s[j][j] = sqrt(d);
-    }
-    __syncthreads();
-    const double rdjj = 1.0 / s[j][j];
-    for (int r = j + 1 + tid; r < jb; r += 256) s[r][j] *= rdjj;
-    __syncthreads();
-    const int w = jb - j - 1;
-    for (int idx = tid; idx < w * w; idx += 256) {
-      const int r = j + 1 + idx % w, c = j + 1 + idx / w;
-      if (r >= c) s[r][c] -= s[r][j] * s[c][j];
-    }
-    __syncthreads();
-  }
-  // inverse of the factor, row by row: inv[r][c] = (delta_rc - sum_{c<=k<r} L[r][k] inv[k][c]) / L[r][r];
-  // the 256 threads are 64 columns x 4 interleaved slices of the k sum
+  // write the factor back (lower part of the jb x jb block)
+#pragma unroll 4
+  for (int c = 0; c < NB; ++c)
+    if (t < jb && c < jb && c <= t) A[(int64_t)c * lda + t] = Ls[t][c];
+  // column c = t of the inverse: x[r] = (delta_rc - sum_{k<r} L[r][k] x[k]) / L[r][r]
   {
-    __shared__ double part[4][NB];
-    const int c = tid & (NB - 1), q = tid >> 6;
+    double x[NB];
+#pragma unroll
     for (int r = 0; r < NB; ++r) {
-      double sum = 0.0;
-      if (r > c)
-        for (int k = c + q; k < r; k += 4) sum += s[r][k] * inv[k][c];
-      part[q][c] = sum;
-      __syncthreads();
-      if (q == 0)
-        inv[r][c] = (r < c) ? 0.0 : (((r == c) ? 1.0 : 0.0) - (part[0][c] + part[1][c] + part[2][c] + part[3][c])) / s[r][r];
-      __syncthreads();
+      double sum = (r == t) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < r; ++k) sum -= Ls[r][k] * x[k];
+      x[r] = (r < t) ? 0.0 : sum * (1.0 / Ls[r][r]);
     }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) dinv[(int64_t)t * NB + r] = x[r];
   }
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx % NB, c = idx / NB;
-    if (r < jb && c < jb && r >= c) A[(int64_t)c * lda + r] = s[r][c];
-    dinv[(int64_t)c * NB + r] = inv[r][c];
-  }
-  if (tid == 0 && bad) atomicCAS(status, 0, blk + 1);
+  if (bad) atomicCAS(status, 0, blk + 1);
 }
 
 Envelope Envelope::dense(int64_t n) {
@@ -371,7 +455,7 @@ void potrf(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac, cons
     const int64_t j0 = t * NB;
     const int jb = (int)std::min<int64_t>(NB, n_fac - j0);
     double* dt = dinv + t * NB * NB;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A + j0 * lda + j0, lda, jb, dt, status, (int)t);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A + j0 * lda + j0, lda, jb, dt, status, (int)t);
     RPF_LAUNCH_CHECK();
     const int64_t r0 = j0 + jb;
     const int64_t rend = std::max<int64_t>(r0, std::min<int64_t>(env.rend[t], n_fac));
@@ -505,7 +589,8 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
   const double* A = Ain + (int64_t)blockIdx.x * m * m;
   double* V = Vout + (int64_t)blockIdx.x * m * m;
   double* w = wout + (int64_t)blockIdx.x * m;
-  for (int i = tid; i < m * m; i += 256) {
+  const int nth = blockDim.x;
+  for (int i = tid; i < m * m; i += nth) {
     const int r = i % m, c = i / m;
     a[r][c] = 0.5 * (A[c * m + r] + A[r * m + c]);
     v[r][c] = (r == c) ? 1.0 : 0.0;
@@ -513,11 +598,18 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
   const int me = m + (m & 1);  // even count for the round-robin schedule
   const int npair = me / 2;
   __shared__ int nrot;
+  __shared__ double floor_abs;
   __syncthreads();
-  // threshold Jacobi: a pair is rotated only while |a_pq| > 1e-15 sqrt(|a_pp a_qq|)
-  // (high relative accuracy); the sweeps stop once a whole sweep rotates nothing
+  // threshold Jacobi: a pair is rotated only while |a_pq| > 1e-15 sqrt(|a_pp a_qq|) (high
+  // relative accuracy) and |a_pq| > 1e-17 max_i |a_ii| (below that a rotation only moves
+  // rounding noise); the sweeps stop once a whole sweep rotates nothing
   for (int sweep = 0; sweep < 30 && m >= 2; ++sweep) {
-    if (tid == 0) nrot = 0;
+    if (tid == 0) {
+      nrot = 0;
+      double d = 0.0;
+      for (int i = 0; i < m; ++i) d = fmax(d, fabs(a[i][i]));
+      floor_abs = fmax(1e-17 * d, 1e-300);
+    }
     __syncthreads();
     for (int step = 0; step < me - 1; ++step) {
       // circle method: indices 0..me-2 rotate, me-1 is fixed
@@ -534,7 +626,7 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
         double c = 1.0, sn = 0.0;
         if (q < m) {
           const double apq = a[p][q];
-          if (fabs(apq) > 1e-15 * sqrt(fabs(a[p][p] * a[q][q])) && fabs(apq) > 1e-300) {
+          if (fabs(apq) > 1e-15 * sqrt(fabs(a[p][p] * a[q][q])) && fabs(apq) > floor_abs) {
             atomicAdd(&nrot, 1);
             const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
             const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
@@ -549,7 +641,7 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int idx = tid; idx < npair * m; idx += 256) {
+      for (int idx = tid; idx < npair * m; idx += nth) {
         const int k = idx / m, r = idx % m;
         const int p = pp[k], q = qq[k];
         if (q >= m) continue;
@@ -563,7 +655,7 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
       }
       __syncthreads();
       // rows: A <- J^T A
-      for (int idx = tid; idx < npair * m; idx += 256) {
+      for (int idx = tid; idx < npair * m; idx += nth) {
         const int k = idx / m, col = idx % m;
         const int p = pp[k], q = qq[k];
         if (q >= m) continue;
@@ -590,16 +682,18 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
     }
   }
   __syncthreads();
-  for (int i = tid; i < m * m; i += 256) {
+  for (int i = tid; i < m * m; i += nth) {
     const int r = i % m, c = i / m;
     V[c * m + r] = v[r][order[c]];
   }
-  for (int i = tid; i < m; i += 256) w[i] = a[order[i]][order[i]];
+  for (int i = tid; i < m; i += nth) w[i] = a[order[i]][order[i]];
 }
 
 void syev_small(hipStream_t s, const double* A, int m, double* V, double* w, int batch) {
   RPF_CHECK(m >= 1 && m <= EIG_MAX, RPF_EINVAL, "syev_small: m out of range");
-  hipLaunchKernelGGL(k_syev_jacobi, dim3(batch), dim3(256), 0, s, A, m, V, w);
+  // one wavefront is enough (and its barriers are cheapest) while m/2 * m <= 128 work items
+  const int threads = (m <= 16) ? 64 : 256;
+  hipLaunchKernelGGL(k_syev_jacobi, dim3(batch), dim3(threads), 0, s, A, m, V, w);
   RPF_LAUNCH_CHECK();
 }
 

@@ -90,7 +90,8 @@ __global__ __launch_bounds__(128) void k_scatter(int n_mult, const int* ep_q, co
       if (q < 0) continue;
       const int p = ep_pat[2 * mult + e];
       const double sg = (double)ep_sign[2 * mult + e];
-      const int64_t ld = yl.ld[p];
+      const int64_t ld = yl.ld[p], slab = yl.slab[p];
+      const int nsp = yl.nsplit[p];
       const double* base = yl.base[p] + ((int64_t)q * m + j0) * ld + (int64_t)ep_bn[2 * mult + e] * DPN;
       double O[9];
       if (DPN == 3) load_rot<DPN>(rot, ep_occ[2 * mult + e], O);
@@ -100,6 +101,9 @@ __global__ __launch_bounds__(128) void k_scatter(int n_mult, const int* ep_q, co
         double v[DPN];
 #pragma unroll
         for (int c = 0; c < DPN; ++c) v[c] = base[j * ld + c];
+        for (int z = 1; z < nsp; ++z)
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) v[c] += base[z * slab + j * ld + c];
         if (DPN == 3) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) acc[c][j] += sg * (O[3 * c] * v[0] + O[3 * c + 1] * v[1 % DPN] + O[3 * c + 2] * v[2 % DPN]);
@@ -462,24 +466,37 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     }
     return;
   }
-  // W-format workspace: one slab per pattern
-  std::vector<int64_t> off(pb->n_pat + 1, 0);
-  for (int p = 0; p < pb->n_pat; ++p)
-    off[p + 1] = off[p] + (int64_t)pats[p]->n_b * (int64_t)pb->occ_of_pat[p].size() * m;
+  // W-format workspace: one slab per pattern (times the K splits for the results)
+  std::vector<int64_t> off(pb->n_pat + 1, 0), yoff(pb->n_pat + 1, 0);
+  std::vector<int> nsp(pb->n_pat, 1);
+  for (int p = 0; p < pb->n_pat; ++p) {
+    const int nb = pats[p]->n_b;
+    const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
+    // split K while the output tiles alone cannot give ~4 workgroups per CU, keeping >= 256 per split
+    const int64_t tiles = std::max<int64_t>(1, gemm_tiles(nb, cols));
+    int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, nb / 256));
+    sp = std::min(sp, 8);
+    nsp[p] = splits_used(nb, sp);
+    off[p + 1] = off[p] + (int64_t)nb * cols;
+    yoff[p + 1] = yoff[p] + (int64_t)nb * cols * sp;
+  }
   pb->xloc.ensure(std::max<int64_t>(off[pb->n_pat], 1));
-  pb->yloc.ensure(std::max<int64_t>(off[pb->n_pat], 1));
+  pb->yloc.ensure(std::max<int64_t>(yoff[pb->n_pat], 1));
   YLoc yl{};
   for (int p = 0; p < pb->n_pat; ++p) {
     const int nb = pats[p]->n_b;
     const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
     double* xp = pb->xloc.p + off[p];
-    double* yp = pb->yloc.p + off[p];
+    double* yp = pb->yloc.p + yoff[p];
     gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, nb, s);
     void* tok = trace_begin(s);
-    dgemm(s, false, false, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, nb, 0.0, yp, nb);
+    if (nsp[p] > 1) dgemm_partials(s, nb, cols, nb, pats[p]->Splus.p, nb, xp, nb, yp, (int)((yoff[p + 1] - yoff[p]) / ((int64_t)nb * cols)));
+    else dgemm(s, false, false, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, nb, 0.0, yp, nb);
     trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
     yl.base[p] = yp;
     yl.ld[p] = nb;
+    yl.slab[p] = (int64_t)nb * cols;
+    yl.nsplit[p] = nsp[p];
   }
   scatter_all(pb, yl, m, Y, ldy, 0.0, s);
   if (project) {

@@ -194,12 +194,10 @@ struct Solver {
     N = pb->n_lambda;
   }
 
-  // column norms^2 of an N x c row-major block -> host
+  // column norms^2 of an N x c row-major block -> host (synchronous)
   std::vector<double> colnorm2(const double* X, int64_t ldx, int c) {
-    const int sp = gemm_splitk_count(c, c, N);
-    ws.ensure((size_t)sp * c * c);
     nrm.ensure((size_t)c * c);
-    dgemm_splitk(s, false, true, c, c, N, 1.0, X, ldx, X, ldx, 0.0, nrm.p, c, ws.p, sp);
+    gram(X, ldx, c, X, ldx, c, nrm.p);
     std::vector<double> full((size_t)c * c), out(c);
     RPF_HIP(hipMemcpyAsync(full.data(), nrm.p, sizeof(double) * c * c, hipMemcpyDeviceToHost, s));
     RPF_HIP(hipStreamSynchronize(s));
@@ -209,9 +207,43 @@ struct Solver {
 
   // Gram C (a x b, col-major ld a) = X^T Y with X: N x a (ldx), Y: N x b (ldy), row-major blocks
   void gram(const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b, double* C) {
-    const int sp = gemm_splitk_count(a, b, N);
-    ws.ensure((size_t)sp * a * b);
-    dgemm_splitk(s, false, true, a, b, N, 1.0, X, ldx, Y, ldy, 0.0, C, a, ws.p, sp);
+    ws.ensure((size_t)gram_chunks(N, a, b) * a * b);
+    rpf::gram(s, N, a, b, X, ldx, Y, ldy, C, ws.p);
+  }
+
+  // lagged convergence check: the norms of iteration i are copied to pinned memory and read
+  // while iteration i+1 is already queued, so the host never drains the stream mid-solve
+  double* hnorm = nullptr;  // pinned, 2 slots of nr*nr
+  hipEvent_t nev[2] = {nullptr, nullptr};
+  DevBuf<double> nrm2[2];
+  void init_lag() {
+    if (!hnorm) {
+      RPF_HIP(hipHostMalloc((void**)&hnorm, sizeof(double) * 2 * nr * nr, hipHostMallocDefault));
+      RPF_HIP(hipEventCreateWithFlags(&nev[0], hipEventDisableTiming));
+      RPF_HIP(hipEventCreateWithFlags(&nev[1], hipEventDisableTiming));
+    }
+  }
+  void post_norms(const double* X, int slot) {
+    nrm2[slot].ensure((size_t)nr * nr);
+    gram(X, nr, nr, X, nr, nr, nrm2[slot].p);
+    RPF_HIP(hipMemcpyAsync(hnorm + (size_t)slot * nr * nr, nrm2[slot].p, sizeof(double) * nr * nr,
+                           hipMemcpyDeviceToHost, s));
+    RPF_HIP(hipEventRecord(nev[slot], s));
+  }
+  bool read_norms(int slot, const std::vector<double>& target) {
+    RPF_HIP(hipEventSynchronize(nev[slot]));
+    bool ok = true;
+    for (int c = 0; c < nr; ++c) {
+      const double v = hnorm[(size_t)slot * nr * nr + (size_t)c * nr + c];
+      RPF_CHECK(std::isfinite(v), RPF_EBREAKDOWN, "block_krylov_solve: residual is not finite");
+      ok &= !(v > target[c]);
+    }
+    return ok;
+  }
+  ~Solver() {
+    if (hnorm) (void)hipHostFree(hnorm);
+    for (auto& e : nev)
+      if (e) (void)hipEventDestroy(e);
   }
 
   void alloc(int64_t ld_lam_unused) {
@@ -254,6 +286,8 @@ struct Solver {
     const bool diag_only = (method == RPF_CLASSICAL);
     RPF_HIP(hipMemsetAsync(drops.p, 0, sizeof(int), s));
     bool conv = false;
+    init_lag();
+    int pending = -1, nchk = 0;
     for (int it = 0; it < max_it; ++it) {
       // multivector from the residual (Q R = R: the residual stays in range Q), re-projected
       hipLaunchKernelGGL(k_permute, dim3(nblocks(N)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
@@ -301,17 +335,20 @@ struct Solver {
       ++nst;
       ++iterations;
       if ((it + 1) % check_every == 0 || it + 1 == max_it) {
-        const std::vector<double> rn = colnorm2(Rs.p, nr, nr);
-        bool ok = true;
-        for (int c = 0; c < nr; ++c) ok &= !(rn[c] > target[c]);
-        for (int c = 0; c < nr; ++c)
-          RPF_CHECK(std::isfinite(rn[c]), RPF_EBREAKDOWN, "block_krylov_solve: residual is not finite");
-        if (ok) {
+        const int slot_n = nchk & 1;
+        post_norms(Rs.p, slot_n);
+        // the previous check is read now, while this iteration is already queued; when it
+        // reports convergence the solve stops after this (extra, still valid) iteration
+        if (pending >= 0 && read_norms(pending, target)) {
           conv = true;
+          pending = -1;
           break;
         }
+        pending = slot_n;
+        ++nchk;
       }
     }
+    if (!conv && pending >= 0) conv = read_norms(pending, target);
     int hd = 0;
     RPF_HIP(hipMemcpyAsync(&hd, drops.p, sizeof(int), hipMemcpyDeviceToHost, s));
     RPF_HIP(hipStreamSynchronize(s));

@@ -79,9 +79,14 @@ __global__ __launch_bounds__(128) void k_gather_lp(int nbn, const int* occ_list,
 // the first MFMA operand so that lanes 0..15 of an accumulator item hold 16 rows
 // of one column of C.
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void k_sgemm_sym(int M, int N, int K, const float* A, int64_t lda, const float* B,
-                                                   int64_t ldb, float* C, int64_t ldc) {
+__global__ __launch_bounds__(256) void k_sgemm_sym(int M, int N, int Kfull, const float* A, int64_t lda,
+                                                   const float* B, int64_t ldb, float* C, int64_t ldc, int kchunk,
+                                                   int64_t slab) {
   constexpr int BK = 16, PAD = 4;
+  // split-K: this workgroup covers k in [kb, K) and writes slab blockIdx.z
+  const int kb = blockIdx.z * kchunk;
+  const int K = min(Kfull, kb + kchunk);
+  C += (int64_t)blockIdx.z * slab;
   constexpr int WTM = BM / 2, WTN = BN / 2, TM = WTM / 16, TN = WTN / 16;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
   __shared__ float sA[BK][BM + PAD];
@@ -123,8 +128,8 @@ __global__ __launch_bounds__(256) void k_sgemm_sym(int M, int N, int K, const fl
       sB[idx % BK][idx / BK] = rb[e];
     }
   };
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  if (kb < K) gload(kb);
+  for (int k0 = kb; k0 < K; k0 += BK) {
     __syncthreads();
     sstore();
     __syncthreads();
@@ -162,8 +167,11 @@ __global__ __launch_bounds__(256) void k_sgemm_sym(int M, int N, int K, const fl
 template <int BM, int BN, bool X3>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* Ah, const uint16_t* Al,
                                                    int64_t lda, const uint16_t* Bh, const uint16_t* Bl, int64_t ldb,
-                                                   float* C, int64_t ldc) {
-  constexpr int BK = 32, RS = BK + 8;  // row stride in bf16 elements (80 bytes)
+                                                   float* C, int64_t ldc, int kchunk, int64_t slab) {
+  constexpr int BK = 64, RS = BK + 8;  // row stride in bf16 elements (144 bytes)
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  C += (int64_t)blockIdx.z * slab;
   constexpr int WTM = BM / 2, WTN = BN / 2, TM = WTM / 16, TN = WTN / 16;
   constexpr int NA = BM * BK / 8 / 256, NB = BN * BK / 8 / 256;  // 16-byte chunks per thread
   static_assert(NA >= 1 && NB >= 1, "tile too small");
@@ -180,7 +188,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
-  // a 16-byte chunk = 8 consecutive k of one row; chunk c of the tile: row c / 4, k offset 8 (c % 4)
+  // a 16-byte chunk = 8 consecutive k of one row; chunk c of the tile: row c / 8, k offset 8 (c % 8)
   auto load_chunk = [&](const uint16_t* P, int64_t ld, int row, int nrow, int k, int krem, uint4& out) {
     if (row < nrow && krem >= 8) {
       out = *reinterpret_cast<const uint4*>(P + (int64_t)row * ld + k);
@@ -194,62 +202,65 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   auto gload = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
-      const int c = tid + e * 256, row = c / 4, kk = 8 * (c % 4);
-      load_chunk(Ah, lda, m0 + row, M, k0 + kk, K - (k0 + kk), rah[e]);
-      if (X3) load_chunk(Al, lda, m0 + row, M, k0 + kk, K - (k0 + kk), ral[e]);
+      const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
+      load_chunk(Ah, lda, m0 + row, M, k0 + kk, kend - (k0 + kk), rah[e]);
+      if (X3) load_chunk(Al, lda, m0 + row, M, k0 + kk, kend - (k0 + kk), ral[e]);
     }
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      const int c = tid + e * 256, row = c / 4, kk = 8 * (c % 4);
-      load_chunk(Bh, ldb, n0 + row, N, k0 + kk, K - (k0 + kk), rbh[e]);
-      if (X3) load_chunk(Bl, ldb, n0 + row, N, k0 + kk, K - (k0 + kk), rbl[e]);
+      const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
+      load_chunk(Bh, ldb, n0 + row, N, k0 + kk, kend - (k0 + kk), rbh[e]);
+      if (X3) load_chunk(Bl, ldb, n0 + row, N, k0 + kk, kend - (k0 + kk), rbl[e]);
     }
   };
   auto sstore = [&]() {
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
-      const int c = tid + e * 256, row = c / 4, kk = 8 * (c % 4);
+      const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
       *reinterpret_cast<uint4*>(&sAh[row * RS + kk]) = rah[e];
       if (X3) *reinterpret_cast<uint4*>(&sAl[row * RS + kk]) = ral[e];
     }
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      const int c = tid + e * 256, row = c / 4, kk = 8 * (c % 4);
+      const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
       *reinterpret_cast<uint4*>(&sBh[row * RS + kk]) = rbh[e];
       if (X3) *reinterpret_cast<uint4*>(&sBl[row * RS + kk]) = rbl[e];
     }
   };
-  // the 16-byte alignment of the vector loads needs lda, ldb, K multiples of 8: guaranteed by the host
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  // the 16-byte alignment of the vector loads needs lda, ldb, kchunk multiples of 8: guaranteed by the host
+  if (kbeg < kend) gload(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
     sstore();
     __syncthreads();
-    if (k0 + BK < K) gload(k0 + BK);
-    const int ko = 8 * (lane >> 4);
-    bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+    if (k0 + BK < kend) gload(k0 + BK);
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int row = wm * WTM + i * 16 + (lane & 15);
-      ah[i] = *reinterpret_cast<const bf16x8*>(&sAh[row * RS + ko]);
-      if (X3) al[i] = *reinterpret_cast<const bf16x8*>(&sAl[row * RS + ko]);
-    }
+    for (int ks = 0; ks < BK; ks += 32) {
+      const int ko = ks + 8 * (lane >> 4);
+      bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int row = wn * WTN + j * 16 + (lane & 15);
-      bh[j] = *reinterpret_cast<const bf16x8*>(&sBh[row * RS + ko]);
-      if (X3) bl[j] = *reinterpret_cast<const bf16x8*>(&sBl[row * RS + ko]);
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i) {
+        const int row = wm * WTM + i * 16 + (lane & 15);
+        ah[i] = *reinterpret_cast<const bf16x8*>(&sAh[row * RS + ko]);
+        if (X3) al[i] = *reinterpret_cast<const bf16x8*>(&sAl[row * RS + ko]);
+      }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah[i], acc[i][j], 0, 0, 0);
-        if (X3) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah[i], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al[i], acc[i][j], 0, 0, 0);
-        }
+        const int row = wn * WTN + j * 16 + (lane & 15);
+        bh[j] = *reinterpret_cast<const bf16x8*>(&sBh[row * RS + ko]);
+        if (X3) bl[j] = *reinterpret_cast<const bf16x8*>(&sBl[row * RS + ko]);
       }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah[i], acc[i][j], 0, 0, 0);
+          if (X3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah[i], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al[i], acc[i][j], 0, 0, 0);
+          }
+        }
+    }
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -267,6 +278,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
 struct YLoc32 {
   const float* base[MAXP];
   int64_t ld[MAXP];
+  int64_t slab[MAXP];
+  int nsplit[MAXP];
 };
 
 template <int DPN>
@@ -300,6 +313,9 @@ __global__ __launch_bounds__(128) void k_scatter_f32(int n_mult, const int* ep_q
         double v[DPN];
 #pragma unroll
         for (int c = 0; c < DPN; ++c) v[c] = (double)base[j * ld + c];
+        for (int z = 1; z < yl.nsplit[p]; ++z)
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) v[c] += (double)base[z * yl.slab[p] + j * ld + c];
         if (DPN == 3) {
 #pragma unroll
           for (int c = 0; c < 3; ++c)
@@ -326,12 +342,24 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
   const bool split = (prec == RPF_BF16X3 || prec == RPF_BF16);
   // W format with ld rounded up to a multiple of 8 (16-byte rows for the bf16 loads)
   std::vector<int64_t> off(pb->n_pat + 1, 0), ld(pb->n_pat);
+  // split K (chunks of multiples of 64) while the 64 x 64 output tiles alone give fewer than
+  // ~4 workgroups per CU; the scatter sums the split slabs
+  std::vector<int64_t> yoff(pb->n_pat + 1, 0);
+  std::vector<int> nsp(pb->n_pat, 1), kch(pb->n_pat, 0);
   for (int p = 0; p < pb->n_pat; ++p) {
-    ld[p] = cdiv(pats[p]->n_b, 8) * 8;
-    off[p + 1] = off[p] + ld[p] * (int64_t)pb->occ_of_pat[p].size() * m;
+    const int nb = pats[p]->n_b;
+    ld[p] = cdiv(nb, 8) * 8;
+    const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
+    off[p + 1] = off[p] + ld[p] * cols;
+    const int64_t tiles = std::max<int64_t>(1, cdiv(nb, 64) * cdiv(cols, 64));
+    int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, ld[p] / 256));
+    sp = std::min(sp, 8);
+    kch[p] = (int)(cdiv(cdiv(ld[p], sp), 64) * 64);
+    nsp[p] = (int)cdiv(ld[p], kch[p]);
+    yoff[p + 1] = yoff[p] + ld[p] * cols * nsp[p];
   }
   const int64_t tot = std::max<int64_t>(off[pb->n_pat], 8);
-  pb->yloc32.ensure(tot);
+  pb->yloc32.ensure(std::max<int64_t>(yoff[pb->n_pat], 8));
   if (split) {
     pb->xhi.ensure(tot);
     pb->xlo.ensure(tot);
@@ -345,9 +373,12 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     const int cols = nq * m;
     const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
     const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
-    float* yp = pb->yloc32.p + off[p];
+    float* yp = pb->yloc32.p + yoff[p];
+    const int64_t slab = ld[p] * (int64_t)cols;
     yl.base[p] = yp;
     yl.ld[p] = ld[p];
+    yl.slab[p] = slab;
+    yl.nsplit[p] = nsp[p];
     if (nq == 0) continue;
     dim3 grid((unsigned)cdiv(nbn, 128), (unsigned)nq);
 #define RPF_GLP(D, MODE)                                                                                        \
@@ -375,17 +406,17 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     void* tok = trace_begin(s);
     if (split) {
       RPF_CHECK(P->ldlp == ld[p], RPF_EINVAL, "low-precision S+ layout mismatch");
-      dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64));
+      dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64), (unsigned)nsp[p]);
       if (prec == RPF_BF16X3)
         hipLaunchKernelGGL((k_gemm_bf16<64, 64, true>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p,
-                           P->Sp_lo.p, ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p]);
+                           P->Sp_lo.p, ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab);
       else
         hipLaunchKernelGGL((k_gemm_bf16<64, 64, false>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p,
-                           P->Sp_lo.p, ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p]);
+                           P->Sp_lo.p, ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab);
     } else {
-      dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64));
+      dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64), (unsigned)nsp[p]);
       hipLaunchKernelGGL((k_sgemm_sym<64, 64>), g2, dim3(256), 0, s, nb, cols, nb, P->Splus32.p, (int64_t)nb,
-                         pb->xloc32.p + off[p], ld[p], yp, ld[p]);
+                         pb->xloc32.p + off[p], ld[p], yp, ld[p], kch[p], slab);
     }
     RPF_LAUNCH_CHECK();
     trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);

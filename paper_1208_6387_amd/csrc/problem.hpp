@@ -8,9 +8,13 @@ namespace rpf {
 constexpr int MAXP = 8;   // patterns per structure
 constexpr int KMAX = 8;   // kernel dimension per pattern (coarse kernels)
 
+// W-format result slabs of every pattern; a split-K product leaves nsplit partial
+// slabs `slab` elements apart, summed by the scatter.
 struct YLoc {
   double* base[MAXP];
   int64_t ld[MAXP];
+  int64_t slab[MAXP];
+  int nsplit[MAXP];
 };
 }  // namespace rpf
 
