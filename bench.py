@@ -25,14 +25,16 @@ PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 HBM_GBPS = 8000.0
 
 WORKLOADS = {
-    # name: (configuration index, method, description)
+    # name: (configuration index, method, description, solver settings)
     "elast-12cube-4x4x4-8rhs": (2, "orthodir", "3-D elasticity, 12^3-brick pattern x 64 occurrences (4x4x4), "
-                                               "8 load cases, clamped x=0"),
+                                               "8 load cases, clamped x=0",
+                                dict(max_blocks=0, inner_tol=1e-4)),
     "elast-12cube-4x4x4": (1, "orthodir", "3-D elasticity, 12^3-brick pattern x 64 occurrences (4x4x4), "
-                                          "1 load case, 8 permutations"),
-    "heat-row-16x16x4": (0, "orthodir", "2-D heat, 16x16 pattern x 4 (row)"),
+                                          "1 load case, 8 permutations", dict(max_blocks=0, inner_tol=1e-4)),
+    "heat-row-16x16x4": (0, "orthodir", "2-D heat, 16x16 pattern x 4 (row)", dict(max_blocks=0, inner_tol=1e-4)),
+    # 512 occurrences x 16 cases: one stored (W, P) block is 456 MB, so ORTHODIR restarts every 48 blocks
     "elast-20cube-8x8x8-16rhs": (4, "orthodir", "3-D elasticity, 20^3-brick pattern x 512 occurrences (8x8x8), "
-                                                "16 load cases + traction"),
+                                                "16 load cases + traction on x=1", dict(max_blocks=48, inner_tol=1e-3)),
 }
 PREC_NAMES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16": 3}
 METHODS = {"classical": 0, "block_cg": 1, "orthodir": 2}
@@ -51,6 +53,7 @@ def main():
     ap.add_argument("--forms", default="fp64", help="comma list of fp64, fp32, bf16x3, bf16 (first is the headline)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-it", type=int, default=3000)
+    ap.add_argument("--max-blocks", type=int, default=None, help="ORTHODIR restart length (default per workload)")
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     ap.add_argument("--cpu-iterations", type=int, default=10)
@@ -70,7 +73,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     R.load()
-    cfg_idx, method_name, desc = WORKLOADS[args.workload]
+    cfg_idx, method_name, desc, settings = WORKLOADS[args.workload]
+    if args.max_blocks is not None:
+        settings = dict(settings, max_blocks=args.max_blocks)
     method = METHODS[method_name]
     log(f"[bench] generating {args.workload}")
     p = W.config(cfg_idx)
@@ -94,7 +99,8 @@ def main():
             if prec != R.FP64:
                 R.pattern_condense(P, prec)
         res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=args.tol, max_it=args.max_it, method=method,
-                                   prec=prec, lam_out=lam, u_out=u)
+                                   prec=prec, inner_tol=settings["inner_tol"], max_blocks=settings["max_blocks"],
+                                   lam_out=lam, u_out=u)
         for P in pats:
             P.free()
         return res
@@ -147,6 +153,7 @@ def main():
         "dtype": "f64" if head == "fp64" else f"{dtype}+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "form": head, "method": method_name,
+                   "max_blocks": settings["max_blocks"], "inner_tol": settings["inner_tol"],
                    "n_lambda": pb.n_lambda, "n_occ": p.n_occ, "n_rhs": p.n_rhs, "n_perm": p.n_perm,
                    "pattern_dofs": [pat.n for pat in p.patterns], "pattern_boundary_dofs": [pat.n_b for pat in p.patterns],
                    "tol": args.tol},

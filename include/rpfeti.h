@@ -172,6 +172,8 @@ typedef struct {
   double inner_tol;    /* relative reduction per refinement sweep (mixed forms; 0: 1e-4) */
   int32_t max_sweeps;  /* refinement sweeps (mixed forms; 0: 30) */
   int32_t check_every; /* read the convergence flag every k iterations (0: 1) */
+  int32_t max_blocks;  /* ORTHODIR: stored (W, P) blocks before a restart (0: as many as max_it and
+                          half of the free device memory allow) */
 } rpf_solve_opts;
 
 typedef struct {

@@ -134,9 +134,10 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
           double* C, double* ws);
 
 // Row-block product for tall interface blocks: Y (N x b, row-major ldy) = beta Y
-// + alpha X (N x a, row-major ldx) M (a x b, column-major, ld a).
+// + alpha X (N x a, row-major ldx) M, M an a x b matrix stored column-major with
+// ld a (mrow = 0) or row-major with ld mrow (mrow > 0).
 void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* M,
-               double beta, double* Y, int64_t ldy);
+               double beta, double* Y, int64_t ldy, int64_t mrow = 0);
 
 // Envelope description of a lower factor: for column block t (NB columns),
 // rows [t*NB+jb, rend[t]) below the diagonal block may be nonzero, and the

@@ -122,25 +122,21 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
       }
 }
 
-// Sum of the split-K partials: one wavefront per 8 outputs, lanes stride over
-// the splits (fixed order, so the result is deterministic).
+// Sum of the split-K partials: one wavefront per output, lanes stride over the
+// splits (fixed order, so the result is deterministic).
 __global__ __launch_bounds__(256) void k_splitk_reduce(int64_t M, int64_t N, int splits, const double* part,
                                                        double beta, double* C, int64_t ldc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 8;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
   const int64_t MN = M * N;
-#pragma unroll
-  for (int o = 0; o < 8; ++o) {
-    const int64_t idx = base + o;
-    if (idx >= MN) break;
-    double s = 0.0;
-    for (int z = lane; z < splits; z += 64) s += part[(int64_t)z * MN + idx];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) {
-      const int64_t m = idx % M, n = idx / M;
-      double* c = C + n * ldc + m;
-      *c = (beta == 0.0) ? s : s + beta * *c;
-    }
+  if (idx >= MN) return;
+  double s = 0.0;
+  for (int z = lane; z < splits; z += 64) s += part[(int64_t)z * MN + idx];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) {
+    const int64_t m = idx % M, n = idx / M;
+    double* c = C + n * ldc + m;
+    *c = (beta == 0.0) ? s : s + beta * *c;
   }
 }
 
@@ -251,7 +247,7 @@ void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t
   const int64_t kchunk = cdiv(cdiv(K, splits), 16) * 16;
   const int gz = (int)cdiv(K, kchunk);
   launch_gemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, 0.0, nullptr, 0, false, splits, ws);
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 32)), dim3(256), 0, s, M, N, gz, ws, beta, C,
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 4)), dim3(256), 0, s, M, N, gz, ws, beta, C,
                      ldc);
   RPF_LAUNCH_CHECK();
 }
@@ -272,12 +268,18 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t N, int a, int b, c
   const int i = i0 + (lane & 15), j = j0 + (lane & 15);
   const bool iok = i < a, jok = j < b;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t r0 = r_beg + 4 * wave; r0 < r_end; r0 += 16) {
-    const int64_t row = r0 + (lane >> 4);
-    const bool rok = row < r_end;
-    const double xa = (rok && iok) ? X[row * ldx + i] : 0.0;
-    const double yb = (rok && jok) ? Y[row * ldy + j] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, acc, 0, 0, 0);
+  // four row groups in flight per wave (loads issued before the MFMAs consume them)
+  for (int64_t r0 = r_beg + 4 * wave; r0 < r_end; r0 += 64) {
+    double xa[4], yb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + 16 * u + (lane >> 4);
+      const bool rok = row < r_end;
+      xa[u] = (rok && iok) ? X[row * ldx + i] : 0.0;
+      yb[u] = (rok && jok) ? Y[row * ldy + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], yb[u], acc, 0, 0, 0);
   }
   // accumulator item r of lane l is C[i0 + l/16 + 4r][j0 + l%16]
 #pragma unroll
@@ -290,9 +292,10 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t N, int a, int b, c
 }
 
 int gram_chunks(int64_t N, int a, int b) {
+  // about one workgroup per CU in total, at least 256 rows per chunk
   const int64_t tiles = cdiv(a, 16) * cdiv(b, 16);
-  int64_t g = cdiv(1024, tiles);
-  g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(N, 64)));
+  int64_t g = cdiv(256, tiles);
+  g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(N, 256)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
 }
 
@@ -307,7 +310,7 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
   hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)tiles, (unsigned)gz), dim3(256), 0, s, N, a, b, X, ldx, Y, ldy,
                      chunk, ws);
   RPF_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * b, 32)), dim3(256), 0, s, (int64_t)a,
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * b, 4)), dim3(256), 0, s, (int64_t)a,
                      (int64_t)b, gz, ws, 0.0, C, (int64_t)a);
   RPF_LAUNCH_CHECK();
 }
@@ -320,7 +323,7 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
 // outputs 4q..4q+3 of row r.  Used for the block updates of the interface
 // solver (rows = interface dofs, row-major blocks).
 __global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, double alpha, const double* X,
-                                                   int64_t ldx, const double* Mm, double beta, double* Y,
+                                                   int64_t ldx, const double* Mm, int64_t mrow, double beta, double* Y,
                                                    int64_t ldy) {
   __shared__ double sx[64][33];
   __shared__ double sm[32][16];
@@ -343,7 +346,10 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, doub
       for (int e = 0; e < 2; ++e) {
         const int idx = tid + 256 * e;
         const int ii = idx & 31, jj = idx >> 5;
-        sm[ii][jj] = (i0 + ii < a && j0 + jj < b) ? Mm[(int64_t)(i0 + ii) + (int64_t)a * (j0 + jj)] : 0.0;
+        sm[ii][jj] = (i0 + ii < a && j0 + jj < b)
+                         ? (mrow > 0 ? Mm[(int64_t)(i0 + ii) * mrow + (j0 + jj)]
+                                     : Mm[(int64_t)(i0 + ii) + (int64_t)a * (j0 + jj)])
+                         : 0.0;
       }
       __syncthreads();
 #pragma unroll 8
@@ -367,10 +373,10 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, doub
 }
 
 void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* Mm,
-               double beta, double* Y, int64_t ldy) {
+               double beta, double* Y, int64_t ldy, int64_t mrow) {
   if (N <= 0 || b <= 0) return;
-  hipLaunchKernelGGL(k_rows_gemm, dim3((unsigned)cdiv(N, 64)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, beta, Y,
-                     ldy);
+  hipLaunchKernelGGL(k_rows_gemm, dim3((unsigned)cdiv(N, 64)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, mrow, beta,
+                     Y, ldy);
   RPF_LAUNCH_CHECK();
 }
 
@@ -600,9 +606,10 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
   __shared__ int nrot;
   __shared__ double floor_abs;
   __syncthreads();
-  // threshold Jacobi: a pair is rotated only while |a_pq| > 1e-15 sqrt(|a_pp a_qq|) (high
-  // relative accuracy) and |a_pq| > 1e-17 max_i |a_ii| (below that a rotation only moves
-  // rounding noise); the sweeps stop once a whole sweep rotates nothing
+  // threshold Jacobi: a pair is rotated only while |a_pq| > 1e-13 sqrt(|a_pp a_qq|) (relative
+  // accuracy of the eigenvalues to about 1e-13, ample for eta^{-1/2}) and |a_pq| > 1e-17
+  // max_i |a_ii| (below that a rotation only moves rounding noise); the sweeps stop once a
+  // whole sweep rotates nothing
   for (int sweep = 0; sweep < 30 && m >= 2; ++sweep) {
     if (tid == 0) {
       nrot = 0;
@@ -626,7 +633,7 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
         double c = 1.0, sn = 0.0;
         if (q < m) {
           const double apq = a[p][q];
-          if (fabs(apq) > 1e-15 * sqrt(fabs(a[p][p] * a[q][q])) && fabs(apq) > floor_abs) {
+          if (fabs(apq) > 1e-13 * sqrt(fabs(a[p][p] * a[q][q])) && fabs(apq) > floor_abs) {
             atomicAdd(&nrot, 1);
             const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
             const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));

@@ -608,7 +608,8 @@ void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s)
   pb->ybuf.ensure((size_t)nG * m);
   coarse_gt(pb, x, ldx, m, pb->cbuf.p, s);
   // y^T (m x nG, ld m) = c^T Ginv (Ginv symmetric)
-  dgemm(s, false, false, m, nG, nG, 1.0, pb->cbuf.p, m, pb->Ginv.p, nG, 0.0, pb->ybuf.p, m);
+  // y = (G^T G)^{-1} c, both n_G x m row-major (the inverse is symmetric)
+  rows_gemm(s, nG, nG, m, 1.0, pb->Ginv.p, nG, pb->cbuf.p, 0.0, pb->ybuf.p, m, m);
   coarse_g(pb, pb->ybuf.p, m, -1.0, x, ldx, 1.0, s);
 }
 

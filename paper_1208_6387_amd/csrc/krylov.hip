@@ -439,7 +439,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
         RPF_HIP(hipStreamSynchronize(s));
       }
       // lambda_0 = G (G^T G)^{-1} e
-      dgemm(s, false, false, nr, nG, nG, 1.0, e.p, nr, pb->Ginv.p, nG, 0.0, yc.p, nr);
+      rows_gemm(s, nG, nG, nr, 1.0, pb->Ginv.p, nG, e.p, 0.0, yc.p, nr, nr);
       coarse_g(pb, yc.p, nr, 1.0, S.lam.p, nr, 0.0, s);
     } else {
       fill(s, S.lam.p, N * nr, 0.0);
@@ -462,7 +462,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     const bool mixed = prec != RPF_FP64;
     const double inner_tol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
     const int max_sweeps = mixed ? (opts->max_sweeps > 0 ? opts->max_sweeps : 30) : 1;
-    S.alloc_store(std::min(opts->max_it, 2000) + 1);
+    S.alloc_store(opts->max_blocks > 0 ? opts->max_blocks : std::min(opts->max_it, 2000) + 1);
     bool converged = false;
     int sweeps = 0;
     std::vector<double> rn = S.r0n;
@@ -520,7 +520,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
       hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, -1.0, S.d.p, 1.0, S.tmp.p);
       RPF_LAUNCH_CHECK();
       coarse_gt(pb, S.tmp.p, nr, nr, ca.p, s);
-      dgemm(s, false, false, nr, nG, nG, 1.0, ca.p, nr, pb->Ginv.p, nG, 0.0, aa.p, nr);
+      rows_gemm(s, nG, nG, nr, 1.0, pb->Ginv.p, nG, ca.p, 0.0, aa.p, nr, nr);
     }
     for (int p = 0; p < pb->n_pat; ++p) {
       const rpf_pattern P = pats[p];
