@@ -291,10 +291,57 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t N, int a, int b, c
     part[((int64_t)blockIdx.y * b + cj) * a + ci] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
 }
 
+// Wide form (X with many columns, e.g. all stored search directions): a workgroup
+// covers 16 column tiles of X (4 per wave) against one 16-column tile of Y over
+// a chunk of rows; each Y fragment is loaded once and feeds 4 MFMAs, so Y is
+// re-read cdiv(a, 256) times instead of cdiv(a, 16).  No cross-wave reduction:
+// every wave owns its tiles.
+__global__ __launch_bounds__(256) void k_gram_wide(int64_t N, int a, int b, const double* X, int64_t ldx,
+                                                   const double* Y, int64_t ldy, int64_t chunk, double* part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ta = (a + 15) / 16, ga = (ta + 15) / 16;
+  const int grp = blockIdx.x % ga, tj = blockIdx.x / ga;
+  const int j = tj * 16 + (lane & 15);
+  const bool jok = j < b;
+  const int tbase = grp * 16 + wave * 4;
+  const int64_t r_beg = (int64_t)blockIdx.y * chunk;
+  const int64_t r_end = min(N, r_beg + chunk);
+  v4d acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int64_t r0 = r_beg; r0 < r_end; r0 += 8) {
+    double yb[2], xa[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t row = r0 + 4 * u + (lane >> 4);
+      const bool rok = row < r_end;
+      yb[u] = (rok && jok) ? Y[row * ldy + j] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = (tbase + t) * 16 + (lane & 15);
+        xa[u][t] = (rok && i < a) ? X[row * ldx + i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][t], yb[u], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ci = (tbase + t) * 16 + (lane >> 4) + 4 * r, cj = tj * 16 + (lane & 15);
+      if (ci < a && cj < b) part[((int64_t)blockIdx.y * b + cj) * a + ci] = acc[t][r];
+    }
+}
+
+static bool gram_is_wide(int a) { return a > 64; }
+
 int gram_chunks(int64_t N, int a, int b) {
-  // about one workgroup per CU in total, at least 256 rows per chunk
-  const int64_t tiles = cdiv(a, 16) * cdiv(b, 16);
-  int64_t g = cdiv(256, tiles);
+  // about one to two workgroups per CU in total, at least 256 rows per chunk
+  const int64_t tiles = gram_is_wide(a) ? cdiv(cdiv(a, 16), 16) * cdiv(b, 16) : cdiv(a, 16) * cdiv(b, 16);
+  int64_t g = cdiv(gram_is_wide(a) ? 512 : 256, tiles);
   g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(N, 256)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
 }
@@ -305,10 +352,16 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
   const int g = gram_chunks(N, a, b);
   const int64_t chunk = cdiv(N, g);
   const int gz = (int)cdiv(N, chunk);
-  const int64_t tiles = cdiv(a, 16) * cdiv(b, 16);
   RPF_CHECK(gz <= 65535, RPF_EINVAL, "gram: too many chunks");
-  hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)tiles, (unsigned)gz), dim3(256), 0, s, N, a, b, X, ldx, Y, ldy,
-                     chunk, ws);
+  if (gram_is_wide(a)) {
+    const int64_t groups = cdiv(cdiv(a, 16), 16) * cdiv(b, 16);
+    hipLaunchKernelGGL(k_gram_wide, dim3((unsigned)groups, (unsigned)gz), dim3(256), 0, s, N, a, b, X, ldx, Y, ldy,
+                       chunk, ws);
+  } else {
+    const int64_t tiles = cdiv(a, 16) * cdiv(b, 16);
+    hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)tiles, (unsigned)gz), dim3(256), 0, s, N, a, b, X, ldx, Y,
+                       ldy, chunk, ws);
+  }
   RPF_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * b, 4)), dim3(256), 0, s, (int64_t)a,
                      (int64_t)b, gz, ws, 0.0, C, (int64_t)a);

@@ -351,7 +351,8 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     ld[p] = cdiv(nb, 8) * 8;
     const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
     off[p + 1] = off[p] + ld[p] * cols;
-    const int64_t tiles = std::max<int64_t>(1, cdiv(nb, 64) * cdiv(cols, 64));
+    const int T = (split && nb >= 128 && cols >= 128) ? 128 : 64;  // bf16 tile edge (64x64 per wave at 128)
+    const int64_t tiles = std::max<int64_t>(1, cdiv(nb, T) * cdiv(cols, T));
     int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, ld[p] / 256));
     sp = std::min(sp, 8);
     kch[p] = (int)(cdiv(cdiv(ld[p], sp), 64) * 64);
@@ -406,13 +407,18 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     void* tok = trace_begin(s);
     if (split) {
       RPF_CHECK(P->ldlp == ld[p], RPF_EINVAL, "low-precision S+ layout mismatch");
-      dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64), (unsigned)nsp[p]);
-      if (prec == RPF_BF16X3)
-        hipLaunchKernelGGL((k_gemm_bf16<64, 64, true>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p,
-                           P->Sp_lo.p, ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab);
-      else
-        hipLaunchKernelGGL((k_gemm_bf16<64, 64, false>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p,
-                           P->Sp_lo.p, ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab);
+      const bool big = nb >= 128 && cols >= 128;
+      const int T = big ? 128 : 64;
+      dim3 g2((unsigned)cdiv(nb, T), (unsigned)cdiv(cols, T), (unsigned)nsp[p]);
+#define RPF_BF(BMN, X3)                                                                                          \
+  hipLaunchKernelGGL((k_gemm_bf16<BMN, BMN, X3>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p, P->Sp_lo.p, \
+                     ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab)
+      if (prec == RPF_BF16X3) {
+        if (big) RPF_BF(128, true); else RPF_BF(64, true);
+      } else {
+        if (big) RPF_BF(128, false); else RPF_BF(64, false);
+      }
+#undef RPF_BF
     } else {
       dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64), (unsigned)nsp[p]);
       hipLaunchKernelGGL((k_sgemm_sym<64, 64>), g2, dim3(256), 0, s, nb, cols, nb, P->Splus32.p, (int64_t)nb,
