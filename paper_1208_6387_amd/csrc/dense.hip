@@ -660,15 +660,16 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
   __shared__ double floor_abs;
   __syncthreads();
   // threshold Jacobi: a pair is rotated only while |a_pq| > 1e-13 sqrt(|a_pp a_qq|) (relative
-  // accuracy of the eigenvalues to about 1e-13, ample for eta^{-1/2}) and |a_pq| > 1e-17
-  // max_i |a_ii| (below that a rotation only moves rounding noise); the sweeps stop once a
-  // whole sweep rotates nothing
+  // accuracy of the eigenvalues to about 1e-13, ample for eta^{-1/2}) and |a_pq| > 1e-15
+  // max_i |a_ii| (eigenvalues below 1e-12 of the largest are dropped by the caller, and
+  // below this floor a rotation only moves rounding noise); the sweeps stop once a whole
+  // sweep rotates nothing
   for (int sweep = 0; sweep < 30 && m >= 2; ++sweep) {
     if (tid == 0) {
       nrot = 0;
       double d = 0.0;
       for (int i = 0; i < m; ++i) d = fmax(d, fabs(a[i][i]));
-      floor_abs = fmax(1e-17 * d, 1e-300);
+      floor_abs = fmax(1e-15 * d, 1e-300);
     }
     __syncthreads();
     for (int step = 0; step < me - 1; ++step) {

@@ -129,82 +129,63 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Partial sums of (Z^T A^(s)T x)[r][j]: workgroup (s, sp) covers the boundary
-// nodes [256 sp, 256 sp + 256) of occurrence s; part[((s*nsplit + sp)*KMAX + r)*m + j].
+// dofs [dper sp, dper (sp+1)) of occurrence s.  The contraction over dofs runs on
+// v_mfma_f64_16x16x4_f64: lane l gathers x_loc[d][j] = (A^(s)T x)[d][j] for dof
+// d = d0 + l/16 and column j = j0 + l%16 (sum over the multipliers at the node,
+// rotated to the pattern frame) and loads Z[d][l%16]; the accumulator then holds
+// (modes x columns).  part[((s*nsplit + sp)*KMAX + r)*m + j].
 template <int DPN>
 __global__ __launch_bounds__(256) void k_coarse_gt(const int* occ_pat, const int* slot_off, const int* nbn_p,
                                                    const double* const* Zp, const int* kp, const int* goff,
                                                    const int* l2m_ptr, const int* l2m_code, const double* rot,
                                                    const double* x, int64_t ldx, int m, int nsplit, double* part) {
-  __shared__ double red[4][KMAX * JB];
+  __shared__ double red[4][256];
   const int s = blockIdx.x, sp = blockIdx.y;
   const int p = occ_pat[s];
-  const int k = kp[p], nbn = min(nbn_p[p], 256 * (sp + 1));
+  const int k = kp[p];
+  const int nd = nbn_p[p] * DPN;
+  const int dper = ((nd + nsplit - 1) / nsplit + 15) / 16 * 16;
+  const int d_beg = sp * dper, d_end = min(nd, d_beg + dper);
   const double* Z = Zp[p];
-  const int64_t ldz = (int64_t)nbn_p[p] * DPN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15;
   double O[9];
   if (DPN == 3) load_rot<DPN>(rot, s, O);
-  for (int j0 = 0; j0 < m; j0 += JB) {
-    const int jn = min(JB, m - j0);
-    double acc[KMAX][JB];
-#pragma unroll
-    for (int r = 0; r < KMAX; ++r)
-#pragma unroll
-      for (int j = 0; j < JB; ++j) acc[r][j] = 0.0;
-    for (int bn = 256 * sp + tid; bn < nbn; bn += 256) {
-      const int slot = slot_off[s] + bn;
-      double g[DPN][JB];
-#pragma unroll
-      for (int cc = 0; cc < DPN; ++cc)
-#pragma unroll
-        for (int j = 0; j < JB; ++j) g[cc][j] = 0.0;
-      for (int e = l2m_ptr[slot]; e < l2m_ptr[slot + 1]; ++e) {
-        const int code = l2m_code[e];
-        const double sg = (code & 1) ? -1.0 : 1.0;
-        const int64_t mult = code >> 1;
-#pragma unroll
-        for (int cc = 0; cc < DPN; ++cc) {
-          const double* row = x + (mult * DPN + cc) * ldx + j0;
-#pragma unroll
-          for (int j = 0; j < JB; ++j)
-            if (j < jn) g[cc][j] += sg * row[j];
+  for (int j0 = 0; j0 < m; j0 += 16) {
+    const int j = j0 + (lane & 15);
+    const bool jok = j < m;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int d0 = d_beg + 4 * wave; d0 < d_end; d0 += 16) {
+      const int d = d0 + (lane >> 4);
+      const bool dok = d < d_end;
+      double xv = 0.0;
+      if (dok && jok) {
+        const int bn = d / DPN, c2 = d % DPN;
+        const int slot = slot_off[s] + bn;
+        for (int e = l2m_ptr[slot]; e < l2m_ptr[slot + 1]; ++e) {
+          const int code = l2m_code[e];
+          const double sg = (code & 1) ? -1.0 : 1.0;
+          const int64_t mult = code >> 1;
+          if (DPN == 3) {
+            const double* xr = x + mult * 3 * ldx + j;
+            xv += sg * (O[c2] * xr[0] + O[3 + c2] * xr[ldx] + O[6 + c2] * xr[2 * ldx]);
+          } else {
+            xv += sg * x[(mult * DPN + c2) * ldx + j];
+          }
         }
       }
-      double xl[DPN][JB];
-#pragma unroll
-      for (int j = 0; j < JB; ++j) {
-        if (DPN == 3) {
-#pragma unroll
-          for (int c2 = 0; c2 < 3; ++c2)
-            xl[c2 % DPN][j] = O[c2] * g[0][j] + O[3 + c2] * g[1 % DPN][j] + O[6 + c2] * g[2 % DPN][j];
-        } else {
-#pragma unroll
-          for (int cc = 0; cc < DPN; ++cc) xl[cc][j] = g[cc][j];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < KMAX; ++r) {
-        if (r >= k) break;
-#pragma unroll
-        for (int cc = 0; cc < DPN; ++cc) {
-          const double z = Z[r * ldz + (int64_t)bn * DPN + cc];
-#pragma unroll
-          for (int j = 0; j < JB; ++j) acc[r][j] += z * xl[cc][j];
-        }
-      }
+      const double zv = (dok && r < k) ? Z[(int64_t)r * nd + d] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, xv, acc, 0, 0, 0);
     }
+    // accumulator item q of lane l: mode l/16 + 4q, column j0 + l%16
 #pragma unroll
-    for (int r = 0; r < KMAX; ++r)
-#pragma unroll
-      for (int j = 0; j < JB; ++j) {
-        const double v = wave_sum(acc[r][j]);
-        if (lane == 0) red[wave][r * JB + j] = v;
-      }
+    for (int q = 0; q < 4; ++q) red[wave][((lane >> 4) + 4 * q) * 16 + (lane & 15)] = acc[q];
     __syncthreads();
-    if (tid < KMAX * JB) {
-      const int r = tid / JB, j = tid % JB;
-      if (r < k && j < jn)
-        part[(((int64_t)s * nsplit + sp) * KMAX + r) * m + j0 + j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    {
+      const int mi = tid / 16, jj = tid % 16;
+      if (mi < k && j0 + jj < m)
+        part[(((int64_t)s * nsplit + sp) * KMAX + mi) * m + j0 + jj] =
+            red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
     }
     __syncthreads();
   }
@@ -564,8 +545,10 @@ void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
 }
 
 void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, hipStream_t s) {
-  const int max_nbn = *std::max_element(pb->pat_nbn.begin(), pb->pat_nbn.end());
-  const int nsplit = (int)std::max<int64_t>(1, cdiv(max_nbn, 256));
+  // dof slices per occurrence: about 1024 workgroups in all, at least 256 dofs per slice
+  const int max_nd = *std::max_element(pb->pat_nbn.begin(), pb->pat_nbn.end()) * pb->dpn;
+  const int nsplit = (int)std::max<int64_t>(
+      1, std::min<int64_t>(cdiv(1024, pb->n_occ), cdiv(max_nd, 256)));
   pb->cpart.ensure((size_t)pb->n_occ * nsplit * KMAX * m);
 #define RPF_CGT(D)                                                                                             \
   hipLaunchKernelGGL(k_coarse_gt<D>, dim3(pb->n_occ, nsplit), dim3(256), 0, s, pb->d_occ_pat.p, pb->d_slot_off.p, \

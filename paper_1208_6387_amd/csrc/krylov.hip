@@ -22,15 +22,17 @@ constexpr double ETA_DROP = 1e-12;
 
 // ---------------------------------------------------------------------------- kernels
 // Zb[l*m + r*np + k] = z[src*nr + r], src = perm[k][mult]*dpn + c  (section 3.1 multivector)
+// one thread per output entry (consecutive threads write consecutive entries of a row)
 __global__ void k_permute(int64_t n_lambda, int dpn, int n_mult, int nr, int np, const int* perm, const double* z,
                           int64_t ldz, double* Zb, int64_t ldb) {
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= n_lambda) return;
+  const int m = nr * np;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_lambda * m) return;
+  const int64_t l = idx / m;
+  const int col = (int)(idx % m), r = col / np, k = col % np;
   const int64_t mult = l / dpn, c = l % dpn;
-  for (int k = 0; k < np; ++k) {
-    const int64_t src = (perm ? (int64_t)perm[(int64_t)k * n_mult + mult] : mult) * dpn + c;
-    for (int r = 0; r < nr; ++r) Zb[l * ldb + r * np + k] = z[src * ldz + r];
-  }
+  const int64_t src = (perm ? (int64_t)perm[(int64_t)k * n_mult + mult] : mult) * dpn + c;
+  Zb[l * ldb + col] = z[src * ldz + r];
 }
 
 // T = V diag(w_i^{-1/2}) keeping w_i > drop * w_max (eigen form), or
@@ -290,7 +292,7 @@ struct Solver {
     int pending = -1, nchk = 0;
     for (int it = 0; it < max_it; ++it) {
       // multivector from the residual (Q R = R: the residual stays in range Q), re-projected
-      hipLaunchKernelGGL(k_permute, dim3(nblocks(N)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
+      hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
                          np > 1 ? pb->d_perm.p : (const int*)nullptr, Rs.p, (int64_t)nr, Zb.p, (int64_t)m);
       RPF_LAUNCH_CHECK();
       if (np > 1) project(pb, Zb.p, m, m, s);
