@@ -118,7 +118,10 @@ void pattern_free(rpf_pattern p);
  * occ_rot: 9 doubles per occurrence, row-major rotation from the pattern
  * frame to the global frame (used when dofs_per_node == 3), or NULL for
  * identity.  perm_node: n_perm x n_mult, (Pi_k z)[mult] = z[perm_node[k*n_mult+mult]]
- * applied to every component, or NULL with n_perm == 1 (identity). */
+ * applied to every component (and, with rotations, turned into the frame of
+ * the target multiplier, see feti_permute), or NULL with n_perm == 1
+ * (identity).  The solver's multivector is [Pi_0 r, .., Pi_{n_perm-1} r]
+ * (section 3.1), so row 0 is normally the identity. */
 typedef struct {
   int32_t dofs_per_node;
   int32_t n_patterns;
@@ -138,6 +141,7 @@ typedef struct {
 
 rpf_status problem_create(const rpf_problem_desc* desc, rpf_problem* out);
 int64_t problem_n_lambda(rpf_problem pb);
+int32_t problem_n_perm(rpf_problem pb);  /* permutations of the structure (1: none) */
 void problem_free(rpf_problem pb);
 
 /* ------------------------------------------------------------------ operator */
@@ -156,6 +160,20 @@ void problem_free(rpf_problem pb);
 rpf_status feti_apply(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X, int64_t ldx,
                       double* Y, int64_t ldy, int32_t prec, uint32_t flags, void* stream);
 
+/* Permuted multivector (section 3.1): W[:, l*n_perm + k] = Pi_k z_l for the
+ * nr columns of Z and the structure's n_perm permutations (the rows of
+ * perm_node; a structure created without permutations has n_perm = 1 and
+ * Pi_0 = identity).  With rotated
+ * occurrences each moved multiplier is turned into the frame of its new
+ * place, O_t O_s^T z (O_t, O_s: rotations of the first-endpoint occurrences
+ * of the target and source multipliers; section 5.2).  With
+ * RPF_APPLY_PROJECT, W <- Q W (the re-projection of the solver; needs the
+ * patterns, else patterns may be NULL).  Z: device, N_lambda x nr row-major
+ * (ldz >= nr); W: device, N_lambda x (nr*n_perm) row-major
+ * (ldw >= nr*n_perm); must not overlap.  Asynchronous.  Errors: RPF_EINVAL. */
+rpf_status feti_permute(rpf_problem pb, const rpf_pattern* patterns, int32_t nr, const double* Z, int64_t ldz,
+                        double* W, int64_t ldw, uint32_t flags, void* stream);
+
 /* ------------------------------------------------------------------ solver */
 
 typedef enum {
@@ -170,7 +188,9 @@ typedef struct {
   int32_t method;      /* rpf_method */
   int32_t prec;        /* rpf_prec of the inner operator */
   double inner_tol;    /* relative reduction per refinement sweep (mixed forms; 0: 1e-4) */
-  int32_t max_sweeps;  /* refinement sweeps (mixed forms; 0: 30) */
+  int32_t max_sweeps;  /* sweeps, each restarting from the FP64 residual of the current iterate
+                          (0: 30 for the mixed forms, 4 for FP64, where a further sweep only runs
+                          when the recursive residual met tol and the recomputed one did not) */
   int32_t check_every; /* read the convergence flag every k iterations (0: 1) */
   int32_t max_blocks;  /* ORTHODIR: stored (W, P) blocks before a restart (0: as many as max_it and
                           half of the free device memory allow) */

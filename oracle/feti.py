@@ -29,7 +29,8 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 KERNEL_TAU = 1e-10      # READING: eigenvalues below tau * lambda_max(S) span the kernel
-ETA_DROP = 1e-12        # READING: eigenvalues of eta below this * max are dropped (section 4.3)
+ETA_DROP = 1e-12        # READING: eigenvalues of eta below this * (energy of the block before
+                        # orthogonalisation) are dropped (section 4.3)
 
 
 # =========================================================================== pattern level
@@ -230,14 +231,28 @@ class FetiOracle:
     def permute(self, z: np.ndarray) -> np.ndarray:
         """Multivector [Pi_0 z, .., Pi_{np-1} z] for every column of z (section 3.1, eq. for w~).
 
-        Columns are ordered (load case, permutation): column l*np + k = Pi_k z_l.
+        Columns are ordered (load case, permutation): column l*np + k = Pi_k z_l.  With rotated
+        occurrences the permuted values are carried into the frame of their new place (section 5.2):
+        READING: the value taken from multiplier m' for multiplier m is O^(a(m)) O^(a(m'))^T z[m'],
+        a(.) the occurrence of the first endpoint, so the field seen from the pattern frame is moved.
         """
-        P = self.pb.perm_dof()
-        nr = z.shape[1]
-        out = np.empty((z.shape[0], nr * P.shape[0]))
-        for l in range(nr):
-            for k in range(P.shape[0]):
-                out[:, l * P.shape[0] + k] = z[P[k], l]
+        pb = self.pb
+        Pn = pb.perm_node
+        nr, dpn, nm = z.shape[1], pb.dpn, pb.n_mult_nodes
+        np_ = Pn.shape[0]
+        out = np.empty((z.shape[0], nr * np_))
+        zn = z.reshape(nm, dpn, nr)
+        rotate = dpn == 3 and pb.has_rotation
+        for k in range(np_):
+            src = Pn[k]
+            moved = zn[src]                                    # (nm, dpn, nr)
+            if rotate:
+                Ot = pb.occ_rot[pb.mult_occ[:, 0]]             # frame of the target's first endpoint
+                Os = pb.occ_rot[pb.mult_occ[src, 0]]           # frame of the source's first endpoint
+                Rk = np.einsum("mab,mcb->mac", Ot, Os)         # O_t O_s^T
+                moved = np.einsum("mab,mbr->mar", Rk, moved)
+            for l in range(nr):
+                out[:, l * np_ + k] = moved[:, :, l].reshape(-1)
         return out
 
     # -- solvers (Table 1) ----------------------------------------------------------------
@@ -281,7 +296,12 @@ class FetiOracle:
 
         full_reorth=True: every new block is F-orthogonalised against all stored blocks and
         F-normalised, W <- W eta^{-1/2}, P <- P eta^{-1/2} with eta = P^T W (section 4.3);
-        eigenvalues of eta below ETA_DROP * max are dropped (pseudo-inverse, section 4.3).
+        eigenvalues of eta below ETA_DROP * e are dropped (pseudo-inverse, section 4.3).
+        READING of the scale e: the largest F-energy z^T F z of a column of the block before
+        the orthogonalisation (with F-orthonormal stored blocks it is |P_i^T z|^2 summed over
+        the stored blocks plus the diagonal of eta), and at least the largest eigenvalue of
+        eta; a direction is dropped when almost none of its energy is new, which also ends
+        the iteration once the stored blocks span the whole space.
         full_reorth=False: the short recurrence of Table 1 (beta against the previous block),
         with a pseudo-inverse of W^T P.
         Stopping (READING): max over load cases of ||r_c|| / ||r0_c|| <= tol.
@@ -299,13 +319,17 @@ class FetiOracle:
         j = 0
         while np.max(np.linalg.norm(r, axis=0) / r0) > tol and j < max_it:
             if full_reorth:
+                e_pre = np.zeros(Zb.shape[1])
                 for Wi, Pi in zip(Ws, Ps):
-                    Zb = Zb - Wi @ (Pi.T @ Zb)
+                    B = Pi.T @ Zb
+                    e_pre += (B * B).sum(axis=0)
+                    Zb = Zb - Wi @ B
                 Pb = self.Q(self.F(Zb))
                 eta = Zb.T @ Pb
                 eta = 0.5 * (eta + eta.T)
                 ev, V = np.linalg.eigh(eta)
-                keep = ev > ETA_DROP * max(ev.max(), 0.0)
+                e_pre += np.diag(eta)
+                keep = ev > ETA_DROP * max(ev.max(), e_pre.max(), 0.0)
                 drops += int((~keep).sum())
                 if not keep.any():
                     break

@@ -19,7 +19,7 @@ from ._lib import (APPLY_PROJECT, BF16, BF16X3, BLOCK_CG, CLASSICAL, FP32, FP64,
                    check, load)
 
 __all__ = ["Pattern", "Problem", "pattern_factor", "pattern_condense", "pattern_export", "problem_create",
-           "feti_apply", "block_krylov_solve", "dgemm", "dposv", "dsyev_small", "load", "RpfError",
+           "feti_apply", "feti_permute", "block_krylov_solve", "dgemm", "dposv", "dsyev_small", "load", "RpfError",
            "FP64", "FP32", "BF16X3", "BF16", "CLASSICAL", "BLOCK_CG", "ORTHODIR", "APPLY_PROJECT"]
 
 
@@ -64,6 +64,7 @@ class Problem:
     def __init__(self, handle: C.c_void_p):
         self.handle = handle
         self.n_lambda = int(load().problem_n_lambda(handle))
+        self.n_perm = int(load().problem_n_perm(handle))
 
     def free(self):
         if self.handle:
@@ -144,6 +145,22 @@ def feti_apply(pb: Problem, patterns, X: torch.Tensor, prec: int = FP64, project
     check(load().feti_apply(pb.handle, _handles(patterns), m, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), prec,
                             APPLY_PROJECT if project else 0, _stream(stream)))
     return Y
+
+
+def feti_permute(pb: Problem, Z: torch.Tensor, patterns=None, project: bool = False,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """[Pi_0 z_l, .., Pi_{n_perm-1} z_l] for every column l of a row-major N_lambda x nr block
+    (column l*n_perm + k), optionally re-projected by Q (then the patterns are needed)."""
+    assert Z.is_cuda and Z.dtype == torch.float64 and Z.dim() == 2 and Z.shape[0] == pb.n_lambda
+    assert Z.stride(1) == 1
+    nr = Z.shape[1]
+    W = out if out is not None else torch.empty((pb.n_lambda, nr * pb.n_perm), dtype=torch.float64,
+                                                device=Z.device)
+    assert W.stride(1) == 1 and W.shape[1] >= nr * pb.n_perm
+    hs = _handles(patterns) if patterns is not None else None
+    check(load().feti_permute(pb.handle, hs, nr, _ptr(Z), Z.stride(0), _ptr(W), W.stride(0),
+                              APPLY_PROJECT if project else 0, _stream(stream)))
+    return W
 
 
 @dataclass

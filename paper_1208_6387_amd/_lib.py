@@ -16,7 +16,8 @@ APPLY_PROJECT = 1
 
 # every symbol the header declares
 EXPORTS = ["rpf_last_error", "rpf_version", "pattern_factor", "pattern_condense", "pattern_info", "pattern_export",
-           "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "feti_apply", "block_krylov_solve",
+           "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "problem_n_perm", "feti_apply", "feti_permute",
+           "block_krylov_solve",
            "rpf_dgemm", "rpf_dposv", "rpf_dsyev_small", "rpf_trace_enable", "rpf_trace_read"]
 
 
@@ -66,7 +67,9 @@ def load() -> C.CDLL:
         "problem_create": (i32, [C.POINTER(ProblemDesc), C.POINTER(vp)]),
         "problem_n_lambda": (i64, [vp]),
         "problem_free": (None, [vp]),
+        "problem_n_perm": (i32, [vp]),
         "feti_apply": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, C.c_uint32, vp]),
+        "feti_permute": (i32, [vp, vp, i32, vp, i64, vp, i64, C.c_uint32, vp]),
         "block_krylov_solve": (i32, [vp, vp, i32, vp, C.POINTER(SolveOpts), vp, i64, vp, C.POINTER(SolveStats), vp]),
         "rpf_dgemm": (i32, [i32, i32, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64, vp]),
         "rpf_dposv": (i32, [i64, vp, i64, i64, vp, i64, vp]),

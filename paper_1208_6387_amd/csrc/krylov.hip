@@ -18,43 +18,97 @@
 namespace rpf {
 namespace {
 
+// A direction of a new block is dropped when its F-energy after the orthogonalisation is below
+// eta_drop(prec) times the block's energy before it (section 4.3: rank deficiency of eta).  The
+// ratio is limited by the accuracy of the product: noise of relative size eps leaves an energy
+// fraction of about eps^2, so the low-precision forms use larger thresholds.
 constexpr double ETA_DROP = 1e-12;
+inline double eta_drop(int prec) {
+  switch (prec) {
+    case RPF_FP32: return 1e-10;
+    case RPF_BF16X3: return 1e-8;
+    case RPF_BF16: return 1e-3;
+    default: return ETA_DROP;
+  }
+}
 
 // ---------------------------------------------------------------------------- kernels
 // Zb[l*m + r*np + k] = z[src*nr + r], src = perm[k][mult]*dpn + c  (section 3.1 multivector)
-// one thread per output entry (consecutive threads write consecutive entries of a row)
-__global__ void k_permute(int64_t n_lambda, int dpn, int n_mult, int nr, int np, const int* perm, const double* z,
-                          int64_t ldz, double* Zb, int64_t ldb) {
+// One thread per output entry (consecutive threads write consecutive entries of a row).
+// With rotated occurrences (dpn 3) the value moved from multiplier src to mult is
+// carried into the frame of its new place: O_t O_s^T z[src], O_t / O_s the rotations
+// of the first-endpoint occurrences of mult / src (section 5.2).
+__global__ void k_permute(int64_t n_lambda, int dpn, int n_mult, int nr, int np, const int* perm, const int* ep_occ,
+                          const double* rot, const double* z, int64_t ldz, double* Zb, int64_t ldb) {
   const int m = nr * np;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_lambda * m) return;
   const int64_t l = idx / m;
   const int col = (int)(idx % m), r = col / np, k = col % np;
   const int64_t mult = l / dpn, c = l % dpn;
-  const int64_t src = (perm ? (int64_t)perm[(int64_t)k * n_mult + mult] : mult) * dpn + c;
-  Zb[l * ldb + col] = z[src * ldz + r];
+  const int64_t sm = perm ? (int64_t)perm[(int64_t)k * n_mult + mult] : mult;
+  if (rot && dpn == 3 && sm != mult) {
+    const double* Ot = rot + 9 * (int64_t)ep_occ[2 * mult];
+    const double* Os = rot + 9 * (int64_t)ep_occ[2 * sm];
+    double v = 0.0;
+    for (int c2 = 0; c2 < 3; ++c2) {
+      const double Rcc = Ot[3 * c] * Os[3 * c2] + Ot[3 * c + 1] * Os[3 * c2 + 1] + Ot[3 * c + 2] * Os[3 * c2 + 2];
+      v += Rcc * z[(sm * 3 + c2) * ldz + r];
+    }
+    Zb[l * ldb + col] = v;
+  } else {
+    Zb[l * ldb + col] = z[(sm * dpn + c) * ldz + r];
+  }
 }
 
-// T = V diag(w_i^{-1/2}) keeping w_i > drop * w_max (eigen form), or
-// T = diag(eta_ii^{-1/2}) (diagonal form, classical CG per load case).
-__global__ void k_make_T(int m, const double* eta, const double* V, const double* w, int diag_only, double* T,
-                         int* drops) {
+// T = V diag(w_i^{-1/2}) over the kept eigenpairs of eta (eigen form), or T = diag(eta_ii^{-1/2})
+// (diagonal form, classical CG per load case).  The energy of column c before the orthogonalisation
+// is |B_c|^2 + eta_cc (B = P_stored^T Z, ka x m, ld ka; F-orthonormal stored blocks); an eigenpair is
+// kept when w_i > tau * max(w_max, max_c energy_c) (diagonal form: eta_cc > tau * energy_c).  When
+// nothing is kept, 1 is written to flag0 and flag1 (the stored blocks already span the space seen
+// by the product).  256 threads.
+__global__ __launch_bounds__(256) void k_make_T(int m, const double* eta, const double* V, const double* w,
+                                                int diag_only, int ka, const double* B, double tau, double* T,
+                                                int* drops, double* flag0, double* flag1) {
   __shared__ double scale[64];
-  __shared__ double wmax;
-  const int tid = threadIdx.x;
+  __shared__ double epre[64];
+  __shared__ double wmax, emax;
+  __shared__ int kept;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int c = wv; c < m; c += 4) {
+    double acc = 0.0;
+    for (int i = lane; i < ka; i += 64) {
+      const double b = B[(int64_t)c * ka + i];
+      acc += b * b;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) epre[c] = acc + eta[c * m + c];
+  }
+  __syncthreads();
   if (tid == 0) {
-    double mx = 0.0;
-    for (int i = 0; i < m; ++i) mx = fmax(mx, diag_only ? eta[i * m + i] : w[i]);
+    double mx = 0.0, me = 0.0;
+    for (int i = 0; i < m; ++i) {
+      mx = fmax(mx, diag_only ? eta[i * m + i] : w[i]);
+      me = fmax(me, epre[i]);
+    }
     wmax = mx;
+    emax = me;
+    kept = 0;
   }
   __syncthreads();
   if (tid < m) {
     const double wi = diag_only ? eta[tid * m + tid] : w[tid];
-    const bool keep = wi > ETA_DROP * wmax && wmax > 0.0;
+    const double ref = diag_only ? epre[tid] : fmax(wmax, emax);
+    const bool keep = wi > 0.0 && wi > tau * ref;
     scale[tid] = keep ? 1.0 / sqrt(wi) : 0.0;
-    if (!keep) atomicAdd(drops, 1);
+    if (keep) atomicAdd(&kept, 1);
+    else atomicAdd(drops, 1);
   }
   __syncthreads();
+  if (tid == 0 && kept == 0) {
+    flag0[0] = 1.0;
+    flag1[0] = 1.0;
+  }
   for (int i = tid; i < m * m; i += blockDim.x) {
     const int r = i % m, c = i / m;
     if (diag_only) T[i] = (r == c) ? scale[c] : 0.0;
@@ -215,32 +269,42 @@ struct Solver {
 
   // lagged convergence check: the norms of iteration i are copied to pinned memory and read
   // while iteration i+1 is already queued, so the host never drains the stream mid-solve
-  double* hnorm = nullptr;  // pinned, 2 slots of nr*nr
+  // Each slot holds the nr x nr Gram of the residual and, after it, the "exhausted" flag that
+  // k_make_T raises when a whole block was dropped.
+  double* hnorm = nullptr;  // pinned, 2 slots of nr*nr + 1
   hipEvent_t nev[2] = {nullptr, nullptr};
   DevBuf<double> nrm2[2];
+
+  size_t slot_len() const { return (size_t)nr * nr + 1; }
   void init_lag() {
     if (!hnorm) {
-      RPF_HIP(hipHostMalloc((void**)&hnorm, sizeof(double) * 2 * nr * nr, hipHostMallocDefault));
+      RPF_HIP(hipHostMalloc((void**)&hnorm, sizeof(double) * 2 * slot_len(), hipHostMallocDefault));
       RPF_HIP(hipEventCreateWithFlags(&nev[0], hipEventDisableTiming));
       RPF_HIP(hipEventCreateWithFlags(&nev[1], hipEventDisableTiming));
     }
+    for (int k = 0; k < 2; ++k) {
+      nrm2[k].ensure(slot_len());
+      fill(s, nrm2[k].p + (size_t)nr * nr, 1, 0.0);
+    }
   }
   void post_norms(const double* X, int slot) {
-    nrm2[slot].ensure((size_t)nr * nr);
     gram(X, nr, nr, X, nr, nr, nrm2[slot].p);
-    RPF_HIP(hipMemcpyAsync(hnorm + (size_t)slot * nr * nr, nrm2[slot].p, sizeof(double) * nr * nr,
+    RPF_HIP(hipMemcpyAsync(hnorm + (size_t)slot * slot_len(), nrm2[slot].p, sizeof(double) * slot_len(),
                            hipMemcpyDeviceToHost, s));
     RPF_HIP(hipEventRecord(nev[slot], s));
   }
-  bool read_norms(int slot, const std::vector<double>& target) {
+  enum Check { GOING = 0, CONVERGED = 1, EXHAUSTED = 2 };
+  Check read_norms(int slot, const std::vector<double>& target) {
     RPF_HIP(hipEventSynchronize(nev[slot]));
+    const double* h = hnorm + (size_t)slot * slot_len();
     bool ok = true;
     for (int c = 0; c < nr; ++c) {
-      const double v = hnorm[(size_t)slot * nr * nr + (size_t)c * nr + c];
+      const double v = h[(size_t)c * nr + c];
       RPF_CHECK(std::isfinite(v), RPF_EBREAKDOWN, "block_krylov_solve: residual is not finite");
       ok &= !(v > target[c]);
     }
-    return ok;
+    if (ok) return CONVERGED;
+    return h[(size_t)nr * nr] != 0.0 ? EXHAUSTED : GOING;
   }
   ~Solver() {
     if (hnorm) (void)hipHostFree(hnorm);
@@ -280,27 +344,32 @@ struct Solver {
   }
 
   // One inner Krylov run on F_prec: starts from residual Rs (N x nr), accumulates
-  // the correction into dlam; stops when every column satisfies ||r_c||^2 <= target_c.
-  // Returns true when converged.
-  bool inner(int prec, const std::vector<double>& target, int max_it, int check_every) {
+  // the correction into dlam; stops when every column satisfies ||r_c||^2 <= target_c
+  // (CONVERGED), when a whole block was dropped (EXHAUSTED) or after max_it iterations.
+  Check inner(int prec, const std::vector<double>& target, int max_it, int check_every) {
     fill(s, dlam.p, N * nr, 0.0);
     int nst = 0;  // stored blocks
     const bool diag_only = (method == RPF_CLASSICAL);
     RPF_HIP(hipMemsetAsync(drops.p, 0, sizeof(int), s));
-    bool conv = false;
+    Check conv = GOING;
     init_lag();
+    const double tau = eta_drop(prec);
     int pending = -1, nchk = 0;
     for (int it = 0; it < max_it; ++it) {
       // multivector from the residual (Q R = R: the residual stays in range Q), re-projected
       hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
-                         np > 1 ? pb->d_perm.p : (const int*)nullptr, Rs.p, (int64_t)nr, Zb.p, (int64_t)m);
+                         np > 1 ? pb->d_perm.p : (const int*)nullptr, pb->d_ep_occ.p,
+                         pb->has_rot ? pb->d_rot.p : (const double*)nullptr, Rs.p, (int64_t)nr, Zb.p, (int64_t)m);
       RPF_LAUNCH_CHECK();
       if (np > 1) project(pb, Zb.p, m, m, s);
       // ORTHODIR: orthogonalise against every stored block (restart when the store is full);
       // block CG / classical: against the previous block only, two alternating slots
       int slot, first, nb;
       if (method == RPF_ORTHODIR) {
-        if (nst == max_blocks) nst = 0;
+        // restart when the store is full; in a low-precision run also once the stored blocks
+        // could span the whole interface space: past that point the new directions are made
+        // of the product's rounding error, which F-orthogonalisation cannot remove
+        if (nst == max_blocks || (prec != RPF_FP64 && (int64_t)(nst + 1) * m > N)) nst = 0;
         slot = nst;
         first = 0;
         nb = nst;
@@ -322,7 +391,8 @@ struct Solver {
       // eta = Zb^T P, T = eta^{-1/2} (pseudo-inverse on dropped directions)
       gram(Zb.p, m, m, Pb.p, m, m, eta.p);
       if (!diag_only) syev_small(s, eta.p, m, V.p, w.p, 1);
-      hipLaunchKernelGGL(k_make_T, dim3(1), dim3(64), 0, s, m, eta.p, V.p, w.p, diag_only ? 1 : 0, T.p, drops.p);
+      hipLaunchKernelGGL(k_make_T, dim3(1), dim3(256), 0, s, m, eta.p, V.p, w.p, diag_only ? 1 : 0, nb * m, Bt.p, tau,
+                         T.p, drops.p, nrm2[0].p + (size_t)nr * nr, nrm2[1].p + (size_t)nr * nr);
       RPF_LAUNCH_CHECK();
       // W_j = Zb T, P_j = P T into the store
       double* Wj = Wall.p + (int64_t)slot * m;
@@ -341,8 +411,7 @@ struct Solver {
         post_norms(Rs.p, slot_n);
         // the previous check is read now, while this iteration is already queued; when it
         // reports convergence the solve stops after this (extra, still valid) iteration
-        if (pending >= 0 && read_norms(pending, target)) {
-          conv = true;
+        if (pending >= 0 && (conv = read_norms(pending, target)) != GOING) {
           pending = -1;
           break;
         }
@@ -350,7 +419,7 @@ struct Solver {
         ++nchk;
       }
     }
-    if (!conv && pending >= 0) conv = read_norms(pending, target);
+    if (conv == GOING && pending >= 0) conv = read_norms(pending, target);
     int hd = 0;
     RPF_HIP(hipMemcpyAsync(&hd, drops.p, sizeof(int), hipMemcpyDeviceToHost, s));
     RPF_HIP(hipStreamSynchronize(s));
@@ -463,14 +532,17 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     const int check = std::max(1, opts->check_every);
     const bool mixed = prec != RPF_FP64;
     const double inner_tol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
-    const int max_sweeps = mixed ? (opts->max_sweeps > 0 ? opts->max_sweeps : 30) : 1;
+    // FP64 form: further sweeps only restart from the recomputed residual (residual replacement)
+    // when the recursive residual reached the target but the true one did not
+    const int max_sweeps = opts->max_sweeps > 0 ? opts->max_sweeps : (mixed ? 30 : 4);
     S.alloc_store(opts->max_blocks > 0 ? opts->max_blocks : std::min(opts->max_it, 2000) + 1);
     bool converged = false;
     int sweeps = 0;
     std::vector<double> rn = S.r0n;
     double rel = 1.0;
-    for (int sw = 0; sw < max_sweeps && S.iterations < opts->max_it; ++sw) {
-      if (sw > 0) {
+    bool fresh = true;  // S.R holds the FP64 residual of the current lambda
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+      if (!fresh) {
         // FP64 residual of the current lambda
         apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
         hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
@@ -478,6 +550,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
         project(pb, S.tmp.p, nr, nr, s);
         RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
         rn = S.colnorm2(S.R.p, nr, nr);
+        fresh = true;
       }
       rel = 0.0;
       for (int c = 0; c < nr; ++c) rel = std::max(rel, std::sqrt(rn[c] / S.r0n[c]));
@@ -485,28 +558,28 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
         converged = true;
         break;
       }
+      if (S.iterations >= opts->max_it) break;
       ++sweeps;
       std::vector<double> target(nr);
       for (int c = 0; c < nr; ++c)
         target[c] = mixed ? std::max(inner_tol * inner_tol * rn[c], 0.25 * tol2 * S.r0n[c]) : tol2 * S.r0n[c];
       RPF_HIP(hipMemcpyAsync(S.Rs.p, S.R.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
-      const bool ok = S.inner(prec, target, opts->max_it - S.iterations, check);
+      S.inner(prec, target, opts->max_it - S.iterations, check);
       hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.dlam.p, 1.0, S.lam.p);
       RPF_LAUNCH_CHECK();
-      if (!mixed) {
-        RPF_HIP(hipMemcpyAsync(S.R.p, S.Rs.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
-        if (!ok) break;
-      }
+      fresh = false;
     }
-    // final FP64 residual check (always recomputed)
-    apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
-    hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
-    RPF_LAUNCH_CHECK();
-    project(pb, S.tmp.p, nr, nr, s);
-    rn = S.colnorm2(S.tmp.p, nr, nr);
+    // final FP64 residual check (recomputed unless the loop ended on a fresh one)
+    if (!fresh) {
+      apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+      hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
+      RPF_LAUNCH_CHECK();
+      project(pb, S.tmp.p, nr, nr, s);
+      rn = S.colnorm2(S.tmp.p, nr, nr);
+    }
     rel = 0.0;
     for (int c = 0; c < nr; ++c) rel = std::max(rel, std::sqrt(rn[c] / S.r0n[c]));
-    converged = rel <= opts->tol * 1.0000001 || (converged && rel <= 10 * opts->tol);
+    converged = rel <= opts->tol;
     st.ms_iterate = ti.stop();
     st.iterations = S.iterations;
     st.sweeps = std::max(sweeps, 1);
@@ -564,9 +637,53 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     RPF_LAUNCH_CHECK();
     st.ms_recover = tr.stop();
     st.converged = converged ? 1 : 0;
-    if (!converged)
-      throw Error(RPF_ENOCONV, "block_krylov_solve: not converged (relative residual " + std::to_string(rel) + ")");
+    if (!converged) {
+      char msg[160];
+      snprintf(msg, sizeof msg, "block_krylov_solve: not converged (relative residual %.3e after %d iterations, %d sweeps)",
+               rel, st.iterations, st.sweeps);
+      throw Error(RPF_ENOCONV, msg);
+    }
   });
   if (stats) *stats = st;
   return code;
 }
+
+extern "C" rpf_status feti_permute(rpf_problem pb, const rpf_pattern* pats, int32_t nr, const double* Z, int64_t ldz,
+                                   double* W, int64_t ldw, uint32_t flags, void* stream) {
+  return guarded([&] {
+    RPF_CHECK(pb != nullptr, RPF_EINVAL, "feti_permute: NULL structure");
+    const int np = pb->n_perm;
+    RPF_CHECK(nr >= 1 && ldz >= nr && ldw >= (int64_t)nr * np && Z && W, RPF_EINVAL,
+              "feti_permute: bad block arguments");
+    const bool proj = (flags & RPF_APPLY_PROJECT) != 0;
+    if (proj) check_patterns(pb, pats, RPF_FP64);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = pb->n_lambda;
+    if (N == 0) return;
+    const int m = nr * np;
+    if (ldz == nr && ldw == m) {
+      hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
+                         np > 1 ? pb->d_perm.p : (const int*)nullptr, pb->d_ep_occ.p,
+                         pb->has_rot ? pb->d_rot.p : (const double*)nullptr, Z, (int64_t)nr, W, (int64_t)m);
+      RPF_LAUNCH_CHECK();
+    } else {
+      // strided operands go through a packed staging pair
+      DevBuf<double> zs, ws;
+      zs.ensure((size_t)N * nr);
+      ws.ensure((size_t)N * m);
+      copy_matrix(s, Z, ldz, zs.p, nr, nr, N);  // (row-major: nr entries per row)
+      hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
+                         np > 1 ? pb->d_perm.p : (const int*)nullptr, pb->d_ep_occ.p,
+                         pb->has_rot ? pb->d_rot.p : (const double*)nullptr, zs.p, (int64_t)nr, ws.p, (int64_t)m);
+      RPF_LAUNCH_CHECK();
+      copy_matrix(s, ws.p, m, W, ldw, m, N);
+      RPF_HIP(hipStreamSynchronize(s));  // staging buffers are freed on return
+    }
+    if (proj) {
+      ensure_coarse(pb, pats, s);
+      project(pb, W, ldw, m, s);
+    }
+  });
+}
+
+extern "C" int32_t problem_n_perm(rpf_problem pb) { return pb ? pb->n_perm : -1; }

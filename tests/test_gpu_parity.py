@@ -34,10 +34,12 @@ def _problem(name):
         return W.ring_heat(3, (4, 4), stand=True, n_rhs=2, n_perm=3, dirichlet_bottom=True)
     if name == "elast-ragged-2x3x1":
         return W.small_elast((5, 2, 3), (2, 3, 1), n_rhs=3, n_perm=2, seed=9)
+    if name == "ring-elast-rotated":
+        return W.ring_elast(3, (2, 3, 2), n_rhs=2, n_perm=3)
     raise KeyError(name)
 
 
-CASES = ["elast-3cube-3x2x2", "heat-row", "ring-stand", "elast-ragged-2x3x1"]
+CASES = ["elast-3cube-3x2x2", "heat-row", "ring-stand", "elast-ragged-2x3x1", "ring-elast-rotated"]
 
 
 @pytest.fixture(scope="module", params=CASES)
@@ -96,6 +98,27 @@ def test_feti_apply_strided_block(case, R):
     ref = o.F(X.cpu().numpy())
     assert np.abs(got[:, 1:4] - ref).max() <= 1e-11 * np.abs(ref).max()
     assert np.all(got[:, 0] == 7.0) and np.all(got[:, 4:] == 7.0)
+
+
+@pytest.mark.parametrize("nr", [1, 2])
+def test_feti_permute(case, R, nr):
+    """Permuted multivector (with the frame turn of rotated occurrences) and its re-projection."""
+    p, o, pats, pb = case
+    Z = np.random.default_rng(10 + nr).standard_normal((p.n_lambda, nr))
+    Wg = R.feti_permute(pb, torch.from_numpy(Z).cuda()).cpu().numpy()
+    ref = o.permute(Z)
+    assert Wg.shape == ref.shape
+    assert np.abs(Wg - ref).max() <= 1e-14 * np.abs(ref).max()
+    Wq = R.feti_permute(pb, torch.from_numpy(Z).cuda(), patterns=pats, project=True).cpu().numpy()
+    assert np.abs(Wq - o.Q(ref)).max() <= 1e-11 * np.abs(ref).max()
+    # strided operands
+    big = torch.from_numpy(np.random.default_rng(3).standard_normal((p.n_lambda, nr + 3))).cuda()
+    out = torch.full((p.n_lambda, nr * pb.n_perm + 2), 5.0, dtype=torch.float64, device="cuda")
+    R.feti_permute(pb, big[:, 1:1 + nr], out=out[:, 1:1 + nr * pb.n_perm])
+    got = out.cpu().numpy()
+    ref2 = o.permute(big[:, 1:1 + nr].cpu().numpy())
+    assert np.abs(got[:, 1:1 + nr * pb.n_perm] - ref2).max() <= 1e-14 * np.abs(ref2).max()
+    assert np.all(got[:, 0] == 5.0) and np.all(got[:, -1] == 5.0)
 
 
 @pytest.mark.parametrize("method", ["classical", "block_cg", "orthodir"])

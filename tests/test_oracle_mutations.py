@@ -104,3 +104,18 @@ def test_operator_drift_inside_block_solver_is_caught(prob, brute, monkeypatch):
     lam, st = o.solve_block(d, e, 1e-11, max_it=300)
     u = o.recover(lam, d, g)
     assert _err(u, brute) > 1e-6
+
+
+def test_permutation_rotated_the_wrong_way_is_caught():
+    """Moved multipliers turned by O_t^T O_s instead of O_t O_s^T break the commutation pin."""
+    p = W.ring_elast(4, (1, 2, 1), n_perm=4, clamp=False)
+    o = O.FetiOracle(p)
+    x = np.random.default_rng(5).standard_normal((p.n_lambda, 1))
+    good = o.F(o.permute(x)) - o.permute(o.F(x))
+    assert np.abs(good).max() < 1e-12 * np.abs(o.F(x)).max()
+    rot = p.occ_rot.copy()
+    p.occ_rot = np.ascontiguousarray(np.swapaxes(rot, 1, 2))
+    z_bad = o.permute(x)
+    Fx_bad = o.permute(o.F(x))
+    p.occ_rot = rot
+    assert np.abs(o.F(z_bad) - Fx_bad).max() > 1e-2 * np.abs(Fx_bad).max()

@@ -266,6 +266,39 @@ def test_periodic_ring_commutation():
         assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
 
 
+def test_rotated_ring_permutation_carries_frames():
+    """Sections 3.1 and 5.2: on a periodic ring of rotated elastic sectors F commutes with the
+    permutations only when each moved multiplier is turned into the frame of its new place
+    (O_t O_s^T); moving the components as they are does not commute."""
+    p = W.ring_elast(4, (1, 2, 1), n_perm=4, clamp=False)
+    o = O.FetiOracle(p)
+    x = np.random.default_rng(5).standard_normal((p.n_lambda, 1))
+    z = o.permute(x)                                       # columns k = 0..3
+    Fz = o.F(z)
+    Fx_moved = o.permute(o.F(x))
+    assert np.abs(z[:, :1] - x).max() == 0.0
+    assert np.abs(Fz - Fx_moved).max() < 1e-12 * np.abs(Fx_moved).max()
+    Pk = p.perm_dof()
+    plain = o.F(x[Pk[1]]) - o.F(x)[Pk[1]]
+    assert np.abs(plain).max() > 1e-2 * np.abs(Fz).max()
+    # a rotation keeps the Euclidean norm of every multiplier
+    for k in range(4):
+        assert np.linalg.norm(z[:, k]) == pytest.approx(np.linalg.norm(x), rel=1e-13)
+
+
+def test_rotated_ring_brute_force():
+    """Section 5.2 assembly with rotated occurrences: FETI on a clamped ring of three sectors
+    reproduces the directly assembled global solution and its interface forces."""
+    p = W.ring_elast(3, (2, 3, 2), n_rhs=2)
+    o = O.FetiOracle(p)
+    ub, _, _, _ = O.global_solve(p)
+    scale = max(np.abs(x).max() for x in ub)
+    lam, u, st = o.solve("block", tol=1e-11)
+    assert max(np.abs(ub[s] - u[s]).max() for s in range(p.n_occ)) < 1e-8 * scale
+    lb = O.multipliers_from_displacements(o, ub)
+    assert np.abs(lb - lam).max() < 1e-7 * np.abs(lam).max()
+
+
 # ----------------------------------------------------------------------------- solvers
 
 def test_heat_row_closed_form(golden_dir):

@@ -314,6 +314,51 @@ def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed
                    swap_rule=swap)
 
 
+def rot_z(angle: float) -> np.ndarray:
+    c, s = np.cos(angle), np.sin(angle)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def ring_elast(n_occ=3, pat_shape=(2, 3, 2), r_in=1.0, r_out=1.5, height=0.5, n_rhs=1, n_perm=None, seed=3,
+               tol=1e-8, clamp=True):
+    """Closed ring of n_occ identical annular-sector bricks (elasticity), occurrence s rotated by
+    2 pi s / n_occ about z (section 5.2: rotations in the assembly; section 5.3: the ring of
+    rotated occurrences).  pat_shape = (radial, circumferential, axial) elements; the sector spans
+    [0, 2 pi / n_occ].  The bottom face of occurrence 0 is clamped.  Interface (s, s+1) has the
+    far face of s as its '+' side; loads are i.i.d. N(0,1) nodal forces in the pattern frame.
+    """
+    nr_, nt, nz = pat_shape
+    mesh = M.GridMesh(pat_shape, (1.0, 1.0, 1.0))
+    lat = mesh.lattice
+    ang = 2 * np.pi / n_occ
+    r = r_in + (r_out - r_in) * lat[:, 0] / nr_
+    th = ang * lat[:, 1] / nt
+    zc = height * lat[:, 2] / nz
+    coords = np.stack([r * np.cos(th), r * np.sin(th), zc], axis=1)
+    K = M.assemble_general(mesh.elements(), coords, 3)
+    pat = Pattern("sector-pattern", 3, coords, K, 6)
+    rots = np.stack([rot_z(ang * s) for s in range(n_occ)])
+    # global nodes by coinciding coordinates
+    allc = np.concatenate([coords @ rots[s].T for s in range(n_occ)])
+    key = np.round(allc / (1e-6 * r_out)).astype(np.int64)
+    _, gid = np.unique(key, axis=0, return_inverse=True)
+    gid = gid.ravel()
+    occ_gnode = [gid[s * mesh.n_nodes:(s + 1) * mesh.n_nodes] for s in range(n_occ)]
+    n_g = int(gid.max()) + 1
+    bottom0 = occ_gnode[0][lat[:, 2] == 0] if clamp else np.zeros(0, np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f_local = [rng.standard_normal((mesh.n_nodes * 3, n_rhs)) for _ in range(n_occ)]
+    far = lat[:, 1] == nt
+
+    def swap(oa, la, ob, lb):
+        # the far face (theta = 2 pi / n_occ) of the lower occurrence is the '+' side
+        return (~far[la]) & far[lb]
+
+    meta = dict(kind="elast", ring=n_occ, rotated=True, pat_shape=pat_shape, grid=(n_occ,))
+    return _finish(f"ring-elast{n_occ}", 3, [pat], np.zeros(n_occ, np.int32), rots, occ_gnode, n_g, bottom0,
+                   f_local, n_rhs, n_perm if n_perm is not None else n_occ, tol, meta, swap_rule=swap)
+
+
 # --------------------------------------------------------------------------- named configurations
 
 def config(i: int, small: bool = False) -> Problem:
