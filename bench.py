@@ -50,13 +50,17 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="elast-12cube-4x4x4-8rhs", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp64", help="comma list of fp64, fp32, bf16x3, bf16 (first is the headline)")
+    ap.add_argument("--forms", default="bf16x3,fp64",
+                    help="comma list of fp64, fp32, bf16x3, bf16 (first is the headline)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-it", type=int, default=3000)
     ap.add_argument("--max-blocks", type=int, default=None, help="ORTHODIR restart length (default per workload)")
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     ap.add_argument("--cpu-iterations", type=int, default=10)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain elementwise copy of MIB MiB (read + write) three times, the reference "
+                         "kernel that scales HBM traffic counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -77,6 +81,15 @@ def main():
     if args.max_blocks is not None:
         settings = dict(settings, max_blocks=args.max_blocks)
     method = METHODS[method_name]
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written per launch")
+        del a, b
     log(f"[bench] generating {args.workload}")
     p = W.config(cfg_idx)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
@@ -133,12 +146,24 @@ def main():
 
     head = forms[0]
     hr = results[head]
-    tr = hr["trace"]
-    gemm_ms = tr["ms"] / max(tr["count"], 1)
-    gemm_flops = tr["flops"] / max(tr["count"], 1)
-    dtype = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16": "bf16"}[head]
-    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
-    peak = PEAKS_TFLOPS[dtype]
+
+    def roofline(form):
+        tr = results[form]["trace"]
+        n = max(tr["count"], 1)
+        gemm_ms = tr["ms"] / n
+        flops = tr["flops"] / n
+        dt = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16": "bf16"}[form]
+        achieved = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+        peak = PEAKS_TFLOPS[dt]
+        return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic_for(args.workload, form),
+                "kernel": {"fp64": "k_dgemm (FP64 MFMA 16x16x4)", "fp32": "k_sgemm_sym (FP32 MFMA 16x16x4)",
+                           "bf16x3": "k_gemm_bf16 X3 (bf16 MFMA 16x16x32, three products)",
+                           "bf16": "k_gemm_bf16 (bf16 MFMA 16x16x32)"}[form],
+                "avg_launch_ms": round(gemm_ms, 4), "gflop_per_launch": round(flops / 1e9, 4),
+                "launches_per_step": tr["count"] / args.steps,
+                "share_of_step": round(tr["ms"] / args.steps / results[form]["ms"], 4)}
+
     out = {
         "metric": "time-to-solution at 1e-8 interface residual",
         "value": round(hr["ms"], 3),
@@ -150,7 +175,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else f"{dtype}+f64",
+        "dtype": "f64" if head == "fp64" else ("f32+f64" if head == "fp32" else "bf16+f64"),
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "form": head, "method": method_name,
                    "max_blocks": settings["max_blocks"], "inner_tol": settings["inner_tol"],
@@ -161,14 +186,12 @@ def main():
         "sweeps": hr["stats"]["sweeps"],
         "rel_residual": hr["stats"]["rel_residual"],
         "phase_ms": {k: round(hr["stats"][k], 3) for k in ("ms_loads", "ms_coarse", "ms_iterate", "ms_recover")},
-        "flexibility_gemm": {"launches_per_step": tr["count"] / args.steps, "avg_ms": gemm_ms,
-                             "gflop_per_launch": gemm_flops / 1e9, "tflops": achieved},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "flexibility GEMM S+ W (k_dgemm 128x128)"},
+        "roofline": roofline(head),
         "forms": {k: {"ms": round(v["ms"], 3), "iterations": v["stats"]["iterations"],
                       "sweeps": v["stats"]["sweeps"], "rel_residual": v["stats"]["rel_residual"],
-                      "gemm_tflops": (v["trace"]["flops"] / max(v["trace"]["ms"], 1e-9) / 1e9)}
+                      "phase_ms": {q: round(v["stats"][q], 3) for q in ("ms_loads", "ms_coarse", "ms_iterate",
+                                                                        "ms_recover")},
+                      "roofline": roofline(k)}
                   for k, v in results.items()},
     }
     if "fp64" in results and len(results) > 1:
@@ -177,6 +200,28 @@ def main():
     if args.cpu:
         out["cpu_baseline"] = cpu_baseline(p, cfg_idx, hr["stats"]["iterations"], args.cpu_iterations, args.tol)
     print(json.dumps(out), flush=True)
+
+
+def traffic_for(workload, form):
+    """HBM bytes per launch of the flexibility product from the committed counter summary
+    (profiles/traffic.json), or None when none was taken for this workload and form, or when the
+    kernel source changed since (the file records a hash of the source it was measured on)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        table = json.load(fh)
+    rec = table.get(f"{workload}/{form}")
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_1208_6387_amd", "csrc", rec["source"])
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(p, cfg_idx, gpu_iterations, n_it, tol):

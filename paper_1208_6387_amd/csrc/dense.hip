@@ -425,11 +425,58 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, doub
   }
 }
 
+// Same product for few rows and a long inner dimension (e.g. the coarse solve with the explicit
+// inverse of G^T G): one wavefront per row, lanes stride the inner index (coalesced reads of the
+// row of X), 16 output columns per pass reduced across the wavefront with shuffles.
+__global__ __launch_bounds__(256) void k_rows_gemm_wave(int64_t N, int a, int b, double alpha, const double* X,
+                                                        int64_t ldx, const double* Mm, int64_t mrow, double beta,
+                                                        double* Y, int64_t ldy) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const double* x = X + row * ldx;
+  for (int j0 = 0; j0 < b; j0 += 16) {
+    const int nj = min(16, b - j0);
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    for (int i = lane; i < a; i += 64) {
+      const double xv = x[i];
+      if (mrow > 0) {
+        const double* mr = Mm + (int64_t)i * mrow + j0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (u < nj) acc[u] += xv * mr[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (u < nj) acc[u] += xv * Mm[(int64_t)i + (int64_t)a * (j0 + u)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      for (int off = 32; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, 64);
+    if (lane < nj) {
+      double v = 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v = (lane == u) ? acc[u] : v;
+      double* y = Y + row * ldy + j0 + lane;
+      *y = (beta == 0.0) ? alpha * v : beta * *y + alpha * v;
+    }
+  }
+}
+
 void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* Mm,
                double beta, double* Y, int64_t ldy, int64_t mrow) {
   if (N <= 0 || b <= 0) return;
-  hipLaunchKernelGGL(k_rows_gemm, dim3((unsigned)cdiv(N, 64)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, mrow, beta,
-                     Y, ldy);
+  if (a >= 128 && cdiv(N, 64) < 512) {
+    // few row blocks: a wavefront per row keeps the whole chip busy on the inner dimension
+    hipLaunchKernelGGL(k_rows_gemm_wave, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, mrow,
+                       beta, Y, ldy);
+  } else {
+    hipLaunchKernelGGL(k_rows_gemm, dim3((unsigned)cdiv(N, 64)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, mrow,
+                       beta, Y, ldy);
+  }
   RPF_LAUNCH_CHECK();
 }
 
