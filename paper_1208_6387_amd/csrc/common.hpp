@@ -138,6 +138,10 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
 // ld a (mrow = 0) or row-major with ld mrow (mrow > 0).
 void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* M,
                double beta, double* Y, int64_t ldy, int64_t mrow = 0);
+// Two such products sharing M in one launch: Y1 = beta1 Y1 + alpha1 X1 M, Y2 = beta2 Y2 + alpha2 X2 M.
+void rows_gemm2(hipStream_t s, int64_t N, int a, int b, const double* M, int64_t mrow, double alpha1,
+                const double* X1, int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2,
+                const double* X2, int64_t ldx2, double beta2, double* Y2, int64_t ldy2);
 
 // Envelope description of a lower factor: for column block t (NB columns),
 // rows [t*NB+jb, rend[t]) below the diagonal block may be nonzero, and the
@@ -172,6 +176,10 @@ void add_diag(hipStream_t s, double* A, int64_t lda, int64_t n, double v);
 // Symmetric eigen-decomposition of small m x m matrices (m <= 64), one
 // workgroup each: A (m x m, ld m, column-major) -> V (columns), w ascending.
 void syev_small(hipStream_t s, const double* A, int m, double* V, double* w, int batch = 1);
+// Block-solver normalisation T = V diag(w^{-1/2}) over the kept eigenpairs of eta (w_i > tau *
+// max(w_max, state[1])), skipped when state[0] != 0; drops counted, flag0/flag1 set when none kept.
+void eta_eigen_T(hipStream_t s, const double* eta, int m, const double* state, double tau, double* T, int* drops,
+                 double* flag0, double* flag1);
 
 // Orthonormalise the k columns of Y (n x k, ld) in place (modified Gram-Schmidt, twice).
 void orthonormalize(hipStream_t s, double* Y, int64_t n, int64_t ld, int k);

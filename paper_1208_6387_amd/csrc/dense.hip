@@ -466,9 +466,175 @@ __global__ __launch_bounds__(256) void k_rows_gemm_wave(int64_t N, int a, int b,
   }
 }
 
+// Thin products (a <= 64 inner, b <= 16 outputs per row): one thread per row.  M is
+// staged once per workgroup in LDS (read back as broadcasts); each thread streams its
+// row of X with 16-byte loads and writes its row of Y the same way, so the kernel runs
+// at the memory rate.  blockIdx.y selects one of up to two (X, Y) pairs sharing M.
+struct RowsPair {
+  const double* X;
+  double* Y;
+  int64_t ldx, ldy;
+  double alpha, beta;
+};
+struct RowsPairs {
+  RowsPair p[2];
+};
+
+__global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, const double* Mm, int64_t mrow,
+                                                    RowsPairs pr, int vec) {
+  __shared__ double sm[64 * 16];
+  for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+    const int i = e >> 4, j = e & 15;
+    sm[e] = (i < a && j < b) ? (mrow > 0 ? Mm[(int64_t)i * mrow + j] : Mm[i + (int64_t)a * j]) : 0.0;
+  }
+  __syncthreads();
+  const RowsPair& P = pr.p[blockIdx.y];
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= N) return;
+  double acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+  const double* x = P.X + row * P.ldx;
+  for (int i0 = 0; i0 < a; i0 += 8) {
+    double xv[8];
+    if (vec && i0 + 8 <= a) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 t = *reinterpret_cast<const double2*>(x + i0 + 2 * u);
+        xv[2 * u] = t.x;
+        xv[2 * u + 1] = t.y;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = (i0 + u < a) ? x[i0 + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double* mr = sm + (i0 + u) * 16;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] += xv[u] * mr[j];
+    }
+  }
+  double* y = P.Y + row * P.ldy;
+  if (vec && (b & 1) == 0) {
+#pragma unroll
+    for (int j = 0; j < 16; j += 2) {
+      if (j < b) {
+        double2 o;
+        if (P.beta == 0.0) {
+          o.x = P.alpha * acc[j];
+          o.y = P.alpha * acc[j + 1];
+        } else {
+          const double2 t = *reinterpret_cast<const double2*>(y + j);
+          o.x = P.beta * t.x + P.alpha * acc[j];
+          o.y = P.beta * t.y + P.alpha * acc[j + 1];
+        }
+        *reinterpret_cast<double2*>(y + j) = o;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < b) y[j] = (P.beta == 0.0) ? P.alpha * acc[j] : P.beta * y[j] + P.alpha * acc[j];
+  }
+}
+
+// Narrow products (a, b <= 16): 256 rows per workgroup.  The rows of X are copied into LDS with
+// lane-consecutive loads (a row is a contiguous run of a doubles), each thread then forms its row
+// of the product from LDS, and the result leaves through LDS with lane-consecutive stores, so
+// global traffic is coalesced in both directions.  blockIdx.y selects one of the (X, Y) pairs.
+__global__ __launch_bounds__(256) void k_rows_tile(int64_t N, int a, int b, const double* Mm, int64_t mrow,
+                                                   RowsPairs pr) {
+  __shared__ double sm[16][16];
+  __shared__ double xs[256][17];
+  const int tid = threadIdx.x;
+  {
+    const int i = tid >> 4, j = tid & 15;
+    sm[i][j] = (i < a && j < b) ? (mrow > 0 ? Mm[(int64_t)i * mrow + j] : Mm[i + (int64_t)a * j]) : 0.0;
+  }
+  const RowsPair& P = pr.p[blockIdx.y];
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int rows = (int)min<int64_t>(256, N - r0);
+  for (int e = tid; e < rows * a; e += 256) {
+    const int rr = e / a, cc = e - rr * a;
+    xs[rr][cc] = P.X[(r0 + rr) * P.ldx + cc];
+  }
+  __syncthreads();
+  double acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+  if (tid < rows) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i < a) {
+        const double xv = xs[tid][i];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] += xv * sm[i][j];
+      }
+    }
+  }
+  __syncthreads();  // xs is reused for the output rows
+  if (tid < rows) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < b) xs[tid][j] = acc[j];
+  }
+  __syncthreads();
+  for (int e = tid; e < rows * b; e += 256) {
+    const int rr = e / b, cc = e - rr * b;
+    double* y = P.Y + (r0 + rr) * P.ldy + cc;
+    const double v = P.alpha * xs[rr][cc];
+    *y = (P.beta == 0.0) ? v : P.beta * *y + v;
+  }
+}
+
+namespace {
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+void launch_rows_small(hipStream_t s, int64_t N, int a, int b, const double* Mm, int64_t mrow, const RowsPairs& pr,
+                       int npairs) {
+  if (a <= 16 && b <= 16) {
+    hipLaunchKernelGGL(k_rows_tile, dim3((unsigned)cdiv(N, 256), (unsigned)npairs), dim3(256), 0, s, N, a, b, Mm,
+                       mrow, pr);
+    RPF_LAUNCH_CHECK();
+    return;
+  }
+  int vec = 1;
+  for (int k = 0; k < npairs; ++k) {
+    const RowsPair& q = pr.p[k];
+    vec &= aligned16(q.X) && aligned16(q.Y) && (q.ldx % 2 == 0) && (q.ldy % 2 == 0);
+  }
+  hipLaunchKernelGGL(k_rows_small, dim3((unsigned)cdiv(N, 256), (unsigned)npairs), dim3(256), 0, s, N, a, b, Mm,
+                     mrow, pr, vec);
+  RPF_LAUNCH_CHECK();
+}
+}  // namespace
+
+void rows_gemm2(hipStream_t s, int64_t N, int a, int b, const double* M, int64_t mrow, double alpha1,
+                const double* X1, int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2,
+                const double* X2, int64_t ldx2, double beta2, double* Y2, int64_t ldy2) {
+  if (N <= 0 || b <= 0) return;
+  if (a <= 64 && b <= 16) {
+    RowsPairs pr{};
+    pr.p[0] = {X1, Y1, ldx1, ldy1, alpha1, beta1};
+    pr.p[1] = {X2, Y2, ldx2, ldy2, alpha2, beta2};
+    launch_rows_small(s, N, a, b, M, mrow, pr, 2);
+  } else {
+    rows_gemm(s, N, a, b, alpha1, X1, ldx1, M, beta1, Y1, ldy1, mrow);
+    rows_gemm(s, N, a, b, alpha2, X2, ldx2, M, beta2, Y2, ldy2, mrow);
+  }
+}
+
 void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* Mm,
                double beta, double* Y, int64_t ldy, int64_t mrow) {
   if (N <= 0 || b <= 0) return;
+  if (a <= 64 && b <= 16 && N >= 4096) {
+    RowsPairs pr{};
+    pr.p[0] = {X, Y, ldx, ldy, alpha, beta};
+    pr.p[1] = pr.p[0];
+    launch_rows_small(s, N, a, b, Mm, mrow, pr, 1);
+    return;
+  }
   if (a >= 128 && cdiv(N, 64) < 512) {
     // few row blocks: a wavefront per row keeps the whole chip busy on the inner dimension
     hipLaunchKernelGGL(k_rows_gemm_wave, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, mrow,
@@ -482,13 +648,18 @@ void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const doubl
 
 // ============================================================================ Cholesky
 // One NB x NB diagonal block on a single wavefront: lane t keeps row t of the
-// block in registers and the factor is built column by column (right-looking),
-// each finished column broadcast through LDS; then lane c forms column c of the
-// inverse factor by forward substitution against the rows of L in LDS.  Rows
+// block in registers and the factor is built column by column (right-looking):
+// lane j takes the square root and its reciprocal, the other lanes scale their
+// entry of column j and publish it through LDS, then update the rest of their row.
+// The inverse factor is formed right-looking as well (lane c holds column c of
+// L^{-1}; step k finalises row k and updates the rows below with column k of L),
+// so every step issues one batch of independent LDS reads instead of a chain of
+// dependent ones.  Both results leave through LDS with coalesced stores.  Rows
 // and columns beyond jb are padded with the identity.
 __global__ __launch_bounds__(64) void k_potrf_diag(double* A, int64_t lda, int jb, double* dinv, int* status,
                                                    int blk) {
   __shared__ double Ls[NB][NB + 1];
+  __shared__ double rdiag[NB];
   const int t = threadIdx.x;
   bool bad = false;
   {
@@ -509,10 +680,11 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* A, int64_t lda, int j
         }
         a[j] = sqrt(d);
         Ls[j][j] = a[j];
+        rdiag[j] = 1.0 / a[j];
       }
       __syncthreads();
       if (t > j) {
-        a[j] *= 1.0 / Ls[j][j];
+        a[j] *= rdiag[j];
         Ls[t][j] = a[j];
       }
       __syncthreads();
@@ -525,23 +697,28 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* A, int64_t lda, int j
     }
   }
   __syncthreads();
-  // write the factor back (lower part of the jb x jb block)
+  // write the factor back (lower part of the jb x jb block), coalesced over rows
 #pragma unroll 4
   for (int c = 0; c < NB; ++c)
     if (t < jb && c < jb && c <= t) A[(int64_t)c * lda + t] = Ls[t][c];
-  // column c = t of the inverse: x[r] = (delta_rc - sum_{k<r} L[r][k] x[k]) / L[r][r]
-  {
-    double x[NB];
+  // column t of the inverse factor, right-looking
+  double x[NB];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      double sum = (r == t) ? 1.0 : 0.0;
+  for (int r = 0; r < NB; ++r) x[r] = (r == t) ? 1.0 : 0.0;
 #pragma unroll
-      for (int k = 0; k < r; ++k) sum -= Ls[r][k] * x[k];
-      x[r] = (r < t) ? 0.0 : sum * (1.0 / Ls[r][r]);
-    }
+  for (int k = 0; k < NB; ++k) {
+    x[k] *= rdiag[k];
+    const double xk = x[k];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) dinv[(int64_t)t * NB + r] = x[r];
+    for (int r = k + 1; r < NB; ++r) x[r] -= Ls[r][k] * xk;
   }
+  __syncthreads();  // every lane is done reading L
+#pragma unroll
+  for (int r = 0; r < NB; ++r) Ls[r][t] = x[r];
+  __syncthreads();
+  // dinv column-major: dinv[c * NB + r] = (L^{-1})[r][c]; lane r writes row r of each column
+#pragma unroll 4
+  for (int c = 0; c < NB; ++c) dinv[(int64_t)c * NB + t] = Ls[t][c];
   if (bad) atomicCAS(status, 0, blk + 1);
 }
 
@@ -684,7 +861,15 @@ void add_diag(hipStream_t s, double* A, int64_t lda, int64_t n, double v) {
 // m-1 steps per sweep), one workgroup per matrix, m <= 64.
 constexpr int EIG_MAX = 64;
 
-__global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, double* Vout, double* wout) {
+// TMODE: the matrix is eta of the block solver and the kernel writes T = V diag(w^{-1/2}) over the
+// kept eigenpairs (w_i > tau * max(w_max, state[1]); the others are counted in *drops and, when
+// none is kept, 1 is written to flag0 and flag1); it returns at once when state[0] != 0 (T was
+// already formed from a Cholesky factor of eta).
+template <bool TMODE>
+__global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, double* Vout, double* wout,
+                                                     const double* state, double tau, double* T, int* drops,
+                                                     double* flag0, double* flag1) {
+  if (TMODE && state[0] != 0.0) return;
   __shared__ double a[EIG_MAX][EIG_MAX + 1];
   __shared__ double v[EIG_MAX][EIG_MAX + 1];
   __shared__ int pp[EIG_MAX / 2], qq[EIG_MAX / 2];
@@ -790,18 +975,52 @@ __global__ __launch_bounds__(256) void k_syev_jacobi(const double* Ain, int m, d
     }
   }
   __syncthreads();
-  for (int i = tid; i < m * m; i += nth) {
-    const int r = i % m, c = i / m;
-    V[c * m + r] = v[r][order[c]];
+  if (!TMODE) {
+    for (int i = tid; i < m * m; i += nth) {
+      const int r = i % m, c = i / m;
+      V[c * m + r] = v[r][order[c]];
+    }
+    for (int i = tid; i < m; i += nth) w[i] = a[order[i]][order[i]];
+  } else {
+    __shared__ double scale[EIG_MAX];
+    __shared__ int kept;
+    if (tid == 0) kept = 0;
+    __syncthreads();
+    const double ref = fmax(a[order[m - 1]][order[m - 1]], state[1]);
+    if (tid < m) {
+      const double wi = a[order[tid]][order[tid]];
+      const bool keep = wi > 0.0 && wi > tau * ref;
+      scale[tid] = keep ? 1.0 / sqrt(wi) : 0.0;
+      if (keep) atomicAdd(&kept, 1);
+      else atomicAdd(drops, 1);
+    }
+    __syncthreads();
+    if (tid == 0 && kept == 0) {
+      flag0[0] = 1.0;
+      flag1[0] = 1.0;
+    }
+    for (int i = tid; i < m * m; i += nth) {
+      const int r = i % m, c = i / m;
+      T[c * m + r] = v[r][order[c]] * scale[c];
+    }
   }
-  for (int i = tid; i < m; i += nth) w[i] = a[order[i]][order[i]];
 }
 
 void syev_small(hipStream_t s, const double* A, int m, double* V, double* w, int batch) {
   RPF_CHECK(m >= 1 && m <= EIG_MAX, RPF_EINVAL, "syev_small: m out of range");
   // one wavefront is enough (and its barriers are cheapest) while m/2 * m <= 128 work items
   const int threads = (m <= 16) ? 64 : 256;
-  hipLaunchKernelGGL(k_syev_jacobi, dim3(batch), dim3(threads), 0, s, A, m, V, w);
+  hipLaunchKernelGGL(k_syev_jacobi<false>, dim3(batch), dim3(threads), 0, s, A, m, V, w, (const double*)nullptr, 0.0,
+                     (double*)nullptr, (int*)nullptr, (double*)nullptr, (double*)nullptr);
+  RPF_LAUNCH_CHECK();
+}
+
+void eta_eigen_T(hipStream_t s, const double* eta, int m, const double* state, double tau, double* T, int* drops,
+                 double* flag0, double* flag1) {
+  RPF_CHECK(m >= 1 && m <= EIG_MAX, RPF_EINVAL, "eta_eigen_T: m out of range");
+  const int threads = (m <= 16) ? 64 : 256;
+  hipLaunchKernelGGL(k_syev_jacobi<true>, dim3(1), dim3(threads), 0, s, eta, m, (double*)nullptr, (double*)nullptr,
+                     state, tau, T, drops, flag0, flag1);
   RPF_LAUNCH_CHECK();
 }
 

@@ -191,6 +191,149 @@ __global__ __launch_bounds__(256) void k_coarse_gt(const int* occ_pat, const int
   }
 }
 
+// Same partial sums with coalesced row reads: a group of JW lanes takes one boundary node
+// (lane = interface column j), sums the signed multiplier rows at the node (each row read as
+// JW consecutive doubles), turns the sum into the pattern frame (O^T) and accumulates the
+// k mode products Z[bn]^T x_loc in registers; the 256/JW groups are summed through LDS at
+// the end.  Workgroup (s, sp) covers a slice of the boundary nodes of occurrence s.
+template <int DPN, int JW>
+__global__ __launch_bounds__(256) void k_coarse_gt_rows(const int* occ_pat, const int* slot_off, const int* nbn_p,
+                                                        const double* const* Zp, const int* kp, const int* l2m_ptr,
+                                                        const int* l2m_code, const double* rot, const double* x,
+                                                        int64_t ldx, int m, int nsplit, double* part) {
+  constexpr int NG = 256 / JW;
+  __shared__ double red[NG][KMAX][JW];
+  const int s = blockIdx.x, sp = blockIdx.y;
+  const int p = occ_pat[s];
+  const int k = kp[p];
+  const int nbn = nbn_p[p];
+  const int64_t nd = (int64_t)nbn * DPN;
+  const int nper = (nbn + nsplit - 1) / nsplit;
+  const int n_beg = sp * nper, n_end = min(nbn, n_beg + nper);
+  const double* Z = Zp[p];
+  const int tid = threadIdx.x, g = tid / JW, jl = tid % JW;
+  const int base_slot = slot_off[s];
+  double O[9];
+  if (DPN == 3) load_rot<DPN>(rot, s, O);
+  for (int j0 = 0; j0 < m; j0 += JW) {
+    const int j = j0 + jl;
+    const bool jok = j < m;
+    double acc[KMAX];
+#pragma unroll
+    for (int r = 0; r < KMAX; ++r) acc[r] = 0.0;
+    for (int bn = n_beg + g; bn < n_end; bn += NG) {
+      const int slot = base_slot + bn;
+      const int e0 = l2m_ptr[slot], e1 = l2m_ptr[slot + 1];
+      double xg[DPN];
+#pragma unroll
+      for (int c = 0; c < DPN; ++c) xg[c] = 0.0;
+      for (int e = e0; e < e1; ++e) {
+        const int code = l2m_code[e];
+        const double sg = (code & 1) ? -1.0 : 1.0;
+        const int64_t mult = code >> 1;
+        if (jok) {
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) xg[c] += sg * x[(mult * DPN + c) * ldx + j];
+        }
+      }
+      double xl[DPN];
+      if (DPN == 3) {
+#pragma unroll
+        for (int c2 = 0; c2 < 3; ++c2) xl[c2] = O[c2] * xg[0] + O[3 + c2] * xg[1 % DPN] + O[6 + c2] * xg[2 % DPN];
+      } else {
+#pragma unroll
+        for (int c = 0; c < DPN; ++c) xl[c] = xg[c];
+      }
+      const double* zr = Z + (int64_t)bn * DPN;
+#pragma unroll
+      for (int r = 0; r < KMAX; ++r) {
+        if (r < k) {
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) acc[r] += zr[r * nd + c] * xl[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < KMAX; ++r) red[g][r][jl] = acc[r];
+    __syncthreads();
+    for (int i = tid; i < KMAX * JW; i += 256) {
+      const int r = i / JW, jj = i % JW;
+      if (r < k && j0 + jj < m) {
+        double v = 0.0;
+        for (int gg = 0; gg < NG; ++gg) v += red[gg][r][jj];
+        part[(((int64_t)s * nsplit + sp) * KMAX + r) * m + j0 + jj] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// x = beta x + alpha G y with the rows of G staged in LDS: the workgroup first forms, for every
+// multiplier it touches and both endpoints, sign * O Z[bn] (DPN x k), then thread (mult, j)
+// contracts them with y_s.  Used when m >= 8 (at most 34 multipliers per workgroup).
+template <int DPN>
+__global__ __launch_bounds__(256) void k_coarse_g_lds(int n_mult, const int* ep_occ, const int* ep_bn,
+                                                      const int8_t* ep_sign, const int* occ_pat, const int* nbn_p,
+                                                      const double* const* Zp, const int* kp, const int* goff,
+                                                      const double* rot, const double* y, int m, double alpha,
+                                                      double* x, int64_t ldx, double beta) {
+  constexpr int MW = 34;
+  __shared__ double gz[MW][2][DPN][KMAX];
+  const int64_t first = (int64_t)blockIdx.x * 256;
+  const int mult_lo = (int)(first / m);
+  const int mult_hi = (int)min<int64_t>(n_mult, (first + 255) / m + 1);
+  const int nmw = mult_hi - mult_lo;
+  for (int i = threadIdx.x; i < nmw * 2 * DPN * KMAX; i += 256) {
+    const int r = i % KMAX, c = (i / KMAX) % DPN, e = (i / (KMAX * DPN)) % 2, w = i / (KMAX * DPN * 2);
+    const int mult = mult_lo + w;
+    const int s = ep_occ[2 * mult + e];
+    double v = 0.0;
+    if (s >= 0) {
+      const int p = occ_pat[s];
+      if (r < kp[p]) {
+        const int64_t ldz = (int64_t)nbn_p[p] * DPN;
+        const double* zr = Zp[p] + (int64_t)ep_bn[2 * mult + e] * DPN + r * ldz;
+        if (DPN == 3) {
+          const double* O = rot ? rot + 9 * (int64_t)s : nullptr;
+          v = O ? (O[3 * c] * zr[0] + O[3 * c + 1] * zr[1 % DPN] + O[3 * c + 2] * zr[2 % DPN]) : zr[c];
+        } else {
+          v = zr[c];
+        }
+        v *= (double)ep_sign[2 * mult + e];
+      }
+    }
+    gz[w][e][c][r] = v;
+  }
+  __syncthreads();
+  const int64_t idx = first + threadIdx.x;
+  if (idx >= (int64_t)n_mult * m) return;
+  const int mult = (int)(idx / m), j = (int)(idx % m);
+  const int w = mult - mult_lo;
+  double acc[DPN];
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int s = ep_occ[2 * mult + e];
+    if (s < 0) continue;
+    const int k = kp[occ_pat[s]];
+    const double* ys = y + (int64_t)goff[s] * m + j;
+#pragma unroll
+    for (int r = 0; r < KMAX; ++r) {
+      if (r < k) {
+        const double yr = ys[(int64_t)r * m];
+#pragma unroll
+        for (int c = 0; c < DPN; ++c) acc[c] += gz[w][e][c][r] * yr;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) {
+    double* xv = x + ((int64_t)mult * DPN + c) * ldx + j;
+    *xv = (beta == 0.0) ? alpha * acc[c] : beta * *xv + alpha * acc[c];
+  }
+}
+
 // c[(goff[s] + r)*m + j] = sum over the node slices of the partial sums (fixed order)
 __global__ void k_coarse_gt_reduce(int n_occ, int nsplit, const int* occ_pat, const int* kp, const int* goff, int m,
                                    const double* part, double* c) {
@@ -550,16 +693,32 @@ void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, h
   const int nsplit = (int)std::max<int64_t>(
       1, std::min<int64_t>(cdiv(1024, pb->n_occ), cdiv(max_nd, 256)));
   pb->cpart.ensure((size_t)pb->n_occ * nsplit * KMAX * m);
+  const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
+  if (m >= 8) {
+    // lanes over interface columns, coalesced row reads
+#define RPF_CGR(D, JW)                                                                                            \
+  hipLaunchKernelGGL((k_coarse_gt_rows<D, JW>), dim3(pb->n_occ, nsplit), dim3(256), 0, s, pb->d_occ_pat.p,         \
+                     pb->d_slot_off.p, pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_l2m_ptr.p, pb->d_l2m_code.p, rot, \
+                     x, ldx, m, nsplit, pb->cpart.p)
+    const bool w16 = m > 8;
+    switch (pb->dpn) {
+      case 1: if (w16) RPF_CGR(1, 16); else RPF_CGR(1, 8); break;
+      case 2: if (w16) RPF_CGR(2, 16); else RPF_CGR(2, 8); break;
+      default: if (w16) RPF_CGR(3, 16); else RPF_CGR(3, 8);
+    }
+#undef RPF_CGR
+  } else {
 #define RPF_CGT(D)                                                                                             \
   hipLaunchKernelGGL(k_coarse_gt<D>, dim3(pb->n_occ, nsplit), dim3(256), 0, s, pb->d_occ_pat.p, pb->d_slot_off.p, \
                      pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p, pb->d_l2m_ptr.p, pb->d_l2m_code.p,      \
-                     pb->has_rot ? pb->d_rot.p : nullptr, x, ldx, m, nsplit, pb->cpart.p)
-  switch (pb->dpn) {
-    case 1: RPF_CGT(1); break;
-    case 2: RPF_CGT(2); break;
-    default: RPF_CGT(3);
-  }
+                     rot, x, ldx, m, nsplit, pb->cpart.p)
+    switch (pb->dpn) {
+      case 1: RPF_CGT(1); break;
+      case 2: RPF_CGT(2); break;
+      default: RPF_CGT(3);
+    }
 #undef RPF_CGT
+  }
   RPF_LAUNCH_CHECK();
   const int64_t tot = (int64_t)pb->n_occ * KMAX * m;
   hipLaunchKernelGGL(k_coarse_gt_reduce, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, pb->n_occ, nsplit,
@@ -571,14 +730,22 @@ void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, i
               hipStream_t s) {
   if (pb->n_mult == 0) return;
   dim3 grid((unsigned)cdiv((int64_t)pb->n_mult * m, 256));
-#define RPF_CG(D)                                                                                          \
-  hipLaunchKernelGGL(k_coarse_g<D>, grid, dim3(256), 0, s, pb->n_mult, pb->d_ep_occ.p, pb->d_ep_bn.p,       \
+#define RPF_CG(K, D)                                                                                       \
+  hipLaunchKernelGGL(K<D>, grid, dim3(256), 0, s, pb->n_mult, pb->d_ep_occ.p, pb->d_ep_bn.p,               \
                      pb->d_ep_sign.p, pb->d_occ_pat.p, pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p,    \
                      pb->has_rot ? pb->d_rot.p : nullptr, y, m, alpha, x, ldx, beta)
-  switch (pb->dpn) {
-    case 1: RPF_CG(1); break;
-    case 2: RPF_CG(2); break;
-    default: RPF_CG(3);
+  if (m >= 8) {
+    switch (pb->dpn) {
+      case 1: RPF_CG(k_coarse_g_lds, 1); break;
+      case 2: RPF_CG(k_coarse_g_lds, 2); break;
+      default: RPF_CG(k_coarse_g_lds, 3);
+    }
+  } else {
+    switch (pb->dpn) {
+      case 1: RPF_CG(k_coarse_g, 1); break;
+      case 2: RPF_CG(k_coarse_g, 2); break;
+      default: RPF_CG(k_coarse_g, 3);
+    }
   }
 #undef RPF_CG
   RPF_LAUNCH_CHECK();
@@ -590,10 +757,23 @@ void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s)
   pb->cbuf.ensure((size_t)nG * m);
   pb->ybuf.ensure((size_t)nG * m);
   coarse_gt(pb, x, ldx, m, pb->cbuf.p, s);
-  // y^T (m x nG, ld m) = c^T Ginv (Ginv symmetric)
-  // y = (G^T G)^{-1} c, both n_G x m row-major (the inverse is symmetric)
-  rows_gemm(s, nG, nG, m, 1.0, pb->Ginv.p, nG, pb->cbuf.p, 0.0, pb->ybuf.p, m, m);
+  coarse_solve(pb, pb->cbuf.p, pb->ybuf.p, m, s);
   coarse_g(pb, pb->ybuf.p, m, -1.0, x, ldx, 1.0, s);
+}
+
+// y = (G^T G)^{-1} c for n_G x m row-major blocks, with the explicit (symmetric) inverse.  Large
+// coarse spaces go through the split-K FP64 MFMA product y^T (m x n_G) = c^T Ginv; small ones
+// through the row product.
+void coarse_solve(rpf_problem pb, const double* c, double* y, int m, hipStream_t s) {
+  const int nG = pb->n_G;
+  if (nG == 0) return;
+  if (nG >= 1024) {
+    const int sp = gemm_splitk_count(m, nG, nG);
+    pb->cws.ensure((size_t)sp * m * nG);
+    dgemm_splitk(s, false, false, m, nG, nG, 1.0, c, m, pb->Ginv.p, nG, 0.0, y, m, pb->cws.p, sp);
+  } else {
+    rows_gemm(s, nG, nG, m, 1.0, pb->Ginv.p, nG, c, 0.0, y, m, m);
+  }
 }
 
 void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s) { project_block(pb, x, ldx, m, s); }

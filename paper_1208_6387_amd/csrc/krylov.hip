@@ -61,58 +61,129 @@ __global__ void k_permute(int64_t n_lambda, int dpn, int n_mult, int nr, int np,
   }
 }
 
-// T = V diag(w_i^{-1/2}) over the kept eigenpairs of eta (eigen form), or T = diag(eta_ii^{-1/2})
-// (diagonal form, classical CG per load case).  The energy of column c before the orthogonalisation
-// is |B_c|^2 + eta_cc (B = P_stored^T Z, ka x m, ld ka; F-orthonormal stored blocks); an eigenpair is
-// kept when w_i > tau * max(w_max, max_c energy_c) (diagonal form: eta_cc > tau * energy_c).  When
-// nothing is kept, 1 is written to flag0 and flag1 (the stored blocks already span the space seen
-// by the product).  256 threads.
-__global__ __launch_bounds__(256) void k_make_T(int m, const double* eta, const double* V, const double* w,
-                                                int diag_only, int ka, const double* B, double tau, double* T,
-                                                int* drops, double* flag0, double* flag1) {
-  __shared__ double scale[64];
+// Normalisation of a new block (section 4.3): T with T^T eta T = I on the kept directions.
+// The energy of column c before the orthogonalisation is |B_c|^2 + eta_cc (B = P_stored^T Z,
+// ka x m, ld ka; F-orthonormal stored blocks).  Diagonal form (classical CG per load case):
+// T = diag(eta_cc^{-1/2}) keeping eta_cc > tau * energy_c.  Block form: the eigen rule keeps w_i >
+// tau * max(w_max, max_c energy_c); when a Cholesky factor eta = L L^T exists with
+// 1 / |L^{-1}|_F^2 (a lower bound of w_min) above tau * max(trace eta, max_c energy_c) (an upper
+// bound of that reference), no eigenpair would be dropped and T = L^{-T} spans the same
+// directions, so it is used and state[0] = 1; otherwise state[0] = 0, state[1] = max_c energy_c
+// and the eigen form (eta_eigen_T) decides.  When nothing is kept, 1 goes to flag0 and flag1.
+// One wavefront; MM >= m is the unrolled register length.
+template <int MM>
+__global__ __launch_bounds__(64) void k_eta_chol(int m, const double* eta, int diag_only, int ka, const double* B,
+                                                 double tau, double* T, int* drops, double* flag0, double* flag1,
+                                                 double* state) {
   __shared__ double epre[64];
-  __shared__ double wmax, emax;
-  __shared__ int kept;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int c = wv; c < m; c += 4) {
+  __shared__ double Ls[MM][MM + 1];
+  __shared__ double rdiag[MM];
+  __shared__ double emax_s, trace_s;
+  __shared__ int bad_s;
+  const int t = threadIdx.x;
+  for (int c = 0; c < m; ++c) {
     double acc = 0.0;
-    for (int i = lane; i < ka; i += 64) {
+    for (int i = t; i < ka; i += 64) {
       const double b = B[(int64_t)c * ka + i];
       acc += b * b;
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) epre[c] = acc + eta[c * m + c];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (t == 0) epre[c] = acc + eta[c * m + c];
   }
-  __syncthreads();
-  if (tid == 0) {
-    double mx = 0.0, me = 0.0;
-    for (int i = 0; i < m; ++i) {
-      mx = fmax(mx, diag_only ? eta[i * m + i] : w[i]);
-      me = fmax(me, epre[i]);
+  if (t == 0) {
+    double me = 0.0, tr = 0.0;
+    for (int c = 0; c < m; ++c) {
+      me = fmax(me, epre[c]);
+      tr += fmax(eta[c * m + c], 0.0);
     }
-    wmax = mx;
-    emax = me;
-    kept = 0;
+    emax_s = me;
+    trace_s = tr;
+    bad_s = 0;
   }
   __syncthreads();
-  if (tid < m) {
-    const double wi = diag_only ? eta[tid * m + tid] : w[tid];
-    const double ref = diag_only ? epre[tid] : fmax(wmax, emax);
-    const bool keep = wi > 0.0 && wi > tau * ref;
-    scale[tid] = keep ? 1.0 / sqrt(wi) : 0.0;
-    if (keep) atomicAdd(&kept, 1);
-    else atomicAdd(drops, 1);
+  if (diag_only) {
+    bool keep = false;
+    if (t < m) {
+      const double wi = eta[t * m + t];
+      keep = wi > 0.0 && wi > tau * epre[t];
+      if (!keep) atomicAdd(drops, 1);
+    }
+    const bool any = __any(keep);
+    for (int i = t; i < m * m; i += 64) {
+      const int r = i % m, c = i / m;
+      const double wc = eta[c * m + c];
+      T[i] = (r == c && wc > 0.0 && wc > tau * epre[c]) ? 1.0 / sqrt(wc) : 0.0;
+    }
+    if (t == 0) {
+      if (!any) {
+        flag0[0] = 1.0;
+        flag1[0] = 1.0;
+      }
+      state[0] = 1.0;
+    }
+    return;
+  }
+  // Cholesky, lane t owns row t
+  double a[MM];
+#pragma unroll
+  for (int c = 0; c < MM; ++c) a[c] = (t < m && c < m && c <= t) ? 0.5 * (eta[c * m + t] + eta[t * m + c]) : 0.0;
+#pragma unroll
+  for (int j = 0; j < MM; ++j) {
+    if (j >= m) break;
+    if (t == j) {
+      double d = a[j];
+      if (!(d > 0.0)) {
+        bad_s = 1;
+        d = 1.0;
+      }
+      a[j] = sqrt(d);
+      rdiag[j] = 1.0 / a[j];
+    }
+    __syncthreads();
+    if (t > j && t < m) {
+      a[j] *= rdiag[j];
+      Ls[t][j] = a[j];
+    }
+    __syncthreads();
+    if (t > j && t < m) {
+      const double ltj = a[j];
+#pragma unroll
+      for (int c = j + 1; c < MM; ++c)
+        if (c <= t) a[c] -= ltj * Ls[c][j];
+    }
   }
   __syncthreads();
-  if (tid == 0 && kept == 0) {
-    flag0[0] = 1.0;
-    flag1[0] = 1.0;
+  // column t of L^{-1}, right-looking
+  double x[MM];
+#pragma unroll
+  for (int r = 0; r < MM; ++r) x[r] = (r == t) ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < MM; ++k) {
+    if (k < m) {
+      x[k] *= rdiag[k];
+      const double xk = x[k];
+#pragma unroll
+      for (int r = k + 1; r < MM; ++r)
+        if (r < m) x[r] -= Ls[r][k] * xk;
+    }
   }
-  for (int i = tid; i < m * m; i += blockDim.x) {
-    const int r = i % m, c = i / m;
-    if (diag_only) T[i] = (r == c) ? scale[c] : 0.0;
-    else T[i] = V[i] * scale[c];
+  double fro = 0.0;
+#pragma unroll
+  for (int r = 0; r < MM; ++r) fro += (t < m && r < m) ? x[r] * x[r] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, 64);
+  const double ref_up = fmax(trace_s, emax_s);
+  const bool ok = bad_s == 0 && fro > 0.0 && (1.0 / fro) > tau * ref_up;
+  if (ok) {
+    // T = L^{-T}: T[c + m r] = (L^{-1})[r][c] = x[r] of lane c
+    if (t < m) {
+#pragma unroll
+      for (int r = 0; r < MM; ++r)
+        if (r < m) T[t + (int64_t)m * r] = x[r];
+    }
+  }
+  if (t == 0) {
+    state[0] = ok ? 1.0 : 0.0;
+    state[1] = emax_s;
   }
 }
 
@@ -238,7 +309,7 @@ struct Solver {
   int64_t ldW = 0;
   int max_blocks = 0;
   // small matrices
-  DevBuf<double> eta, V, w, T, alpha, Bt, nrm, ws;
+  DevBuf<double> eta, V, w, T, alpha, Bt, nrm, ws, estate;
   DevBuf<int> drops;
   std::vector<double> r0n;  // ||r0_c||^2 of the FP64 residual
   int iterations = 0, rank_drops = 0;
@@ -328,6 +399,7 @@ struct Solver {
     T.ensure((size_t)m * m);
     alpha.ensure((size_t)m * nr);
     drops.ensure(1);
+    estate.ensure(2);
   }
 
   void alloc_store(int want_blocks) {
@@ -390,20 +462,30 @@ struct Solver {
       apply_F(pb, pats, m, Zb.p, m, Pb.p, m, prec, true, s);
       // eta = Zb^T P, T = eta^{-1/2} (pseudo-inverse on dropped directions)
       gram(Zb.p, m, m, Pb.p, m, m, eta.p);
-      if (!diag_only) syev_small(s, eta.p, m, V.p, w.p, 1);
-      hipLaunchKernelGGL(k_make_T, dim3(1), dim3(256), 0, s, m, eta.p, V.p, w.p, diag_only ? 1 : 0, nb * m, Bt.p, tau,
-                         T.p, drops.p, nrm2[0].p + (size_t)nr * nr, nrm2[1].p + (size_t)nr * nr);
+      {
+        double* f0 = nrm2[0].p + (size_t)nr * nr;
+        double* f1 = nrm2[1].p + (size_t)nr * nr;
+        const int dg = diag_only ? 1 : 0;
+#define RPF_ETA(MM)                                                                                             \
+  hipLaunchKernelGGL(k_eta_chol<MM>, dim3(1), dim3(64), 0, s, m, eta.p, dg, nb * m, Bt.p, tau, T.p, drops.p, f0, f1, \
+                     estate.p)
+        if (m <= 8) RPF_ETA(8);
+        else if (m <= 16) RPF_ETA(16);
+        else if (m <= 32) RPF_ETA(32);
+        else RPF_ETA(64);
+#undef RPF_ETA
+        RPF_LAUNCH_CHECK();
+        if (!diag_only) eta_eigen_T(s, eta.p, m, estate.p, tau, T.p, drops.p, f0, f1);
+      }
       RPF_LAUNCH_CHECK();
       // W_j = Zb T, P_j = P T into the store
       double* Wj = Wall.p + (int64_t)slot * m;
       double* Pj = Pall.p + (int64_t)slot * m;
-      rows_gemm(s, N, m, m, 1.0, Zb.p, m, T.p, 0.0, Wj, ldW);
-      rows_gemm(s, N, m, m, 1.0, Pb.p, m, T.p, 0.0, Pj, ldW);
+      rows_gemm2(s, N, m, m, T.p, 0, 1.0, Zb.p, m, 0.0, Wj, ldW, 1.0, Pb.p, m, 0.0, Pj, ldW);
       // alpha = W_j^T R ; lambda += W_j alpha ; R -= P_j alpha
       gram(Wj, ldW, m, Rs.p, nr, nr, alpha.p);
       if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * nr)), dim3(256), 0, s, alpha.p, m, nr, (int64_t)m);
-      rows_gemm(s, N, m, nr, 1.0, Wj, ldW, alpha.p, 1.0, dlam.p, nr);
-      rows_gemm(s, N, m, nr, -1.0, Pj, ldW, alpha.p, 1.0, Rs.p, nr);
+      rows_gemm2(s, N, m, nr, alpha.p, 0, 1.0, Wj, ldW, 1.0, dlam.p, nr, -1.0, Pj, ldW, 1.0, Rs.p, nr);
       ++nst;
       ++iterations;
       if ((it + 1) % check_every == 0 || it + 1 == max_it) {
@@ -510,7 +592,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
         RPF_HIP(hipStreamSynchronize(s));
       }
       // lambda_0 = G (G^T G)^{-1} e
-      rows_gemm(s, nG, nG, nr, 1.0, pb->Ginv.p, nG, e.p, 0.0, yc.p, nr, nr);
+      coarse_solve(pb, e.p, yc.p, nr, s);
       coarse_g(pb, yc.p, nr, 1.0, S.lam.p, nr, 0.0, s);
     } else {
       fill(s, S.lam.p, N * nr, 0.0);
@@ -595,7 +677,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
       hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, -1.0, S.d.p, 1.0, S.tmp.p);
       RPF_LAUNCH_CHECK();
       coarse_gt(pb, S.tmp.p, nr, nr, ca.p, s);
-      rows_gemm(s, nG, nG, nr, 1.0, pb->Ginv.p, nG, ca.p, 0.0, aa.p, nr, nr);
+      coarse_solve(pb, ca.p, aa.p, nr, s);
     }
     for (int p = 0; p < pb->n_pat; ++p) {
       const rpf_pattern P = pats[p];

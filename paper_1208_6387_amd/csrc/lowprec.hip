@@ -199,18 +199,39 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
       out = *reinterpret_cast<uint4*>(t);
     }
   };
+  // Interior tiles (the workgroup-uniform common case) take unconditional 16-byte loads in one
+  // straight-line block, so all of a stage's loads are in flight together; edge tiles go through
+  // the guarded path.
+  const bool rows_full = (m0 + BM <= M) && (n0 + BN <= N);
   auto gload = [&](int k0) {
+    if (rows_full && k0 + BK <= kend) {
 #pragma unroll
-    for (int e = 0; e < NA; ++e) {
-      const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
-      load_chunk(Ah, lda, m0 + row, M, k0 + kk, kend - (k0 + kk), rah[e]);
-      if (X3) load_chunk(Al, lda, m0 + row, M, k0 + kk, kend - (k0 + kk), ral[e]);
-    }
+      for (int e = 0; e < NA; ++e) {
+        const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
+        const int64_t o = (int64_t)(m0 + row) * lda + k0 + kk;
+        rah[e] = *reinterpret_cast<const uint4*>(Ah + o);
+        if (X3) ral[e] = *reinterpret_cast<const uint4*>(Al + o);
+      }
 #pragma unroll
-    for (int e = 0; e < NB; ++e) {
-      const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
-      load_chunk(Bh, ldb, n0 + row, N, k0 + kk, kend - (k0 + kk), rbh[e]);
-      if (X3) load_chunk(Bl, ldb, n0 + row, N, k0 + kk, kend - (k0 + kk), rbl[e]);
+      for (int e = 0; e < NB; ++e) {
+        const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
+        const int64_t o = (int64_t)(n0 + row) * ldb + k0 + kk;
+        rbh[e] = *reinterpret_cast<const uint4*>(Bh + o);
+        if (X3) rbl[e] = *reinterpret_cast<const uint4*>(Bl + o);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < NA; ++e) {
+        const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
+        load_chunk(Ah, lda, m0 + row, M, k0 + kk, kend - (k0 + kk), rah[e]);
+        if (X3) load_chunk(Al, lda, m0 + row, M, k0 + kk, kend - (k0 + kk), ral[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const int c = tid + e * 256, row = c / 8, kk = 8 * (c % 8);
+        load_chunk(Bh, ldb, n0 + row, N, k0 + kk, kend - (k0 + kk), rbh[e]);
+        if (X3) load_chunk(Bl, ldb, n0 + row, N, k0 + kk, kend - (k0 + kk), rbl[e]);
+      }
     }
   };
   auto sstore = [&]() {
@@ -250,16 +271,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
         bh[j] = *reinterpret_cast<const bf16x8*>(&sBh[row * RS + ko]);
         if (X3) bl[j] = *reinterpret_cast<const bf16x8*>(&sBl[row * RS + ko]);
       }
+      // the three products of one accumulator are issued TM*TN MFMAs apart (independent chains)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah[i], acc[i][j], 0, 0, 0);
-          if (X3) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah[i], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al[i], acc[i][j], 0, 0, 0);
-          }
-        }
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah[i], acc[i][j], 0, 0, 0);
+      if (X3) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah[i], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al[i], acc[i][j], 0, 0, 0);
+      }
     }
   }
 #pragma unroll

@@ -48,7 +48,7 @@ struct rpf_problem_s {
   std::vector<int> goff;
   rpf::DevBuf<int> d_goff, d_kp, d_nbn;
   rpf::DevBuf<const double*> d_Zp;
-  rpf::DevBuf<double> Ginv, cbuf, ybuf, cpart;
+  rpf::DevBuf<double> Ginv, cbuf, ybuf, cpart, cws;
 };
 
 namespace rpf {
@@ -71,6 +71,7 @@ void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, i
 // x <- Q x = x - G (G^T G)^{-1} G^T x
 void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
 void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
+void coarse_solve(rpf_problem pb, const double* c, double* y, int m, hipStream_t s);
 // F X with a low-precision flexibility product (FP32 or bf16 split), FP64 in and out
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
                      int64_t ldy, int prec, hipStream_t s);
