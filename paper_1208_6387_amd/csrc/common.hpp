@@ -14,6 +14,27 @@
 namespace rpf {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+// XCD-aware tile order for 2-D GEMM grids.  Workgroups are dispatched round-robin over the 8
+// XCDs, each with its own L2.  The tiles are listed group by group of CG column tiles, row tile
+// by row tile inside a group, and XCD x takes the x-th contiguous eighth of that list; the
+// workgroups that run together on one XCD then share their row panel of A in its L2 (and the
+// group's column panels of B while they stay resident).  Identity when the counts do not divide.
+__device__ inline void xcd_tile(int nx, int ny, int& tx, int& ty) {
+  constexpr int NXCD = 8;
+  const int cg = ny < 8 ? ny : 8;
+  const int T = nx * ny;
+  if (T % NXCD != 0 || ny % cg != 0) {
+    tx = blockIdx.x;
+    ty = blockIdx.y;
+    return;
+  }
+  const int w = blockIdx.x + nx * blockIdx.y;
+  const int q = (w % NXCD) * (T / NXCD) + w / NXCD;
+  const int cc = q % cg, r = (q / cg) % nx, g = q / (cg * nx);
+  tx = r;
+  ty = g * cg + cc;
+}
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // ----------------------------------------------------------------------------- errors
@@ -138,6 +159,10 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
 // ld a (mrow = 0) or row-major with ld mrow (mrow > 0).
 void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx, const double* M,
                double beta, double* Y, int64_t ldy, int64_t mrow = 0);
+// Y = beta Z + alpha X M with the beta term read from another block Z (a <= 64, b <= 16, M
+// column-major with ld a).
+void rows_gemm_from(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx,
+                    const double* M, double beta, const double* Z, int64_t ldz, double* Y, int64_t ldy);
 // Two such products sharing M in one launch: Y1 = beta1 Y1 + alpha1 X1 M, Y2 = beta2 Y2 + alpha2 X2 M.
 void rows_gemm2(hipStream_t s, int64_t N, int a, int b, const double* M, int64_t mrow, double alpha1,
                 const double* X1, int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2,

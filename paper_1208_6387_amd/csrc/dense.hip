@@ -34,7 +34,9 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
   __shared__ double sB[BK][BN + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  int tx, ty;
+  xcd_tile(gridDim.x, gridDim.y, tx, ty);
+  const int64_t m0 = (int64_t)tx * BM, n0 = (int64_t)ty * BN;
   if (lower && n0 >= m0 + BM) return;  // tile strictly above the diagonal
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = K < kbeg + kchunk ? K : kbeg + kchunk;
@@ -475,6 +477,8 @@ struct RowsPair {
   double* Y;
   int64_t ldx, ldy;
   double alpha, beta;
+  const double* Z;  // source of the beta term (NULL: Y itself), row stride ldz
+  int64_t ldz;
 };
 struct RowsPairs {
   RowsPair p[2];
@@ -516,6 +520,7 @@ __global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, con
     }
   }
   double* y = P.Y + row * P.ldy;
+  const double* z = P.Z ? P.Z + row * P.ldz : y;
   if (vec && (b & 1) == 0) {
 #pragma unroll
     for (int j = 0; j < 16; j += 2) {
@@ -525,7 +530,7 @@ __global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, con
           o.x = P.alpha * acc[j];
           o.y = P.alpha * acc[j + 1];
         } else {
-          const double2 t = *reinterpret_cast<const double2*>(y + j);
+          const double2 t = *reinterpret_cast<const double2*>(z + j);
           o.x = P.beta * t.x + P.alpha * acc[j];
           o.y = P.beta * t.y + P.alpha * acc[j + 1];
         }
@@ -535,7 +540,7 @@ __global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, con
   } else {
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-      if (j < b) y[j] = (P.beta == 0.0) ? P.alpha * acc[j] : P.beta * y[j] + P.alpha * acc[j];
+      if (j < b) y[j] = (P.beta == 0.0) ? P.alpha * acc[j] : P.beta * z[j] + P.alpha * acc[j];
   }
 }
 
@@ -584,7 +589,7 @@ __global__ __launch_bounds__(256) void k_rows_tile(int64_t N, int a, int b, cons
     const int rr = e / b, cc = e - rr * b;
     double* y = P.Y + (r0 + rr) * P.ldy + cc;
     const double v = P.alpha * xs[rr][cc];
-    *y = (P.beta == 0.0) ? v : P.beta * *y + v;
+    *y = (P.beta == 0.0) ? v : P.beta * (P.Z ? P.Z[(r0 + rr) * P.ldz + cc] : *y) + v;
   }
 }
 
@@ -602,7 +607,8 @@ void launch_rows_small(hipStream_t s, int64_t N, int a, int b, const double* Mm,
   int vec = 1;
   for (int k = 0; k < npairs; ++k) {
     const RowsPair& q = pr.p[k];
-    vec &= aligned16(q.X) && aligned16(q.Y) && (q.ldx % 2 == 0) && (q.ldy % 2 == 0);
+    vec &= aligned16(q.X) && aligned16(q.Y) && (q.ldx % 2 == 0) && (q.ldy % 2 == 0) &&
+           (!q.Z || (aligned16(q.Z) && q.ldz % 2 == 0));
   }
   hipLaunchKernelGGL(k_rows_small, dim3((unsigned)cdiv(N, 256), (unsigned)npairs), dim3(256), 0, s, N, a, b, Mm,
                      mrow, pr, vec);
@@ -610,14 +616,24 @@ void launch_rows_small(hipStream_t s, int64_t N, int a, int b, const double* Mm,
 }
 }  // namespace
 
+void rows_gemm_from(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx,
+                    const double* M, double beta, const double* Z, int64_t ldz, double* Y, int64_t ldy) {
+  if (N <= 0 || b <= 0) return;
+  RPF_CHECK(a <= 64 && b <= 16, RPF_EINVAL, "rows_gemm_from: block too wide");
+  RowsPairs pr{};
+  pr.p[0] = {X, Y, ldx, ldy, alpha, beta, Z, ldz};
+  pr.p[1] = pr.p[0];
+  launch_rows_small(s, N, a, b, M, 0, pr, 1);
+}
+
 void rows_gemm2(hipStream_t s, int64_t N, int a, int b, const double* M, int64_t mrow, double alpha1,
                 const double* X1, int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2,
                 const double* X2, int64_t ldx2, double beta2, double* Y2, int64_t ldy2) {
   if (N <= 0 || b <= 0) return;
   if (a <= 64 && b <= 16) {
     RowsPairs pr{};
-    pr.p[0] = {X1, Y1, ldx1, ldy1, alpha1, beta1};
-    pr.p[1] = {X2, Y2, ldx2, ldy2, alpha2, beta2};
+    pr.p[0] = {X1, Y1, ldx1, ldy1, alpha1, beta1, nullptr, 0};
+    pr.p[1] = {X2, Y2, ldx2, ldy2, alpha2, beta2, nullptr, 0};
     launch_rows_small(s, N, a, b, M, mrow, pr, 2);
   } else {
     rows_gemm(s, N, a, b, alpha1, X1, ldx1, M, beta1, Y1, ldy1, mrow);
@@ -630,7 +646,7 @@ void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const doubl
   if (N <= 0 || b <= 0) return;
   if (a <= 64 && b <= 16 && N >= 4096) {
     RowsPairs pr{};
-    pr.p[0] = {X, Y, ldx, ldy, alpha, beta};
+    pr.p[0] = {X, Y, ldx, ldy, alpha, beta, nullptr, 0};
     pr.p[1] = pr.p[0];
     launch_rows_small(s, N, a, b, Mm, mrow, pr, 1);
     return;

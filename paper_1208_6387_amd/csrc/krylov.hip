@@ -187,6 +187,22 @@ __global__ __launch_bounds__(64) void k_eta_chol(int m, const double* eta, int d
   }
 }
 
+// Y_i = op(T_i) X_i for nb blocks: T_i is m x m column-major at Ts + i m m (op = transpose when
+// trans), X and Y are (nb m) x c column-major with ld nb m.  One workgroup per block.
+__global__ __launch_bounds__(256) void k_tblocks(int nb, int m, int c, const double* Ts, int trans, const double* X,
+                                                 double* Y) {
+  const int i = blockIdx.x;
+  const int64_t ld = (int64_t)nb * m;
+  const double* Ti = Ts + (int64_t)i * m * m;
+  for (int e = threadIdx.x; e < m * c; e += blockDim.x) {
+    const int r = e % m, col = e / m;
+    double v = 0.0;
+    for (int k = 0; k < m; ++k)
+      v += (trans ? Ti[k + (int64_t)r * m] : Ti[r + (int64_t)k * m]) * X[(int64_t)col * ld + (int64_t)i * m + k];
+    Y[(int64_t)col * ld + (int64_t)i * m + r] = v;
+  }
+}
+
 // keep only the diagonal of an m x n column-major matrix (ld)
 __global__ void k_mask_diag(double* A, int m, int n, int64_t ld) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,7 +213,7 @@ __global__ void k_mask_diag(double* A, int m, int n, int64_t ld) {
 
 __global__ void k_axpby(int64_t count, double a, const double* x, double b, double* y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) y[i] = a * x[i] + b * y[i];
+  if (i < count) y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
 }
 
 // strided rows: y[l*ldy + j] = a x[l*ldx + j] + b y[l*ldy + j]
@@ -206,7 +222,8 @@ __global__ void k_axpby_rows(int64_t rows, int cols, double a, const double* x, 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows * cols) return;
   const int64_t l = i / cols, j = i % cols;
-  y[l * ldy + j] = a * x[l * ldx + j] + b * y[l * ldy + j];
+  // b = 0 overwrites (y may hold anything, NaN included)
+  y[l * ldy + j] = (b == 0.0) ? a * x[l * ldx + j] : a * x[l * ldx + j] + b * y[l * ldy + j];
 }
 
 // split occurrence loads into interior / boundary W-format blocks of pattern p
@@ -305,11 +322,14 @@ struct Solver {
   int nr, np, m, method;
   int64_t N;
   // interface blocks (row-major, ld = nr or m)
-  DevBuf<double> lam, d, R, Rs, tmp, Zb, Pb, Wall, Pall, dlam;
+  // Krylov store: for every stored block j the raw directions Z_j and P_j = Q^T F Z_j (N x m each,
+  // slot j of the row-major N x ldW arrays) and the normalisation T_j (m x m); the F-orthonormal
+  // block is W_j = Z_j T_j with F W_j = P_j T_j, never formed explicitly.
+  DevBuf<double> lam, d, R, Rs, tmp, Zall, Pall, Tall, dlam;
   int64_t ldW = 0;
   int max_blocks = 0;
   // small matrices
-  DevBuf<double> eta, V, w, T, alpha, Bt, nrm, ws, estate;
+  DevBuf<double> eta, V, w, T, alpha, gam, Bt, Cb, Mo, nrm, ws, estate;
   DevBuf<int> drops;
   std::vector<double> r0n;  // ||r0_c||^2 of the FP64 residual
   int iterations = 0, rank_drops = 0;
@@ -391,13 +411,12 @@ struct Solver {
     Rs.ensure((size_t)N * nr);
     dlam.ensure((size_t)N * nr);
     tmp.ensure((size_t)N * std::max(nr, m));
-    Zb.ensure((size_t)N * m);
-    Pb.ensure((size_t)N * m);
     eta.ensure((size_t)m * m);
     V.ensure((size_t)m * m);
     w.ensure(m);
     T.ensure((size_t)m * m);
     alpha.ensure((size_t)m * nr);
+    gam.ensure((size_t)m * nr);
     drops.ensure(1);
     estate.ensure(2);
   }
@@ -410,9 +429,12 @@ struct Solver {
     max_blocks = std::max(1, std::min(want_blocks, cap));
     if (method != RPF_ORTHODIR) max_blocks = 2;
     ldW = (int64_t)max_blocks * m;
-    Wall.ensure((size_t)N * ldW);
+    Zall.ensure((size_t)N * ldW);
     Pall.ensure((size_t)N * ldW);
+    Tall.ensure((size_t)max_blocks * m * m);
     Bt.ensure((size_t)ldW * m);
+    Cb.ensure((size_t)ldW * m);
+    Mo.ensure((size_t)ldW * m);
   }
 
   // One inner Krylov run on F_prec: starts from residual Rs (N x nr), accumulates
@@ -428,12 +450,6 @@ struct Solver {
     const double tau = eta_drop(prec);
     int pending = -1, nchk = 0;
     for (int it = 0; it < max_it; ++it) {
-      // multivector from the residual (Q R = R: the residual stays in range Q), re-projected
-      hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
-                         np > 1 ? pb->d_perm.p : (const int*)nullptr, pb->d_ep_occ.p,
-                         pb->has_rot ? pb->d_rot.p : (const double*)nullptr, Rs.p, (int64_t)nr, Zb.p, (int64_t)m);
-      RPF_LAUNCH_CHECK();
-      if (np > 1) project(pb, Zb.p, m, m, s);
       // ORTHODIR: orthogonalise against every stored block (restart when the store is full);
       // block CG / classical: against the previous block only, two alternating slots
       int slot, first, nb;
@@ -450,24 +466,51 @@ struct Solver {
         first = (it + 1) % 2;
         nb = it > 0 ? 1 : 0;
       }
-      if (nb > 0) {
-        // F-orthogonalise against the stored blocks: Zb -= W (P^T Zb)   (P_i^T W_i = I)
-        const double* Pp = Pall.p + (int64_t)first * m;
-        const double* Wp = Wall.p + (int64_t)first * m;
-        gram(Pp, ldW, nb * m, Zb.p, m, m, Bt.p);
-        if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * m)), dim3(256), 0, s, Bt.p, nb * m, m, (int64_t)nb * m);
-        rows_gemm(s, N, nb * m, m, -1.0, Wp, ldW, Bt.p, 1.0, Zb.p, m);
+      double* Zs = Zall.p + (int64_t)slot * m;  // this block's directions, row stride ldW
+      double* Ps = Pall.p + (int64_t)slot * m;
+      // multivector from the residual (Q R = R: the residual stays in range Q), re-projected when
+      // permuted; with one permutation it is the residual itself and is read from Rs below
+      const bool direct = (np == 1);
+      const bool fused = direct && nb > 0 && nb * m <= 16;  // orthogonalised straight from Rs
+      if (!direct) {
+        hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
+                           pb->d_perm.p, pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr, Rs.p,
+                           (int64_t)nr, Zs, ldW);
+        RPF_LAUNCH_CHECK();
+        project(pb, Zs, ldW, m, s);
+      } else if (!fused) {
+        hipLaunchKernelGGL(k_axpby_rows, dim3(nblocks(N * nr)), dim3(256), 0, s, N, nr, 1.0, Rs.p, (int64_t)nr, 0.0,
+                           Zs, ldW);
+        RPF_LAUNCH_CHECK();
       }
-      // P = Q^T F Zb
-      apply_F(pb, pats, m, Zb.p, m, Pb.p, m, prec, true, s);
-      // eta = Zb^T P, T = eta^{-1/2} (pseudo-inverse on dropped directions)
-      gram(Zb.p, m, m, Pb.p, m, m, eta.p);
+      const double* zsrc = fused ? Rs.p : Zs;
+      const int64_t ldzs = fused ? (int64_t)nr : ldW;
+      if (nb > 0) {
+        // F-orthogonalise against the stored blocks: with W_i = Z_i T_i and F W_i = P_i T_i,
+        // B = [F W_i]^T Z = T_i^T (P_i^T Z) and Z -= sum_i Z_i (T_i B_i)
+        const int ka = nb * m;
+        gram(Pall.p + (int64_t)first * m, ldW, ka, zsrc, ldzs, m, Cb.p);
+        hipLaunchKernelGGL(k_tblocks, dim3(nb), dim3(256), 0, s, nb, m, m, Tall.p + (int64_t)first * m * m, 1, Cb.p,
+                           Bt.p);
+        if (diag_only)
+          hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)ka * m)), dim3(256), 0, s, Bt.p, ka, m, (int64_t)ka);
+        hipLaunchKernelGGL(k_tblocks, dim3(nb), dim3(256), 0, s, nb, m, m, Tall.p + (int64_t)first * m * m, 0, Bt.p,
+                           Mo.p);
+        RPF_LAUNCH_CHECK();
+        if (fused) rows_gemm_from(s, N, ka, m, -1.0, Zall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Rs.p, nr, Zs, ldW);
+        else rows_gemm(s, N, ka, m, -1.0, Zall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Zs, ldW);
+      }
+      // P = Q^T F Z
+      apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, true, s);
+      // eta = Z^T P, T with T^T eta T = I on the kept directions
+      gram(Zs, ldW, m, Ps, ldW, m, eta.p);
+      double* Tj = Tall.p + (int64_t)slot * m * m;
       {
         double* f0 = nrm2[0].p + (size_t)nr * nr;
         double* f1 = nrm2[1].p + (size_t)nr * nr;
         const int dg = diag_only ? 1 : 0;
 #define RPF_ETA(MM)                                                                                             \
-  hipLaunchKernelGGL(k_eta_chol<MM>, dim3(1), dim3(64), 0, s, m, eta.p, dg, nb * m, Bt.p, tau, T.p, drops.p, f0, f1, \
+  hipLaunchKernelGGL(k_eta_chol<MM>, dim3(1), dim3(64), 0, s, m, eta.p, dg, nb * m, Bt.p, tau, Tj, drops.p, f0, f1, \
                      estate.p)
         if (m <= 8) RPF_ETA(8);
         else if (m <= 16) RPF_ETA(16);
@@ -475,17 +518,15 @@ struct Solver {
         else RPF_ETA(64);
 #undef RPF_ETA
         RPF_LAUNCH_CHECK();
-        if (!diag_only) eta_eigen_T(s, eta.p, m, estate.p, tau, T.p, drops.p, f0, f1);
+        if (!diag_only) eta_eigen_T(s, eta.p, m, estate.p, tau, Tj, drops.p, f0, f1);
       }
+      // alpha = W^T R = T^T (Z^T R); gamma = T alpha; lambda += Z gamma; R -= P gamma
+      gram(Zs, ldW, m, Rs.p, nr, nr, alpha.p);
+      hipLaunchKernelGGL(k_tblocks, dim3(1), dim3(256), 0, s, 1, m, nr, Tj, 1, alpha.p, gam.p);
+      if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * nr)), dim3(256), 0, s, gam.p, m, nr, (int64_t)m);
+      hipLaunchKernelGGL(k_tblocks, dim3(1), dim3(256), 0, s, 1, m, nr, Tj, 0, gam.p, alpha.p);
       RPF_LAUNCH_CHECK();
-      // W_j = Zb T, P_j = P T into the store
-      double* Wj = Wall.p + (int64_t)slot * m;
-      double* Pj = Pall.p + (int64_t)slot * m;
-      rows_gemm2(s, N, m, m, T.p, 0, 1.0, Zb.p, m, 0.0, Wj, ldW, 1.0, Pb.p, m, 0.0, Pj, ldW);
-      // alpha = W_j^T R ; lambda += W_j alpha ; R -= P_j alpha
-      gram(Wj, ldW, m, Rs.p, nr, nr, alpha.p);
-      if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * nr)), dim3(256), 0, s, alpha.p, m, nr, (int64_t)m);
-      rows_gemm2(s, N, m, nr, alpha.p, 0, 1.0, Wj, ldW, 1.0, dlam.p, nr, -1.0, Pj, ldW, 1.0, Rs.p, nr);
+      rows_gemm2(s, N, m, nr, alpha.p, 0, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0, Rs.p, nr);
       ++nst;
       ++iterations;
       if ((it + 1) % check_every == 0 || it + 1 == max_it) {

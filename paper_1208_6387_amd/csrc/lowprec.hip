@@ -181,7 +181,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   __shared__ __attribute__((aligned(16))) uint16_t sBl[BN * RS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  int tx, ty;
+  xcd_tile(gridDim.x, gridDim.y, tx, ty);
+  const int m0 = tx * BM, n0 = ty * BN;
   f32x4 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
