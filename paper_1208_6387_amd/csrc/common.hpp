@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -14,6 +15,23 @@
 namespace rpf {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Exact timing of one kernel: when the tracer has armed a (start, stop) pair for this thread, the
+// next RPF_TIMED_LAUNCH records them around the kernel itself (hipExtLaunchKernelGGL) and disarms.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents& launch_events();
+#define RPF_TIMED_LAUNCH(K, G, B, SH, S, ...)                                          \
+  do {                                                                                 \
+    rpf::LaunchEvents& le_ = rpf::launch_events();                                     \
+    if (le_.start) {                                                                   \
+      hipExtLaunchKernelGGL(K, G, B, SH, S, le_.start, le_.stop, 0u, __VA_ARGS__);     \
+      le_.start = le_.stop = nullptr;                                                  \
+    } else {                                                                           \
+      hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                                 \
+    }                                                                                  \
+  } while (0)
 
 // XCD-aware tile order for 2-D GEMM grids.  Workgroups are dispatched round-robin over the 8
 // XCDs, each with its own L2.  The tiles are listed group by group of CG column tiles, row tile

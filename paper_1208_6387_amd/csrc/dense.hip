@@ -169,19 +169,19 @@ void launch_cfg(Cfg c, dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K
                 int64_t ldc, int lower, int64_t kchunk, double* part) {
   switch (c) {
     case BIG:
-      hipLaunchKernelGGL((k_dgemm<128, 128, 2, 2, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+      RPF_TIMED_LAUNCH((k_dgemm<128, 128, 2, 2, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
                          ldb, beta, C, ldc, lower, kchunk, part);
       break;
     case M16:
-      hipLaunchKernelGGL((k_dgemm<16, 256, 1, 4, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+      RPF_TIMED_LAUNCH((k_dgemm<16, 256, 1, 4, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
                          ldb, beta, C, ldc, lower, kchunk, part);
       break;
     case N16:
-      hipLaunchKernelGGL((k_dgemm<256, 16, 4, 1, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+      RPF_TIMED_LAUNCH((k_dgemm<256, 16, 4, 1, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
                          ldb, beta, C, ldc, lower, kchunk, part);
       break;
     default:
-      hipLaunchKernelGGL((k_dgemm<64, 64, 2, 2, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+      RPF_TIMED_LAUNCH((k_dgemm<64, 64, 2, 2, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
                          ldb, beta, C, ldc, lower, kchunk, part);
       break;
   }
@@ -738,6 +738,11 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* A, int64_t lda, int j
   if (bad) atomicCAS(status, 0, blk + 1);
 }
 
+LaunchEvents& launch_events() {
+  static thread_local LaunchEvents ev;
+  return ev;
+}
+
 Envelope Envelope::dense(int64_t n) {
   Envelope e;
   const int64_t nb = cdiv(n, NB);
@@ -784,6 +789,45 @@ void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* 
           double* B, int64_t ldb, int64_t nrhs, bool trans) {
   if (n <= 0 || nrhs <= 0) return;
   const int64_t nblk = cdiv(n, NB);
+  bool dense = true;
+  for (int64_t t = 0; t < nblk && dense; ++t) dense = env.cstart[t] <= 0 && env.rend[t] >= n;
+  if (dense && nrhs >= 4096) {
+    // Full factor, many right-hand sides (the identity of the condensation): left-looking by row
+    // blocks.  Block t first takes the contributions of all solved blocks, B_t -= L_t,prev X_prev
+    // (one product with a long inner dimension, split over K when its output tiles alone cannot
+    // fill the chip), then X_t = inv(L_tt) B_t; B is read once per block instead of rewritten for
+    // every trailing update.
+    DevBuf<double> ws;
+    auto update = [&](bool ta, int jb, int64_t kdim, const double* A, const double* Bsrc, double* C) {
+      if (kdim <= 0) return;
+      const int sp = gemm_splitk_count(jb, nrhs, kdim);
+      if (sp > 1) {
+        ws.ensure((size_t)sp * jb * nrhs);
+        dgemm_splitk(s, ta, false, jb, nrhs, kdim, -1.0, A, ldl, Bsrc, ldb, 1.0, C, ldb, ws.p, sp);
+      } else {
+        dgemm(s, ta, false, jb, nrhs, kdim, -1.0, A, ldl, Bsrc, ldb, 1.0, C, ldb);
+      }
+    };
+    if (!trans) {
+      for (int64_t t = 0; t < nblk; ++t) {
+        const int64_t j0 = t * NB;
+        const int jb = (int)std::min<int64_t>(NB, n - j0);
+        update(false, jb, j0, L + j0, B, B + j0);
+        // in place: the single row tile of this product reads all of B_t before writing it
+        dgemm(s, false, false, jb, nrhs, jb, 1.0, dinv + t * NB * NB, NB, B + j0, ldb, 0.0, B + j0, ldb);
+      }
+    } else {
+      for (int64_t t = nblk - 1; t >= 0; --t) {
+        const int64_t j0 = t * NB;
+        const int jb = (int)std::min<int64_t>(NB, n - j0);
+        const int64_t r0 = j0 + jb;
+        update(true, jb, n - r0, L + j0 * ldl + r0, B + r0, B + j0);
+        dgemm(s, true, false, jb, nrhs, jb, 1.0, dinv + t * NB * NB, NB, B + j0, ldb, 0.0, B + j0, ldb);
+      }
+    }
+    return;
+  }
+  // Banded factors: right-looking, each solved block updates the rows of its envelope below.
   if (!trans) {
     for (int64_t t = 0; t < nblk; ++t) {
       const int64_t j0 = t * NB;

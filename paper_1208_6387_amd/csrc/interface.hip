@@ -545,6 +545,10 @@ void gather_pattern(rpf_problem pb, int p, int nbn, const double* lam, int64_t l
                     int64_t ldx, hipStream_t s) {
   const int nq = (int)pb->occ_of_pat[p].size();
   if (nq == 0 || nbn == 0) return;
+  if (m >= 8 && nbn == pb->pat_nbn[p]) {
+    gather_rows(pb, p, lam, ldl, m, 2, X, nullptr, nullptr, nullptr, ldx, s);
+    return;
+  }
   dim3 grid((unsigned)cdiv(nbn, 128), (unsigned)nq);
   const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
   const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
@@ -963,22 +967,33 @@ hipEvent_t take_event(TraceState& t) {
 
 bool trace_on() { return tstate().on; }
 
+// The pair armed here is recorded by the next timed kernel launch on this thread (the
+// flexibility product), so the measured interval is that kernel alone; if no kernel consumed it,
+// both events are recorded at the end (empty interval).
 void* trace_begin(hipStream_t s) {
+  (void)s;
   TraceState& t = tstate();
   std::lock_guard<std::mutex> g(t.mu);
   if (!t.on) return nullptr;
-  hipEvent_t a = take_event(t);
-  RPF_HIP(hipEventRecord(a, s));
-  return (void*)a;
+  LaunchEvents& le = launch_events();
+  le.start = take_event(t);
+  le.stop = take_event(t);
+  t.pending.push_back({le.start, le.stop, 0.0});
+  return (void*)(t.pending.size());
 }
 
 void trace_end(void* tok, hipStream_t s, double flops) {
   if (!tok) return;
   TraceState& t = tstate();
   std::lock_guard<std::mutex> g(t.mu);
-  hipEvent_t b = take_event(t);
-  RPF_HIP(hipEventRecord(b, s));
-  t.pending.push_back({(hipEvent_t)tok, b, flops});
+  LaunchEvents& le = launch_events();
+  if (le.start) {
+    RPF_HIP(hipEventRecord(le.start, s));
+    RPF_HIP(hipEventRecord(le.stop, s));
+    le.start = le.stop = nullptr;
+  }
+  const size_t idx = (size_t)tok - 1;
+  if (idx < t.pending.size()) t.pending[idx].flops = flops;
 }
 }  // namespace rpf
 

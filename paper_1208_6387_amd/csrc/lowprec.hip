@@ -73,6 +73,106 @@ __global__ __launch_bounds__(128) void k_gather_lp(int nbn, const int* occ_list,
   }
 }
 
+// Gather with lanes over interface columns: a group of JW lanes takes one boundary node and sums
+// the signed multiplier rows at it (each row read as JW consecutive doubles), turned into the
+// pattern frame; the workgroup collects a tile of NBK nodes x JW columns in LDS and writes it
+// out column by column with consecutive lanes on consecutive dofs.  mode 0: FP32 (Xf), 1: bf16
+// hi/lo split (Xh, Xl), 2: FP64 (X64).  Grid: (node blocks, occurrences of the pattern).
+template <int DPN, int MODE, int JW>
+__global__ __launch_bounds__(256) void k_gather_rows(int nbn, const int* occ_list, const int* slot_off,
+                                                     const int* l2m_ptr, const int* l2m_code, const double* rot,
+                                                     const double* lam, int64_t ldl, int m, double* X64, float* Xf,
+                                                     uint16_t* Xh, uint16_t* Xl, int64_t ldx) {
+  constexpr int NG = 256 / JW, NBK = 64;
+  __shared__ double tile[JW][NBK * DPN + 1];
+  const int q = blockIdx.y, s = occ_list[q];
+  const int n0 = blockIdx.x * NBK;
+  const int nn = min(NBK, nbn - n0);
+  const int tid = threadIdx.x, g = tid / JW, jl = tid % JW;
+  const int base_slot = slot_off[s] + n0;
+  double O[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) O[i] = rot ? rot[9 * s + i] : ((i % 4 == 0) ? 1.0 : 0.0);
+  const int nd = nn * DPN;
+  for (int j0 = 0; j0 < m; j0 += JW) {
+    const int j = j0 + jl;
+    const bool jok = j < m;
+    for (int b = g; b < nn; b += NG) {
+      const int e0 = l2m_ptr[base_slot + b], e1 = l2m_ptr[base_slot + b + 1];
+      double xg[DPN];
+#pragma unroll
+      for (int c = 0; c < DPN; ++c) xg[c] = 0.0;
+      for (int e = e0; e < e1; ++e) {
+        const int code = l2m_code[e];
+        const double sg = (code & 1) ? -1.0 : 1.0;
+        const int64_t mult = code >> 1;
+        if (jok) {
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) xg[c] += sg * lam[(mult * DPN + c) * ldl + j];
+        }
+      }
+#pragma unroll
+      for (int c2 = 0; c2 < DPN; ++c2) {
+        const double v = (DPN == 3) ? O[c2] * xg[0] + O[3 + c2] * xg[1 % DPN] + O[6 + c2] * xg[2 % DPN] : xg[c2];
+        tile[jl][b * DPN + c2] = v;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < JW * nd; e += 256) {
+      const int jj = e / nd, t = e - jj * nd;
+      if (j0 + jj < m) {
+        const double v = tile[jj][t];
+        const int64_t o = ((int64_t)q * m + j0 + jj) * ldx + (int64_t)n0 * DPN + t;
+        if (MODE == 2) {
+          X64[o] = v;
+        } else if (MODE == 0) {
+          Xf[o] = (float)v;
+        } else {
+          const uint16_t h = bf16_bits((float)v);
+          Xh[o] = h;
+          Xl[o] = bf16_bits((float)(v - (double)bf16_val(h)));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// zero the rows [nb, ld) of every column of the bf16 hi/lo W-format blocks
+__global__ void k_zero_pad(uint16_t* Xh, uint16_t* Xl, int64_t ld, int nb, int cols) {
+  const int64_t pad = ld - nb;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pad * cols) return;
+  const int64_t o = (i / pad) * ld + nb + (i % pad);
+  Xh[o] = 0;
+  Xl[o] = 0;
+}
+
+void gather_rows(rpf_problem pb, int p, const double* lam, int64_t ldl, int m, int mode, double* X64, float* Xf,
+                 uint16_t* Xh, uint16_t* Xl, int64_t ldx, hipStream_t s) {
+  const int nq = (int)pb->occ_of_pat[p].size(), nbn = pb->pat_nbn[p];
+  if (nq == 0 || nbn == 0) return;
+  dim3 grid((unsigned)cdiv(nbn, 64), (unsigned)nq);
+  const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
+  const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
+  const bool w16 = m > 8;
+#define RPF_GR(D, MD, JW)                                                                                     \
+  hipLaunchKernelGGL((k_gather_rows<D, MD, JW>), grid, dim3(256), 0, s, nbn, occ, pb->d_slot_off.p,             \
+                     pb->d_l2m_ptr.p, pb->d_l2m_code.p, rot, lam, ldl, m, X64, Xf, Xh, Xl, ldx)
+#define RPF_GRM(D)                                          \
+  if (mode == 0) { if (w16) RPF_GR(D, 0, 16); else RPF_GR(D, 0, 8); } \
+  else if (mode == 1) { if (w16) RPF_GR(D, 1, 16); else RPF_GR(D, 1, 8); } \
+  else { if (w16) RPF_GR(D, 2, 16); else RPF_GR(D, 2, 8); }
+  switch (pb->dpn) {
+    case 1: RPF_GRM(1); break;
+    case 2: RPF_GRM(2); break;
+    default: RPF_GRM(3);
+  }
+#undef RPF_GRM
+#undef RPF_GR
+  RPF_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------------------- FP32 MFMA GEMM
 // C (M x N, FP32, col-major ldc) = A (M x K, symmetric S+ read as k-contiguous rows, lda) * B (K x N, col-major)
 // Tile 64x64, 4 waves of 32x32, BK = 16.  Like the FP64 kernel the B fragment is
@@ -373,14 +473,18 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
   // split K (chunks of multiples of 64) while the 64 x 64 output tiles alone give fewer than
   // ~4 workgroups per CU; the scatter sums the split slabs
   std::vector<int64_t> yoff(pb->n_pat + 1, 0);
-  std::vector<int> nsp(pb->n_pat, 1), kch(pb->n_pat, 0);
+  std::vector<int> nsp(pb->n_pat, 1), kch(pb->n_pat, 0), tile_m(pb->n_pat, 64), tile_n(pb->n_pat, 64);
   for (int p = 0; p < pb->n_pat; ++p) {
     const int nb = pats[p]->n_b;
     ld[p] = cdiv(nb, 8) * 8;
     const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
     off[p + 1] = off[p] + ld[p] * cols;
-    const int T = (split && nb >= 128 && cols >= 128) ? 128 : 64;  // bf16 tile edge (64x64 per wave at 128)
-    const int64_t tiles = std::max<int64_t>(1, cdiv(nb, T) * cdiv(cols, T));
+    // bf16 workgroup tile: 128 x 128 (64 x 64 per wave) when both sides allow it, else 64 x 64
+    const int tm = (split && nb >= 128 && cols >= 128) ? 128 : 64;
+    const int tn = tm;
+    tile_m[p] = tm;
+    tile_n[p] = tn;
+    const int64_t tiles = std::max<int64_t>(1, cdiv(nb, tm) * cdiv(cols, tn));
     int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, ld[p] / 256));
     sp = std::min(sp, 8);
     kch[p] = (int)(cdiv(cdiv(ld[p], sp), 64) * 64);
@@ -416,13 +520,22 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
                      pb->xlo.p + off[p], ld[p])
     if (split) {
       // the padded rows between n_b and ld must hold zeros for the 16-byte loads
-      if (ld[p] != nb) RPF_HIP(hipMemsetAsync(pb->xhi.p + off[p], 0, sizeof(uint16_t) * ld[p] * cols, s));
-      if (ld[p] != nb) RPF_HIP(hipMemsetAsync(pb->xlo.p + off[p], 0, sizeof(uint16_t) * ld[p] * cols, s));
-      switch (pb->dpn) {
-        case 1: RPF_GLP(1, 1); break;
-        case 2: RPF_GLP(2, 1); break;
-        default: RPF_GLP(3, 1);
+      if (ld[p] != nb) {
+        const int64_t npad = (ld[p] - nb) * (int64_t)cols;
+        hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, pb->xhi.p + off[p],
+                           pb->xlo.p + off[p], ld[p], nb, cols);
       }
+      if (m >= 8) {
+        gather_rows(pb, p, X, ldx, m, 1, nullptr, nullptr, pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], s);
+      } else {
+        switch (pb->dpn) {
+          case 1: RPF_GLP(1, 1); break;
+          case 2: RPF_GLP(2, 1); break;
+          default: RPF_GLP(3, 1);
+        }
+      }
+    } else if (m >= 8) {
+      gather_rows(pb, p, X, ldx, m, 0, nullptr, pb->xloc32.p + off[p], nullptr, nullptr, ld[p], s);
     } else {
       switch (pb->dpn) {
         case 1: RPF_GLP(1, 0); break;
@@ -435,21 +548,22 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     void* tok = trace_begin(s);
     if (split) {
       RPF_CHECK(P->ldlp == ld[p], RPF_EINVAL, "low-precision S+ layout mismatch");
-      const bool big = nb >= 128 && cols >= 128;
-      const int T = big ? 128 : 64;
-      dim3 g2((unsigned)cdiv(nb, T), (unsigned)cdiv(cols, T), (unsigned)nsp[p]);
-#define RPF_BF(BMN, X3)                                                                                          \
-  hipLaunchKernelGGL((k_gemm_bf16<BMN, BMN, X3>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p, P->Sp_lo.p, \
+      const int tm = tile_m[p], tn = tile_n[p];
+      dim3 g2((unsigned)cdiv(nb, tm), (unsigned)cdiv(cols, tn), (unsigned)nsp[p]);
+#define RPF_BF(BM_, BN_, X3)                                                                                      \
+  RPF_TIMED_LAUNCH((k_gemm_bf16<BM_, BN_, X3>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p, P->Sp_lo.p, \
                      ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab)
       if (prec == RPF_BF16X3) {
-        if (big) RPF_BF(128, true); else RPF_BF(64, true);
+        if (tm == 128) RPF_BF(128, 128, true);
+        else RPF_BF(64, 64, true);
       } else {
-        if (big) RPF_BF(128, false); else RPF_BF(64, false);
+        if (tm == 128) RPF_BF(128, 128, false);
+        else RPF_BF(64, 64, false);
       }
 #undef RPF_BF
     } else {
       dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64), (unsigned)nsp[p]);
-      hipLaunchKernelGGL((k_sgemm_sym<64, 64>), g2, dim3(256), 0, s, nb, cols, nb, P->Splus32.p, (int64_t)nb,
+      RPF_TIMED_LAUNCH((k_sgemm_sym<64, 64>), g2, dim3(256), 0, s, nb, cols, nb, P->Splus32.p, (int64_t)nb,
                          pb->xloc32.p + off[p], ld[p], yp, ld[p], kch[p], slab);
     }
     RPF_LAUNCH_CHECK();

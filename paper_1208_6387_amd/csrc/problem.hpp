@@ -73,6 +73,10 @@ void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
 void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
 void coarse_solve(rpf_problem pb, const double* c, double* y, int m, hipStream_t s);
 // F X with a low-precision flexibility product (FP32 or bf16 split), FP64 in and out
+// Gather A^(s)T lam for every occurrence of pattern p into the W format (lanes over interface
+// columns; needs m >= 8 for full lanes).  mode 0: FP32 Xf, 1: bf16 hi/lo Xh/Xl, 2: FP64 X64.
+void gather_rows(rpf_problem pb, int p, const double* lam, int64_t ldl, int m, int mode, double* X64, float* Xf,
+                 uint16_t* Xh, uint16_t* Xl, int64_t ldx, hipStream_t s);
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
                      int64_t ldy, int prec, hipStream_t s);
 // event tracing of the flexibility products

@@ -135,3 +135,25 @@ def test_config4_solution_properties(R):
     for s in rng.choice(p.n_occ, 12, replace=False):
         res_s = pat.K @ u[s] - p.f_local[s] + _local_forces(p, lam, s, pat)
         assert np.abs(res_s).max() <= 1e-8 * np.abs(p.f_local[s]).max(), s
+
+
+def test_config4_operator_forms(R):
+    """512 occurrences: the low-precision products (large-tile kernels) against the FP64 one, and the
+    FP64 operator's symmetry x^T F y = y^T F x (a property of F at any size)."""
+    from paper_1208_6387_amd import structure as ST
+    p = W.config(4)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats, (R.FP64, R.BF16X3, R.FP32))
+    pb = ST.create_problem(p)
+    g = torch.Generator(device="cuda").manual_seed(4)
+    X = torch.randn(pb.n_lambda, 16, dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.randn(pb.n_lambda, 16, dtype=torch.float64, device="cuda", generator=g)
+    FX = R.feti_apply(pb, pats, X)
+    FY = R.feti_apply(pb, pats, Y)
+    a = (Y * FX).sum(0)
+    b = (X * FY).sum(0)
+    assert torch.max(torch.abs(a - b) / torch.abs(a)).item() < 1e-11
+    scale = FX.abs().max().item()
+    for prec, tol in ((R.BF16X3, 5e-5), (R.FP32, 5e-5)):
+        Z = R.feti_apply(pb, pats, X, prec=prec)
+        assert (Z - FX).abs().max().item() <= tol * scale, prec
