@@ -169,6 +169,10 @@ void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t
 // Tall-skinny Gram C (a x b, column-major ld a) = X^T Y for row-major X (N x a, ldx)
 // and Y (N x b, ldy); ws must hold gram_chunks(N, a, b) * a * b doubles.
 int gram_chunks(int64_t N, int a, int b);
+// C (a x (b1 + b2), column-major ld a) = X^T [Y1 | Y2]; one pass over X when a, b1, b2 <= 16.
+// ws must hold gram_chunks(N, a, 16) * a * (b1 + b2) doubles (and what two gram calls need).
+void gram_pair(hipStream_t s, int64_t N, int a, const double* X, int64_t ldx, int b1, const double* Y1,
+               int64_t ldy1, int b2, const double* Y2, int64_t ldy2, double* C, double* ws);
 void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy,
           double* C, double* ws);
 
@@ -181,6 +185,12 @@ void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const doubl
 // column-major with ld a).
 void rows_gemm_from(hipStream_t s, int64_t N, int a, int b, double alpha, const double* X, int64_t ldx,
                     const double* M, double beta, const double* Z, int64_t ldz, double* Y, int64_t ldy);
+// The paired product below (a, b <= 16, M column-major) that also returns the column sums of
+// squares of Y2 after the update: sq[c * ldsq], c < b (part: cdiv(N, 256) * b doubles of
+// workspace).  Returns false, doing nothing, when the block is too wide.
+bool rows_gemm2_sq(hipStream_t s, int64_t N, int a, int b, const double* M, double alpha1, const double* X1,
+                   int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2, const double* X2,
+                   int64_t ldx2, double beta2, double* Y2, int64_t ldy2, double* part, double* sq, int64_t ldsq);
 // Two such products sharing M in one launch: Y1 = beta1 Y1 + alpha1 X1 M, Y2 = beta2 Y2 + alpha2 X2 M.
 void rows_gemm2(hipStream_t s, int64_t N, int a, int b, const double* M, int64_t mrow, double alpha1,
                 const double* X1, int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2,

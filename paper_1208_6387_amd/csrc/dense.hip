@@ -293,6 +293,49 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t N, int a, int b, c
     part[((int64_t)blockIdx.y * b + cj) * a + ci] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
 }
 
+// Pair form: C = X^T [Y1 | Y2] for a <= 16 and b1, b2 <= 16, each workgroup computing both
+// 16 x 16 tiles from one read of X (the two Grams of a block step share their left operand).
+// part[chunk] holds a x (b1 + b2), column-major.
+__global__ __launch_bounds__(256) void k_gram_pair(int64_t N, int a, const double* X, int64_t ldx, int b1,
+                                                   const double* Y1, int64_t ldy1, int b2, const double* Y2,
+                                                   int64_t ldy2, int64_t chunk, double* part) {
+  __shared__ double red[4][2][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r_beg = (int64_t)blockIdx.x * chunk;
+  const int64_t r_end = min(N, r_beg + chunk);
+  const int i = lane & 15, j = lane & 15;
+  const bool iok = i < a, j1 = j < b1, j2 = j < b2;
+  v4d acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r0 = r_beg + 4 * wave; r0 < r_end; r0 += 64) {
+    double xa[4], y1[4], y2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + 16 * u + (lane >> 4);
+      const bool rok = row < r_end;
+      xa[u] = (rok && iok) ? X[row * ldx + i] : 0.0;
+      y1[u] = (rok && j1) ? Y1[row * ldy1 + j] : 0.0;
+      y2[u] = (rok && j2) ? Y2[row * ldy2 + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], y1[u], acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], y2[u], acc2, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    red[wave][0][((lane >> 4) + 4 * r) * 16 + (lane & 15)] = acc1[r];
+    red[wave][1][((lane >> 4) + 4 * r) * 16 + (lane & 15)] = acc2[r];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int ci = t / 16, cj = t % 16;
+  const int bt = b1 + b2;
+  double* pc = part + (int64_t)blockIdx.x * a * bt;
+  if (ci < a && cj < b1) pc[(int64_t)cj * a + ci] = red[0][0][t] + red[1][0][t] + red[2][0][t] + red[3][0][t];
+  if (ci < a && cj < b2) pc[(int64_t)(b1 + cj) * a + ci] = red[0][1][t] + red[1][1][t] + red[2][1][t] + red[3][1][t];
+}
+
 // Wide form (X with many columns, e.g. all stored search directions): a workgroup
 // covers 16 column tiles of X (4 per wave) against one 16-column tile of Y over
 // a chunk of rows; each Y fragment is loaded once and feeds 4 MFMAs, so Y is
@@ -367,6 +410,25 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
   RPF_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * b, 4)), dim3(256), 0, s, (int64_t)a,
                      (int64_t)b, gz, ws, 0.0, C, (int64_t)a);
+  RPF_LAUNCH_CHECK();
+}
+
+void gram_pair(hipStream_t s, int64_t N, int a, const double* X, int64_t ldx, int b1, const double* Y1,
+               int64_t ldy1, int b2, const double* Y2, int64_t ldy2, double* C, double* ws) {
+  if (a <= 0 || b1 + b2 <= 0) return;
+  if (a > 16 || b1 > 16 || b2 > 16) {
+    gram(s, N, a, b1, X, ldx, Y1, ldy1, C, ws);
+    gram(s, N, a, b2, X, ldx, Y2, ldy2, C + (int64_t)a * b1, ws);
+    return;
+  }
+  const int g = gram_chunks(N, a, 16);
+  const int64_t chunk = cdiv(N, g);
+  const int gz = (int)cdiv(N, chunk);
+  hipLaunchKernelGGL(k_gram_pair, dim3((unsigned)gz), dim3(256), 0, s, N, a, X, ldx, b1, Y1, ldy1, b2, Y2, ldy2,
+                     chunk, ws);
+  RPF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * (b1 + b2), 4)), dim3(256), 0, s, (int64_t)a,
+                     (int64_t)(b1 + b2), gz, ws, 0.0, C, (int64_t)a);
   RPF_LAUNCH_CHECK();
 }
 
@@ -482,6 +544,7 @@ struct RowsPair {
 };
 struct RowsPairs {
   RowsPair p[2];
+  double* colsq;  // optional: per-workgroup column sums of squares of pair 1's output (k_rows_tile)
 };
 
 __global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, const double* Mm, int64_t mrow,
@@ -584,12 +647,29 @@ __global__ __launch_bounds__(256) void k_rows_tile(int64_t N, int a, int b, cons
     for (int j = 0; j < 16; ++j)
       if (j < b) xs[tid][j] = acc[j];
   }
+  // with colsq (b divides 256), every element a thread writes lies in column tid % b: the thread
+  // sums their squares and the column sums are formed in a fixed order (deterministic)
+  const bool want_sq = pr.colsq != nullptr && blockIdx.y == 1;
+  double myq = 0.0;
   __syncthreads();
   for (int e = tid; e < rows * b; e += 256) {
     const int rr = e / b, cc = e - rr * b;
     double* y = P.Y + (r0 + rr) * P.ldy + cc;
     const double v = P.alpha * xs[rr][cc];
-    *y = (P.beta == 0.0) ? v : P.beta * (P.Z ? P.Z[(r0 + rr) * P.ldz + cc] : *y) + v;
+    const double out = (P.beta == 0.0) ? v : P.beta * (P.Z ? P.Z[(r0 + rr) * P.ldz + cc] : *y) + v;
+    *y = out;
+    myq += out * out;
+  }
+  if (want_sq) {
+    __syncthreads();
+    double* red = &xs[0][0];
+    red[tid] = myq;
+    __syncthreads();
+    if (tid < b) {
+      double t = 0.0;
+      for (int k = tid; k < 256; k += b) t += red[k];
+      pr.colsq[(int64_t)blockIdx.x * b + tid] = t;
+    }
   }
 }
 
@@ -624,6 +704,24 @@ void rows_gemm_from(hipStream_t s, int64_t N, int a, int b, double alpha, const 
   pr.p[0] = {X, Y, ldx, ldy, alpha, beta, Z, ldz};
   pr.p[1] = pr.p[0];
   launch_rows_small(s, N, a, b, M, 0, pr, 1);
+}
+
+bool rows_gemm2_sq(hipStream_t s, int64_t N, int a, int b, const double* M, double alpha1, const double* X1,
+                   int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2, const double* X2,
+                   int64_t ldx2, double beta2, double* Y2, int64_t ldy2, double* part, double* sq, int64_t ldsq) {
+  if (N <= 0 || b <= 0 || a > 16 || b > 16 || 256 % b != 0) return false;
+  RowsPairs pr{};
+  pr.p[0] = {X1, Y1, ldx1, ldy1, alpha1, beta1, nullptr, 0};
+  pr.p[1] = {X2, Y2, ldx2, ldy2, alpha2, beta2, nullptr, 0};
+  pr.colsq = part;
+  const unsigned nwg = (unsigned)cdiv(N, 256);
+  hipLaunchKernelGGL(k_rows_tile, dim3(nwg, 2), dim3(256), 0, s, N, a, b, M, (int64_t)0, pr);
+  RPF_LAUNCH_CHECK();
+  // sq[c * ldsq] = sum over workgroups of part[wg * b + c]
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(b, 4)), dim3(256), 0, s, (int64_t)1, (int64_t)b, (int)nwg,
+                     part, 0.0, sq, ldsq);
+  RPF_LAUNCH_CHECK();
+  return true;
 }
 
 void rows_gemm2(hipStream_t s, int64_t N, int a, int b, const double* M, int64_t mrow, double alpha1,

@@ -692,10 +692,13 @@ void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
 }
 
 void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, hipStream_t s) {
-  // dof slices per occurrence: about 1024 workgroups in all, at least 256 dofs per slice
-  const int max_nd = *std::max_element(pb->pat_nbn.begin(), pb->pat_nbn.end()) * pb->dpn;
-  const int nsplit = (int)std::max<int64_t>(
-      1, std::min<int64_t>(cdiv(1024, pb->n_occ), cdiv(max_nd, 256)));
+  // slices per occurrence: about 1024 workgroups in all, at least 256 dofs per slice; with lanes
+  // over columns also at most ~8 nodes per lane group, so that the dependent loads of many
+  // nodes are in flight at once
+  const int max_nbn = *std::max_element(pb->pat_nbn.begin(), pb->pat_nbn.end());
+  const int max_nd = max_nbn * pb->dpn;
+  int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, pb->n_occ), cdiv(max_nd, 256)));
+  if (m >= 8) nsplit = std::max<int>(nsplit, (int)cdiv(max_nbn, (m > 8 ? 16 : 32) * 8));
   pb->cpart.ensure((size_t)pb->n_occ * nsplit * KMAX * m);
   const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
   if (m >= 8) {

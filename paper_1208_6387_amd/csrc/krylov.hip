@@ -329,7 +329,7 @@ struct Solver {
   int64_t ldW = 0;
   int max_blocks = 0;
   // small matrices
-  DevBuf<double> eta, V, w, T, alpha, gam, Bt, Cb, Mo, nrm, ws, estate;
+  DevBuf<double> eta, V, w, T, alpha, gam, Bt, Cb, Mo, nrm, ws, estate, sqpart;
   DevBuf<int> drops;
   std::vector<double> r0n;  // ||r0_c||^2 of the FP64 residual
   int iterations = 0, rank_drops = 0;
@@ -378,8 +378,9 @@ struct Solver {
       fill(s, nrm2[k].p + (size_t)nr * nr, 1, 0.0);
     }
   }
-  void post_norms(const double* X, int slot) {
-    gram(X, nr, nr, X, nr, nr, nrm2[slot].p);
+  // have_sq: the diagonal of nrm2[slot] already holds the squared residual norms
+  void post_norms(const double* X, int slot, bool have_sq = false) {
+    if (!have_sq) gram(X, nr, nr, X, nr, nr, nrm2[slot].p);
     RPF_HIP(hipMemcpyAsync(hnorm + (size_t)slot * slot_len(), nrm2[slot].p, sizeof(double) * slot_len(),
                            hipMemcpyDeviceToHost, s));
     RPF_HIP(hipEventRecord(nev[slot], s));
@@ -411,7 +412,7 @@ struct Solver {
     Rs.ensure((size_t)N * nr);
     dlam.ensure((size_t)N * nr);
     tmp.ensure((size_t)N * std::max(nr, m));
-    eta.ensure((size_t)m * m);
+    eta.ensure((size_t)m * (m + nr));
     V.ensure((size_t)m * m);
     w.ensure(m);
     T.ensure((size_t)m * m);
@@ -502,8 +503,14 @@ struct Solver {
       }
       // P = Q^T F Z
       apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, true, s);
-      // eta = Z^T P, T with T^T eta T = I on the kept directions
-      gram(Zs, ldW, m, Ps, ldW, m, eta.p);
+      // [eta | Z^T R] = Z^T [P | R] in one pass over Z; T with T^T eta T = I on the kept directions
+      {
+        const size_t need = std::max((size_t)gram_chunks(N, m, 16) * m * (m + nr),
+                                     (size_t)gram_chunks(N, m, std::max(m, nr)) * m * std::max(m, nr));
+        ws.ensure(need);
+        gram_pair(s, N, m, Zs, ldW, m, Ps, ldW, nr, Rs.p, nr, eta.p, ws.p);
+      }
+      double* zr = eta.p + (int64_t)m * m;
       double* Tj = Tall.p + (int64_t)slot * m * m;
       {
         double* f0 = nrm2[0].p + (size_t)nr * nr;
@@ -521,17 +528,23 @@ struct Solver {
         if (!diag_only) eta_eigen_T(s, eta.p, m, estate.p, tau, Tj, drops.p, f0, f1);
       }
       // alpha = W^T R = T^T (Z^T R); gamma = T alpha; lambda += Z gamma; R -= P gamma
-      gram(Zs, ldW, m, Rs.p, nr, nr, alpha.p);
-      hipLaunchKernelGGL(k_tblocks, dim3(1), dim3(256), 0, s, 1, m, nr, Tj, 1, alpha.p, gam.p);
+      hipLaunchKernelGGL(k_tblocks, dim3(1), dim3(256), 0, s, 1, m, nr, Tj, 1, zr, gam.p);
       if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * nr)), dim3(256), 0, s, gam.p, m, nr, (int64_t)m);
       hipLaunchKernelGGL(k_tblocks, dim3(1), dim3(256), 0, s, 1, m, nr, Tj, 0, gam.p, alpha.p);
       RPF_LAUNCH_CHECK();
-      rows_gemm2(s, N, m, nr, alpha.p, 0, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0, Rs.p, nr);
+      const bool check = (it + 1) % check_every == 0 || it + 1 == max_it;
+      const int slot_n = nchk & 1;
+      // the residual update also returns the squared column norms (into the check slot)
+      sqpart.ensure((size_t)cdiv(N, 256) * nr);
+      const bool have_sq =
+          check && rows_gemm2_sq(s, N, m, nr, alpha.p, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0, Rs.p, nr,
+                                 sqpart.p, nrm2[slot_n].p, nr + 1);
+      if (!have_sq)
+        rows_gemm2(s, N, m, nr, alpha.p, 0, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0, Rs.p, nr);
       ++nst;
       ++iterations;
-      if ((it + 1) % check_every == 0 || it + 1 == max_it) {
-        const int slot_n = nchk & 1;
-        post_norms(Rs.p, slot_n);
+      if (check) {
+        post_norms(Rs.p, slot_n, have_sq);
         // the previous check is read now, while this iteration is already queued; when it
         // reports convergence the solve stops after this (extra, still valid) iteration
         if (pending >= 0 && (conv = read_norms(pending, target)) != GOING) {
