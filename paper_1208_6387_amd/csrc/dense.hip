@@ -883,12 +883,131 @@ void schur_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fa
         true);
 }
 
+// Panel triangular solve for many right-hand sides: one workgroup owns PW = 16 columns of B and
+// walks all diagonal blocks in order (persistent), left-looking: for block t it forms
+// B_t - L_t,band X_band on FP64 MFMA, stages the result in LDS and multiplies it by the inverted
+// diagonal block, overwriting B_t with X_t.  Forward (L X = B) uses the rows of block t from column
+// lo[t]; backward (L^T X = B) the rows j0 + 64 .. hi[t] of column block t.  The band is split over
+// the four waves (wave w takes every fourth group of 16 k, all 64 rows of the block: four
+// independent accumulators), the loads of a wave's next group are in flight while the MFMAs of
+// the current one run, and the four partial products are summed in LDS.  The band operands come
+// from L2 (every workgroup reads the same band of L; its own panel of X was written by itself one
+// block earlier).
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_trsm_panel(const double* L, int64_t ldl, int64_t n, const double* dinv,
+                                                    const int64_t* lo, const int64_t* hi, double* B, int64_t ldb,
+                                                    int64_t nrhs) {
+  constexpr int PW = 16;
+  __shared__ double S[NB][PW + 1];
+  __shared__ double red[4][NB][PW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t col = (int64_t)blockIdx.x * PW + li;
+  const bool cok = col < nrhs;
+  const int64_t nblk = (n + NB - 1) / NB;
+  for (int64_t step = 0; step < nblk; ++step) {
+    const int64_t t = FWD ? step : nblk - 1 - step;
+    const int64_t j0 = t * NB;
+    const int jb = (int)min<int64_t>(NB, n - j0);
+    v4d acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    int64_t kb, ke;
+    if (FWD) {
+      kb = max<int64_t>(0, lo[t]);
+      ke = j0;
+    } else {
+      kb = j0 + jb;
+      ke = min<int64_t>(hi[t], n);
+    }
+    // group g covers k in [kb + 16 g, kb + 16 g + 16); wave w takes g = w, w + 4, ...
+    auto load = [&](int64_t k0, double* a, double* b) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t k = k0 + 4 * u + lk;
+        const bool kok = k < ke;
+        b[u] = (kok && cok) ? B[k + col * ldb] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t row = j0 + 16 * q + li;
+          a[4 * q + u] = (kok && row < j0 + jb) ? (FWD ? L[row + k * ldl] : L[k + row * ldl]) : 0.0;
+        }
+      }
+    };
+    double a[16], b[4], na[16], nb[4];
+    int64_t k0 = kb + 16 * w;
+    if (k0 < ke) load(k0, a, b);
+    for (; k0 < ke; k0 += 64) {
+      const bool more = k0 + 64 < ke;
+      if (more) load(k0 + 64, na, nb);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[4 * q + u], b[u], acc[q], 0, 0, 0);
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u] = na[u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) b[u] = nb[u];
+      }
+    }
+    // accumulator item r of tile q, lane l: row 16 q + l/16 + 4 r, column l % 16
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[w][16 * q + lk + 4 * r][li] = acc[q][r];
+    __syncthreads();
+    for (int e = tid; e < NB * PW; e += 256) {
+      const int ri = e / PW, cj = e % PW;
+      const int64_t gc = (int64_t)blockIdx.x * PW + cj;
+      const double bv = (ri < jb && gc < nrhs) ? B[j0 + ri + gc * ldb] : 0.0;
+      S[ri][cj] = bv - (red[0][ri][cj] + red[1][ri][cj] + red[2][ri][cj] + red[3][ri][cj]);
+    }
+    __syncthreads();
+    // X_t = inv(L_tt) S (forward) or inv(L_tt)^T S (backward): dinv column-major NB x NB; wave w
+    // forms rows 16 w .. 16 w + 15
+    v4d x = {0.0, 0.0, 0.0, 0.0};
+    const double* D = dinv + t * NB * NB;
+#pragma unroll 4
+    for (int kk = 0; kk < NB; kk += 4) {
+      const int k = kk + lk, i = 16 * w + li;
+      const double av = FWD ? D[i + k * NB] : D[k + i * NB];
+      x = __builtin_amdgcn_mfma_f64_16x16x4f64(av, S[k][li], x, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ri = 16 * w + lk + 4 * r;
+      if (ri < jb && cok) B[j0 + ri + col * ldb] = x[r];
+    }
+    __syncthreads();  // X_t is read by the band products of the following blocks
+  }
+}
+
 void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* dinv, const Envelope& env,
           double* B, int64_t ldb, int64_t nrhs, bool trans) {
   if (n <= 0 || nrhs <= 0) return;
   const int64_t nblk = cdiv(n, NB);
   bool dense = true;
   for (int64_t t = 0; t < nblk && dense; ++t) dense = env.cstart[t] <= 0 && env.rend[t] >= n;
+  if (!dense && nrhs >= 2048) {
+    // banded factor, many right-hand sides: one persistent pass per 16-column panel
+    std::vector<int64_t> bounds(2 * nblk);
+    for (int64_t t = 0; t < nblk; ++t) {
+      bounds[t] = env.cstart[t];
+      bounds[nblk + t] = env.rend[t];
+    }
+    DevBuf<int64_t> db;
+    db.upload(bounds.data(), bounds.size(), s);
+    const dim3 grid((unsigned)cdiv(nrhs, 16));
+    if (!trans)
+      hipLaunchKernelGGL(k_trsm_panel<true>, grid, dim3(256), 0, s, L, ldl, n, dinv, db.p, db.p + nblk, B, ldb, nrhs);
+    else
+      hipLaunchKernelGGL(k_trsm_panel<false>, grid, dim3(256), 0, s, L, ldl, n, dinv, db.p, db.p + nblk, B, ldb,
+                         nrhs);
+    RPF_LAUNCH_CHECK();
+    RPF_HIP(hipStreamSynchronize(s));  // the bounds buffer is freed on return
+    return;
+  }
   if (dense && nrhs >= 4096) {
     // Full factor, many right-hand sides (the identity of the condensation): left-looking by row
     // blocks.  Block t first takes the contributions of all solved blocks, B_t -= L_t,prev X_prev
