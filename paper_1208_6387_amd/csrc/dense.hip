@@ -126,6 +126,19 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
 
 // Sum of the split-K partials: one wavefront per output, lanes stride over the
 // splits (fixed order, so the result is deterministic).
+// Few slabs, many outputs: one thread per output, slabs summed in order (coalesced over outputs).
+__global__ __launch_bounds__(256) void k_splitk_reduce_thread(int64_t M, int64_t N, int splits, const double* part,
+                                                              double beta, double* C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t MN = M * N;
+  if (idx >= MN) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * MN + idx];
+  const int64_t m = idx % M, n = idx / M;
+  double* c = C + n * ldc + m;
+  *c = (beta == 0.0) ? s : s + beta * *c;
+}
+
 __global__ __launch_bounds__(256) void k_splitk_reduce(int64_t M, int64_t N, int splits, const double* part,
                                                        double beta, double* C, int64_t ldc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -249,8 +262,12 @@ void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t
   const int64_t kchunk = cdiv(cdiv(K, splits), 16) * 16;
   const int gz = (int)cdiv(K, kchunk);
   launch_gemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, 0.0, nullptr, 0, false, splits, ws);
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 4)), dim3(256), 0, s, M, N, gz, ws, beta, C,
-                     ldc);
+  if (gz <= 32)
+    hipLaunchKernelGGL(k_splitk_reduce_thread, dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s, M, N, gz, ws, beta,
+                       C, ldc);
+  else
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 4)), dim3(256), 0, s, M, N, gz, ws, beta, C,
+                       ldc);
   RPF_LAUNCH_CHECK();
 }
 
@@ -706,6 +723,22 @@ void rows_gemm_from(hipStream_t s, int64_t N, int a, int b, double alpha, const 
   launch_rows_small(s, N, a, b, M, 0, pr, 1);
 }
 
+// out[c * ldo] = sum_z part[z * b + c]: one workgroup per column c, a fixed partition of z over the
+// threads and a fixed tree (deterministic).
+__global__ __launch_bounds__(256) void k_colsum(int nz, int b, const double* part, double* out, int64_t ldo) {
+  __shared__ double red[256];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  double v = 0.0;
+  for (int z = tid; z < nz; z += 256) v += part[(int64_t)z * b + c];
+  red[tid] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) out[(int64_t)c * ldo] = red[0];
+}
+
 bool rows_gemm2_sq(hipStream_t s, int64_t N, int a, int b, const double* M, double alpha1, const double* X1,
                    int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2, const double* X2,
                    int64_t ldx2, double beta2, double* Y2, int64_t ldy2, double* part, double* sq, int64_t ldsq) {
@@ -718,8 +751,7 @@ bool rows_gemm2_sq(hipStream_t s, int64_t N, int a, int b, const double* M, doub
   hipLaunchKernelGGL(k_rows_tile, dim3(nwg, 2), dim3(256), 0, s, N, a, b, M, (int64_t)0, pr);
   RPF_LAUNCH_CHECK();
   // sq[c * ldsq] = sum over workgroups of part[wg * b + c]
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(b, 4)), dim3(256), 0, s, (int64_t)1, (int64_t)b, (int)nwg,
-                     part, 0.0, sq, ldsq);
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)b), dim3(256), 0, s, (int)nwg, b, part, sq, ldsq);
   RPF_LAUNCH_CHECK();
   return true;
 }

@@ -398,6 +398,69 @@ __global__ __launch_bounds__(256) void k_coarse_g(int n_mult, const int* ep_occ,
   }
 }
 
+// Rows of G per multiplier, built once per coarse space: Grow[((mult*2 + e)*DPN + c)*km + r] =
+// sign_e (O_e Z[bn_e])[c][r] (zero past the pattern's kernel or for a missing endpoint), and the
+// first coarse index of each endpoint's occurrence (-1 when absent).
+template <int DPN>
+__global__ void k_build_grows(int n_mult, int km, const int* ep_occ, const int* ep_bn, const int8_t* ep_sign,
+                              const int* occ_pat, const int* nbn_p, const double* const* Zp, const int* kp,
+                              const int* goff, const double* rot, double* Grow, int* ep_goff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = 2 * DPN * km;
+  if (i >= (int64_t)n_mult * per) return;
+  const int r = (int)(i % km), c = (int)((i / km) % DPN), e = (int)((i / (km * DPN)) % 2);
+  const int mult = (int)(i / per);
+  const int s = ep_occ[2 * mult + e];
+  double v = 0.0;
+  if (s >= 0) {
+    const int p = occ_pat[s];
+    if (r < kp[p]) {
+      const int64_t ldz = (int64_t)nbn_p[p] * DPN;
+      const double* zr = Zp[p] + (int64_t)ep_bn[2 * mult + e] * DPN + r * ldz;
+      if (DPN == 3 && rot) {
+        const double* O = rot + 9 * (int64_t)s;
+        v = O[3 * c] * zr[0] + O[3 * c + 1] * zr[1 % DPN] + O[3 * c + 2] * zr[2 % DPN];
+      } else {
+        v = zr[c];
+      }
+      v *= (double)ep_sign[2 * mult + e];
+    }
+  }
+  Grow[i] = v;
+  if (r == 0 && c == 0) ep_goff[2 * mult + e] = s >= 0 ? goff[s] : -1;
+}
+
+// x = beta x + alpha G y from the stored rows of G: one thread per (multiplier, column).
+template <int DPN, int KM>
+__global__ __launch_bounds__(256) void k_coarse_g_rows(int n_mult, const double* Grow, const int* ep_goff, int nG,
+                                                       const double* y, int m, double alpha, double* x, int64_t ldx,
+                                                       double beta) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_mult * m) return;
+  const int mult = (int)(idx / m), j = (int)(idx % m);
+  double acc[DPN];
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int go = ep_goff[2 * mult + e];
+    if (go < 0) continue;
+    const double* g = Grow + ((int64_t)mult * 2 + e) * DPN * KM;
+    double yr[KM];
+#pragma unroll
+    for (int r = 0; r < KM; ++r) yr[r] = (go + r < nG) ? y[((int64_t)go + r) * m + j] : 0.0;  // rows past k: G is 0
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+#pragma unroll
+      for (int r = 0; r < KM; ++r) acc[c] += g[c * KM + r] * yr[r];
+  }
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) {
+    double* xv = x + ((int64_t)mult * DPN + c) * ldx + j;
+    *xv = (beta == 0.0) ? alpha * acc[c] : beta * *xv + alpha * acc[c];
+  }
+}
+
 // Coarse matrix, diagonal blocks: (G^T G)_{s,s} = sum_bn count(s,bn) Z[bn]^T Z[bn]
 // (rotations are orthogonal and signs square to one).  One workgroup per occurrence.
 template <int DPN>
@@ -689,6 +752,26 @@ void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
     pb->coarse_key.clear();
     throw Error(RPF_ENOTSPD, "coarse matrix G^T G is singular (the structure has no Dirichlet condition?)");
   }
+  // rows of G per multiplier for the projections (x -= G y)
+  int km = 0;
+  for (int p = 0; p < pb->n_pat; ++p) km = std::max(km, kp[p]);
+  pb->g_km = km <= 1 ? 1 : km <= 3 ? 3 : km <= 6 ? 6 : KMAX;
+  if (pb->n_mult > 0) {
+    const int64_t tot = (int64_t)pb->n_mult * 2 * pb->dpn * pb->g_km;
+    pb->d_grow.ensure((size_t)tot);
+    pb->d_ep_goff.ensure((size_t)2 * pb->n_mult);
+#define RPF_BG(D)                                                                                                \
+  hipLaunchKernelGGL(k_build_grows<D>, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, pb->n_mult, pb->g_km,      \
+                     pb->d_ep_occ.p, pb->d_ep_bn.p, pb->d_ep_sign.p, pb->d_occ_pat.p, pb->d_nbn.p, pb->d_Zp.p,     \
+                     pb->d_kp.p, pb->d_goff.p, pb->has_rot ? pb->d_rot.p : nullptr, pb->d_grow.p, pb->d_ep_goff.p)
+    switch (pb->dpn) {
+      case 1: RPF_BG(1); break;
+      case 2: RPF_BG(2); break;
+      default: RPF_BG(3);
+    }
+#undef RPF_BG
+    RPF_LAUNCH_CHECK();
+  }
 }
 
 void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, hipStream_t s) {
@@ -737,6 +820,27 @@ void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, i
               hipStream_t s) {
   if (pb->n_mult == 0) return;
   dim3 grid((unsigned)cdiv((int64_t)pb->n_mult * m, 256));
+  if (pb->d_grow.p && pb->g_km > 0) {
+#define RPF_CGR(D, KM)                                                                                       \
+  hipLaunchKernelGGL((k_coarse_g_rows<D, KM>), grid, dim3(256), 0, s, pb->n_mult, pb->d_grow.p, pb->d_ep_goff.p, \
+                     pb->n_G, y, m, alpha, x, ldx, beta)
+#define RPF_CGK(D)                                       \
+  switch (pb->g_km) {                                     \
+    case 1: RPF_CGR(D, 1); break;                         \
+    case 3: RPF_CGR(D, 3); break;                         \
+    case 6: RPF_CGR(D, 6); break;                         \
+    default: RPF_CGR(D, KMAX);                            \
+  }
+    switch (pb->dpn) {
+      case 1: RPF_CGK(1); break;
+      case 2: RPF_CGK(2); break;
+      default: RPF_CGK(3);
+    }
+#undef RPF_CGK
+#undef RPF_CGR
+    RPF_LAUNCH_CHECK();
+    return;
+  }
 #define RPF_CG(K, D)                                                                                       \
   hipLaunchKernelGGL(K<D>, grid, dim3(256), 0, s, pb->n_mult, pb->d_ep_occ.p, pb->d_ep_bn.p,               \
                      pb->d_ep_sign.p, pb->d_occ_pat.p, pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_goff.p,    \

@@ -47,6 +47,10 @@ struct rpf_problem_s {
   int n_G = 0;
   std::vector<int> goff;
   rpf::DevBuf<int> d_goff, d_kp, d_nbn;
+  // rows of G per multiplier (2 endpoints x dpn x g_km) and each endpoint's first coarse index
+  rpf::DevBuf<double> d_grow;
+  rpf::DevBuf<int> d_ep_goff;
+  int g_km = 0;
   rpf::DevBuf<const double*> d_Zp;
   rpf::DevBuf<double> Ginv, cbuf, ybuf, cpart, cws;
 };
