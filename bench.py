@@ -25,16 +25,17 @@ PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 HBM_GBPS = 8000.0
 
 WORKLOADS = {
-    # name: (configuration index, method, description, solver settings)
-    "elast-12cube-4x4x4-8rhs": (2, "orthodir", "3-D elasticity, 12^3-brick pattern x 64 occurrences (4x4x4), "
+    # name: (configuration index, method, description, solver settings).  One permutation per load
+    # case: the short block-CG recurrence (block ORTHODIR stays available through --method).
+    "elast-20cube-8x8x8-16rhs": (4, "block_cg", "3-D elasticity, 20^3-brick pattern x 512 occurrences (8x8x8), "
+                                                "16 load cases + traction on x=1, clamped x=0",
+                                 dict(max_blocks=48, inner_tol=1e-4)),
+    "elast-12cube-4x4x4-8rhs": (2, "block_cg", "3-D elasticity, 12^3-brick pattern x 64 occurrences (4x4x4), "
                                                "8 load cases, clamped x=0",
                                 dict(max_blocks=0, inner_tol=1e-4)),
     "elast-12cube-4x4x4": (1, "orthodir", "3-D elasticity, 12^3-brick pattern x 64 occurrences (4x4x4), "
                                           "1 load case, 8 permutations", dict(max_blocks=0, inner_tol=1e-4)),
     "heat-row-16x16x4": (0, "orthodir", "2-D heat, 16x16 pattern x 4 (row)", dict(max_blocks=0, inner_tol=1e-4)),
-    # 512 occurrences x 16 cases: one stored (W, P) block is 456 MB, so ORTHODIR restarts every 48 blocks
-    "elast-20cube-8x8x8-16rhs": (4, "orthodir", "3-D elasticity, 20^3-brick pattern x 512 occurrences (8x8x8), "
-                                                "16 load cases + traction on x=1", dict(max_blocks=48, inner_tol=1e-3)),
 }
 PREC_NAMES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16": 3}
 METHODS = {"classical": 0, "block_cg": 1, "orthodir": 2}
@@ -49,7 +50,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="elast-12cube-4x4x4-8rhs", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="elast-20cube-8x8x8-16rhs", choices=sorted(WORKLOADS))
+    ap.add_argument("--method", default=None, choices=sorted(METHODS), help="solver (default per workload)")
     ap.add_argument("--forms", default="bf16x3,fp64",
                     help="comma list of fp64, fp32, bf16x3, bf16 (first is the headline)")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -78,6 +80,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     R.load()
     cfg_idx, method_name, desc, settings = WORKLOADS[args.workload]
+    if args.method is not None:
+        method_name = args.method
     if args.max_blocks is not None:
         settings = dict(settings, max_blocks=args.max_blocks)
     method = METHODS[method_name]
@@ -198,7 +202,9 @@ def main():
         out["speedup_vs_fp64"] = {k: round(results["fp64"]["ms"] / v["ms"], 3) for k, v in results.items()}
 
     if args.cpu:
-        out["cpu_baseline"] = cpu_baseline(p, cfg_idx, hr["stats"]["iterations"], args.cpu_iterations, args.tol)
+        # the oracle computes in FP64: it is timed for the FP64 form's iteration count when measured
+        it_ref = results.get("fp64", hr)["stats"]["iterations"]
+        out["cpu_baseline"] = cpu_baseline(p, cfg_idx, it_ref, args.cpu_iterations, args.tol)
     print(json.dumps(out), flush=True)
 
 
@@ -224,18 +230,23 @@ def traffic_for(workload, form):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(p, cfg_idx, gpu_iterations, n_it, tol):
-    """The CPU oracle as it stands, on a bounded sample: full setup (Schur complement, kernel, S+,
-    assembly operators, coarse matrix) and condensed loads, then n_it iterations of the same block
-    solver; extrapolated linearly in iterations to the GPU's iteration count."""
-    import numpy as np
-
-    import oracle as O
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
     except Exception:
-        threads = len(os.sched_getaffinity(0))
+        return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(p, cfg_idx, gpu_iterations, n_it, tol):
+    """The CPU oracle as it stands, on a bounded sample.  Small patterns: full setup (Schur
+    complement, kernel, S+, assembly operators, coarse matrix) and condensed loads, then n_it
+    iterations of the same block solver, extrapolated linearly in iterations.  Large patterns (where
+    the full oracle takes hours): its steps timed on samples and scaled, see cpu_baseline_sampled."""
+    if max(len(pat.bdofs) for pat in p.patterns) > 4000:
+        return cpu_baseline_sampled(p, gpu_iterations)
+    import oracle as O
+    threads = _blas_threads()
     log(f"[bench] cpu baseline: oracle setup + {n_it} iterations on {threads} BLAS threads")
     t0 = time.perf_counter()
     o = O.FetiOracle(p)
@@ -248,6 +259,79 @@ def cpu_baseline(p, cfg_idx, gpu_iterations, n_it, tol):
     return {"value": round(est * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
             "sample": f"setup+loads ({(t1 - t0):.1f} s) and {n_it} ORTHODIR iterations ({per_it * 1e3:.0f} ms each) "
                       f"timed, extrapolated to {gpu_iterations} iterations; recovery not included"}
+
+
+def cpu_baseline_sampled(p, gpu_iterations, n_cols=256, q=2048, n_sample_occ=8):
+    """Oracle time-to-solution of a large workload from timed samples of its own steps (about 20 s):
+    - pattern: the sparse LU of K_ii (full); its solve with n_cols of the K_ib columns, scaled to the
+      n_b columns of the Schur complement plus the interior solves of the loads and the recovery
+      (2 n_occ n_rhs columns); the Schur product K_ib^T X for those columns against all n_b,
+      scaled by n_b / n_cols; the kernel eigendecomposition and the pseudo-inverse on a q x q block,
+      scaled by (n_b / q)^3;
+    - iterations: the oracle's F loop body (A^(s) S+ A^(s)T X on the full structure) for
+      n_sample_occ occurrences, with a stand-in S+ of the true size (its cost does not depend on the
+      values), scaled to all occurrences and to the iteration count; the projections and the vector
+      updates are not included;
+    - loads and recovery: one such occurrence product each."""
+    import numpy as np
+    import scipy.sparse.linalg as spla
+
+    import oracle as O
+    from oracle import feti as OF
+    threads = _blas_threads()
+    log(f"[bench] cpu baseline (sampled oracle steps) on {threads} BLAS threads")
+    rng = np.random.default_rng(0)
+    pat = p.patterns[0]
+    n_occ = p.n_occ
+    K = pat.K.tocsc()
+    b = np.asarray(pat.bdofs, np.int64)
+    mask = np.ones(K.shape[0], bool)
+    mask[b] = False
+    i = np.nonzero(mask)[0]
+    nb = len(b)
+    t = {}
+    t0 = time.perf_counter()
+    lu = spla.splu(K[i][:, i].tocsc())
+    t["lu"] = time.perf_counter() - t0
+    Kib = K[i][:, b].toarray()
+    t0 = time.perf_counter()
+    X = lu.solve(np.ascontiguousarray(Kib[:, :n_cols]))
+    t["solves"] = (time.perf_counter() - t0) / n_cols * (nb + 2 * n_occ * p.n_rhs)
+    t0 = time.perf_counter()
+    Kib.T @ X
+    t["schur"] = (time.perf_counter() - t0) * nb / n_cols
+    qq = min(q, nb)
+    A = K[b[:qq]][:, b[:qq]].toarray()
+    A = 0.5 * (A + A.T) + qq * np.eye(qq)
+    t0 = time.perf_counter()
+    OF.pseudo_inverse(A, OF.kernel_basis(A, 1e-10))
+    t["dense"] = (time.perf_counter() - t0) * (nb / qq) ** 3
+    # the F loop body on the real structure for a few occurrences (oracle assembly code)
+    stub = type("StandInPattern", (), {})()
+    stub.n_b = nb
+    stub.Splus = rng.standard_normal((nb, nb))
+    o = O.FetiOracle.__new__(O.FetiOracle)
+    o.pb, o.dpn, o.n_lambda, o.pats = p, p.dpn, p.n_lambda, [stub]
+    pos = np.full(pat.n_nodes, -1, np.int64)
+    pos[pat.bnodes] = np.arange(len(pat.bnodes))
+    o.bpos = [pos]
+    occs = np.linspace(0, n_occ - 1, n_sample_occ).astype(int)
+    As = [o._assembly(int(s_)) for s_ in occs]
+    Xs = rng.standard_normal((p.n_lambda, p.n_rhs))
+    Y = np.zeros_like(Xs)
+    t0 = time.perf_counter()
+    for As_ in As:
+        Y += As_ @ (stub.Splus @ (As_.T @ Xs))
+    f_occ = (time.perf_counter() - t0) / len(As)
+    t["iterations"] = f_occ * n_occ * gpu_iterations
+    t["loads_recovery"] = 2 * f_occ * n_occ
+    est = sum(t.values())
+    detail = ", ".join(f"{k} {v:.1f} s" for k, v in t.items())
+    return {"value": round(est * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"oracle steps timed on samples and scaled (LU of K_ii in full; interior solves and Schur "
+                      f"product on {n_cols} of {nb} boundary columns; kernel and pseudo-inverse on a {qq}x{qq} "
+                      f"block scaled by (n_b/{qq})^3; the F loop body for {n_sample_occ} of {n_occ} occurrences "
+                      f"scaled to all and to {gpu_iterations} iterations; projections not included): {detail}"}
 
 
 if __name__ == "__main__":
