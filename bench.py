@@ -139,7 +139,9 @@ def main():
             stats.append(res.stats)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        tr = R.trace_read()
+        # products of the form's own precision; a low-precision solve also runs a few FP64 products
+        # (the residuals of its refinement sweeps), which are not the kernel this form is bound by
+        tr = R.trace_read(prec)
         R.trace_enable(False)
         ms = (t1 - t0) * 1e3 / args.steps
         st = stats[-1]

@@ -223,11 +223,14 @@ rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* patterns, int32
  * occurrences of a pattern), the hot kernel of every iteration.  While enabled,
  * every such product launched by feti_apply or block_krylov_solve is bracketed
  * by HIP events on its own stream.  rpf_trace_read synchronises those events,
- * returns the number of products, their summed duration in ms and their
- * algorithmic flop count (2 n_b^2 columns each), then resets the counters.
+ * returns the number of products computed in precision prec (an rpf_prec
+ * value; prec < 0 counts every product), their summed duration in ms and their
+ * algorithmic flop count (2 n_b^2 columns each), then drops every recorded
+ * product, counted or not.  A low-precision solve also runs FP64 products (the
+ * residuals of its refinement sweeps): read them with prec = RPF_FP64.
  * Process-wide; not meant for concurrent solves. */
 rpf_status rpf_trace_enable(int32_t on);
-rpf_status rpf_trace_read(int64_t* count, double* total_ms, double* flops);
+rpf_status rpf_trace_read(int32_t prec, int64_t* count, double* total_ms, double* flops);
 
 /* ------------------------------------------------------------------ dense helpers */
 

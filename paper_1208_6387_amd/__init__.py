@@ -233,8 +233,9 @@ def trace_enable(on: bool = True) -> None:
     check(load().rpf_trace_enable(1 if on else 0))
 
 
-def trace_read() -> dict:
-    """Products launched since the last read: count, summed kernel ms, algorithmic flops."""
+def trace_read(prec: int = -1) -> dict:
+    """Products launched since the last read in precision prec (FP64, FP32, BF16X3 or BF16; -1 for all): count,
+    summed kernel ms, algorithmic flops.  Every recorded product is dropped by the read."""
     n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
-    check(load().rpf_trace_read(C.byref(n), C.byref(ms), C.byref(fl)))
+    check(load().rpf_trace_read(int(prec), C.byref(n), C.byref(ms), C.byref(fl)))
     return {"count": n.value, "ms": ms.value, "flops": fl.value}

@@ -75,7 +75,7 @@ def load() -> C.CDLL:
         "rpf_dposv": (i32, [i64, vp, i64, i64, vp, i64, vp]),
         "rpf_dsyev_small": (i32, [i32, i32, vp, vp, vp, vp]),
         "rpf_trace_enable": (i32, [i32]),
-        "rpf_trace_read": (i32, [C.POINTER(i64), C.POINTER(f64), C.POINTER(f64)]),
+        "rpf_trace_read": (i32, [i32, C.POINTER(i64), C.POINTER(f64), C.POINTER(f64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -680,7 +680,7 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     double* xp = pb->xloc.p + off[p];
     double* yp = pb->yloc.p + yoff[p];
     gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, nb, s);
-    void* tok = trace_begin(s);
+    void* tok = trace_begin(s, RPF_FP64);
     if (nsp[p] > 1) dgemm_partials(s, nb, cols, nb, pats[p]->Splus.p, nb, xp, nb, yp, (int)((yoff[p + 1] - yoff[p]) / ((int64_t)nb * cols)));
     else dgemm(s, false, false, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, nb, 0.0, yp, nb);
     trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
@@ -1053,7 +1053,7 @@ struct TraceState {
   std::mutex mu;
   bool on = false;
   std::vector<hipEvent_t> pool;
-  struct Rec { hipEvent_t a, b; double flops; };
+  struct Rec { hipEvent_t a, b; double flops; int prec; };
   std::vector<Rec> pending;
 };
 TraceState& tstate() {
@@ -1077,7 +1077,7 @@ bool trace_on() { return tstate().on; }
 // The pair armed here is recorded by the next timed kernel launch on this thread (the
 // flexibility product), so the measured interval is that kernel alone; if no kernel consumed it,
 // both events are recorded at the end (empty interval).
-void* trace_begin(hipStream_t s) {
+void* trace_begin(hipStream_t s, int prec) {
   (void)s;
   TraceState& t = tstate();
   std::lock_guard<std::mutex> g(t.mu);
@@ -1085,7 +1085,7 @@ void* trace_begin(hipStream_t s) {
   LaunchEvents& le = launch_events();
   le.start = take_event(t);
   le.stop = take_event(t);
-  t.pending.push_back({le.start, le.stop, 0.0});
+  t.pending.push_back({le.start, le.stop, 0.0, prec});
   return (void*)(t.pending.size());
 }
 
@@ -1112,7 +1112,7 @@ extern "C" rpf_status rpf_trace_enable(int32_t on) {
   });
 }
 
-extern "C" rpf_status rpf_trace_read(int64_t* count, double* total_ms, double* flops) {
+extern "C" rpf_status rpf_trace_read(int32_t prec, int64_t* count, double* total_ms, double* flops) {
   return guarded([&] {
     TraceState& t = tstate();
     std::lock_guard<std::mutex> g(t.mu);
@@ -1122,9 +1122,11 @@ extern "C" rpf_status rpf_trace_read(int64_t* count, double* total_ms, double* f
       RPF_HIP(hipEventSynchronize(r.b));
       float e = 0.f;
       RPF_HIP(hipEventElapsedTime(&e, r.a, r.b));
-      ms += e;
-      fl += r.flops;
-      ++n;
+      if (prec < 0 || r.prec == prec) {
+        ms += e;
+        fl += r.flops;
+        ++n;
+      }
       t.pool.push_back(r.a);
       t.pool.push_back(r.b);
     }

@@ -545,7 +545,7 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     }
 #undef RPF_GLP
     RPF_LAUNCH_CHECK();
-    void* tok = trace_begin(s);
+    void* tok = trace_begin(s, (int)prec);
     if (split) {
       RPF_CHECK(P->ldlp == ld[p], RPF_EINVAL, "low-precision S+ layout mismatch");
       const int tm = tile_m[p], tn = tile_n[p];

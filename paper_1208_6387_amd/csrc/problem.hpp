@@ -85,6 +85,6 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
                      int64_t ldy, int prec, hipStream_t s);
 // event tracing of the flexibility products
 bool trace_on();
-void* trace_begin(hipStream_t s);
+void* trace_begin(hipStream_t s, int prec);
 void trace_end(void* tok, hipStream_t s, double flops);
 }  // namespace rpf
