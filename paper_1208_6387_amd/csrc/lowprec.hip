@@ -402,6 +402,128 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
       }
 }
 
+// ---------------------------------------------------------------------------- bf16 MFMA GEMM, 256 x 256 tiles
+// The large-problem form of the product above (same operands, same per-accumulator summation
+// order, so the same bits): 512 threads, eight waves of 128 x 64, k stages of 32 fed by direct
+// global-to-LDS 16-byte loads into two LDS buffers (64 KiB per stage for hi + lo of both
+// operands).  A stage's loads are issued right after the barrier that opens the previous stage,
+// so a whole stage of MFMA work covers their latency, and no staging registers are needed.
+// The two buffers are distinct LDS objects so the compiler can tell that the fragment reads of
+// one stage do not depend on the loads in flight into the other.  Requirements (host-checked):
+// lda, ldb, kchunk and K multiples of 32 with zeros in the padded k range, so every stage is
+// whole; rows past M (or N) are clamped to the last row and their results are never stored.
+// LDS layout of one operand stage: 16 blocks of 16 rows x 64 bytes; the four 16-byte k chunks of
+// row r sit in the order kc ^ swz4(r), which makes the fragment reads (16 rows x one chunk per
+// quarter wave) free of bank conflicts.
+__device__ inline int swz4(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+template <bool X3>
+__global__ __launch_bounds__(512) void k_gemm_bf16_big(int M, int N, int K, const uint16_t* __restrict__ Ah,
+                                                       const uint16_t* __restrict__ Al, int64_t lda,
+                                                       const uint16_t* __restrict__ Bh,
+                                                       const uint16_t* __restrict__ Bl, int64_t ldb,
+                                                       float* __restrict__ C, int64_t ldc, int kchunk,
+                                                       int64_t slab) {
+  constexpr int BK = 32, NARR = X3 ? 4 : 2, AB = 256 * 64;  // bytes of one operand stage
+  constexpr int WPA = 8 / NARR, EPW = 16 / WPA;            // waves per operand, 1 KiB blocks per wave
+  __shared__ __attribute__((aligned(1024))) uint8_t lds0[NARR * AB];
+  __shared__ __attribute__((aligned(1024))) uint8_t lds1[NARR * AB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  int tx, ty;
+  xcd_tile(gridDim.x, gridDim.y, tx, ty);
+  const int m0 = tx * 256, n0 = ty * 256;
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+  C += (int64_t)blockIdx.z * slab;
+  const int nst = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  // this wave loads operand la (Ah, Al, Bh, Bl; or Ah, Bh), 16-row blocks lb0 .. lb0 + EPW - 1;
+  // lane l of a block load fetches row l / 4, chunk (l % 4) ^ swz4(row)
+  const int la = wave / WPA, lb0 = (wave % WPA) * EPW;
+  const bool isA = la < NARR / 2;
+  const uint16_t* P = X3 ? (la == 0 ? Ah : la == 1 ? Al : la == 2 ? Bh : Bl) : (la == 0 ? Ah : Bh);
+  const int64_t ld = isA ? lda : ldb;
+  const int base = isA ? m0 : n0, lim = isA ? M : N;
+  const int lr = lane >> 2, lkc = (lane & 3) ^ swz4(lr);
+  const uint16_t* src[EPW];
+#pragma unroll
+  for (int e = 0; e < EPW; ++e) {
+    const int row = min(base + (lb0 + e) * 16 + lr, lim - 1);
+    src[e] = P + (int64_t)row * ld + kbeg + 8 * lkc;
+  }
+  auto issue = [&](uint8_t* buf, int k) {
+#pragma unroll
+    for (int e = 0; e < EPW; ++e)
+      __builtin_amdgcn_global_load_lds((const void*)(src[e] + k), (void*)(buf + la * AB + (lb0 + e) * 1024), 16, 0, 0);
+  };
+  const int fr = lane & 15, foff = fr * 64 + (((lane >> 4) ^ swz4(fr)) * 16);
+  auto frag = [&](const uint8_t* buf, int a, int row0) -> bf16x8 {
+    return *reinterpret_cast<const bf16x8*>(buf + a * AB + row0 * 64 + foff);
+  };
+  constexpr int IAH = 0, IAL = 1, IBH = X3 ? 2 : 1, IBL = 3;
+  f32x4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // one stage: wait for this stage's loads, barrier (all waves are also done with the other
+  // buffer), start the next stage's loads into the other buffer, then read fragments and multiply
+  auto stage = [&](const uint8_t* cur, uint8_t* nxt, int s) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (s + 1 < nst) issue(nxt, (s + 1) * BK);
+    __builtin_amdgcn_sched_barrier(0);
+    bf16x8 bh[4], bl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bh[j] = frag(cur, IBH, wn * 64 + j * 16);
+      if (X3) bl[j] = frag(cur, IBL, wn * 64 + j * 16);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bf16x8 ah[4], al[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ah[i] = frag(cur, IAH, wm * 128 + (h * 4 + i) * 16);
+        if (X3) al[i] = frag(cur, IAL, wm * 128 + (h * 4 + i) * 16);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[h * 4 + i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah[i], acc[h * 4 + i][j], 0, 0, 0);
+      if (X3) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[h * 4 + i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah[i], acc[h * 4 + i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[h * 4 + i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al[i], acc[h * 4 + i][j], 0, 0, 0);
+      }
+    }
+  };
+  if (nst > 0) issue(lds0, 0);
+  int s = 0;
+  for (; s + 1 < nst; s += 2) {
+    stage(lds0, lds1, s);
+    stage(lds1, lds0, s + 1);
+  }
+  if (s < nst) stage(lds0, lds1, s);
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 128 + i * 16 + (lane & 15);
+        const int n = n0 + wn * 64 + j * 16 + 4 * (lane >> 4) + r;
+        if (m < M && n < N) C[(int64_t)n * ldc + m] = acc[i][j][r];
+      }
+}
+
 // ---------------------------------------------------------------------------- scatter from FP32
 struct YLoc32 {
   const float* base[MAXP];
@@ -468,7 +590,8 @@ __global__ __launch_bounds__(128) void k_scatter_f32(int n_mult, const int* ep_q
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
                      int64_t ldy, int prec, hipStream_t s) {
   const bool split = (prec == RPF_BF16X3 || prec == RPF_BF16);
-  // W format with ld rounded up to a multiple of 8 (16-byte rows for the bf16 loads)
+  // W format with ld rounded up to a multiple of 64: every 64-k chunk of a row is one 128-byte
+  // cache line (unaligned rows would make each chunk touch two lines)
   std::vector<int64_t> off(pb->n_pat + 1, 0), ld(pb->n_pat);
   // split K (chunks of multiples of 64) while the 64 x 64 output tiles alone give fewer than
   // ~4 workgroups per CU; the scatter sums the split slabs
@@ -476,17 +599,20 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
   std::vector<int> nsp(pb->n_pat, 1), kch(pb->n_pat, 0), tile_m(pb->n_pat, 64), tile_n(pb->n_pat, 64);
   for (int p = 0; p < pb->n_pat; ++p) {
     const int nb = pats[p]->n_b;
-    ld[p] = cdiv(nb, 8) * 8;
+    ld[p] = cdiv(nb, 64) * 64;
     const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
     off[p + 1] = off[p] + ld[p] * cols;
-    // bf16 workgroup tile: 128 x 128 (64 x 64 per wave) when both sides allow it, else 64 x 64
-    const int tm = (split && nb >= 128 && cols >= 128) ? 128 : 64;
+    // bf16 workgroup tile: 256 x 256 when those tiles alone fill the chip (about one per CU), else
+    // 128 x 128 (64 x 64 per wave) when both sides allow it, else 64 x 64
+    const int tm = (split && cdiv(nb, 256) * cdiv(cols, (int64_t)256) >= 240) ? 256
+                   : (split && nb >= 128 && cols >= 128)                       ? 128
+                                                                               : 64;
     const int tn = tm;
     tile_m[p] = tm;
     tile_n[p] = tn;
     const int64_t tiles = std::max<int64_t>(1, cdiv(nb, tm) * cdiv(cols, tn));
     int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, ld[p] / 256));
-    sp = std::min(sp, 8);
+    sp = tm == 256 ? 1 : std::min(sp, 8);
     kch[p] = (int)(cdiv(cdiv(ld[p], sp), 64) * 64);
     nsp[p] = (int)cdiv(ld[p], kch[p]);
     yoff[p + 1] = yoff[p] + ld[p] * cols * nsp[p];
@@ -553,13 +679,21 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
 #define RPF_BF(BM_, BN_, X3)                                                                                      \
   RPF_TIMED_LAUNCH((k_gemm_bf16<BM_, BN_, X3>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p, P->Sp_lo.p, \
                      ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab)
-      if (prec == RPF_BF16X3) {
+#define RPF_BIG(X3)                                                                                            \
+  RPF_TIMED_LAUNCH((k_gemm_bf16_big<X3>), g2, dim3(512), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p, P->Sp_lo.p,    \
+                     ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab)
+      if (tm == 256) {
+        RPF_CHECK(ld[p] % 32 == 0 && kch[p] % 32 == 0, RPF_EINVAL, "bf16 operand layout not in 32-k stages");
+        if (prec == RPF_BF16X3) RPF_BIG(true);
+        else RPF_BIG(false);
+      } else if (prec == RPF_BF16X3) {
         if (tm == 128) RPF_BF(128, 128, true);
         else RPF_BF(64, 64, true);
       } else {
         if (tm == 128) RPF_BF(128, 128, false);
         else RPF_BF(64, 64, false);
       }
+#undef RPF_BIG
 #undef RPF_BF
     } else {
       dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64), (unsigned)nsp[p]);

@@ -331,7 +331,7 @@ extern "C" rpf_status pattern_condense(rpf_pattern p, int32_t prec, void* stream
       p->condensed |= 1u << RPF_FP32;
     }
     if ((prec == RPF_BF16X3 || prec == RPF_BF16) && !(p->condensed & (1u << RPF_BF16X3))) {
-      p->ldlp = cdiv(nb, 8) * 8;
+      p->ldlp = cdiv(nb, 64) * 64;  // 128-byte rows, the layout of the low-precision products
       const int64_t cntp = (int64_t)nb * p->ldlp;
       p->Sp_hi.alloc(cntp);
       p->Sp_lo.alloc(cntp);

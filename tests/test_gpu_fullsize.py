@@ -87,6 +87,23 @@ def test_config2_operator(config2, R):
     assert np.abs(Y - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("form,tol", [("bf16x3", 5e-5), ("bf16", 3e-2)])
+def test_config2_operator_large_tiles(config2, R, form, tol):
+    """97 columns per occurrence make 64 x 97 = 6208 product columns: with n_b = 2598 that is 11 x 25
+    tiles of 256 x 256, enough for the large-tile bf16 kernel, and both sides are ragged (2598 =
+    10 x 256 + 38, 6208 = 24 x 256 + 64).  Checked against the oracle's FP64 operator."""
+    p, o, pats, pb = config2
+    prec = R.BF16X3 if form == "bf16x3" else R.BF16
+    X = np.random.default_rng(97).standard_normal((p.n_lambda, 97))
+    Y = R.feti_apply(pb, pats, torch.from_numpy(X).cuda(), prec=prec).cpu().numpy()
+    ref = o.F(X)
+    err = np.abs(Y - ref).max() / np.abs(ref).max()
+    assert 0.0 < err <= tol, (form, err)
+    # every column, the ragged last ones included, is within the bound on its own
+    colerr = np.abs(Y - ref).max(0) / np.abs(ref).max(0)
+    assert colerr.max() <= 4 * tol, (form, colerr.max(), int(colerr.argmax()))
+
+
 @pytest.mark.parametrize("form,method", [("fp64", "orthodir"), ("bf16x3", "orthodir"), ("bf16x3", "block_cg")])
 def test_config2_solution(config2, R, form, method):
     from paper_1208_6387_amd import structure as ST
