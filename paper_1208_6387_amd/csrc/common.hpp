@@ -188,6 +188,13 @@ void rows_gemm_from(hipStream_t s, int64_t N, int a, int b, double alpha, const 
 // The paired product below (a, b <= 16, M column-major) that also returns the column sums of
 // squares of Y2 after the update: sq[c * ldsq], c < b (part: cdiv(N, 256) * b doubles of
 // workspace).  Returns false, doing nothing, when the block is too wide.
+// Y = beta Y + alpha X M (a, b <= 16, b divides 256), and from the same pass: sq[c * ldsq] = the
+// squared column norms of the new Y (skipped when sq is NULL) and G (a x b, column-major) =
+// X^T Y_new.  sqpart and gpart are workspaces of (cdiv(N, 256) + 256) * b and
+// (cdiv(N, 256) + 256) * a * b doubles.  Returns false (nothing launched) when the shape is not supported.
+bool rows_update_gram(hipStream_t s, int64_t N, int a, int b, const double* M, const double* X, int64_t ldx,
+                      double alpha, double beta, double* Y, int64_t ldy, double* sqpart, double* sq, int64_t ldsq,
+                      double* gpart, double* G);
 bool rows_gemm2_sq(hipStream_t s, int64_t N, int a, int b, const double* M, double alpha1, const double* X1,
                    int64_t ldx1, double beta1, double* Y1, int64_t ldy1, double alpha2, const double* X2,
                    int64_t ldx2, double beta2, double* Y2, int64_t ldy2, double* part, double* sq, int64_t ldsq);

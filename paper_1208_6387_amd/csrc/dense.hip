@@ -640,9 +640,26 @@ __global__ __launch_bounds__(256) void k_rows_tile(int64_t N, int a, int b, cons
   const RowsPair& P = pr.p[blockIdx.y];
   const int64_t r0 = (int64_t)blockIdx.x * 256;
   const int rows = (int)min<int64_t>(256, N - r0);
-  for (int e = tid; e < rows * a; e += 256) {
-    const int rr = e / a, cc = e - rr * a;
-    xs[rr][cc] = P.X[(r0 + rr) * P.ldx + cc];
+  // full 256 x 16 tiles (the common case) issue all sixteen loads of a thread before the first
+  // LDS store, so they are in flight together
+  const bool full = rows == 256 && a == 16;
+  if (full) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      t[u] = P.X[(r0 + (e >> 4)) * P.ldx + (e & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      xs[e >> 4][e & 15] = t[u];
+    }
+  } else {
+    for (int e = tid; e < rows * a; e += 256) {
+      const int rr = e / a, cc = e - rr * a;
+      xs[rr][cc] = P.X[(r0 + rr) * P.ldx + cc];
+    }
   }
   __syncthreads();
   double acc[16];
@@ -669,13 +686,34 @@ __global__ __launch_bounds__(256) void k_rows_tile(int64_t N, int a, int b, cons
   const bool want_sq = pr.colsq != nullptr && blockIdx.y == 1;
   double myq = 0.0;
   __syncthreads();
-  for (int e = tid; e < rows * b; e += 256) {
-    const int rr = e / b, cc = e - rr * b;
-    double* y = P.Y + (r0 + rr) * P.ldy + cc;
-    const double v = P.alpha * xs[rr][cc];
-    const double out = (P.beta == 0.0) ? v : P.beta * (P.Z ? P.Z[(r0 + rr) * P.ldz + cc] : *y) + v;
-    *y = out;
-    myq += out * out;
+  if (rows == 256 && b == 16) {
+    // same element order as below; the sixteen beta-term loads go out together
+    double zv[16];
+    if (P.beta != 0.0) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + u * 256;
+        const int64_t row = r0 + (e >> 4);
+        zv[u] = P.Z ? P.Z[row * P.ldz + (e & 15)] : P.Y[row * P.ldy + (e & 15)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      const double v = P.alpha * xs[e >> 4][e & 15];
+      const double out = (P.beta == 0.0) ? v : P.beta * zv[u] + v;
+      P.Y[(r0 + (e >> 4)) * P.ldy + (e & 15)] = out;
+      myq += out * out;
+    }
+  } else {
+    for (int e = tid; e < rows * b; e += 256) {
+      const int rr = e / b, cc = e - rr * b;
+      double* y = P.Y + (r0 + rr) * P.ldy + cc;
+      const double v = P.alpha * xs[rr][cc];
+      const double out = (P.beta == 0.0) ? v : P.beta * (P.Z ? P.Z[(r0 + rr) * P.ldz + cc] : *y) + v;
+      *y = out;
+      myq += out * out;
+    }
   }
   if (want_sq) {
     __syncthreads();
@@ -687,6 +725,122 @@ __global__ __launch_bounds__(256) void k_rows_tile(int64_t N, int a, int b, cons
       for (int k = tid; k < 256; k += b) t += red[k];
       pr.colsq[(int64_t)blockIdx.x * b + tid] = t;
     }
+  }
+}
+
+// Residual update of a block step with both of its by-products from the same pass:
+// Y = beta Y + alpha X M (X: N x a rows, M: a x b column-major, a, b <= 16), the per-workgroup
+// column sums of squares of the new Y (sqpart[wg * b + c], fixed order, deterministic), and
+// the per-workgroup Gram partial X^T Y_new (gpart[(wg * b + j) * a + i]) - the next step's
+// X^T R, which would otherwise take another pass over both blocks.  The rows of X and of the new
+// Y stay in LDS; the Gram partial is formed with v_mfma_f64_16x16x4_f64 (each wave four rows per
+// MFMA over its 64 rows) and the four waves are summed in LDS.
+__global__ __launch_bounds__(256) void k_rows_update_gram(int64_t N, int a, int b, const double* Mm,
+                                                          const double* X, int64_t ldx, double alpha, double beta,
+                                                          double* Y, int64_t ldy, double* sqpart, double* gpart) {
+  __shared__ double sm[16][16];
+  __shared__ double xs[256][17];
+  __shared__ double ys[256][17];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    const int i = tid >> 4, j = tid & 15;
+    sm[i][j] = (i < a && j < b) ? Mm[i + (int64_t)a * j] : 0.0;
+  }
+  double myq = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int rows = (int)min<int64_t>(256, N - r0);
+  if (rows == 256 && a == 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      t[u] = X[(r0 + (e >> 4)) * ldx + (e & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      xs[e >> 4][e & 15] = t[u];
+    }
+  } else {
+    for (int e = tid; e < 256 * 16; e += 256) {
+      const int rr = e >> 4, cc = e & 15;
+      xs[rr][cc] = (rr < rows && cc < a) ? X[(r0 + rr) * ldx + cc] : 0.0;
+    }
+  }
+  __syncthreads();
+  {
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const double xv = xs[tid][i];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] += xv * sm[i][j];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) ys[tid][j] = acc[j];
+  }
+  __syncthreads();
+  if (rows == 256 && b == 16) {
+    double zv[16];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + u * 256;
+        zv[u] = Y[(r0 + (e >> 4)) * ldy + (e & 15)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      const double v = alpha * ys[e >> 4][e & 15];
+      const double out = (beta == 0.0) ? v : beta * zv[u] + v;
+      Y[(r0 + (e >> 4)) * ldy + (e & 15)] = out;
+      ys[e >> 4][e & 15] = out;
+      myq += out * out;
+    }
+  } else {
+    for (int e = tid; e < 256 * b; e += 256) {
+      const int rr = e / b, cc = e - rr * b;
+      double out = 0.0;  // rows past N count as zero in the Gram
+      if (rr < rows) {
+        double* y = Y + (r0 + rr) * ldy + cc;
+        const double v = alpha * ys[rr][cc];
+        out = (beta == 0.0) ? v : beta * *y + v;
+        *y = out;
+      }
+      ys[rr][cc] = out;
+      myq += out * out;
+    }
+    for (int e = tid; e < 256 * 16; e += 256)
+      if ((e & 15) >= b) ys[e >> 4][e & 15] = 0.0;
+  }
+  __syncthreads();
+  // Gram partial over this tile's rows: wave w takes rows 64 w .. 64 w + 63
+  v4d g = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int row = wave * 64 + 4 * q + (lane >> 4);
+    g = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[row][lane & 15], ys[row][lane & 15], g, 0, 0, 0);
+  }
+  __syncthreads();  // xs becomes the reduction buffer
+  double* red = &xs[0][0];
+  // accumulator item r of lane l is (i = l / 16 + 4 r, j = l % 16)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave * 256 + ((lane >> 4) + 4 * r) * 16 + (lane & 15)] = g[r];
+  red[1024 + tid] = myq;
+  __syncthreads();
+  {
+    const int i = tid >> 4, j = tid & 15;
+    if (i < a && j < b)
+      gpart[((int64_t)blockIdx.x * b + j) * a + i] = red[tid] + red[256 + tid] + red[512 + tid] + red[768 + tid];
+  }
+  // every element a thread wrote lies in column tid % b (b divides 256)
+  if (tid < b) {
+    double t = 0.0;
+    for (int k = tid; k < 256; k += b) t += red[1024 + k];
+    sqpart[(int64_t)blockIdx.x * b + tid] = t;
   }
 }
 
@@ -753,6 +907,52 @@ bool rows_gemm2_sq(hipStream_t s, int64_t N, int a, int b, const double* M, doub
   // sq[c * ldsq] = sum over workgroups of part[wg * b + c]
   hipLaunchKernelGGL(k_colsum, dim3((unsigned)b), dim3(256), 0, s, (int)nwg, b, part, sq, ldsq);
   RPF_LAUNCH_CHECK();
+  return true;
+}
+
+// Sum of nrec records of len <= 256 doubles (record r at part[r * len]): workgroup g sums the
+// records g per .. g per + per - 1 with thread t on element t (coalesced) and writes element t
+// to out[g * rstride + t * inc].  record_sum runs it twice (groups, then their sums); the order
+// of every sum is fixed (deterministic).
+__global__ __launch_bounds__(256) void k_recsum(int nrec, int len, int per, const double* part, double* out,
+                                                int64_t rstride, int64_t inc) {
+  const int t = threadIdx.x;
+  if (t >= len) return;
+  const int r0 = blockIdx.x * per, r1 = min(nrec, r0 + per);
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  int r = r0;
+  for (; r + 4 <= r1; r += 4) {
+    v0 += part[(int64_t)r * len + t];
+    v1 += part[(int64_t)(r + 1) * len + t];
+    v2 += part[(int64_t)(r + 2) * len + t];
+    v3 += part[(int64_t)(r + 3) * len + t];
+  }
+  for (; r < r1; ++r) v0 += part[(int64_t)r * len + t];
+  out[(int64_t)blockIdx.x * rstride + t * inc] = (v0 + v1) + (v2 + v3);
+}
+
+// out[t * inc] = sum of the nrec records; tmp holds 256 records
+void record_sum(hipStream_t s, int nrec, int len, const double* part, double* tmp, double* out, int64_t inc) {
+  const int groups = std::min(256, std::max(1, nrec));
+  const int per = (int)cdiv(nrec, groups);
+  const int g = (int)cdiv(nrec, per);
+  hipLaunchKernelGGL(k_recsum, dim3((unsigned)g), dim3(256), 0, s, nrec, len, per, part, tmp, (int64_t)len,
+                     (int64_t)1);
+  hipLaunchKernelGGL(k_recsum, dim3(1), dim3(256), 0, s, g, len, g, tmp, out, (int64_t)0, inc);
+  RPF_LAUNCH_CHECK();
+}
+
+bool rows_update_gram(hipStream_t s, int64_t N, int a, int b, const double* M, const double* X, int64_t ldx,
+                      double alpha, double beta, double* Y, int64_t ldy, double* sqpart, double* sq, int64_t ldsq,
+                      double* gpart, double* G) {
+  if (N <= 0 || a <= 0 || b <= 0 || a > 16 || b > 16 || 256 % b != 0) return false;
+  const int nwg = (int)cdiv(N, 256);
+  hipLaunchKernelGGL(k_rows_update_gram, dim3((unsigned)nwg), dim3(256), 0, s, N, a, b, M, X, ldx, alpha, beta, Y,
+                     ldy, sqpart, gpart);
+  RPF_LAUNCH_CHECK();
+  // the first-pass sums go past the partials (the workspaces hold 256 records more)
+  if (sq) record_sum(s, nwg, b, sqpart, sqpart + (int64_t)nwg * b, sq, ldsq);
+  record_sum(s, nwg, a * b, gpart, gpart + (int64_t)nwg * a * b, G, 1);
   return true;
 }
 

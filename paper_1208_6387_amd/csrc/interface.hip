@@ -191,18 +191,25 @@ __global__ __launch_bounds__(256) void k_coarse_gt(const int* occ_pat, const int
   }
 }
 
-// Same partial sums with coalesced row reads: a group of JW lanes takes one boundary node
-// (lane = interface column j), sums the signed multiplier rows at the node (each row read as
-// JW consecutive doubles), turns the sum into the pattern frame (O^T) and accumulates the
-// k mode products Z[bn]^T x_loc in registers; the 256/JW groups are summed through LDS at
-// the end.  Workgroup (s, sp) covers a slice of the boundary nodes of occurrence s.
+// Same partial sums with coalesced row reads: a group of JW lanes (lane = interface column j)
+// takes (node, multiplier) incidences of the occurrence one at a time, reads the signed
+// multiplier row (JW consecutive doubles), turns it into the pattern frame (O^T) and accumulates
+// the k mode products Z[bn]^T x_loc in registers; the 256/JW groups are summed through LDS at
+// the end.  The incidences of a slice of boundary nodes are one contiguous run of the slot
+// lists, so a group walks them four at a time with all their loads issued together (no
+// per-node chain of dependent loads).  Workgroup (s, sp) covers a slice of the boundary nodes
+// of occurrence s.
+constexpr int GT_MAX_NODES = 128;  // boundary nodes per slice of k_coarse_gt_rows (host-enforced)
 template <int DPN, int JW>
 __global__ __launch_bounds__(256) void k_coarse_gt_rows(const int* occ_pat, const int* slot_off, const int* nbn_p,
                                                         const double* const* Zp, const int* kp, const int* l2m_ptr,
-                                                        const int* l2m_code, const double* rot, const double* x,
-                                                        int64_t ldx, int m, int nsplit, double* part) {
+                                                        const int* l2m_code, const int* l2m_bn, const double* rot,
+                                                        const double* x, int64_t ldx, int m, int nsplit,
+                                                        double* part) {
   constexpr int NG = 256 / JW;
   __shared__ double red[NG][KMAX][JW];
+  // the slice's mode rows, zl[(bn - n_beg) DPN KMAX + c KMAX + r] = Z[r][bn DPN + c] (zero for r >= k)
+  __shared__ double zl[GT_MAX_NODES * DPN * KMAX];
   const int s = blockIdx.x, sp = blockIdx.y;
   const int p = occ_pat[s];
   const int k = kp[p];
@@ -211,8 +218,16 @@ __global__ __launch_bounds__(256) void k_coarse_gt_rows(const int* occ_pat, cons
   const int nper = (nbn + nsplit - 1) / nsplit;
   const int n_beg = sp * nper, n_end = min(nbn, n_beg + nper);
   const double* Z = Zp[p];
+  for (int i = threadIdx.x; i < max(n_end - n_beg, 0) * DPN * KMAX; i += 256) {
+    const int r = i % KMAX, dof = i / KMAX;  // dof within the slice
+    zl[i] = r < k ? Z[r * nd + (int64_t)n_beg * DPN + dof] : 0.0;
+  }
+  __syncthreads();
   const int tid = threadIdx.x, g = tid / JW, jl = tid % JW;
   const int base_slot = slot_off[s];
+  // slices past the last node are empty (and must not index past the occurrence's slots)
+  const int e_beg = l2m_ptr[base_slot + min(n_beg, nbn)];
+  const int e_end = n_end > n_beg ? l2m_ptr[base_slot + n_end] : e_beg;
   double O[9];
   if (DPN == 3) load_rot<DPN>(rot, s, O);
   for (int j0 = 0; j0 < m; j0 += JW) {
@@ -221,36 +236,41 @@ __global__ __launch_bounds__(256) void k_coarse_gt_rows(const int* occ_pat, cons
     double acc[KMAX];
 #pragma unroll
     for (int r = 0; r < KMAX; ++r) acc[r] = 0.0;
-    for (int bn = n_beg + g; bn < n_end; bn += NG) {
-      const int slot = base_slot + bn;
-      const int e0 = l2m_ptr[slot], e1 = l2m_ptr[slot + 1];
-      double xg[DPN];
+    constexpr int U = 4;
+    for (int e0 = e_beg + g; e0 < e_end; e0 += NG * U) {
+      int code[U], bnu[U];
 #pragma unroll
-      for (int c = 0; c < DPN; ++c) xg[c] = 0.0;
-      for (int e = e0; e < e1; ++e) {
-        const int code = l2m_code[e];
-        const double sg = (code & 1) ? -1.0 : 1.0;
-        const int64_t mult = code >> 1;
-        if (jok) {
-#pragma unroll
-          for (int c = 0; c < DPN; ++c) xg[c] += sg * x[(mult * DPN + c) * ldx + j];
-        }
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NG;
+        const bool ok = e < e_end;
+        code[u] = ok ? l2m_code[e] : 0;
+        bnu[u] = ok ? l2m_bn[e] : -1;
       }
-      double xl[DPN];
-      if (DPN == 3) {
+      double xv[U][DPN];
 #pragma unroll
-        for (int c2 = 0; c2 < 3; ++c2) xl[c2] = O[c2] * xg[0] + O[3 + c2] * xg[1 % DPN] + O[6 + c2] * xg[2 % DPN];
-      } else {
+      for (int u = 0; u < U; ++u) {
+        const int64_t mult = code[u] >> 1;
 #pragma unroll
-        for (int c = 0; c < DPN; ++c) xl[c] = xg[c];
+        for (int c = 0; c < DPN; ++c) xv[u][c] = (bnu[u] >= 0 && jok) ? x[(mult * DPN + c) * ldx + j] : 0.0;
       }
-      const double* zr = Z + (int64_t)bn * DPN;
 #pragma unroll
-      for (int r = 0; r < KMAX; ++r) {
-        if (r < k) {
+      for (int u = 0; u < U; ++u) {
+        if (bnu[u] < 0) continue;
+        const double sg = (code[u] & 1) ? -1.0 : 1.0;
+        double xl[DPN];
+        if (DPN == 3) {
 #pragma unroll
-          for (int c = 0; c < DPN; ++c) acc[r] += zr[r * nd + c] * xl[c];
+          for (int c2 = 0; c2 < 3; ++c2)
+            xl[c2] = sg * (O[c2] * xv[u][0] + O[3 + c2] * xv[u][1 % DPN] + O[6 + c2] * xv[u][2 % DPN]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) xl[c] = sg * xv[u][c];
         }
+        const double* zr = zl + (bnu[u] - n_beg) * DPN * KMAX;
+#pragma unroll
+        for (int c = 0; c < DPN; ++c)
+#pragma unroll
+          for (int r = 0; r < KMAX; ++r) acc[r] += zr[c * KMAX + r] * xl[c];
       }
     }
 #pragma unroll
@@ -430,34 +450,73 @@ __global__ void k_build_grows(int n_mult, int km, const int* ep_occ, const int* 
   if (r == 0 && c == 0) ep_goff[2 * mult + e] = s >= 0 ? goff[s] : -1;
 }
 
-// x = beta x + alpha G y from the stored rows of G: one thread per (multiplier, column).
-template <int DPN, int KM>
+// x = beta x + alpha G y from the stored rows of G: one thread per (multiplier, JQ consecutive
+// columns).  With JQ = 4 (m a multiple of 4, 16-byte aligned rows) the G rows of a multiplier
+// are read by 4 threads instead of m and the x and y accesses are 16-byte vectors.
+template <int DPN, int KM, int JQ>
 __global__ __launch_bounds__(256) void k_coarse_g_rows(int n_mult, const double* Grow, const int* ep_goff, int nG,
                                                        const double* y, int m, double alpha, double* x, int64_t ldx,
                                                        double beta) {
+  const int mq = m / JQ;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n_mult * m) return;
-  const int mult = (int)(idx / m), j = (int)(idx % m);
-  double acc[DPN];
+  if (idx >= (int64_t)n_mult * mq) return;
+  const int mult = (int)(idx / mq), j0 = (int)(idx % mq) * JQ;
+  double acc[DPN][JQ];
 #pragma unroll
-  for (int c = 0; c < DPN; ++c) acc[c] = 0.0;
+  for (int c = 0; c < DPN; ++c)
+#pragma unroll
+    for (int q = 0; q < JQ; ++q) acc[c][q] = 0.0;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int go = ep_goff[2 * mult + e];
     if (go < 0) continue;
     const double* g = Grow + ((int64_t)mult * 2 + e) * DPN * KM;
-    double yr[KM];
+    double yr[KM][JQ];
 #pragma unroll
-    for (int r = 0; r < KM; ++r) yr[r] = (go + r < nG) ? y[((int64_t)go + r) * m + j] : 0.0;  // rows past k: G is 0
+    for (int r = 0; r < KM; ++r) {
+      const double* yp = y + ((int64_t)go + r) * m + j0;
+      const bool ok = go + r < nG;  // rows past k: G is 0
+      if (JQ == 4) {
+        const double2 u = ok ? *reinterpret_cast<const double2*>(yp) : double2{0.0, 0.0};
+        const double2 v = ok ? *reinterpret_cast<const double2*>(yp + 2) : double2{0.0, 0.0};
+        yr[r][0] = u.x;
+        yr[r][1 % JQ] = u.y;
+        yr[r][2 % JQ] = v.x;
+        yr[r][3 % JQ] = v.y;
+      } else {
+#pragma unroll
+        for (int q = 0; q < JQ; ++q) yr[r][q] = ok ? yp[q] : 0.0;
+      }
+    }
 #pragma unroll
     for (int c = 0; c < DPN; ++c)
 #pragma unroll
-      for (int r = 0; r < KM; ++r) acc[c] += g[c * KM + r] * yr[r];
+      for (int r = 0; r < KM; ++r) {
+        const double gv = g[c * KM + r];
+#pragma unroll
+        for (int q = 0; q < JQ; ++q) acc[c][q] += gv * yr[r][q];
+      }
   }
 #pragma unroll
   for (int c = 0; c < DPN; ++c) {
-    double* xv = x + ((int64_t)mult * DPN + c) * ldx + j;
-    *xv = (beta == 0.0) ? alpha * acc[c] : beta * *xv + alpha * acc[c];
+    double* xv = x + ((int64_t)mult * DPN + c) * ldx + j0;
+    if (JQ == 4) {
+      double2 u = double2{alpha * acc[c][0], alpha * acc[c][1 % JQ]};
+      double2 v = double2{alpha * acc[c][2 % JQ], alpha * acc[c][3 % JQ]};
+      if (beta != 0.0) {
+        const double2 ou = *reinterpret_cast<const double2*>(xv);
+        const double2 ov = *reinterpret_cast<const double2*>(xv + 2);
+        u.x += beta * ou.x;
+        u.y += beta * ou.y;
+        v.x += beta * ov.x;
+        v.y += beta * ov.y;
+      }
+      *reinterpret_cast<double2*>(xv) = u;
+      *reinterpret_cast<double2*>(xv + 2) = v;
+    } else {
+#pragma unroll
+      for (int q = 0; q < JQ; ++q) xv[q] = (beta == 0.0) ? alpha * acc[c][q] : beta * xv[q] + alpha * acc[c][q];
+    }
   }
 }
 
@@ -781,15 +840,15 @@ void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, h
   const int max_nbn = *std::max_element(pb->pat_nbn.begin(), pb->pat_nbn.end());
   const int max_nd = max_nbn * pb->dpn;
   int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, pb->n_occ), cdiv(max_nd, 256)));
-  if (m >= 8) nsplit = std::max<int>(nsplit, (int)cdiv(max_nbn, (m > 8 ? 16 : 32) * 8));
+  if (m >= 8) nsplit = std::max<int>(nsplit, (int)cdiv(max_nbn, GT_MAX_NODES));
   pb->cpart.ensure((size_t)pb->n_occ * nsplit * KMAX * m);
   const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
   if (m >= 8) {
     // lanes over interface columns, coalesced row reads
 #define RPF_CGR(D, JW)                                                                                            \
   hipLaunchKernelGGL((k_coarse_gt_rows<D, JW>), dim3(pb->n_occ, nsplit), dim3(256), 0, s, pb->d_occ_pat.p,         \
-                     pb->d_slot_off.p, pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_l2m_ptr.p, pb->d_l2m_code.p, rot, \
-                     x, ldx, m, nsplit, pb->cpart.p)
+                     pb->d_slot_off.p, pb->d_nbn.p, pb->d_Zp.p, pb->d_kp.p, pb->d_l2m_ptr.p, pb->d_l2m_code.p,      \
+                     pb->d_l2m_bn.p, rot, x, ldx, m, nsplit, pb->cpart.p)
     const bool w16 = m > 8;
     switch (pb->dpn) {
       case 1: if (w16) RPF_CGR(1, 16); else RPF_CGR(1, 8); break;
@@ -821,9 +880,15 @@ void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, i
   if (pb->n_mult == 0) return;
   dim3 grid((unsigned)cdiv((int64_t)pb->n_mult * m, 256));
   if (pb->d_grow.p && pb->g_km > 0) {
-#define RPF_CGR(D, KM)                                                                                       \
-  hipLaunchKernelGGL((k_coarse_g_rows<D, KM>), grid, dim3(256), 0, s, pb->n_mult, pb->d_grow.p, pb->d_ep_goff.p, \
-                     pb->n_G, y, m, alpha, x, ldx, beta)
+    const bool quad = m % 4 == 0 && ldx % 2 == 0 && ((uintptr_t)x & 15) == 0 && ((uintptr_t)y & 15) == 0;
+    dim3 gq((unsigned)cdiv((int64_t)pb->n_mult * (m / 4), 256));
+#define RPF_CGR(D, KM)                                                                                            \
+  if (quad)                                                                                                       \
+    hipLaunchKernelGGL((k_coarse_g_rows<D, KM, 4>), gq, dim3(256), 0, s, pb->n_mult, pb->d_grow.p,               \
+                       pb->d_ep_goff.p, pb->n_G, y, m, alpha, x, ldx, beta);                                      \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_coarse_g_rows<D, KM, 1>), grid, dim3(256), 0, s, pb->n_mult, pb->d_grow.p,             \
+                       pb->d_ep_goff.p, pb->n_G, y, m, alpha, x, ldx, beta)
 #define RPF_CGK(D)                                       \
   switch (pb->g_km) {                                     \
     case 1: RPF_CGR(D, 1); break;                         \
@@ -978,12 +1043,13 @@ extern "C" rpf_status problem_create(const rpf_problem_desc* d, rpf_problem* out
     }
     std::vector<int> l2m_ptr(nslot + 1, 0);
     for (int i = 0; i < nslot; ++i) l2m_ptr[i + 1] = l2m_ptr[i] + cnt[i + 1];
-    std::vector<int> fillp(l2m_ptr.begin(), l2m_ptr.end() - 1), l2m_code(l2m_ptr[nslot]);
+    std::vector<int> fillp(l2m_ptr.begin(), l2m_ptr.end() - 1), l2m_code(l2m_ptr[nslot]), l2m_bn(l2m_ptr[nslot]);
     for (int i = 0; i < nm; ++i)
       for (int e = 0; e < 2; ++e) {
         const int s = ep_occ[2 * i + e];
         if (s < 0) continue;
         const int slot = pb->slot_off[s] + ep_bn[2 * i + e];
+        l2m_bn[fillp[slot]] = ep_bn[2 * i + e];
         l2m_code[fillp[slot]++] = (i << 1) | (ep_sign[2 * i + e] < 0 ? 1 : 0);
       }
     pb->pair_ptr.push_back(0);
@@ -1007,7 +1073,10 @@ extern "C" rpf_status problem_create(const rpf_problem_desc* d, rpf_problem* out
     pb->d_occ_pat.upload(pb->occ_pat.data(), pb->occ_pat.size(), s0);
     pb->d_nbn.upload(pb->pat_nbn.data(), pb->pat_nbn.size(), s0);
     pb->d_l2m_ptr.upload(l2m_ptr.data(), l2m_ptr.size(), s0);
-    if (!l2m_code.empty()) pb->d_l2m_code.upload(l2m_code.data(), l2m_code.size(), s0);
+    if (!l2m_code.empty()) {
+      pb->d_l2m_code.upload(l2m_code.data(), l2m_code.size(), s0);
+      pb->d_l2m_bn.upload(l2m_bn.data(), l2m_bn.size(), s0);
+    }
     if (nm > 0) {
       pb->d_ep_q.upload(ep_q.data(), ep_q.size(), s0);
       pb->d_ep_bn.upload(ep_bn.data(), ep_bn.size(), s0);

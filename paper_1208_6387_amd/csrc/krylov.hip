@@ -329,7 +329,7 @@ struct Solver {
   int64_t ldW = 0;
   int max_blocks = 0;
   // small matrices
-  DevBuf<double> eta, V, w, T, alpha, gam, Bt, Cb, Mo, nrm, ws, estate, sqpart;
+  DevBuf<double> eta, V, w, T, alpha, gam, Bt, Cb, Mo, nrm, ws, estate, sqpart, gpart;
   DevBuf<int> drops;
   std::vector<double> r0n;  // ||r0_c||^2 of the FP64 residual
   int iterations = 0, rank_drops = 0;
@@ -450,6 +450,9 @@ struct Solver {
     init_lag();
     const double tau = eta_drop(prec);
     int pending = -1, nchk = 0;
+    // block CG with one permutation: the residual update also leaves the next step's P^T R in Cb
+    const bool upd_gram = method != RPF_ORTHODIR && np == 1 && m <= 16 && nr <= 16 && 256 % nr == 0;
+    bool have_gram = false;
     for (int it = 0; it < max_it; ++it) {
       // ORTHODIR: orthogonalise against every stored block (restart when the store is full);
       // block CG / classical: against the previous block only, two alternating slots
@@ -490,7 +493,7 @@ struct Solver {
         // F-orthogonalise against the stored blocks: with W_i = Z_i T_i and F W_i = P_i T_i,
         // B = [F W_i]^T Z = T_i^T (P_i^T Z) and Z -= sum_i Z_i (T_i B_i)
         const int ka = nb * m;
-        gram(Pall.p + (int64_t)first * m, ldW, ka, zsrc, ldzs, m, Cb.p);
+        if (!(fused && have_gram)) gram(Pall.p + (int64_t)first * m, ldW, ka, zsrc, ldzs, m, Cb.p);
         hipLaunchKernelGGL(k_tblocks, dim3(nb), dim3(256), 0, s, nb, m, m, Tall.p + (int64_t)first * m * m, 1, Cb.p,
                            Bt.p);
         if (diag_only)
@@ -536,11 +539,22 @@ struct Solver {
       const int slot_n = nchk & 1;
       // the residual update also returns the squared column norms (into the check slot)
       sqpart.ensure((size_t)cdiv(N, 256) * nr);
-      const bool have_sq =
-          check && rows_gemm2_sq(s, N, m, nr, alpha.p, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0, Rs.p, nr,
-                                 sqpart.p, nrm2[slot_n].p, nr + 1);
-      if (!have_sq)
-        rows_gemm2(s, N, m, nr, alpha.p, 0, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0, Rs.p, nr);
+      bool have_sq = false;
+      have_gram = false;
+      if (upd_gram) {
+        gpart.ensure((size_t)(cdiv(N, 256) + 256) * m * nr);
+        sqpart.ensure((size_t)(cdiv(N, 256) + 256) * nr);
+        rows_gemm(s, N, m, nr, 1.0, Zs, ldW, alpha.p, 1.0, dlam.p, nr, 0);
+        have_gram = rows_update_gram(s, N, m, nr, alpha.p, Ps, ldW, -1.0, 1.0, Rs.p, nr, sqpart.p,
+                                     check ? nrm2[slot_n].p : nullptr, nr + 1, gpart.p, Cb.p);
+        RPF_CHECK(have_gram, RPF_EINVAL, "block step: residual update shape");
+        have_sq = check;
+      } else {
+        have_sq = check && rows_gemm2_sq(s, N, m, nr, alpha.p, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0,
+                                         Rs.p, nr, sqpart.p, nrm2[slot_n].p, nr + 1);
+        if (!have_sq)
+          rows_gemm2(s, N, m, nr, alpha.p, 0, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0, Rs.p, nr);
+      }
       ++nst;
       ++iterations;
       if (check) {

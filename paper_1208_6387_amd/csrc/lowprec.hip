@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
 
 // ---------------------------------------------------------------------------- bf16 MFMA GEMM, 256 x 256 tiles
 // The large-problem form of the product above (same operands, same per-accumulator summation
-// order, so the same bits): 512 threads, eight waves of 128 x 64, k stages of 32 fed by direct
+// order, so the same bits), with a row-major result (see the scatter): 512 threads, eight waves of 128 x 64, k stages of 32 fed by direct
 // global-to-LDS 16-byte loads into two LDS buffers (64 KiB per stage for hi + lo of both
 // operands).  A stage's loads are issued right after the barrier that opens the previous stage,
 // so a whole stage of MFMA work covers their latency, and no staging registers are needed.
@@ -512,39 +512,53 @@ __global__ __launch_bounds__(512) void k_gemm_bf16_big(int M, int N, int K, cons
     stage(lds1, lds0, s + 1);
   }
   if (s < nst) stage(lds0, lds1, s);
+  // row-major result (C[m * ldc + n], ldc a multiple of 4): a lane holds four consecutive n of one
+  // row m, written as one 16-byte store
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + wm * 128 + i * 16 + (lane & 15);
+      const int n = n0 + wn * 64 + j * 16 + 4 * (lane >> 4);
+      if (m >= M) continue;
+      float* row = C + (int64_t)m * ldc;
+      if (n + 3 < N) {
+        *reinterpret_cast<f32x4*>(row + n) = acc[i][j];
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 128 + i * 16 + (lane & 15);
-        const int n = n0 + wn * 64 + j * 16 + 4 * (lane >> 4) + r;
-        if (m < M && n < N) C[(int64_t)n * ldc + m] = acc[i][j][r];
+        for (int r = 0; r < 4; ++r)
+          if (n + r < N) row[n + r] = acc[i][j][r];
       }
+    }
 }
 
 // ---------------------------------------------------------------------------- scatter from FP32
+// Local results of the low-precision product, per pattern: column-major (row r of column q m + j
+// at base[(q m + j) ld + r], nsplit slabs of partial sums slab apart) or, from the 256 x 256
+// kernel, row-major (base[r ld + q m + j], one slab), where the m columns of an occurrence are
+// contiguous for the scatter.
 struct YLoc32 {
   const float* base[MAXP];
   int64_t ld[MAXP];
   int64_t slab[MAXP];
   int nsplit[MAXP];
+  int rowmajor[MAXP];
 };
 
-template <int DPN>
+// JB columns per pass (8: the whole pass stays in registers)
+template <int DPN, int JB>
 __global__ __launch_bounds__(128) void k_scatter_f32(int n_mult, const int* ep_q, const int* ep_bn,
                                                      const int8_t* ep_pat, const int8_t* ep_sign, const int* ep_occ,
                                                      const double* rot, YLoc32 yl, int m, double* Y, int64_t ldy) {
   const int mult = blockIdx.x * blockDim.x + threadIdx.x;
   if (mult >= n_mult) return;
-  for (int j0 = 0; j0 < m; j0 += 8) {
-    const int jn = min(8, m - j0);
-    double acc[DPN][8];
+  for (int j0 = 0; j0 < m; j0 += JB) {
+    const int jn = min(JB, m - j0);
+    double acc[DPN][JB];
 #pragma unroll
     for (int c = 0; c < DPN; ++c)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[c][j] = 0.0;
+      for (int j = 0; j < JB; ++j) acc[c][j] = 0.0;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int q = ep_q[2 * mult + e];
@@ -552,20 +566,42 @@ __global__ __launch_bounds__(128) void k_scatter_f32(int n_mult, const int* ep_q
       const int p = ep_pat[2 * mult + e];
       const double sg = (double)ep_sign[2 * mult + e];
       const int64_t ld = yl.ld[p];
-      const float* base = yl.base[p] + ((int64_t)q * m + j0) * ld + (int64_t)ep_bn[2 * mult + e] * DPN;
+      const bool rm = yl.rowmajor[p] != 0;
+      const int64_t bn = ep_bn[2 * mult + e];
+      const float* base = rm ? yl.base[p] + bn * DPN * ld + (int64_t)q * m + j0
+                             : yl.base[p] + ((int64_t)q * m + j0) * ld + bn * DPN;
+      // element (c, j) of this endpoint: base[c sc + j sj]
+      const int64_t sc = rm ? ld : 1, sj = rm ? 1 : ld;
       double O[9];
       const int s = ep_occ[2 * mult + e];
 #pragma unroll
       for (int i = 0; i < 9; ++i) O[i] = rot ? rot[9 * s + i] : ((i % 4 == 0) ? 1.0 : 0.0);
+      // row-major with whole, 16-byte aligned groups: JB / 4 vector loads per dof
+      float yv[DPN][JB];
+      if (rm && jn == JB && (m & 3) == 0) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+        for (int c = 0; c < DPN; ++c)
+#pragma unroll
+          for (int v4 = 0; v4 < JB / 4; ++v4) {
+            const f32x4 t = *reinterpret_cast<const f32x4*>(base + c * ld + 4 * v4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) yv[c][4 * v4 + u] = t[u];
+          }
+      } else {
+#pragma unroll
+        for (int c = 0; c < DPN; ++c)
+#pragma unroll
+          for (int j = 0; j < JB; ++j) yv[c][j] = j < jn ? base[c * sc + j * sj] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
         if (j >= jn) break;
         double v[DPN];
 #pragma unroll
-        for (int c = 0; c < DPN; ++c) v[c] = (double)base[j * ld + c];
+        for (int c = 0; c < DPN; ++c) v[c] = (double)yv[c][j];
         for (int z = 1; z < yl.nsplit[p]; ++z)
 #pragma unroll
-          for (int c = 0; c < DPN; ++c) v[c] += (double)base[z * yl.slab[p] + j * ld + c];
+          for (int c = 0; c < DPN; ++c) v[c] += (double)base[z * yl.slab[p] + c * sc + j * sj];
         if (DPN == 3) {
 #pragma unroll
           for (int c = 0; c < 3; ++c)
@@ -580,9 +616,73 @@ __global__ __launch_bounds__(128) void k_scatter_f32(int n_mult, const int* ep_q
     for (int c = 0; c < DPN; ++c) {
       double* row = Y + ((int64_t)mult * DPN + c) * ldy + j0;
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < JB; ++j)
         if (j < jn) row[j] = acc[c][j];
     }
+  }
+}
+
+// Scatter from the row-major result of the 256 x 256 kernel with one thread per (multiplier, 4
+// consecutive columns): per endpoint one 16-byte load per dof row, the output rows leave as
+// 16-byte stores, and four threads share a multiplier's index loads (m a multiple of 4).
+template <int DPN>
+__global__ __launch_bounds__(256) void k_scatter_f32_quad(int n_mult, const int* ep_q, const int* ep_bn,
+                                                          const int8_t* ep_pat, const int8_t* ep_sign,
+                                                          const int* ep_occ, const double* rot, YLoc32 yl, int m,
+                                                          double* Y, int64_t ldy) {
+  const int mq = m >> 2;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_mult * mq) return;
+  const int mult = (int)(idx / mq), j0 = (int)(idx % mq) * 4;
+  int q[2], bn[2], pt[2], so[2];
+  double sg[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    q[e] = ep_q[2 * mult + e];
+    bn[e] = ep_bn[2 * mult + e];
+    pt[e] = ep_pat[2 * mult + e];
+    sg[e] = (double)ep_sign[2 * mult + e];
+    so[e] = ep_occ[2 * mult + e];
+  }
+  f32x4 yv[2][DPN];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const bool ok = q[e] >= 0;
+    const int p = ok ? pt[e] : 0;
+    const float* base = yl.base[p] + (int64_t)(ok ? bn[e] : 0) * DPN * yl.ld[p] + (int64_t)(ok ? q[e] : 0) * m + j0;
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+      yv[e][c] = ok ? *reinterpret_cast<const f32x4*>(base + c * yl.ld[p]) : f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  double acc[DPN][4];
+#pragma unroll
+  for (int c = 0; c < DPN; ++c)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[c][u] = 0.0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    if (q[e] < 0) continue;
+    double O[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) O[i] = rot ? rot[9 * so[e] + i] : ((i % 4 == 0) ? 1.0 : 0.0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (DPN == 3) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          acc[c % DPN][u] += sg[e] * (O[3 * c] * (double)yv[e][0][u] + O[3 * c + 1] * (double)yv[e][1 % DPN][u] +
+                                      O[3 * c + 2] * (double)yv[e][2 % DPN][u]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < DPN; ++c) acc[c][u] += sg[e] * (double)yv[e][c][u];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) {
+    double* row = Y + ((int64_t)mult * DPN + c) * ldy + j0;
+    *reinterpret_cast<double2*>(row) = double2{acc[c][0], acc[c][1]};
+    *reinterpret_cast<double2*>(row + 2) = double2{acc[c][2], acc[c][3]};
   }
 }
 
@@ -595,7 +695,7 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
   std::vector<int64_t> off(pb->n_pat + 1, 0), ld(pb->n_pat);
   // split K (chunks of multiples of 64) while the 64 x 64 output tiles alone give fewer than
   // ~4 workgroups per CU; the scatter sums the split slabs
-  std::vector<int64_t> yoff(pb->n_pat + 1, 0);
+  std::vector<int64_t> yoff(pb->n_pat + 1, 0), ldr(pb->n_pat, 0);
   std::vector<int> nsp(pb->n_pat, 1), kch(pb->n_pat, 0), tile_m(pb->n_pat, 64), tile_n(pb->n_pat, 64);
   for (int p = 0; p < pb->n_pat; ++p) {
     const int nb = pats[p]->n_b;
@@ -615,7 +715,9 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     sp = tm == 256 ? 1 : std::min(sp, 8);
     kch[p] = (int)(cdiv(cdiv(ld[p], sp), 64) * 64);
     nsp[p] = (int)cdiv(ld[p], kch[p]);
-    yoff[p + 1] = yoff[p] + ld[p] * cols * nsp[p];
+    // the 256 x 256 kernel's row-major result: n_b rows of ldr[p] (a multiple of 16 floats)
+    ldr[p] = cdiv(cols, (int64_t)16) * 16;
+    yoff[p + 1] = yoff[p] + (tm == 256 ? (int64_t)nb * ldr[p] : ld[p] * cols * nsp[p]);
   }
   const int64_t tot = std::max<int64_t>(off[pb->n_pat], 8);
   pb->yloc32.ensure(std::max<int64_t>(yoff[pb->n_pat], 8));
@@ -634,10 +736,12 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
     float* yp = pb->yloc32.p + yoff[p];
     const int64_t slab = ld[p] * (int64_t)cols;
+    const bool rowmajor = tile_m[p] == 256;
     yl.base[p] = yp;
-    yl.ld[p] = ld[p];
+    yl.ld[p] = rowmajor ? ldr[p] : ld[p];
     yl.slab[p] = slab;
     yl.nsplit[p] = nsp[p];
+    yl.rowmajor[p] = rowmajor ? 1 : 0;
     if (nq == 0) continue;
     dim3 grid((unsigned)cdiv(nbn, 128), (unsigned)nq);
 #define RPF_GLP(D, MODE)                                                                                        \
@@ -681,7 +785,7 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
                      ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab)
 #define RPF_BIG(X3)                                                                                            \
   RPF_TIMED_LAUNCH((k_gemm_bf16_big<X3>), g2, dim3(512), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p, P->Sp_lo.p,    \
-                     ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab)
+                     ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ldr[p], kch[p], slab)
       if (tm == 256) {
         RPF_CHECK(ld[p] % 32 == 0 && kch[p] % 32 == 0, RPF_EINVAL, "bf16 operand layout not in 32-k stages");
         if (prec == RPF_BF16X3) RPF_BIG(true);
@@ -706,13 +810,29 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
   if (pb->n_mult == 0) return;
   dim3 grid((unsigned)cdiv(pb->n_mult, 128));
   const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
-#define RPF_SF(D)                                                                                              \
-  hipLaunchKernelGGL(k_scatter_f32<D>, grid, dim3(128), 0, s, pb->n_mult, pb->d_ep_q.p, pb->d_ep_bn.p,          \
+  bool all_rm = true;
+  for (int p = 0; p < pb->n_pat; ++p) all_rm &= yl.rowmajor[p] != 0 || pb->occ_of_pat[p].empty();
+  if (all_rm && m % 4 == 0 && ldy % 2 == 0 && ((uintptr_t)Y & 15) == 0) {
+    dim3 gq((unsigned)cdiv((int64_t)pb->n_mult * (m / 4), 256));
+#define RPF_SQ(D)                                                                                                \
+  hipLaunchKernelGGL(k_scatter_f32_quad<D>, gq, dim3(256), 0, s, pb->n_mult, pb->d_ep_q.p, pb->d_ep_bn.p,       \
+                     pb->d_ep_pat.p, pb->d_ep_sign.p, pb->d_ep_occ.p, rot, yl, m, Y, ldy)
+    switch (pb->dpn) {
+      case 1: RPF_SQ(1); break;
+      case 2: RPF_SQ(2); break;
+      default: RPF_SQ(3);
+    }
+#undef RPF_SQ
+    RPF_LAUNCH_CHECK();
+    return;
+  }
+#define RPF_SF(D, JB)                                                                                          \
+  hipLaunchKernelGGL((k_scatter_f32<D, JB>), grid, dim3(128), 0, s, pb->n_mult, pb->d_ep_q.p, pb->d_ep_bn.p,    \
                      pb->d_ep_pat.p, pb->d_ep_sign.p, pb->d_ep_occ.p, rot, yl, m, Y, ldy)
   switch (pb->dpn) {
-    case 1: RPF_SF(1); break;
-    case 2: RPF_SF(2); break;
-    default: RPF_SF(3);
+    case 1: RPF_SF(1, 8); break;
+    case 2: RPF_SF(2, 8); break;
+    default: RPF_SF(3, 8);
   }
 #undef RPF_SF
   RPF_LAUNCH_CHECK();

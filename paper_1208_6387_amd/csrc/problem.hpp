@@ -29,6 +29,7 @@ struct rpf_problem_s {
 
   rpf::DevBuf<int> d_occ_of_pat, d_slot_off, d_occ_pat;
   rpf::DevBuf<int> d_l2m_ptr, d_l2m_code;    // per slot: multipliers (code = mult << 1 | negative)
+  rpf::DevBuf<int> d_l2m_bn;                 // boundary node of every slot-list entry
   rpf::DevBuf<int> d_ep_q, d_ep_bn, d_ep_occ;  // per multiplier endpoint
   rpf::DevBuf<int8_t> d_ep_pat, d_ep_sign;
   rpf::DevBuf<double> d_rot;

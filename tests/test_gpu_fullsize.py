@@ -88,13 +88,15 @@ def test_config2_operator(config2, R):
 
 
 @pytest.mark.parametrize("form,tol", [("bf16x3", 5e-5), ("bf16", 3e-2)])
-def test_config2_operator_large_tiles(config2, R, form, tol):
+@pytest.mark.parametrize("ncol", [97, 96])
+def test_config2_operator_large_tiles(config2, R, form, tol, ncol):
     """97 columns per occurrence make 64 x 97 = 6208 product columns: with n_b = 2598 that is 11 x 25
     tiles of 256 x 256, enough for the large-tile bf16 kernel, and both sides are ragged (2598 =
-    10 x 256 + 38, 6208 = 24 x 256 + 64).  Checked against the oracle's FP64 operator."""
+    10 x 256 + 38, 6208 = 24 x 256 + 64); 96 columns (a multiple of 4) take the four-column scatter
+    from the row-major result.  Checked against the oracle's FP64 operator."""
     p, o, pats, pb = config2
     prec = R.BF16X3 if form == "bf16x3" else R.BF16
-    X = np.random.default_rng(97).standard_normal((p.n_lambda, 97))
+    X = np.random.default_rng(ncol).standard_normal((p.n_lambda, ncol))
     Y = R.feti_apply(pb, pats, torch.from_numpy(X).cuda(), prec=prec).cpu().numpy()
     ref = o.F(X)
     err = np.abs(Y - ref).max() / np.abs(ref).max()
