@@ -912,8 +912,8 @@ bool rows_gemm2_sq(hipStream_t s, int64_t N, int a, int b, const double* M, doub
 
 // Sum of nrec records of len <= 256 doubles (record r at part[r * len]): workgroup g sums the
 // records g per .. g per + per - 1 with thread t on element t (coalesced) and writes element t
-// to out[g * rstride + t * inc].  record_sum runs it twice (groups, then their sums); the order
-// of every sum is fixed (deterministic).
+// to out[g * rstride + t * inc].  record_sum runs it over groups of records, then sums the groups
+// with k_recsum_final; the order of every sum is fixed (deterministic).
 __global__ __launch_bounds__(256) void k_recsum(int nrec, int len, int per, const double* part, double* out,
                                                 int64_t rstride, int64_t inc) {
   const int t = threadIdx.x;
@@ -931,6 +931,20 @@ __global__ __launch_bounds__(256) void k_recsum(int nrec, int len, int per, cons
   out[(int64_t)blockIdx.x * rstride + t * inc] = (v0 + v1) + (v2 + v3);
 }
 
+// Final pass: 1024 threads, four per element (records r = k mod 4 for thread part k), combined in
+// a fixed order through LDS.
+__global__ __launch_bounds__(1024) void k_recsum_final(int nrec, int len, const double* part, double* out,
+                                                       int64_t inc) {
+  __shared__ double red[4][256];
+  const int t = threadIdx.x & 255, k = threadIdx.x >> 8;
+  double v = 0.0;
+  if (t < len)
+    for (int r = k; r < nrec; r += 4) v += part[(int64_t)r * len + t];
+  red[k][t] = v;
+  __syncthreads();
+  if (k == 0 && t < len) out[t * inc] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+}
+
 // out[t * inc] = sum of the nrec records; tmp holds 256 records
 void record_sum(hipStream_t s, int nrec, int len, const double* part, double* tmp, double* out, int64_t inc) {
   const int groups = std::min(256, std::max(1, nrec));
@@ -938,7 +952,7 @@ void record_sum(hipStream_t s, int nrec, int len, const double* part, double* tm
   const int g = (int)cdiv(nrec, per);
   hipLaunchKernelGGL(k_recsum, dim3((unsigned)g), dim3(256), 0, s, nrec, len, per, part, tmp, (int64_t)len,
                      (int64_t)1);
-  hipLaunchKernelGGL(k_recsum, dim3(1), dim3(256), 0, s, g, len, g, tmp, out, (int64_t)0, inc);
+  hipLaunchKernelGGL(k_recsum_final, dim3(1), dim3(1024), 0, s, g, len, tmp, out, inc);
   RPF_LAUNCH_CHECK();
 }
 

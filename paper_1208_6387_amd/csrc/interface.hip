@@ -748,6 +748,11 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     yl.slab[p] = (int64_t)nb * cols;
     yl.nsplit[p] = nsp[p];
   }
+  pb->last_yl = yl;
+  pb->last_x = X;
+  pb->last_ldx = ldx;
+  pb->last_m = m;
+  ++pb->fp64_gen;
   scatter_all(pb, yl, m, Y, ldy, 0.0, s);
   if (project) {
     ensure_coarse(pb, pats, s);

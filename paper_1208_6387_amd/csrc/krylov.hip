@@ -216,6 +216,15 @@ __global__ void k_axpby(int64_t count, double a, const double* x, double b, doub
   if (i < count) y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
 }
 
+// out = a - sum_z b[z slab + .] (nsplit slabs of partial sums)
+__global__ void k_sub_slabs(int64_t count, const double* a, const double* b, int64_t slab, int nsplit, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double v = a[i];
+  for (int z = 0; z < nsplit; ++z) v -= b[z * slab + i];
+  out[i] = v;
+}
+
 // strided rows: y[l*ldy + j] = a x[l*ldx + j] + b y[l*ldy + j]
 __global__ void k_axpby_rows(int64_t rows, int cols, double a, const double* x, int64_t ldx, double b, double* y,
                              int64_t ldy) {
@@ -665,12 +674,18 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     } else {
       fill(s, S.lam.p, N * nr, 0.0);
     }
-    // r_0 = Q^T (d - F lambda_0)
-    apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+    // r_0 = Q^T (d - F lambda_0).  Here and at every later residual, S.tmp keeps the unprojected
+    // d - F lambda of the current lambda: the recovery reuses it.  A mixed solve forms r_0 with the
+    // low-precision product: it only seeds the first sweep, whose inner solve stops at inner_tol,
+    // far above that product's error; every residual after a sweep (and so every convergence
+    // decision) is FP64.
+    const bool lp_r0 = prec != RPF_FP64;
+    apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, lp_r0 ? prec : RPF_FP64, false, s);
+    uint64_t res_gen = lp_r0 ? ~(uint64_t)0 : pb->fp64_gen;  // the FP64 product behind S.tmp, if any
     hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
     RPF_LAUNCH_CHECK();
-    project(pb, S.tmp.p, nr, nr, s);
     RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
+    project(pb, S.R.p, nr, nr, s);
     S.r0n = S.colnorm2(S.R.p, nr, nr);
     for (double& v : S.r0n)
       if (!(v > 0.0)) v = 1.0;
@@ -695,10 +710,11 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
       if (!fresh) {
         // FP64 residual of the current lambda
         apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+        res_gen = pb->fp64_gen;
         hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
         RPF_LAUNCH_CHECK();
-        project(pb, S.tmp.p, nr, nr, s);
         RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
+        project(pb, S.R.p, nr, nr, s);
         rn = S.colnorm2(S.R.p, nr, nr);
         fresh = true;
       }
@@ -722,10 +738,12 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     // final FP64 residual check (recomputed unless the loop ended on a fresh one)
     if (!fresh) {
       apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+      res_gen = pb->fp64_gen;
       hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
       RPF_LAUNCH_CHECK();
-      project(pb, S.tmp.p, nr, nr, s);
-      rn = S.colnorm2(S.tmp.p, nr, nr);
+      RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
+      project(pb, S.R.p, nr, nr, s);
+      rn = S.colnorm2(S.R.p, nr, nr);
     }
     rel = 0.0;
     for (int c = 0; c < nr; ++c) rel = std::max(rel, std::sqrt(rn[c] / S.r0n[c]));
@@ -738,27 +756,38 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
 
     // ------------------------------------------------------------ recovery (eq. 2)
     Timer tr(s);
-    // alpha = (G^T G)^{-1} G^T (F lambda - d)
+    // alpha = (G^T G)^{-1} G^T (F lambda - d), with d - F lambda of the final lambda in S.tmp (its
+    // last FP64 residual)
     DevBuf<double> ca(std::max<int64_t>((int64_t)nG * nr, 1)), aa(std::max<int64_t>((int64_t)nG * nr, 1));
     if (nG > 0) {
-      apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
-      hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, -1.0, S.d.p, 1.0, S.tmp.p);
-      RPF_LAUNCH_CHECK();
       coarse_gt(pb, S.tmp.p, nr, nr, ca.p, s);
+      hipLaunchKernelGGL(k_axpby, dim3(nblocks((int64_t)nG * nr)), dim3(256), 0, s, (int64_t)nG * nr, -1.0, ca.p, 0.0,
+                         ca.p);
+      RPF_LAUNCH_CHECK();
       coarse_solve(pb, ca.p, aa.p, nr, s);
     }
+    // S+ A^T lambda of the final lambda is still in the problem's local product buffer when the
+    // last FP64 product was that of the final residual (no other FP64 product since)
+    const bool reuse = pb->fp64_gen == res_gen && pb->last_x == S.lam.p && pb->last_m == nr && pb->last_ldx == nr;
     for (int p = 0; p < pb->n_pat; ++p) {
       const rpf_pattern P = pats[p];
       const int nq = (int)pb->occ_of_pat[p].size();
       const int64_t cols = (int64_t)nq * nr;
       const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
-      DevBuf<double> X((size_t)P->n_b * cols), Ub((size_t)P->n_b * cols);
-      // u_b = S+ (g - A^T lambda) + Z alpha_s
-      gather_pattern(pb, p, pb->pat_nbn[p], S.lam.p, nr, nr, X.p, P->n_b, s);
-      hipLaunchKernelGGL(k_axpby, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, (int64_t)P->n_b * cols, 1.0,
-                         G[p].p, -1.0, X.p);
-      RPF_LAUNCH_CHECK();
-      dgemm(s, false, false, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, X.p, P->n_b, 0.0, Ub.p, P->n_b);
+      DevBuf<double> Ub((size_t)P->n_b * cols);
+      // u_b = S+ (g - A^T lambda) + Z alpha_s = S+ g - S+ A^T lambda + Z alpha_s
+      if (reuse) {
+        hipLaunchKernelGGL(k_sub_slabs, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, (int64_t)P->n_b * cols,
+                           Yg.p + off[p], pb->last_yl.base[p], pb->last_yl.slab[p], pb->last_yl.nsplit[p], Ub.p);
+        RPF_LAUNCH_CHECK();
+      } else {
+        DevBuf<double> X((size_t)P->n_b * cols);
+        gather_pattern(pb, p, pb->pat_nbn[p], S.lam.p, nr, nr, X.p, P->n_b, s);
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, (int64_t)P->n_b * cols,
+                           1.0, G[p].p, -1.0, X.p);
+        RPF_LAUNCH_CHECK();
+        dgemm(s, false, false, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, X.p, P->n_b, 0.0, Ub.p, P->n_b);
+      }
       if (nG > 0 && P->k > 0) {
         hipLaunchKernelGGL(k_add_kernel_term, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, P->n_b, P->k, nq,
                            nr, occ, pb->d_goff.p, P->Z.p, aa.p, Ub.p);

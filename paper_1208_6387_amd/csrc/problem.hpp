@@ -40,6 +40,13 @@ struct rpf_problem_s {
 
   // W-format workspaces
   rpf::DevBuf<double> xloc, yloc;
+  // the local products S+ A^T X of the last FP64 operator product (in yloc), its X, ldx and m;
+  // fp64_gen counts FP64 products, so a reader can tell that yloc still holds them
+  rpf::YLoc last_yl{};
+  const double* last_x = nullptr;
+  int64_t last_ldx = 0;
+  int last_m = 0;
+  uint64_t fp64_gen = 0;
   rpf::DevBuf<float> xloc32, yloc32;
   rpf::DevBuf<uint16_t> xhi, xlo;
 
