@@ -36,6 +36,10 @@ WORKLOADS = {
     "elast-12cube-4x4x4": (1, "orthodir", "3-D elasticity, 12^3-brick pattern x 64 occurrences (4x4x4), "
                                           "1 load case, 8 permutations", dict(max_blocks=0, inner_tol=1e-4)),
     "heat-row-16x16x4": (0, "orthodir", "2-D heat, 16x16 pattern x 4 (row)", dict(max_blocks=0, inner_tol=1e-4)),
+    "uneven-plate48-sector16-base16": (3, "orthodir", "3-D elasticity, uneven batch: 24x8x2 plates x 48 (7.5 deg "
+                                                      "steps), 16x6x4 ring sectors x 16, one 16^3 base block; "
+                                                      "1 load case, 8 permutations",
+                                       dict(max_blocks=0, inner_tol=1e-4)),
 }
 PREC_NAMES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16": 3}
 METHODS = {"classical": 0, "block_cg": 1, "orthodir": 2}

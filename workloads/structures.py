@@ -359,6 +359,99 @@ def ring_elast(n_occ=3, pat_shape=(2, 3, 2), r_in=1.0, r_out=1.5, height=0.5, n_
                    f_local, n_rhs, n_perm if n_perm is not None else n_occ, tol, meta, swap_rule=swap)
 
 
+def uneven_three(plate=(24, 8, 2), sector=(6, 16, 4), base=16, n_sectors=16, plates_per_sector=3,
+                 n_rhs=1, n_perm=8, seed=0, tol=1e-8):
+    """Three elasticity patterns of uneven size joined by algebraic glue (node lists and frame
+    rotations, not one geometric mesh):
+
+    * ring sectors (pattern 1; shape = (radial, circumferential, axial) elements) spanning
+      2 pi / n_sectors, occurrence s rotated by 2 pi s / n_sectors about z, closed into a ring
+      through their end faces (these do coincide geometrically);
+    * a base block (pattern 2; base^3 elements) whose top face, over the sector's bottom-face
+      node grid (circumferential x radial), is glued to the bottom face of sector 0; the base's
+      bottom face is clamped;
+    * thin plates (pattern 0; shape = (length, width, thickness) elements), plate q rotated by
+      2 pi q / (n_sectors plates_per_sector) about z, glued by a 5 x 3 node patch of their root
+      face (x = 0; width nodes 2..6, all thickness nodes) to patch q % plates_per_sector of the
+      outer face of sector q // plates_per_sector (circumferential nodes 1 + 5w .. 5 + 5w, axial
+      nodes 1..3).
+
+    Occurrences: sectors first, then plates, then the base.  Loads are i.i.d. N(0,1) nodal forces
+    in each occurrence's frame.
+    """
+    nr_, nt, nz = sector
+    assert nr_ >= 1 and nt >= 5 * plates_per_sector + 1 and nz >= 4 and plate[1] >= 7 and plate[2] == 2
+    assert base >= nt and base >= nr_
+    # ---- patterns
+    pm = M.GridMesh(plate, (plate[0] / 8.0, plate[1] / 8.0, plate[2] / 8.0))
+    Kp = M.assemble(pm, M.hex_elasticity(*pm.h), 3)
+    sm = M.GridMesh(sector, (1.0, 1.0, 1.0))
+    lat = sm.lattice
+    ang = 2 * np.pi / n_sectors
+    r_in, r_out, height = 2.0, 3.0, 0.5
+    r = r_in + (r_out - r_in) * lat[:, 0] / nr_
+    th = ang * lat[:, 1] / nt
+    zc = height * lat[:, 2] / nz
+    scoords = np.stack([r * np.cos(th), r * np.sin(th), zc], axis=1)
+    Ks = M.assemble_general(sm.elements(), scoords, 3)
+    bm = M.GridMesh((base,) * 3, (2.0,) * 3)
+    Kb = M.assemble(bm, M.hex_elasticity(*bm.h), 3)
+    pats = [Pattern("plate-pattern", 3, pm.coords, Kp, 6), Pattern("sector-pattern", 3, scoords, Ks, 6),
+            Pattern("base-pattern", 3, bm.coords, Kb, 6)]
+    n_plates = n_sectors * plates_per_sector
+    # ---- sectors: global nodes by coinciding coordinates
+    srot = np.stack([rot_z(ang * s) for s in range(n_sectors)])
+    allc = np.concatenate([scoords @ srot[s].T for s in range(n_sectors)])
+    key = np.round(allc / (1e-6 * r_out)).astype(np.int64)
+    _, gid = np.unique(key, axis=0, return_inverse=True)
+    gid = gid.ravel()
+    occ_gnode = [gid[s * sm.n_nodes:(s + 1) * sm.n_nodes].astype(np.int64) for s in range(n_sectors)]
+    n_g = int(gid.max()) + 1
+    sec_node = lambda ir, it, iz: sm.node_id(np.stack([ir, it, iz], axis=-1))
+    # ---- plates
+    prot = np.stack([rot_z(2 * np.pi * q / n_plates) for q in range(n_plates)])
+    jj, kk = np.meshgrid(np.arange(2, 7), np.arange(3), indexing="ij")
+    root = pm.node_id(np.stack([np.zeros_like(jj), jj, kk], axis=-1)).ravel()
+    for q in range(n_plates):
+        g = n_g + np.arange(pm.n_nodes, dtype=np.int64)
+        n_g += pm.n_nodes
+        sidx, w = divmod(q, plates_per_sector)
+        target = sec_node(np.full_like(jj, nr_), 1 + 5 * w + (jj - 2), 1 + kk).ravel()
+        g[root] = occ_gnode[sidx][target]
+        occ_gnode.append(g)
+    # ---- base: top-face patch over the sector's (circumferential x radial) bottom node grid
+    g = n_g + np.arange(bm.n_nodes, dtype=np.int64)
+    n_g += bm.n_nodes
+    ti, ri = np.meshgrid(np.arange(nt + 1), np.arange(nr_ + 1), indexing="ij")
+    top = bm.node_id(np.stack([ti, ri, np.full_like(ti, base)], axis=-1)).ravel()
+    g[top] = occ_gnode[0][sec_node(ri, ti, np.zeros_like(ti)).ravel()]
+    occ_gnode.append(g)
+    dir_g = g[bm.face_nodes(2, 0)]
+    # compact the global numbering
+    used, inv = np.unique(np.concatenate(occ_gnode), return_inverse=True)
+    off = np.cumsum([0] + [len(x) for x in occ_gnode])
+    occ_gnode = [inv[off[i]:off[i + 1]].astype(np.int64) for i in range(len(off) - 1)]
+    dir_g = np.searchsorted(used, dir_g)
+    n_g = len(used)
+    occ_pattern = [1] * n_sectors + [0] * n_plates + [2]
+    rots = np.concatenate([srot, prot, np.eye(3)[None]])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f_local = [rng.standard_normal((len(x) * 3, n_rhs)) for x in occ_gnode]
+    far = lat[:, 1] == nt
+
+    def swap(oa, la, ob, lb):
+        # ring interfaces: the far end face of the lower sector is the '+' side
+        ring = (oa < n_sectors) & (ob < n_sectors)
+        out = np.zeros(len(oa), bool)
+        out[ring] = (~far[la[ring]]) & far[lb[ring]]
+        return out
+
+    meta = dict(kind="elast", uneven=True, rotated=True, plate=tuple(plate), sector=tuple(sector), base=base,
+                n_sectors=n_sectors, plates_per_sector=plates_per_sector, seed=seed)
+    return _finish(f"uneven-plate{n_plates}-sector{n_sectors}-base{base}", 3, pats, occ_pattern, rots, occ_gnode,
+                   n_g, dir_g, f_local, n_rhs, n_perm, tol, meta, swap_rule=swap)
+
+
 # --------------------------------------------------------------------------- named configurations
 
 def config(i: int, small: bool = False) -> Problem:
@@ -367,7 +460,8 @@ def config(i: int, small: bool = False) -> Problem:
     0: 2-D heat, 16x16 Q1 square pattern, 1x4 row, f = 1, u = 0 on the left edge.
     1: 3-D elasticity, 12^3 brick pattern, 4x4x4 grid, clamped x = 0, N(0,1) nodal forces.
     2: same with 8 load cases.
-    3: uneven three-pattern batch (not built here yet).
+    3: uneven three-pattern batch: 24x8x2 plates x 48 (rotated by 7.5 deg steps), 16x6x4 ring
+       sectors x 16 (22.5 deg steps), one 16^3 base block clamped at the bottom (uneven_three).
     4: 20^3 brick pattern, 8x8x8 grid, 16 load cases plus traction (1,0,0) on x = 1.
     """
     seed = BASE_SEED + i
@@ -380,6 +474,8 @@ def config(i: int, small: bool = False) -> Problem:
     if i == 2:
         return grid_structure("elast-12cube-4x4x4-8rhs", "elast", (12, 12, 12), (0.25,) * 3, (4, 4, 4), n_rhs=8,
                               n_perm=1, dirichlet=(0, 0), seed=seed)
+    if i == 3:
+        return uneven_three(seed=seed)
     if i == 4:
         return grid_structure("elast-20cube-8x8x8-16rhs", "elast", (20, 20, 20), (0.125,) * 3, (8, 8, 8),
                               n_rhs=16, n_perm=1, dirichlet=(0, 0), traction=(0, 1, (1.0, 0.0, 0.0)), seed=seed)
