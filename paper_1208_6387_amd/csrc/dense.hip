@@ -1095,29 +1095,53 @@ Envelope Envelope::dense(int64_t n) {
   return e;
 }
 
+// Two levels: NB-wide steps (diagonal block, panel) inside panels of PANEL = 4 NB columns.  A step
+// updates only the columns of its own panel (rank NB); everything to the right of a panel gets
+// one rank-PANEL update once the panel is done, so the trailing matrix and the boundary rows are
+// read and written once per panel instead of once per step, by GEMMs with K = PANEL (compute-bound
+// instead of memory-bound).  The result is the same factor (the updates of one column commute).
 void potrf(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac, const Envelope& env, double* dinv,
            int* status) {
+  constexpr int64_t PANEL = 4 * NB;
   const int64_t nblk = cdiv(n_fac, NB);
   RPF_CHECK((int64_t)env.rend.size() >= nblk, RPF_EINVAL, "potrf: envelope too short");
-  for (int64_t t = 0; t < nblk; ++t) {
-    const int64_t j0 = t * NB;
-    const int jb = (int)std::min<int64_t>(NB, n_fac - j0);
-    double* dt = dinv + t * NB * NB;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A + j0 * lda + j0, lda, jb, dt, status, (int)t);
-    RPF_LAUNCH_CHECK();
-    const int64_t r0 = j0 + jb;
-    const int64_t rend = std::max<int64_t>(r0, std::min<int64_t>(env.rend[t], n_fac));
-    double* col = A + j0 * lda;
-    // panel: L21 = A21 L11^{-T}, in place (one N tile covers the jb columns)
-    if (rend > r0) dgemm(s, false, true, rend - r0, jb, jb, 1.0, col + r0, lda, dt, NB, 0.0, col + r0, lda);
-    if (n > n_fac) dgemm(s, false, true, n - n_fac, jb, jb, 1.0, col + n_fac, lda, dt, NB, 0.0, col + n_fac, lda);
-    // trailing update restricted to the envelope; the boundary-boundary block is deferred
-    if (rend > r0) {
-      dgemm(s, false, true, rend - r0, rend - r0, jb, -1.0, col + r0, lda, col + r0, lda, 1.0, A + r0 * lda + r0,
-            lda, true);
+  for (int64_t P0 = 0; P0 < n_fac; P0 += PANEL) {
+    const int64_t P1 = std::min<int64_t>(P0 + PANEL, n_fac);
+    int64_t pend = P1;  // rows (and columns) reached by the panel's envelope
+    for (int64_t j0 = P0; j0 < P1; j0 += NB) {
+      const int64_t t = j0 / NB;
+      const int jb = (int)std::min<int64_t>(NB, n_fac - j0);
+      double* dt = dinv + t * NB * NB;
+      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A + j0 * lda + j0, lda, jb, dt, status, (int)t);
+      RPF_LAUNCH_CHECK();
+      const int64_t r0 = j0 + jb;
+      const int64_t rend = std::max<int64_t>(r0, std::min<int64_t>(env.rend[t], n_fac));
+      pend = std::max(pend, rend);
+      double* col = A + j0 * lda;
+      // panel: L21 = A21 L11^{-T}, in place (one N tile covers the jb columns)
+      if (rend > r0) dgemm(s, false, true, rend - r0, jb, jb, 1.0, col + r0, lda, dt, NB, 0.0, col + r0, lda);
+      if (n > n_fac) dgemm(s, false, true, n - n_fac, jb, jb, 1.0, col + n_fac, lda, dt, NB, 0.0, col + n_fac, lda);
+      // update of the remaining columns of this panel (rows within the envelope, boundary rows)
+      const int64_t cend = std::min(rend, P1);
+      if (cend > r0) {
+        dgemm(s, false, true, rend - r0, cend - r0, jb, -1.0, col + r0, lda, col + r0, lda, 1.0,
+              A + r0 * lda + r0, lda, true);
+        if (n > n_fac)
+          dgemm(s, false, true, n - n_fac, cend - r0, jb, -1.0, col + n_fac, lda, col + r0, lda, 1.0,
+                A + r0 * lda + n_fac, lda);
+      }
+    }
+    // rank-PANEL update of everything right of the panel (the boundary-boundary block is deferred);
+    // rows of a step's columns past its own envelope end are zero, so one product over the
+    // panel's whole envelope is exact
+    if (pend > P1) {
+      const int64_t K = P1 - P0;
+      double* pc = A + P0 * lda;
+      dgemm(s, false, true, pend - P1, pend - P1, K, -1.0, pc + P1, lda, pc + P1, lda, 1.0, A + P1 * lda + P1, lda,
+            true);
       if (n > n_fac)
-        dgemm(s, false, true, n - n_fac, rend - r0, jb, -1.0, col + n_fac, lda, col + r0, lda, 1.0,
-              A + r0 * lda + n_fac, lda);
+        dgemm(s, false, true, n - n_fac, pend - P1, K, -1.0, pc + n_fac, lda, pc + P1, lda, 1.0, A + P1 * lda + n_fac,
+              lda);
     }
   }
 }
