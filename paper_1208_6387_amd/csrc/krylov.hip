@@ -264,16 +264,38 @@ __global__ void k_merge_u(int n_p, int n_i, int n_b, int nq, int nr, const int* 
 }
 
 // Y[row, col] = beta Y + alpha * sum_e A_csr[row, e] X[colidx[e], col]   (CSR SpMM, column-major X, Y)
+// One thread per (row, SPMM_CB consecutive columns): a CSR entry is read once for all of them and
+// their SPMM_CB gathers from X are independent, so a row's walk is not a chain of one-at-a-time
+// loads.  Consecutive threads take consecutive rows (coalesced stores of Y).
+constexpr int SPMM_CB = 8;
 __global__ void k_spmm(int rows, int64_t cols, const int* ptr, const int* idx, const double* val, const double* X,
                        int64_t ldx, double alpha, double* Y, int64_t ldy, double beta) {
+  const int64_t ncb = (cols + SPMM_CB - 1) / SPMM_CB;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)rows * cols) return;
+  if (i >= (int64_t)rows * ncb) return;
   const int row = (int)(i % rows);
-  const int64_t col = i / rows;
-  double s = 0.0;
-  for (int e = ptr[row]; e < ptr[row + 1]; ++e) s += val[e] * X[col * ldx + idx[e]];
-  double* y = Y + col * ldy + row;
-  *y = (beta == 0.0) ? alpha * s : beta * *y + alpha * s;
+  const int64_t c0 = (i / rows) * SPMM_CB;
+  const int cn = (int)min<int64_t>(SPMM_CB, cols - c0);
+  double s[SPMM_CB];
+#pragma unroll
+  for (int j = 0; j < SPMM_CB; ++j) s[j] = 0.0;
+  const double* Xc = X + c0 * ldx;
+  for (int e = ptr[row]; e < ptr[row + 1]; ++e) {
+    const int64_t k = idx[e];
+    const double v = val[e];
+#pragma unroll
+    for (int j = 0; j < SPMM_CB; ++j)
+      if (j < cn) s[j] += v * Xc[j * ldx + k];
+  }
+#pragma unroll
+  for (int j = 0; j < SPMM_CB; ++j) {
+    if (j >= cn) break;
+    double* y = Y + (c0 + j) * ldy + row;
+    *y = (beta == 0.0) ? alpha * s[j] : beta * *y + alpha * s[j];
+  }
+}
+inline unsigned spmm_blocks(int rows, int64_t cols) {
+  return (unsigned)cdiv(std::max<int64_t>((int64_t)rows * ((cols + SPMM_CB - 1) / SPMM_CB), 1), 256);
 }
 
 // e[(goff[s] + r')*nr + r] = E_p[r' + k*(q*nr + r)]  (Z^T g of pattern p into the coarse layout)
@@ -638,7 +660,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
         // Y2 = K_ii^{-1} f_i ; g = f_b - K_bi Y2
         trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Y2[p].p, P->n_i, cols, false);
         trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Y2[p].p, P->n_i, cols, true);
-        hipLaunchKernelGGL(k_spmm, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, P->n_b, cols,
+        hipLaunchKernelGGL(k_spmm, dim3(spmm_blocks(P->n_b, cols)), dim3(256), 0, s, P->n_b, cols,
                            P->kbi_ptr.p, P->kbi_col.p, P->kbi_val.p, Y2[p].p, (int64_t)P->n_i, -1.0, G[p].p,
                            (int64_t)P->n_b, 1.0);
         RPF_LAUNCH_CHECK();
@@ -796,7 +818,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
       // u_i = K_ii^{-1} f_i - K_ii^{-1} K_ib u_b
       DevBuf<double> Ti(std::max<int64_t>((int64_t)P->n_i * cols, 1));
       if (P->n_i > 0) {
-        hipLaunchKernelGGL(k_spmm, dim3(nblocks((int64_t)P->n_i * cols)), dim3(256), 0, s, P->n_i, cols, P->kib_ptr.p,
+        hipLaunchKernelGGL(k_spmm, dim3(spmm_blocks(P->n_i, cols)), dim3(256), 0, s, P->n_i, cols, P->kib_ptr.p,
                            P->kib_col.p, P->kib_val.p, Ub.p, (int64_t)P->n_b, 1.0, Ti.p, (int64_t)P->n_i, 0.0);
         RPF_LAUNCH_CHECK();
         trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Ti.p, P->n_i, cols, false);
