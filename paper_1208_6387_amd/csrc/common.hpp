@@ -188,6 +188,10 @@ void rows_gemm_from(hipStream_t s, int64_t N, int a, int b, double alpha, const 
 // The paired product below (a, b <= 16, M column-major) that also returns the column sums of
 // squares of Y2 after the update: sq[c * ldsq], c < b (part: cdiv(N, 256) * b doubles of
 // workspace).  Returns false, doing nothing, when the block is too wide.
+// Z = R - X M1 (b columns) and Lam += X M2 (c columns) from one read of X (N x a); a, b, c <= 16,
+// M1 and M2 column-major with a rows.  Returns false (nothing launched) for other shapes.
+bool rows_orth_lam(hipStream_t s, int64_t N, int a, int b, int c, const double* X, int64_t ldx, const double* M1,
+                   const double* R, int64_t ldr, double* Z, int64_t ldz, const double* M2, double* Lam, int64_t ldl);
 // Y = beta Y + alpha X M (a, b <= 16, b divides 256), and from the same pass: sq[c * ldsq] = the
 // squared column norms of the new Y (skipped when sq is NULL) and G (a x b, column-major) =
 // X^T Y_new.  sqpart and gpart are workspaces of (cdiv(N, 256) + 256) * b and

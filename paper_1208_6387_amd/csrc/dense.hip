@@ -844,6 +844,104 @@ __global__ __launch_bounds__(256) void k_rows_update_gram(int64_t N, int a, int 
   }
 }
 
+// Two row-block products from one read of X (N x a, a <= 16), for the block step that starts from
+// the residual: Z = R - X M1 (b columns) and Lam += X M2 (c columns), M1, M2 column-major with
+// a rows (b, c <= 16).  X is the previous step's direction block: the orthogonalisation of the new
+// block and the deferred solution update of the previous one share its pass.  Rows of X enter LDS
+// with lane-consecutive loads, each thread forms its row of both products, and the results leave
+// through LDS with lane-consecutive stores (the loads of R and Lam for a tile all in flight).
+__global__ __launch_bounds__(256) void k_rows_orth_lam(int64_t N, int a, int b, int c, const double* M1,
+                                                       const double* M2, const double* X, int64_t ldx,
+                                                       const double* R, int64_t ldr, double* Z, int64_t ldz,
+                                                       double* Lam, int64_t ldl) {
+  __shared__ double sm1[16][16];
+  __shared__ double sm2[16][16];
+  __shared__ double xs[256][17];
+  __shared__ double ys[256][17];
+  const int tid = threadIdx.x;
+  {
+    const int i = tid >> 4, j = tid & 15;
+    sm1[i][j] = (i < a && j < b) ? M1[i + (int64_t)a * j] : 0.0;
+    sm2[i][j] = (i < a && j < c) ? M2[i + (int64_t)a * j] : 0.0;
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int rows = (int)min<int64_t>(256, N - r0);
+  if (rows == 256 && a == 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      t[u] = X[(r0 + (e >> 4)) * ldx + (e & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      xs[e >> 4][e & 15] = t[u];
+    }
+  } else {
+    for (int e = tid; e < 256 * 16; e += 256) {
+      const int rr = e >> 4, cc = e & 15;
+      xs[rr][cc] = (rr < rows && cc < a) ? X[(r0 + rr) * ldx + cc] : 0.0;
+    }
+  }
+  __syncthreads();
+  double acc1[16], acc2[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc1[j] = acc2[j] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const double xv = xs[tid][i];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      acc1[j] += xv * sm1[i][j];
+      acc2[j] += xv * sm2[i][j];
+    }
+  }
+  __syncthreads();  // xs is reused for the first product
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    xs[tid][j] = acc1[j];
+    ys[tid][j] = acc2[j];
+  }
+  __syncthreads();
+  if (rows == 256 && b == 16) {
+    double rv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      rv[u] = R[(r0 + (e >> 4)) * ldr + (e & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      Z[(r0 + (e >> 4)) * ldz + (e & 15)] = rv[u] - xs[e >> 4][e & 15];
+    }
+  } else {
+    for (int e = tid; e < rows * b; e += 256) {
+      const int rr = e / b, cc = e - rr * b;
+      Z[(r0 + rr) * ldz + cc] = R[(r0 + rr) * ldr + cc] - xs[rr][cc];
+    }
+  }
+  if (rows == 256 && c == 16) {
+    double lv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      lv[u] = Lam[(r0 + (e >> 4)) * ldl + (e & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      Lam[(r0 + (e >> 4)) * ldl + (e & 15)] = lv[u] + ys[e >> 4][e & 15];
+    }
+  } else {
+    for (int e = tid; e < rows * c; e += 256) {
+      const int rr = e / c, cc = e - rr * c;
+      Lam[(r0 + rr) * ldl + cc] += ys[rr][cc];
+    }
+  }
+}
+
 namespace {
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
@@ -931,18 +1029,16 @@ __global__ __launch_bounds__(256) void k_recsum(int nrec, int len, int per, cons
   out[(int64_t)blockIdx.x * rstride + t * inc] = (v0 + v1) + (v2 + v3);
 }
 
-// Final pass: 1024 threads, four per element (records r = k mod 4 for thread part k), combined in
-// a fixed order through LDS.
-__global__ __launch_bounds__(1024) void k_recsum_final(int nrec, int len, const double* part, double* out,
-                                                       int64_t inc) {
-  __shared__ double red[4][256];
-  const int t = threadIdx.x & 255, k = threadIdx.x >> 8;
+// Final pass: one wavefront per element (lane l sums the records l, l + 64, ..., then a fixed
+// butterfly across the lanes), so the records' loads of an element are all in flight together.
+__global__ __launch_bounds__(256) void k_recsum_final(int nrec, int len, const double* part, double* out,
+                                                      int64_t inc) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (t >= len) return;
   double v = 0.0;
-  if (t < len)
-    for (int r = k; r < nrec; r += 4) v += part[(int64_t)r * len + t];
-  red[k][t] = v;
-  __syncthreads();
-  if (k == 0 && t < len) out[t * inc] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+  for (int r = lane; r < nrec; r += 64) v += part[(int64_t)r * len + t];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) out[t * inc] = v;
 }
 
 // out[t * inc] = sum of the nrec records; tmp holds 256 records
@@ -952,8 +1048,17 @@ void record_sum(hipStream_t s, int nrec, int len, const double* part, double* tm
   const int g = (int)cdiv(nrec, per);
   hipLaunchKernelGGL(k_recsum, dim3((unsigned)g), dim3(256), 0, s, nrec, len, per, part, tmp, (int64_t)len,
                      (int64_t)1);
-  hipLaunchKernelGGL(k_recsum_final, dim3(1), dim3(1024), 0, s, g, len, tmp, out, inc);
+  hipLaunchKernelGGL(k_recsum_final, dim3((unsigned)cdiv(len, 4)), dim3(256), 0, s, g, len, tmp, out, inc);
   RPF_LAUNCH_CHECK();
+}
+
+bool rows_orth_lam(hipStream_t s, int64_t N, int a, int b, int c, const double* X, int64_t ldx, const double* M1,
+                   const double* R, int64_t ldr, double* Z, int64_t ldz, const double* M2, double* Lam, int64_t ldl) {
+  if (N <= 0 || a <= 0 || a > 16 || b <= 0 || b > 16 || c <= 0 || c > 16) return false;
+  hipLaunchKernelGGL(k_rows_orth_lam, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, a, b, c, M1, M2, X, ldx, R,
+                     ldr, Z, ldz, Lam, ldl);
+  RPF_LAUNCH_CHECK();
+  return true;
 }
 
 bool rows_update_gram(hipStream_t s, int64_t N, int a, int b, const double* M, const double* X, int64_t ldx,
@@ -1007,79 +1112,147 @@ void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const doubl
 }
 
 // ============================================================================ Cholesky
-// One NB x NB diagonal block on a single wavefront: lane t keeps row t of the
-// block in registers and the factor is built column by column (right-looking):
-// lane j takes the square root and its reciprocal, the other lanes scale their
-// entry of column j and publish it through LDS, then update the rest of their row.
-// The inverse factor is formed right-looking as well (lane c holds column c of
-// L^{-1}; step k finalises row k and updates the rows below with column k of L),
-// so every step issues one batch of independent LDS reads instead of a chain of
-// dependent ones.  Both results leave through LDS with coalesced stores.  Rows
-// and columns beyond jb are padded with the identity.
-__global__ __launch_bounds__(64) void k_potrf_diag(double* A, int64_t lda, int jb, double* dinv, int* status,
-                                                   int blk) {
-  __shared__ double Ls[NB][NB + 1];
-  __shared__ double rdiag[NB];
-  const int t = threadIdx.x;
-  bool bad = false;
-  {
-    double a[NB];
+// One NB x NB diagonal block (NB = 64), blocked by 16: four steps, each (1) factors its 16 x 16
+// diagonal block and inverts it on one wavefront (lane r holds row r in registers; the column
+// values of the other rows come by cross-lane shuffles, no LDS round trips), (2) solves the panel
+// below it, L21 = A21 L11^{-T}, and (3) updates the trailing lower triangle, A22 -= L21 L21^T, both
+// on all 256 threads from LDS.  The inverse factor is then assembled block row by block row:
+// W_ik = -W_ii sum_{j=k}^{i-1} L_ij W_jk.  A single right-looking wavefront needs either ~20k
+// unrolled instructions (more than the instruction cache holds) or 64 dependent steps over LDS;
+// this form has 4 short serial steps.  Rows and columns beyond jb are padded with the identity.
+__global__ __launch_bounds__(256) void k_potrf_diag(double* Ag, int64_t lda, int jb, double* dinv, int* status,
+                                                    int blk) {
+  static_assert(NB == 64, "k_potrf_diag assumes 64 x 64 blocks");
+  constexpr int QB = 16;
+  __shared__ double A[NB][NB + 1];
+  __shared__ double W[NB][NB + 1];
+  __shared__ double T[3][QB][QB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & (NB - 1), c = e >> 6;
+    double v = (r == c) ? 1.0 : 0.0;
+    if (r < jb && c < jb && c <= r) v = Ag[(int64_t)c * lda + r];
+    A[r][c] = v;
+    W[r][c] = 0.0;
+  }
+  __syncthreads();
+  for (int kb = 0; kb < NB / QB; ++kb) {
+    const int k0 = kb * QB;
+    if (wave == 0) {
+      // (1) 16 x 16 Cholesky and its inverse; lanes >= 16 carry zeros and are never read back
+      const int r = lane & (QB - 1);
+      double a[QB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      double v = (c == t) ? 1.0 : 0.0;
-      if (t < jb && c < jb && c <= t) v = A[(int64_t)c * lda + t];
-      a[c] = v;
-    }
+      for (int c = 0; c < QB; ++c) a[c] = (lane < QB && c <= r) ? A[k0 + r][k0 + c] : 0.0;
+      double rd[QB];
+      bool badw = false;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      if (t == j) {
-        double d = a[j];
+      for (int j = 0; j < QB; ++j) {
+        double d = __shfl(a[j], j, 64);
         if (!(d > 0.0)) {
-          bad = true;
+          badw = true;
           d = 1.0;
         }
-        a[j] = sqrt(d);
-        Ls[j][j] = a[j];
-        rdiag[j] = 1.0 / a[j];
-      }
-      __syncthreads();
-      if (t > j) {
-        a[j] *= rdiag[j];
-        Ls[t][j] = a[j];
-      }
-      __syncthreads();
-      if (t > j) {
-        const double ltj = a[j];
+        const double piv = sqrt(d);
+        rd[j] = 1.0 / piv;
+        if (r == j) a[j] = piv;
+        if (r > j) a[j] *= rd[j];
 #pragma unroll
-        for (int c = j + 1; c < NB; ++c)
-          if (c <= t) a[c] -= ltj * Ls[c][j];
+        for (int c = j + 1; c < QB; ++c) {
+          const double lcj = __shfl(a[j], c, 64);  // row c's entry in column j
+          if (r >= c) a[c] -= a[j] * lcj;
+        }
       }
+      if (lane < QB) {
+#pragma unroll
+        for (int c = 0; c < QB; ++c)
+          if (c <= r) A[k0 + r][k0 + c] = a[c];
+      }
+      // inverse, lane t = column t: x[k] *= 1/l_kk; x[i] -= l_ik x[k] for i > k
+      double x[QB];
+#pragma unroll
+      for (int i = 0; i < QB; ++i) x[i] = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < QB; ++k) {
+        x[k] *= rd[k];
+#pragma unroll
+        for (int i = k + 1; i < QB; ++i) x[i] -= __shfl(a[k], i, 64) * x[k];  // l_ik from row i's lane
+      }
+      if (lane < QB) {
+#pragma unroll
+        for (int i = 0; i < QB; ++i) W[k0 + i][k0 + r] = (i >= r) ? x[i] : 0.0;
+      }
+      if (badw && lane == 0) bad = 1;
+    }
+    __syncthreads();
+    const int r0 = k0 + QB, rem = NB - r0;
+    if (rem > 0) {
+      // (2) panel: L[r][k0 + c] = sum_{q <= c} A[r][k0 + q] W[k0 + c][k0 + q]
+      double pv[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int e = tid + 256 * u;
+        pv[u] = 0.0;
+        if (e < rem * QB) {
+          const int rr = r0 + e / QB, c = e % QB;
+          double acc = 0.0;
+          for (int q = 0; q <= c; ++q) acc += A[rr][k0 + q] * W[k0 + c][k0 + q];
+          pv[u] = acc;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int e = tid + 256 * u;
+        if (e < rem * QB) A[r0 + e / QB][k0 + e % QB] = pv[u];
+      }
+      __syncthreads();
+      // (3) trailing lower triangle: A[i][c] -= sum_q L[i][k0 + q] L[c][k0 + q], r0 <= c <= i
+      const int ntri = rem * (rem + 1) / 2;
+      for (int e = tid; e < ntri; e += 256) {
+        // e -> (i, c) with i - r0 = ii, c - r0 = cc <= ii, row-wise
+        int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+        while (ii * (ii + 1) / 2 > e) --ii;
+        const int cc = e - ii * (ii + 1) / 2;
+        const int i = r0 + ii, c = r0 + cc;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < QB; ++q) acc += A[i][k0 + q] * A[c][k0 + q];
+        A[i][c] -= acc;
+      }
+      __syncthreads();
     }
   }
-  __syncthreads();
-  // write the factor back (lower part of the jb x jb block), coalesced over rows
-#pragma unroll 4
-  for (int c = 0; c < NB; ++c)
-    if (t < jb && c < jb && c <= t) A[(int64_t)c * lda + t] = Ls[t][c];
-  // column t of the inverse factor, right-looking
-  double x[NB];
+  // off-diagonal blocks of the inverse, block row by block row
+  for (int ib = 1; ib < NB / QB; ++ib) {
+    // T_k = sum_{j=k}^{ib-1} L_{ib,j} W_{j,k} for k < ib
+    for (int e = tid; e < ib * QB * QB; e += 256) {
+      const int k = e / (QB * QB), rr = (e / QB) % QB, cc = e % QB;
+      double acc = 0.0;
+      for (int q = k * QB; q < ib * QB; ++q) acc += A[ib * QB + rr][q] * W[q][k * QB + cc];
+      T[k][rr][cc] = acc;
+    }
+    __syncthreads();
+    // W_{ib,k} = -W_{ib,ib} T_k
+    for (int e = tid; e < ib * QB * QB; e += 256) {
+      const int k = e / (QB * QB), rr = (e / QB) % QB, cc = e % QB;
+      double acc = 0.0;
 #pragma unroll
-  for (int r = 0; r < NB; ++r) x[r] = (r == t) ? 1.0 : 0.0;
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    x[k] *= rdiag[k];
-    const double xk = x[k];
-#pragma unroll
-    for (int r = k + 1; r < NB; ++r) x[r] -= Ls[r][k] * xk;
+      for (int q = 0; q < QB; ++q) acc += W[ib * QB + rr][ib * QB + q] * T[k][q][cc];
+      W[ib * QB + rr][k * QB + cc] = -acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();  // every lane is done reading L
-#pragma unroll
-  for (int r = 0; r < NB; ++r) Ls[r][t] = x[r];
-  __syncthreads();
-  // dinv column-major: dinv[c * NB + r] = (L^{-1})[r][c]; lane r writes row r of each column
-#pragma unroll 4
-  for (int c = 0; c < NB; ++c) dinv[(int64_t)c * NB + t] = Ls[t][c];
-  if (bad) atomicCAS(status, 0, blk + 1);
+  // the factor (lower part of the jb x jb block) and dinv (column-major, upper part zero)
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & (NB - 1), c = e >> 6;
+    if (r < jb && c < jb && c <= r) Ag[(int64_t)c * lda + r] = A[r][c];
+    dinv[(int64_t)c * NB + r] = (r >= c) ? W[r][c] : 0.0;
+  }
+  if (tid == 0 && bad) atomicCAS(status, 0, blk + 1);
 }
 
 LaunchEvents& launch_events() {
@@ -1112,7 +1285,7 @@ void potrf(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac, cons
       const int64_t t = j0 / NB;
       const int jb = (int)std::min<int64_t>(NB, n_fac - j0);
       double* dt = dinv + t * NB * NB;
-      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A + j0 * lda + j0, lda, jb, dt, status, (int)t);
+      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A + j0 * lda + j0, lda, jb, dt, status, (int)t);
       RPF_LAUNCH_CHECK();
       const int64_t r0 = j0 + jb;
       const int64_t rend = std::max<int64_t>(r0, std::min<int64_t>(env.rend[t], n_fac));

@@ -81,24 +81,43 @@ __global__ __launch_bounds__(64) void k_eta_chol(int m, const double* eta, int d
   __shared__ double emax_s, trace_s;
   __shared__ int bad_s;
   const int t = threadIdx.x;
-  for (int c = 0; c < m; ++c) {
-    double acc = 0.0;
-    for (int i = t; i < ka; i += 64) {
-      const double b = B[(int64_t)c * ka + i];
-      acc += b * b;
+  {
+    // squared column norms of B: every column's loads of a 64-row chunk are issued together
+    double part[MM];
+#pragma unroll
+    for (int c = 0; c < MM; ++c) part[c] = 0.0;
+    for (int i0 = 0; i0 < ka; i0 += 64) {
+      const int i = i0 + t;
+#pragma unroll
+      for (int c = 0; c < MM; ++c) {
+        const double b = (c < m && i < ka) ? B[(int64_t)c * ka + i] : 0.0;
+        part[c] += b * b;
+      }
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (t == 0) epre[c] = acc + eta[c * m + c];
-  }
-  if (t == 0) {
-    double me = 0.0, tr = 0.0;
-    for (int c = 0; c < m; ++c) {
-      me = fmax(me, epre[c]);
-      tr += fmax(eta[c * m + c], 0.0);
+    // lane t holds eta_tt; every reduction below is a butterfly across the wave (no serial loops
+    // of dependent loads on one lane)
+    const double dg = t < m ? eta[t * m + t] : 0.0;
+    double mine = 0.0;
+#pragma unroll
+    for (int c = 0; c < MM; ++c) {
+      if (c < m) {
+        double acc = part[c];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        acc += __shfl(dg, c, 64);
+        if (t == c) mine = acc;
+      }
     }
-    emax_s = me;
-    trace_s = tr;
-    bad_s = 0;
+    if (t < m) epre[t] = mine;
+    double me = mine, tr = fmax(dg, 0.0);
+    for (int off = 32; off > 0; off >>= 1) {
+      me = fmax(me, __shfl_xor(me, off, 64));
+      tr += __shfl_xor(tr, off, 64);
+    }
+    if (t == 0) {
+      emax_s = me;
+      trace_s = tr;
+      bad_s = 0;
+    }
   }
   __syncthreads();
   if (diag_only) {
@@ -360,7 +379,7 @@ struct Solver {
   int64_t ldW = 0;
   int max_blocks = 0;
   // small matrices
-  DevBuf<double> eta, V, w, T, alpha, gam, Bt, Cb, Mo, nrm, ws, estate, sqpart, gpart;
+  DevBuf<double> eta, V, w, T, alpha, gam, Bt, Cb, Mo, nrm, ws, estate, sqpart, gpart, alpha_prev;
   DevBuf<int> drops;
   std::vector<double> r0n;  // ||r0_c||^2 of the FP64 residual
   int iterations = 0, rank_drops = 0;
@@ -481,9 +500,13 @@ struct Solver {
     init_lag();
     const double tau = eta_drop(prec);
     int pending = -1, nchk = 0;
-    // block CG with one permutation: the residual update also leaves the next step's P^T R in Cb
+    // block CG with one permutation: the residual update also leaves the next step's P^T R in Cb,
+    // and the solution update of a step is deferred into the next step's orthogonalisation pass,
+    // which reads the same direction block (flushed when the loop ends)
     const bool upd_gram = method != RPF_ORTHODIR && np == 1 && m <= 16 && nr <= 16 && 256 % nr == 0;
-    bool have_gram = false;
+    bool have_gram = false, lam_pending = false;
+    const double* lam_dir = nullptr;  // the direction block of the pending update
+    if (upd_gram) alpha_prev.ensure((size_t)m * nr);
     for (int it = 0; it < max_it; ++it) {
       // ORTHODIR: orthogonalise against every stored block (restart when the store is full);
       // block CG / classical: against the previous block only, two alternating slots
@@ -532,8 +555,17 @@ struct Solver {
         hipLaunchKernelGGL(k_tblocks, dim3(nb), dim3(256), 0, s, nb, m, m, Tall.p + (int64_t)first * m * m, 0, Bt.p,
                            Mo.p);
         RPF_LAUNCH_CHECK();
-        if (fused) rows_gemm_from(s, N, ka, m, -1.0, Zall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Rs.p, nr, Zs, ldW);
-        else rows_gemm(s, N, ka, m, -1.0, Zall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Zs, ldW);
+        if (fused && lam_pending) {
+          // Z_j = R - Z_{j-1} Mo and lambda += Z_{j-1} alpha_{j-1} in one pass over Z_{j-1}
+          RPF_CHECK(lam_dir == Zall.p + (int64_t)first * m, RPF_EINVAL, "block step: deferred update source");
+          RPF_CHECK(rows_orth_lam(s, N, ka, m, nr, lam_dir, ldW, Mo.p, Rs.p, nr, Zs, ldW, alpha_prev.p, dlam.p, nr),
+                    RPF_EINVAL, "block step: orthogonalisation shape");
+          lam_pending = false;
+        } else if (fused) {
+          rows_gemm_from(s, N, ka, m, -1.0, Zall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Rs.p, nr, Zs, ldW);
+        } else {
+          rows_gemm(s, N, ka, m, -1.0, Zall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Zs, ldW);
+        }
       }
       // P = Q^T F Z
       apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, true, s);
@@ -575,7 +607,10 @@ struct Solver {
       if (upd_gram) {
         gpart.ensure((size_t)(cdiv(N, 256) + 256) * m * nr);
         sqpart.ensure((size_t)(cdiv(N, 256) + 256) * nr);
-        rows_gemm(s, N, m, nr, 1.0, Zs, ldW, alpha.p, 1.0, dlam.p, nr, 0);
+        // lambda += Z_j alpha_j is deferred to the next step (or the flush below)
+        RPF_HIP(hipMemcpyAsync(alpha_prev.p, alpha.p, sizeof(double) * m * nr, hipMemcpyDeviceToDevice, s));
+        lam_pending = true;
+        lam_dir = Zs;
         have_gram = rows_update_gram(s, N, m, nr, alpha.p, Ps, ldW, -1.0, 1.0, Rs.p, nr, sqpart.p,
                                      check ? nrm2[slot_n].p : nullptr, nr + 1, gpart.p, Cb.p);
         RPF_CHECK(have_gram, RPF_EINVAL, "block step: residual update shape");
@@ -599,6 +634,10 @@ struct Solver {
         pending = slot_n;
         ++nchk;
       }
+    }
+    if (lam_pending) {
+      rows_gemm(s, N, m, nr, 1.0, lam_dir, ldW, alpha_prev.p, 1.0, dlam.p, nr, 0);
+      lam_pending = false;
     }
     if (conv == GOING && pending >= 0) conv = read_norms(pending, target);
     int hd = 0;
