@@ -124,6 +124,123 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
       }
 }
 
+// FP64 C = alpha A B (+ beta C), column-major; A: M x K with lda, B: K x N with ldb, its k-contiguous
+// columns padded with zeros to a multiple of 32; M and lda even (16-byte loads of A).  The
+// flexibility product's large-problem kernel: 128 x 128 tiles, eight waves of 64 x 32 (two per
+// SIMD, so one wave's LDS waits overlap the other's MFMAs), 32-k stages loaded straight into two
+// LDS buffers, the next stage issued right after the barrier that opens the current one (a whole
+// stage of MFMA work covers the load latency).  Same per-accumulator summation order as k_dgemm,
+// so the same bits.  A stage: A as 32 k-rows of 128 doubles (+16 pad: the two k-rows a
+// half-wave reads sit on opposite bank halves); B as 128 n-rows of 32 doubles with 16-byte chunk
+// kc stored at kc ^ (n % 16) (conflict-free fragment reads).  Rows past M or N are clamped to the
+// last row (their results are never stored); k-rows of A past K are clamped too and meet the
+// zero padding of B.
+template <bool BETA>
+__global__ __launch_bounds__(512) void k_dgemm_big(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                   int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
+                                                   double* __restrict__ C, int64_t ldc) {
+  constexpr int BK = 32, RA = 128 + 16, SA = BK * RA, SB = 128 * BK;
+  __shared__ __attribute__((aligned(1024))) double lA0[SA];
+  __shared__ __attribute__((aligned(1024))) double lA1[SA];
+  __shared__ __attribute__((aligned(1024))) double lB0[SB];
+  __shared__ __attribute__((aligned(1024))) double lB1[SB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;  // wave tile 64 (m) x 32 (n)
+  int tx, ty;
+  xcd_tile(gridDim.x, gridDim.y, tx, ty);
+  const int m0 = tx * 128, n0 = ty * 128;
+  const int nst = (K + BK - 1) / BK;
+  // loads of a stage: wave w takes A k-rows 4w .. 4w + 3 (lane l: doubles m0 + 2l, 2l + 1) and
+  // B blocks 4w .. 4w + 3 of four n-rows (lane l: n-row l / 16, chunk (l % 16) ^ (n % 16))
+  const int am = min(m0 + 2 * lane, M - 2);
+  const double* asrc = A + am;
+  const double* bsrc[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int nl = 4 * (4 * wave + e) + (lane >> 4);
+    const int n = min(n0 + nl, N - 1);
+    const int kc = (lane & 15) ^ (nl & 15);
+    bsrc[e] = B + (int64_t)n * ldb + 2 * kc;
+  }
+  auto issue = [&](double* la, double* lb, int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kr = 4 * wave + e;
+      const int k = min(k0 + kr, K - 1);  // k past K: finite A values times zero B padding
+      __builtin_amdgcn_global_load_lds((const void*)(asrc + (int64_t)k * lda), (void*)(la + kr * RA), 16, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      __builtin_amdgcn_global_load_lds((const void*)(bsrc[e] + k0), (void*)(lb + (4 * wave + e) * 128), 16, 0, 0);
+  };
+  v4d acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int fl = lane & 15, fk = lane >> 4;
+  auto stage = [&](const double* la, const double* lb, double* na, double* nb, int s) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (s + 1 < nst) issue(na, nb, (s + 1) * BK);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int k = kk + fk;
+      double af[4], bf[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = la[k * RA + wm * 64 + i * 16 + fl];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = wn * 32 + j * 16 + fl;
+        bf[j] = lb[n * BK + (((k >> 1) ^ (n & 15)) << 1) + (k & 1)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
+    }
+  };
+  if (nst > 0) issue(lA0, lB0, 0);
+  int s = 0;
+  for (; s + 1 < nst; s += 2) {
+    stage(lA0, lB0, lA1, lB1, s);
+    stage(lA1, lB1, lA0, lB0, s + 1);
+  }
+  if (s < nst) stage(lA0, lB0, lA1, lB1, s);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + fl;
+        const int n = n0 + wn * 32 + j * 16 + fk + 4 * r;
+        if (m < M && n < N) {
+          double* c = C + (int64_t)n * ldc + m;
+          const double v = alpha * acc[i][j][r];
+          *c = BETA ? v + beta * *c : v;
+        }
+      }
+}
+
+
+bool dgemm_flex(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
+  if (M < 2 || N < 1 || K < 1 || (M & 1) || (lda & 1) || (ldb % 32) || K > ldb || M > INT32_MAX || N > INT32_MAX ||
+      ((uintptr_t)A & 15) || ((uintptr_t)B & 15))
+    return false;
+  const dim3 grid((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128));
+  if (beta == 0.0)
+    RPF_TIMED_LAUNCH((k_dgemm_big<false>), grid, dim3(512), 0, s, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
+                     C, ldc);
+  else
+    RPF_TIMED_LAUNCH((k_dgemm_big<true>), grid, dim3(512), 0, s, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
+                     C, ldc);
+  RPF_LAUNCH_CHECK();
+  return true;
+}
+
 // Sum of the split-K partials: one wavefront per output, lanes stride over the
 // splits (fixed order, so the result is deterministic).
 // Few slabs, many outputs: one thread per output, slabs summed in order (coalesced over outputs).

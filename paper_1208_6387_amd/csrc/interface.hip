@@ -663,6 +663,15 @@ void check_patterns(rpf_problem pb, const rpf_pattern* pats, int prec) {
   }
 }
 
+// zero the rows [nb, ld) of every column of a W-format block (the padding the large-problem FP64
+// product reads as part of its last k stage)
+__global__ void k_zero_rows(double* X, int64_t ld, int nb, int64_t cols) {
+  const int64_t pad = ld - nb;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pad * cols) return;
+  X[(i / pad) * ld + nb + (i % pad)] = 0.0;
+}
+
 void gather_pattern(rpf_problem pb, int p, int nbn, const double* lam, int64_t ldl, int m, double* X,
                     int64_t ldx, hipStream_t s) {
   const int nq = (int)pb->occ_of_pat[p].size();
@@ -716,9 +725,12 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     }
     return;
   }
-  // W-format workspace: one slab per pattern (times the K splits for the results)
-  std::vector<int64_t> off(pb->n_pat + 1, 0), yoff(pb->n_pat + 1, 0);
+  // W-format workspace: one slab per pattern (times the K splits for the results).  When the
+  // 128 x 128 tiles alone fill the chip, the product runs on the large-problem kernel, whose W
+  // blocks have their leading dimension padded to a multiple of 32 with zero rows.
+  std::vector<int64_t> off(pb->n_pat + 1, 0), yoff(pb->n_pat + 1, 0), ldw(pb->n_pat);
   std::vector<int> nsp(pb->n_pat, 1);
+  std::vector<char> big(pb->n_pat, 0);
   for (int p = 0; p < pb->n_pat; ++p) {
     const int nb = pats[p]->n_b;
     const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
@@ -727,7 +739,9 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, nb / 256));
     sp = std::min(sp, 8);
     nsp[p] = splits_used(nb, sp);
-    off[p + 1] = off[p] + (int64_t)nb * cols;
+    big[p] = nsp[p] == 1 && nb % 2 == 0 && cdiv(nb, 128) * cdiv(cols, (int64_t)128) >= 256;
+    ldw[p] = big[p] ? cdiv(nb, 32) * 32 : nb;
+    off[p + 1] = off[p] + ldw[p] * cols;
     yoff[p + 1] = yoff[p] + (int64_t)nb * cols * sp;
   }
   pb->xloc.ensure(std::max<int64_t>(off[pb->n_pat], 1));
@@ -738,10 +752,19 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
     double* xp = pb->xloc.p + off[p];
     double* yp = pb->yloc.p + yoff[p];
-    gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, nb, s);
+    const int64_t lw = ldw[p];
+    if (lw > nb) {
+      const int64_t npad = (lw - nb) * cols;
+      hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, xp, lw, nb, cols);
+      RPF_LAUNCH_CHECK();
+    }
+    gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, lw, s);
     void* tok = trace_begin(s, RPF_FP64);
-    if (nsp[p] > 1) dgemm_partials(s, nb, cols, nb, pats[p]->Splus.p, nb, xp, nb, yp, (int)((yoff[p + 1] - yoff[p]) / ((int64_t)nb * cols)));
-    else dgemm(s, false, false, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, nb, 0.0, yp, nb);
+    if (nsp[p] > 1) {
+      dgemm_partials(s, nb, cols, nb, pats[p]->Splus.p, nb, xp, lw, yp, (int)((yoff[p + 1] - yoff[p]) / ((int64_t)nb * cols)));
+    } else if (!(big[p] && dgemm_flex(s, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, lw, 0.0, yp, nb))) {
+      dgemm(s, false, false, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, lw, 0.0, yp, nb);
+    }
     trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
     yl.base[p] = yp;
     yl.ld[p] = nb;

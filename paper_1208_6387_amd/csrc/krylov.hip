@@ -244,6 +244,14 @@ __global__ void k_sub_slabs(int64_t count, const double* a, const double* b, int
   out[i] = v;
 }
 
+// dst[c ldd + r] = src[c lds + r] for r < rows, 0 for rows <= r < ldd (column-major, cols columns)
+__global__ void k_copy_pad(int rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ldd * cols) return;
+  const int64_t r = i % ldd, c = i / ldd;
+  dst[i] = r < rows ? src[c * lds + r] : 0.0;
+}
+
 // strided rows: y[l*ldy + j] = a x[l*ldx + j] + b y[l*ldy + j]
 __global__ void k_axpby_rows(int64_t rows, int cols, double a, const double* x, int64_t ldx, double b, double* y,
                              int64_t ldy) {
@@ -705,7 +713,17 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
         RPF_LAUNCH_CHECK();
       }
       double* yp = Yg.p + off[p];
-      dgemm(s, false, false, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, G[p].p, P->n_b, 0.0, yp, P->n_b);
+      // the large-problem FP64 kernel reads its right operand with a zero-padded leading dimension
+      const int64_t lw = cdiv(P->n_b, 32) * 32;
+      bool done = false;
+      if (P->n_b % 2 == 0 && cdiv(P->n_b, 128) * cdiv(cols, (int64_t)128) >= 256) {
+        pb->xloc.ensure(lw * cols);
+        hipLaunchKernelGGL(k_copy_pad, dim3(nblocks(lw * cols)), dim3(256), 0, s, P->n_b, cols, G[p].p,
+                           (int64_t)P->n_b, pb->xloc.p, lw);
+        RPF_LAUNCH_CHECK();
+        done = dgemm_flex(s, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, pb->xloc.p, lw, 0.0, yp, P->n_b);
+      }
+      if (!done) dgemm(s, false, false, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, G[p].p, P->n_b, 0.0, yp, P->n_b);
       yl.base[p] = yp;
       yl.ld[p] = P->n_b;
     }
