@@ -38,9 +38,10 @@ LaunchEvents& launch_events();
 // by row tile inside a group, and XCD x takes the x-th contiguous eighth of that list; the
 // workgroups that run together on one XCD then share their row panel of A in its L2 (and the
 // group's column panels of B while they stay resident).  Identity when the counts do not divide.
+template <int CG = 8>
 __device__ inline void xcd_tile(int nx, int ny, int& tx, int& ty) {
   constexpr int NXCD = 8;
-  const int cg = ny < 8 ? ny : 8;
+  const int cg = ny < CG ? ny : CG;
   const int T = nx * ny;
   if (T % NXCD != 0 || ny % cg != 0) {
     tx = blockIdx.x;

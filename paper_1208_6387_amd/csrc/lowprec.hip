@@ -431,7 +431,7 @@ __global__ __launch_bounds__(512) void k_gemm_bf16_big(int M, int N, int K, cons
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   int tx, ty;
-  xcd_tile(gridDim.x, gridDim.y, tx, ty);
+  xcd_tile<4>(gridDim.x, gridDim.y, tx, ty);  // column groups of 4: measured ~1.5 % faster than 8
   const int m0 = tx * 256, n0 = ty * 256;
   const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
   C += (int64_t)blockIdx.z * slab;
