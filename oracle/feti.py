@@ -15,6 +15,10 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   analytic rigid modes, S S+ S = S);
 * assembly operators, F, G, Q, lambda_0: pinned (continuity of rigid motions,
   antisymmetry, dense F, projector identities);
+* lumped and Dirichlet preconditioners: pinned (exact inverse on a mirror-image pair,
+  lumped = Dirichlet without interior dofs, multiplicity scaling away from cross-points,
+  spectrum of the preconditioned operator bounded below by 1, K_bb - S >= 0 ordering,
+  unchanged solutions);
 * classical and block solvers, recovery: pinned against a brute-force global
   solve assembled from the global node numbering, and the closed-form 1-D
   solution of the heat row;
@@ -107,12 +111,13 @@ def pseudo_inverse(S: np.ndarray, Z: np.ndarray) -> np.ndarray:
 # =========================================================================== interface level
 
 class FetiOracle:
-    """The dual interface problem (eq. 3) of a Problem, with identity preconditioner.
+    """The dual interface problem (eq. 3) of a Problem.
 
     F = sum_s A^(s) S+ A^(s)T, G = [.. A^(s) t N^(s) ..], d = sum_s A^(s) t K+ f^(s),
-    e^T = [.. f^(s)T N^(s) ..] (section 2).  With the preconditioner taken as the
-    identity (READING), Q = I - G (G^T G)^{-1} G^T and lambda_0 = G (G^T G)^{-1} e
-    (section 2, projector and initialisation).  For elasticity A^(s) carries the
+    e^T = [.. f^(s)T N^(s) ..] (section 2).  With the identity in place of F~^{-1} in the
+    projector (READING), Q = I - G (G^T G)^{-1} G^T and lambda_0 = G (G^T G)^{-1} e
+    (section 2, projector and initialisation).  The solvers take the identity, lumped or
+    Dirichlet preconditioner (section 2) for z = Q F~^{-1} r.  For elasticity A^(s) carries the
     occurrence rotation O^(s) (section 5.2): A^(s)T takes global-frame interface
     values to the pattern frame.
     """
@@ -141,6 +146,7 @@ class FetiOracle:
         self.G = sp.hstack(cols).tocsr() if cols else sp.csr_matrix((self.n_lambda, 0))
         self.GtG = (self.G.T @ self.G).toarray()
         self._GtG_cho = None
+        self._AAt = self._AAt_lu = None
 
     # -- signed Boolean assembly (eq. 2) ------------------------------------------------
     def _assembly(self, s: int) -> sp.csr_matrix:
@@ -199,6 +205,63 @@ class FetiOracle:
             return np.array(X, float)
         return X - self.G @ self.coarse_solve(self.G.T @ X)
 
+    # -- preconditioners (section 2) -------------------------------------------------------
+    def assembly_gram(self) -> sp.csc_matrix:
+        """A A^T = sum_s A^(s) A^(s)T, the Gram matrix of the signed Boolean assembly (eq. 2)."""
+        if self._AAt is None:
+            M = sp.csr_matrix((self.n_lambda, self.n_lambda))
+            for As in self.A:
+                M = M + As @ As.T
+            self._AAt = M.tocsc()
+            self._AAt_lu = spla.splu(self._AAt)
+        return self._AAt
+
+    def scale(self, X: np.ndarray) -> np.ndarray:
+        """The scaling of the preconditioners (section 2), applied to a lambda block: (A A^T)^{-1} X.
+
+        READING: the paper takes diagonal scalings beta^(s) whose sum over the subdomains is the
+        identity.  Its condition, sum_s beta^(s) A^(s) A^(s)T = I wherever no two multipliers
+        share a local dof, is taken in the form that also holds at cross-points joined by a
+        chain of non-redundant multipliers: beta^(s) A^(s) -> (A A^T)^{-1} A^(s), the same for
+        every s.  Away from cross-points A A^T is diagonal (2 on an interface multiplier, 1 on a
+        Dirichlet one), which gives the multiplicity scaling 1/2 and 1.  At a cross-point the
+        chain links share dofs and A A^T couples them; a diagonal 1/2 there makes the
+        preconditioned operator far worse conditioned than no preconditioner at all.
+        """
+        self.assembly_gram()
+        X = np.asarray(X, float)
+        return self._AAt_lu.solve(np.ascontiguousarray(X))
+
+    def local_precond_matrix(self, p: int, kind: str) -> np.ndarray:
+        """The pattern matrix of a preconditioner: S (Dirichlet) or K_bb (lumped), section 2."""
+        if kind == "dirichlet":
+            return self.pats[p].S
+        if kind == "lumped":
+            return self.pats[p].Kbb
+        raise ValueError(kind)
+
+    def precondition(self, X: np.ndarray, kind: str | None) -> np.ndarray:
+        """F~^{-1} X = sum_s beta A^(s) M A^(s)T beta X with beta = (A A^T)^{-1} (see scale),
+        M = S of the pattern (Dirichlet) or its K_bb (lumped), or X itself for the identity
+        preconditioner (kind None); section 2.
+
+        READING: M is the pattern's matrix over the whole pattern boundary (the union of the
+        dofs carrying a multiplier in any occurrence), shared by every occurrence; A^(s)T gives
+        zero on the boundary dofs of s that carry no multiplier, so there they act as fixed.
+        """
+        X = np.asarray(X, float)
+        if kind is None:
+            return X.copy()
+        vec = X.ndim == 1
+        X2 = X[:, None] if vec else X
+        T = self.scale(X2)
+        Y = np.zeros_like(X2)
+        for s in range(self.pb.n_occ):
+            Mloc = self.local_precond_matrix(self.pb.occ_pattern[s], kind)
+            Y += self.A[s] @ (Mloc @ (self.A[s].T @ T))
+        Y = self.scale(Y)
+        return Y[:, 0] if vec else Y
+
     # -- right-hand sides ---------------------------------------------------------------
     def loads(self, f_local=None):
         """Condensed loads g^(s), d = sum A S+ g, e = [Z^T g^(s)] (eq. 3 right-hand side)."""
@@ -256,10 +319,13 @@ class FetiOracle:
         return out
 
     # -- solvers (Table 1) ----------------------------------------------------------------
-    def solve_classical(self, d, e, tol, max_it=2000, lam00=None, record=None):
+    def solve_classical(self, d, e, tol, max_it=2000, lam00=None, record=None, precond=None):
         """Projected CG, Table 1 left column, one load case at a time (FETI-mrhs, section 4.4).
 
         record: optional list receiving lambda after every iteration (first load case).
+        precond: None (identity), "lumped" or "dirichlet": z = Q F~^{-1} r (Table 1, lines 4 and
+        5.5).  READING: the projector keeps the identity in place of F~^{-1} whatever the
+        preconditioner (the paper allows any of them there), so Q and lambda_0 do not change.
         """
         nr = d.shape[1]
         lam = self.lambda0(e, lam00)
@@ -269,7 +335,7 @@ class FetiOracle:
             l = lam[:, c].copy()
             r = self.Q(d[:, c] - self.F(l))
             r0 = np.linalg.norm(r)
-            z = self.Q(r)
+            z = self.Q(self.precondition(r, precond))
             w = z.copy()
             h = [1.0]
             j = 0
@@ -279,7 +345,7 @@ class FetiOracle:
                 alpha = (w @ r) / wp
                 l += alpha * w
                 r -= alpha * p
-                z = self.Q(r)
+                z = self.Q(self.precondition(r, precond))
                 beta = -(p @ z) / wp
                 w = z + beta * w
                 j += 1
@@ -291,8 +357,10 @@ class FetiOracle:
             hist.append(h)
         return lam, dict(iterations=its, history=hist)
 
-    def solve_block(self, d, e, tol, max_it=2000, lam00=None, full_reorth=True, record=None):
+    def solve_block(self, d, e, tol, max_it=2000, lam00=None, full_reorth=True, record=None, precond=None):
         """Multivector projected CG, Table 1 right column.
+
+        precond: as in solve_classical; the permutations act on z = Q F~^{-1} r.
 
         full_reorth=True: every new block is F-orthogonalised against all stored blocks and
         F-normalised, W <- W eta^{-1/2}, P <- P eta^{-1/2} with eta = P^T W (section 4.3);
@@ -310,7 +378,7 @@ class FetiOracle:
         r = self.Q(d - self.F(lam))
         r0 = np.linalg.norm(r, axis=0)
         r0[r0 == 0] = 1.0
-        z = self.Q(r)
+        z = self.Q(self.precondition(r, precond))
         Zb = self.Q(self.permute(z))          # READING: re-project permuted directions
         Ws, Ps = [], []
         W_prev = P_prev = None
@@ -358,7 +426,7 @@ class FetiOracle:
             hist.append(float(np.max(np.linalg.norm(r, axis=0) / r0)))
             if record is not None:
                 record.append(lam.copy())
-            z = self.Q(r)
+            z = self.Q(self.precondition(r, precond))
             Zb = self.Q(self.permute(z))
         return lam, dict(iterations=j, history=hist, rank_drops=drops)
 
@@ -386,13 +454,13 @@ class FetiOracle:
             u.append(us)
         return u
 
-    def solve(self, method="block", tol=None, max_it=2000, full_reorth=True):
+    def solve(self, method="block", tol=None, max_it=2000, full_reorth=True, precond=None):
         tol = self.pb.tol if tol is None else tol
         g, d, e = self.loads()
         if method == "classical":
-            lam, st = self.solve_classical(d, e, tol, max_it)
+            lam, st = self.solve_classical(d, e, tol, max_it, precond=precond)
         else:
-            lam, st = self.solve_block(d, e, tol, max_it, full_reorth=full_reorth)
+            lam, st = self.solve_block(d, e, tol, max_it, full_reorth=full_reorth, precond=precond)
         u = self.recover(lam, d, g)
         return lam, u, st
 

@@ -119,3 +119,47 @@ def test_permutation_rotated_the_wrong_way_is_caught():
     Fx_bad = o.permute(o.F(x))
     p.occ_rot = rot
     assert np.abs(o.F(z_bad) - Fx_bad).max() > 1e-2 * np.abs(Fx_bad).max()
+
+
+def _min_precond_eig(o, kind):
+    I = np.eye(o.n_lambda)
+    F, Q = o.F(I), o.Q(I)
+    w = np.linalg.eigvals(Q @ o.precondition(I, kind) @ Q @ F).real
+    return np.sort(w[np.abs(w) > 1e-9 * np.abs(w).max()])[0]
+
+
+def test_diagonal_half_scaling_at_cross_points_is_caught(prob, monkeypatch):
+    """The diagonal 1/2 (1 on Dirichlet multipliers) applied at cross-points as well breaks the
+    lower spectral bound of the preconditioned operator."""
+    o = O.FetiOracle(prob)
+    assert _min_precond_eig(o, "dirichlet") > 1.0 - 1e-8
+    ends = np.repeat(1.0 / (1 + (prob.mult_occ[:, 1] >= 0)), 3)
+    monkeypatch.setattr(o, "scale", lambda X: ends[:, None] * np.asarray(X) if np.ndim(X) == 2 else ends * X)
+    assert _min_precond_eig(o, "dirichlet") < 0.5
+
+
+def test_dirichlet_with_flexibility_instead_of_schur_is_caught(monkeypatch):
+    p = W.mirror_row_heat(2, (4, 4))
+    o = O.FetiOracle(p)
+    monkeypatch.setattr(o, "local_precond_matrix", lambda pat, kind: o.pats[pat].Splus)
+    I = np.eye(p.n_lambda)
+    assert np.abs(o.precondition(o.F(I), "dirichlet") - I).max() > 0.1
+
+
+def test_lumped_with_schur_instead_of_kbb_is_caught(monkeypatch):
+    """K_bb replaced by S makes the lumped preconditioner equal to the Dirichlet one: the pin on
+    their nonzero positive semi-definite difference fails."""
+    p = W.ring_elast(4, (1, 2, 1), n_perm=1)
+    o = O.FetiOracle(p)
+    monkeypatch.setattr(o, "local_precond_matrix", lambda pat, kind: o.pats[pat].S)
+    I = np.eye(p.n_lambda)
+    diff = o.precondition(I, "lumped") - o.precondition(I, "dirichlet")
+    assert np.abs(diff).max() < 1e-12
+
+
+def test_unscaled_preconditioner_is_caught(monkeypatch):
+    p = W.mirror_row_heat(2, (4, 4))
+    o = O.FetiOracle(p)
+    monkeypatch.setattr(o, "scale", lambda X: np.asarray(X, float))
+    I = np.eye(p.n_lambda)
+    assert np.abs(o.precondition(o.F(I), "dirichlet") - I).max() > 0.5

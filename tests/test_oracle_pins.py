@@ -393,3 +393,100 @@ def test_block_not_slower_than_classical():
     _, _, sc = o.solve("classical")
     _, _, sb = o.solve("block")
     assert sb["iterations"] <= max(sc["iterations"])
+
+
+# ----------------------------------------------------------------------------- preconditioners (section 2)
+
+def test_precond_mirror_pair_is_exact_inverse():
+    """Two mirror-image, non-floating occurrences meeting on one edge: F = 2 S^{-1} on that edge
+    and the Dirichlet preconditioner with the scaling 1/2 is (1/4)(S + S) = S / 2, its exact
+    inverse; preconditioned CG then ends in one iteration.  The lumped one is not exact."""
+    p = W.mirror_row_heat(2, (4, 4))
+    o = O.FetiOracle(p)
+    assert o.pats[0].k == 0 and len(p.patterns[0].bnodes) == 5
+    I = np.eye(p.n_lambda)
+    F = o.F(I)
+    assert np.abs(o.precondition(F, "dirichlet") - I).max() < 1e-13
+    assert np.abs(o.precondition(F, "lumped") - I).max() > 0.1
+    g, d, e = o.loads()
+    lam, st = o.solve_classical(d, e, 1e-12, precond="dirichlet")
+    assert st["iterations"] == [1]
+    ub, _, _, _ = O.global_solve(p)
+    u = o.recover(lam, d, g)
+    assert max(np.abs(a - b).max() for a, b in zip(u, ub)) < 1e-12 * max(np.abs(b).max() for b in ub)
+
+
+def test_precond_lumped_equals_dirichlet_without_interior():
+    """With no interior dof, S = K_bb and the lumped and Dirichlet preconditioners coincide."""
+    p = W.mirror_row_heat(3, (1, 3))
+    o = O.FetiOracle(p)
+    assert len(o.pats[0].i) == 0
+    X = np.random.default_rng(0).standard_normal((p.n_lambda, 3))
+    a, b = o.precondition(X, "lumped"), o.precondition(X, "dirichlet")
+    assert np.abs(a - b).max() < 1e-14 * np.abs(a).max()
+
+
+def test_precond_scaling_is_multiplicity_away_from_cross_points():
+    """The scaling is 1/2 on an interface multiplier and 1 on a Dirichlet one wherever no other
+    multiplier shares an endpoint dof (the paper's diagonal beta with sum_s beta^(s) = I)."""
+    p = W.small_elast((2, 2, 2), (2, 2, 2), n_rhs=1)
+    o = O.FetiOracle(p)
+    keys = {}
+    for e in range(2):
+        for i, (s, n) in enumerate(zip(p.mult_occ[:, e], p.mult_node[:, e])):
+            if s >= 0:
+                keys.setdefault((int(s), int(n)), []).append(i)
+    shared = np.zeros(p.n_mult_nodes, bool)
+    for lst in keys.values():
+        if len(lst) > 1:
+            shared[lst] = True
+    lone = np.nonzero(~shared)[0]
+    assert len(lone) > 0 and shared.any()
+    X = np.eye(p.n_lambda)[:, (lone[:, None] * 3 + np.arange(3)).ravel()]
+    Y = o.scale(X)
+    ends = 1 + (p.mult_occ[lone, 1] >= 0)
+    expect = np.repeat(1.0 / ends, 3)
+    assert np.abs(Y - X * expect[None, :]).max() < 1e-14
+    assert ((ends == 1).any() and (ends == 2).any())
+
+
+@pytest.mark.parametrize("case", ["elast222", "ring4"])
+def test_precond_spectrum_and_order(case):
+    """Spectral facts of the preconditioned operator Q F~^{-1} Q F on range Q: its smallest
+    eigenvalue is 1 or more for a consistent scaling (the dual Dirichlet bound), the Dirichlet
+    form is the better conditioned one, and K_bb - S = K_bi K_ii^{-1} K_ib >= 0 makes the lumped
+    preconditioner dominate the Dirichlet one (a nonzero positive semi-definite difference)."""
+    p = W.small_elast((3, 3, 3), (2, 2, 2), n_rhs=1) if case == "elast222" else W.ring_elast(4, (1, 2, 1), n_perm=1)
+    o = O.FetiOracle(p)
+    I = np.eye(p.n_lambda)
+    F, Q = o.F(I), o.Q(I)
+    conds = {}
+    Ms = {}
+    for kind in (None, "lumped", "dirichlet"):
+        Ms[kind] = o.precondition(I, kind)
+        w = np.linalg.eigvals(Q @ Ms[kind] @ Q @ F).real
+        w = np.sort(w[np.abs(w) > 1e-9 * np.abs(w).max()])
+        conds[kind] = w[-1] / w[0]
+        if kind is not None:
+            assert w[0] > 1.0 - 1e-8, (kind, w[0])
+            assert np.abs(Ms[kind] - Ms[kind].T).max() < 1e-13 * np.abs(Ms[kind]).max()
+    assert conds["dirichlet"] < conds["lumped"] < conds[None] / 10
+    diff = Ms["lumped"] - Ms["dirichlet"]
+    ev = np.linalg.eigvalsh(0.5 * (diff + diff.T))
+    assert ev[0] > -1e-12 * ev[-1] and ev[-1] > 1e-3 * np.abs(Ms["dirichlet"]).max()
+
+
+def test_precond_solutions_match_brute_force():
+    """Preconditioning changes the path, not the solution (eq. 1 solved by the assembled system)."""
+    p = W.small_elast((3, 3, 3), (2, 2, 2), n_rhs=2, n_perm=1)
+    o = O.FetiOracle(p)
+    ub, _, _, _ = O.global_solve(p)
+    scale = max(np.abs(x).max() for x in ub)
+    _, _, s_id = o.solve("block", tol=1e-10)
+    for kind in ("lumped", "dirichlet"):
+        for method in ("classical", "block"):
+            lam, u, st = o.solve(method, tol=1e-10, precond=kind)
+            err = max(np.abs(ub[s] - u[s]).max() for s in range(p.n_occ)) / scale
+            assert err < 1e-9, (kind, method, err)
+            its = max(st["iterations"]) if method == "classical" else st["iterations"]
+            assert its * 3 < s_id["iterations"], (kind, method, its)

@@ -314,6 +314,34 @@ def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed
                    swap_rule=swap)
 
 
+def mirror_row_heat(n_occ=2, pat_shape=(4, 4), reaction=0.1, n_rhs=1, seed=2):
+    """A row of heat patterns with a reaction term (K + reaction * I: no floating occurrence),
+    every other occurrence the mirror image of the first about its shared edge, so that
+    neighbours meet on the same local edge: the right edges of 0 and 1, the left edges of 1 and
+    2, and so on.  With two occurrences the pattern boundary is one edge; with a pattern one
+    element wide and three or more occurrences every node is a boundary node.  No Dirichlet
+    condition (the reaction term makes every occurrence non-singular).
+    """
+    nx, ny = pat_shape
+    mesh = M.GridMesh(pat_shape, (1.0, 1.0))
+    K = (M.assemble(mesh, M.quad_laplace(*mesh.h), 1) + reaction * sp.identity(mesh.n_nodes)).tocsr()
+    K.sort_indices()
+    pats = [Pattern("mirror-pattern", 1, mesh.coords, K, 0)]
+    W = n_occ * nx + 1
+    occ_gnode = []
+    for s in range(n_occ):
+        ix = mesh.lattice[:, 0]
+        gx = s * nx + (nx - ix if s % 2 else ix)
+        occ_gnode.append(gx + W * mesh.lattice[:, 1])
+    n_g = W * (ny + 1)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f_local = [rng.standard_normal((mesh.n_nodes, n_rhs)) for _ in range(n_occ)]
+    rot = np.repeat(np.eye(3)[None], n_occ, axis=0)
+    meta = dict(kind="heat", grid=(n_occ,), pat_shape=pat_shape, reaction=reaction)
+    return _finish(f"mirror-row{n_occ}", 1, pats, [0] * n_occ, rot, occ_gnode, n_g, np.zeros(0, np.int64),
+                   f_local, n_rhs, 1, 1e-10, meta)
+
+
 def rot_z(angle: float) -> np.ndarray:
     c, s = np.cos(angle), np.sin(angle)
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
