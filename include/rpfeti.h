@@ -160,6 +160,29 @@ void problem_free(rpf_problem pb);
 rpf_status feti_apply(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X, int64_t ldx,
                       double* Y, int64_t ldy, int32_t prec, uint32_t flags, void* stream);
 
+/* Preconditioners of the interface problem (section 2).  F~^{-1} =
+ * sum_s beta A^(s) M A^(s)T beta, with M the pattern's Schur complement S
+ * (Dirichlet) or its boundary block K_bb (lumped), over the whole pattern
+ * boundary and shared by every occurrence of the pattern.  The scaling beta
+ * is (A A^T)^{-1}, with A = [.. A^(s) ..] the signed Boolean assembly.  Where
+ * no two multipliers share an endpoint it is the diagonal multiplicity scaling
+ * (1/2 on an interface multiplier, 1 on a single-endpoint one), whose sum over
+ * the subdomains is the identity.  Where multipliers chained at a cross-point
+ * share endpoints it couples them, and keeps sum_s beta A^(s) A^(s)T = I. */
+typedef enum { RPF_PRECOND_NONE = 0, RPF_PRECOND_LUMPED = 1, RPF_PRECOND_DIRICHLET = 2 } rpf_precond;
+
+/* Y = F~^{-1} X for an m-column interface block (section 2, preconditioners;
+ * Table 1 applies it as z = Q F~^{-1} r).  kind: an rpf_precond value
+ * (RPF_PRECOND_NONE copies X).  prec: the arithmetic of the Dirichlet
+ * product S W (as for feti_apply; the patterns must have been condensed with
+ * it); the lumped product with the sparse K_bb always runs in FP64.  With
+ * RPF_APPLY_PROJECT the coarse projector Q is applied to the result.  X, Y:
+ * device, N_lambda x m row-major (ldx, ldy >= m), must not overlap.  patterns
+ * may be NULL only for RPF_PRECOND_NONE without projection.  Asynchronous.
+ * Errors: RPF_EINVAL. */
+rpf_status feti_precond(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X, int64_t ldx,
+                        double* Y, int64_t ldy, int32_t kind, int32_t prec, uint32_t flags, void* stream);
+
 /* Permuted multivector (section 3.1): W[:, l*n_perm + k] = Pi_k z_l for the
  * nr columns of Z and the structure's n_perm permutations (the rows of
  * perm_node; a structure created without permutations has n_perm = 1 and
@@ -194,6 +217,9 @@ typedef struct {
   int32_t check_every; /* read the convergence flag every k iterations (0: 1) */
   int32_t max_blocks;  /* ORTHODIR: stored (W, P) blocks before a restart (0: as many as max_it and
                           half of the free device memory allow) */
+  int32_t precond;     /* rpf_precond: z = Q F~^{-1} r in every iteration (Table 1, lines 4 and 5.5);
+                          the Dirichlet product runs in the inner precision prec.  The projector
+                          keeps the identity in place of F~^{-1}. */
 } rpf_solve_opts;
 
 typedef struct {

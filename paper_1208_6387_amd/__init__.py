@@ -15,12 +15,13 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (APPLY_PROJECT, BF16, BF16X3, BLOCK_CG, CLASSICAL, FP32, FP64, ORTHODIR, RpfError, SolveStats,
-                   check, load)
+from ._lib import (APPLY_PROJECT, BF16, BF16X3, BLOCK_CG, CLASSICAL, FP32, FP64, ORTHODIR, PRECOND_DIRICHLET,
+                   PRECOND_LUMPED, PRECOND_NONE, RpfError, SolveStats, check, load)
 
 __all__ = ["Pattern", "Problem", "pattern_factor", "pattern_condense", "pattern_export", "problem_create",
-           "feti_apply", "feti_permute", "block_krylov_solve", "dgemm", "dposv", "dsyev_small", "load", "RpfError",
-           "FP64", "FP32", "BF16X3", "BF16", "CLASSICAL", "BLOCK_CG", "ORTHODIR", "APPLY_PROJECT"]
+           "feti_apply", "feti_precond", "feti_permute", "block_krylov_solve", "dgemm", "dposv", "dsyev_small",
+           "load", "RpfError", "FP64", "FP32", "BF16X3", "BF16", "CLASSICAL", "BLOCK_CG", "ORTHODIR",
+           "PRECOND_NONE", "PRECOND_LUMPED", "PRECOND_DIRICHLET", "APPLY_PROJECT"]
 
 
 def _stream(stream=None) -> C.c_void_p:
@@ -147,6 +148,20 @@ def feti_apply(pb: Problem, patterns, X: torch.Tensor, prec: int = FP64, project
     return Y
 
 
+def feti_precond(pb: Problem, patterns, X: torch.Tensor, kind: int, prec: int = FP64, project: bool = False,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Y = F~^{-1} X (or Q F~^{-1} X) for a row-major N_lambda x m device block; kind is PRECOND_NONE,
+    PRECOND_LUMPED or PRECOND_DIRICHLET."""
+    assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[0] == pb.n_lambda
+    assert X.stride(1) == 1
+    m = X.shape[1]
+    Y = out if out is not None else torch.empty_like(X)
+    hs = _handles(patterns) if patterns is not None else None
+    check(load().feti_precond(pb.handle, hs, m, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), int(kind), prec,
+                              APPLY_PROJECT if project else 0, _stream(stream)))
+    return Y
+
+
 def feti_permute(pb: Problem, Z: torch.Tensor, patterns=None, project: bool = False,
                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """[Pi_0 z_l, .., Pi_{n_perm-1} z_l] for every column l of a row-major N_lambda x nr block
@@ -174,13 +189,13 @@ class SolveResult:
 def block_krylov_solve(pb: Problem, patterns, f_local: torch.Tensor, n_rhs: int, tol: float = 1e-8,
                        max_it: int = 1000, method: int = ORTHODIR, prec: int = FP64, inner_tol: float = 0.0,
                        max_sweeps: int = 0, check_every: int = 1, max_blocks: int = 0, lam_out=None, u_out=None,
-                       stream=None, raise_on_noconv: bool = True) -> SolveResult:
+                       stream=None, raise_on_noconv: bool = True, precond: int = PRECOND_NONE) -> SolveResult:
     """Solve the interface problem and recover the displacements.  f_local: flat device float64 tensor,
     occurrence blocks of n_p x n_rhs column-major, concatenated."""
     assert f_local.is_cuda and f_local.dtype == torch.float64 and f_local.is_contiguous()
     lam = lam_out if lam_out is not None else torch.empty((pb.n_lambda, n_rhs), dtype=torch.float64, device="cuda")
     u = u_out if u_out is not None else torch.empty_like(f_local)
-    opts = _lib.SolveOpts(tol, max_it, method, prec, inner_tol, max_sweeps, check_every, max_blocks)
+    opts = _lib.SolveOpts(tol, max_it, method, prec, inner_tol, max_sweeps, check_every, max_blocks, int(precond))
     st = SolveStats()
     code = load().block_krylov_solve(pb.handle, _handles(patterns), n_rhs, _ptr(f_local), C.byref(opts), _ptr(lam),
                                      lam.stride(0), _ptr(u), C.byref(st), _stream(stream))

@@ -12,11 +12,13 @@ STATUS_NAMES = {0: "RPF_OK", -1: "RPF_EINVAL", -2: "RPF_ENOTSPD", -3: "RPF_EKERN
                 -5: "RPF_ENOCONV", -6: "RPF_EHIP", -7: "RPF_ENOMEM"}
 FP64, FP32, BF16X3, BF16 = 0, 1, 2, 3
 CLASSICAL, BLOCK_CG, ORTHODIR = 0, 1, 2
+PRECOND_NONE, PRECOND_LUMPED, PRECOND_DIRICHLET = 0, 1, 2
 APPLY_PROJECT = 1
 
 # every symbol the header declares
 EXPORTS = ["rpf_last_error", "rpf_version", "pattern_factor", "pattern_condense", "pattern_info", "pattern_export",
-           "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "problem_n_perm", "feti_apply", "feti_permute",
+           "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "problem_n_perm", "feti_apply",
+           "feti_precond", "feti_permute",
            "block_krylov_solve",
            "rpf_dgemm", "rpf_dposv", "rpf_dsyev_small", "rpf_trace_enable", "rpf_trace_read"]
 
@@ -32,7 +34,7 @@ class ProblemDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_it", C.c_int32), ("method", C.c_int32), ("prec", C.c_int32),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int32), ("check_every", C.c_int32),
-                ("max_blocks", C.c_int32)]
+                ("max_blocks", C.c_int32), ("precond", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -69,6 +71,7 @@ def load() -> C.CDLL:
         "problem_free": (None, [vp]),
         "problem_n_perm": (i32, [vp]),
         "feti_apply": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, C.c_uint32, vp]),
+        "feti_precond": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, i32, C.c_uint32, vp]),
         "feti_permute": (i32, [vp, vp, i32, vp, i64, vp, i64, C.c_uint32, vp]),
         "block_krylov_solve": (i32, [vp, vp, i32, vp, C.POINTER(SolveOpts), vp, i64, vp, C.POINTER(SolveStats), vp]),
         "rpf_dgemm": (i32, [i32, i32, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64, vp]),

@@ -716,9 +716,9 @@ void scatter_all(rpf_problem pb, const YLoc& yl, int m, double* Y, int64_t ldy, 
 }
 
 void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y, int64_t ldy,
-             int prec, bool project, hipStream_t s) {
+             int prec, bool project, hipStream_t s, int op) {
   if (prec != RPF_FP64) {
-    apply_F_lowprec(pb, pats, m, X, ldx, Y, ldy, prec, s);
+    apply_F_lowprec(pb, pats, m, X, ldx, Y, ldy, prec, s, op);
     if (project) {
       ensure_coarse(pb, pats, s);
       project_block(pb, Y, ldy, m, s);
@@ -759,20 +759,22 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
       RPF_LAUNCH_CHECK();
     }
     gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, lw, s);
-    void* tok = trace_begin(s, RPF_FP64);
+    // the tracer times the flexibility products only
+    void* tok = op == OP_FLEX ? trace_begin(s, RPF_FP64) : nullptr;
+    const double* Mp = op == OP_FLEX ? pats[p]->Splus.p : pats[p]->S.p;
     if (nsp[p] > 1) {
-      dgemm_partials(s, nb, cols, nb, pats[p]->Splus.p, nb, xp, lw, yp, (int)((yoff[p + 1] - yoff[p]) / ((int64_t)nb * cols)));
-    } else if (!(big[p] && dgemm_flex(s, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, lw, 0.0, yp, nb))) {
-      dgemm(s, false, false, nb, cols, nb, 1.0, pats[p]->Splus.p, nb, xp, lw, 0.0, yp, nb);
+      dgemm_partials(s, nb, cols, nb, Mp, nb, xp, lw, yp, (int)((yoff[p + 1] - yoff[p]) / ((int64_t)nb * cols)));
+    } else if (!(big[p] && dgemm_flex(s, nb, cols, nb, 1.0, Mp, nb, xp, lw, 0.0, yp, nb))) {
+      dgemm(s, false, false, nb, cols, nb, 1.0, Mp, nb, xp, lw, 0.0, yp, nb);
     }
-    trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
+    if (tok) trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
     yl.base[p] = yp;
     yl.ld[p] = nb;
     yl.slab[p] = (int64_t)nb * cols;
     yl.nsplit[p] = nsp[p];
   }
   pb->last_yl = yl;
-  pb->last_x = X;
+  pb->last_x = op == OP_FLEX ? X : nullptr;
   pb->last_ldx = ldx;
   pb->last_m = m;
   ++pb->fp64_gen;
@@ -781,6 +783,84 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     ensure_coarse(pb, pats, s);
     project_block(pb, Y, ldy, m, s);
   }
+}
+
+// Y = (A A^T)^{-1} X, the scaling of the preconditioners: lambda dof (i, c) combines component c
+// of the multipliers of i's group with the coefficients of C^{-1}.  One thread per (multiplier,
+// column); consecutive threads take consecutive columns of a row.
+template <int DPN>
+__global__ void k_scale_lam(int n_mult, int m, const int* ptr, const int* col, const double* val, const double* X,
+                            int64_t ldx, double* Y, int64_t ldy) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_mult * m) return;
+  const int64_t i = idx / m;
+  const int j = (int)(idx % m);
+  double acc[DPN];
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) acc[c] = 0.0;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+    const int64_t k = col[e];
+    const double v = val[e];
+#pragma unroll
+    for (int c = 0; c < DPN; ++c) acc[c] += v * X[(k * DPN + c) * ldx + j];
+  }
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) Y[(i * DPN + c) * ldy + j] = acc[c];
+}
+
+void scale_lam(rpf_problem pb, int m, const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t s) {
+  const unsigned g = (unsigned)cdiv((int64_t)pb->n_mult * m, 256);
+#define RPF_SCL(D)                                                                                                \
+  hipLaunchKernelGGL(k_scale_lam<D>, dim3(g), dim3(256), 0, s, pb->n_mult, m, pb->d_sc_ptr.p, pb->d_sc_col.p,     \
+                     pb->d_sc_val.p, X, ldx, Y, ldy)
+  switch (pb->dpn) {
+    case 1: RPF_SCL(1); break;
+    case 2: RPF_SCL(2); break;
+    default: RPF_SCL(3);
+  }
+#undef RPF_SCL
+  RPF_LAUNCH_CHECK();
+}
+
+void apply_precond(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
+                   int64_t ldy, int kind, int prec, hipStream_t s) {
+  if (pb->n_mult == 0) return;
+  const int64_t N = pb->n_lambda;
+  pb->pcbuf.ensure((size_t)N * m);
+  double* T = pb->pcbuf.p;
+  // T = (A A^T)^{-1} X; T <- sum_s A^(s) M A^(s)T T (the gathers read T before the scatter
+  // overwrites it); Y = (A A^T)^{-1} T
+  scale_lam(pb, m, X, ldx, T, m, s);
+  if (kind == RPF_PRECOND_DIRICHLET) {
+    apply_F(pb, pats, m, T, m, T, m, prec, false, s, OP_SCHUR);
+  } else {
+    // lumped: the local product with the sparse K_bb, in FP64 (a sparse product over the
+    // occurrences' boundary values, memory bound at any precision)
+    std::vector<int64_t> off(pb->n_pat + 1, 0);
+    for (int p = 0; p < pb->n_pat; ++p)
+      off[p + 1] = off[p] + (int64_t)pats[p]->n_b * (int64_t)pb->occ_of_pat[p].size() * m;
+    pb->xloc.ensure(std::max<int64_t>(off[pb->n_pat], 1));
+    pb->yloc.ensure(std::max<int64_t>(off[pb->n_pat], 1));
+    YLoc yl{};
+    for (int p = 0; p < pb->n_pat; ++p) {
+      const rpf_pattern P = pats[p];
+      const int nb = P->n_b;
+      const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
+      double* xp = pb->xloc.p + off[p];
+      double* yp = pb->yloc.p + off[p];
+      gather_pattern(pb, p, pb->pat_nbn[p], T, m, m, xp, nb, s);
+      if (cols > 0) spmm_csr(s, nb, cols, P->kbb_ptr.p, P->kbb_col.p, P->kbb_val.p, xp, nb, 1.0, yp, nb, 0.0);
+      yl.base[p] = yp;
+      yl.ld[p] = nb;
+      yl.slab[p] = (int64_t)nb * cols;
+      yl.nsplit[p] = 1;
+    }
+    // yloc no longer holds the last flexibility product
+    pb->last_x = nullptr;
+    ++pb->fp64_gen;
+    scatter_all(pb, yl, m, T, m, 0.0, s);
+  }
+  scale_lam(pb, m, T, m, Y, ldy, s);
 }
 
 void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
@@ -1080,6 +1160,91 @@ extern "C" rpf_status problem_create(const rpf_problem_desc* d, rpf_problem* out
         l2m_bn[fillp[slot]] = ep_bn[2 * i + e];
         l2m_code[fillp[slot]++] = (i << 1) | (ep_sign[2 * i + e] < 0 ? 1 : 0);
       }
+    // scaling of the preconditioners: C = A A^T at node level (A^(s) A^(s)T of two multipliers
+    // on the same endpoint is sign sign O O^T = sign sign I), block diagonal over the groups of
+    // multipliers joined through shared endpoints; C^{-1} is formed group by group
+    std::vector<int> sc_ptr(nm + 1, 0), sc_col;
+    std::vector<double> sc_val;
+    {
+      std::vector<int> uf(nm);
+      for (int i = 0; i < nm; ++i) uf[i] = i;
+      auto find = [&](int x) {
+        while (uf[x] != x) x = uf[x] = uf[uf[x]];
+        return x;
+      };
+      for (int sl = 0; sl < nslot; ++sl)
+        for (int e = l2m_ptr[sl] + 1; e < l2m_ptr[sl + 1]; ++e) {
+          const int a = find(l2m_code[l2m_ptr[sl]] >> 1), b = find(l2m_code[e] >> 1);
+          if (a != b) uf[std::max(a, b)] = std::min(a, b);
+        }
+      std::vector<std::vector<int>> members(nm);
+      for (int i = 0; i < nm; ++i) members[find(i)].push_back(i);
+      std::vector<int> lpos(nm, 0);
+      std::vector<std::vector<double>> inv(nm);
+      for (int r = 0; r < nm; ++r) {
+        const std::vector<int>& g = members[r];
+        const int q = (int)g.size();
+        if (q == 0) continue;
+        RPF_CHECK(q <= 64, RPF_EINVAL, "problem_create: more than 64 multipliers share endpoints");
+        for (int a = 0; a < q; ++a) lpos[g[a]] = a;
+        std::vector<double> Cm((size_t)q * q, 0.0), Ci((size_t)q * q, 0.0);
+        for (int a = 0; a < q; ++a) {
+          const int i = g[a];
+          for (int e = 0; e < 2; ++e) {
+            const int so = ep_occ[2 * i + e];
+            if (so < 0) continue;
+            const int sl = pb->slot_off[so] + ep_bn[2 * i + e];
+            for (int f = l2m_ptr[sl]; f < l2m_ptr[sl + 1]; ++f) {
+              const int j = l2m_code[f] >> 1;
+              const double sj = (l2m_code[f] & 1) ? -1.0 : 1.0;
+              Cm[(size_t)a * q + lpos[j]] += (double)ep_sign[2 * i + e] * sj;
+            }
+          }
+        }
+        // Gauss-Jordan with partial pivoting (C is symmetric positive definite for
+        // non-redundant multipliers; a vanishing pivot means redundant ones)
+        for (int a = 0; a < q; ++a) Ci[(size_t)a * q + a] = 1.0;
+        for (int c = 0; c < q; ++c) {
+          int piv = c;
+          for (int r2 = c + 1; r2 < q; ++r2)
+            if (std::fabs(Cm[(size_t)r2 * q + c]) > std::fabs(Cm[(size_t)piv * q + c])) piv = r2;
+          RPF_CHECK(std::fabs(Cm[(size_t)piv * q + c]) > 1e-12, RPF_EINVAL,
+                    "problem_create: redundant multipliers (A A^T is singular)");
+          if (piv != c)
+            for (int k = 0; k < q; ++k) {
+              std::swap(Cm[(size_t)piv * q + k], Cm[(size_t)c * q + k]);
+              std::swap(Ci[(size_t)piv * q + k], Ci[(size_t)c * q + k]);
+            }
+          const double d0 = 1.0 / Cm[(size_t)c * q + c];
+          for (int k = 0; k < q; ++k) {
+            Cm[(size_t)c * q + k] *= d0;
+            Ci[(size_t)c * q + k] *= d0;
+          }
+          for (int r2 = 0; r2 < q; ++r2) {
+            if (r2 == c) continue;
+            const double f = Cm[(size_t)r2 * q + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < q; ++k) {
+              Cm[(size_t)r2 * q + k] -= f * Cm[(size_t)c * q + k];
+              Ci[(size_t)r2 * q + k] -= f * Ci[(size_t)c * q + k];
+            }
+          }
+        }
+        inv[r] = std::move(Ci);
+      }
+      for (int i = 0; i < nm; ++i) {
+        const int r = find(i);
+        const std::vector<int>& g = members[r];
+        const int q = (int)g.size(), a = lpos[i];
+        for (int b = 0; b < q; ++b) {
+          const double v = inv[r][(size_t)a * q + b];
+          if (v == 0.0) continue;
+          sc_col.push_back(g[b]);
+          sc_val.push_back(v);
+        }
+        sc_ptr[i + 1] = (int)sc_col.size();
+      }
+    }
     pb->pair_ptr.push_back(0);
     std::vector<int> pair_mult;
     for (auto& kv : pairs) {
@@ -1118,6 +1283,11 @@ extern "C" rpf_status problem_create(const rpf_problem_desc* d, rpf_problem* out
       pb->d_pair_ptr.upload(pb->pair_ptr.data(), pb->pair_ptr.size(), s0);
       pb->d_pair_mult.upload(pair_mult.data(), pair_mult.size(), s0);
     }
+    if (nm > 0) {
+      pb->d_sc_ptr.upload(sc_ptr.data(), sc_ptr.size(), s0);
+      pb->d_sc_col.upload(sc_col.data(), sc_col.size(), s0);
+      pb->d_sc_val.upload(sc_val.data(), sc_val.size(), s0);
+    }
     if (pb->has_rot) pb->d_rot.upload(d->occ_rot, 9 * (size_t)no, s0);
     if (d->perm_node != nullptr && d->n_perm > 0 && nm > 0) {
       for (int64_t i = 0; i < (int64_t)d->n_perm * nm; ++i)
@@ -1132,6 +1302,29 @@ extern "C" rpf_status problem_create(const rpf_problem_desc* d, rpf_problem* out
 extern "C" int64_t problem_n_lambda(rpf_problem pb) { return pb ? pb->n_lambda : -1; }
 
 extern "C" void problem_free(rpf_problem pb) { delete pb; }
+
+extern "C" rpf_status feti_precond(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X,
+                                   int64_t ldx, double* Y, int64_t ldy, int32_t kind, int32_t prec, uint32_t flags,
+                                   void* stream) {
+  return guarded([&] {
+    RPF_CHECK(pb != nullptr, RPF_EINVAL, "feti_precond: NULL structure");
+    RPF_CHECK(m >= 1 && ldx >= m && ldy >= m && X && Y, RPF_EINVAL, "feti_precond: bad block arguments");
+    RPF_CHECK(kind >= RPF_PRECOND_NONE && kind <= RPF_PRECOND_DIRICHLET, RPF_EINVAL, "feti_precond: kind");
+    RPF_CHECK(prec >= RPF_FP64 && prec <= RPF_BF16, RPF_EINVAL, "feti_precond: precision");
+    const bool proj = (flags & RPF_APPLY_PROJECT) != 0;
+    if (kind != RPF_PRECOND_NONE || proj)
+      check_patterns(pb, patterns, kind == RPF_PRECOND_DIRICHLET ? prec : (proj ? RPF_FP64 : -1));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = pb->n_lambda;
+    if (N == 0) return;
+    if (kind == RPF_PRECOND_NONE) copy_matrix(s, X, ldx, Y, ldy, m, N);
+    else apply_precond(pb, patterns, m, X, ldx, Y, ldy, kind, prec, s);
+    if (proj) {
+      ensure_coarse(pb, patterns, s);
+      project_block(pb, Y, ldy, m, s);
+    }
+  });
+}
 
 extern "C" rpf_status feti_apply(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X,
                                  int64_t ldx, double* Y, int64_t ldy, int32_t prec, uint32_t flags, void* stream) {

@@ -391,6 +391,8 @@ struct Solver {
   DevBuf<int> drops;
   std::vector<double> r0n;  // ||r0_c||^2 of the FP64 residual
   int iterations = 0, rank_drops = 0;
+  int pc = RPF_PRECOND_NONE;  // preconditioner of z = Q F~^{-1} r
+  DevBuf<double> Zp;          // z before the permutations (N x nr)
 
   Solver(rpf_problem p, const rpf_pattern* pt, hipStream_t st, int nr_, int method_)
       : pb(p), pats(pt), s(st), nr(nr_), method(method_) {
@@ -511,7 +513,9 @@ struct Solver {
     // block CG with one permutation: the residual update also leaves the next step's P^T R in Cb,
     // and the solution update of a step is deferred into the next step's orthogonalisation pass,
     // which reads the same direction block (flushed when the loop ends)
-    const bool upd_gram = method != RPF_ORTHODIR && np == 1 && m <= 16 && nr <= 16 && 256 % nr == 0;
+    // (not with a preconditioner: the next block is then Q F~^{-1} R, not R)
+    const bool upd_gram =
+        pc == RPF_PRECOND_NONE && method != RPF_ORTHODIR && np == 1 && m <= 16 && nr <= 16 && 256 % nr == 0;
     bool have_gram = false, lam_pending = false;
     const double* lam_dir = nullptr;  // the direction block of the pending update
     if (upd_gram) alpha_prev.ensure((size_t)m * nr);
@@ -537,8 +541,24 @@ struct Solver {
       // multivector from the residual (Q R = R: the residual stays in range Q), re-projected when
       // permuted; with one permutation it is the residual itself and is read from Rs below
       const bool direct = (np == 1);
-      const bool fused = direct && nb > 0 && nb * m <= 16;  // orthogonalised straight from Rs
-      if (!direct) {
+      // orthogonalised straight from Rs
+      const bool fused = pc == RPF_PRECOND_NONE && direct && nb > 0 && nb * m <= 16;
+      if (pc != RPF_PRECOND_NONE) {
+        // z = Q F~^{-1} r (Table 1), then the multivector of z, re-projected when permuted
+        if (direct) {
+          apply_precond(pb, pats, nr, Rs.p, nr, Zs, ldW, pc, prec, s);
+          project(pb, Zs, ldW, m, s);
+        } else {
+          Zp.ensure((size_t)N * nr);
+          apply_precond(pb, pats, nr, Rs.p, nr, Zp.p, nr, pc, prec, s);
+          project(pb, Zp.p, nr, nr, s);
+          hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
+                             pb->d_perm.p, pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr,
+                             Zp.p, (int64_t)nr, Zs, ldW);
+          RPF_LAUNCH_CHECK();
+          project(pb, Zs, ldW, m, s);
+        }
+      } else if (!direct) {
         hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
                            pb->d_perm.p, pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr, Rs.p,
                            (int64_t)nr, Zs, ldW);
@@ -657,6 +677,14 @@ struct Solver {
 };
 
 }  // namespace
+
+void spmm_csr(hipStream_t s, int rows, int64_t cols, const int* ptr, const int* idx, const double* val,
+              const double* X, int64_t ldx, double alpha, double* Y, int64_t ldy, double beta) {
+  if (rows == 0 || cols == 0) return;
+  hipLaunchKernelGGL(k_spmm, dim3(spmm_blocks(rows, cols)), dim3(256), 0, s, rows, cols, ptr, idx, val, X, ldx, alpha,
+                     Y, ldy, beta);
+  RPF_LAUNCH_CHECK();
+}
 }  // namespace rpf
 
 using namespace rpf;
@@ -672,10 +700,13 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     RPF_CHECK(opts->tol > 0 && opts->max_it >= 1, RPF_EINVAL, "block_krylov_solve: tol / max_it");
     const int prec = opts->prec;
     RPF_CHECK(prec >= RPF_FP64 && prec <= RPF_BF16, RPF_EINVAL, "block_krylov_solve: precision");
+    RPF_CHECK(opts->precond >= RPF_PRECOND_NONE && opts->precond <= RPF_PRECOND_DIRICHLET, RPF_EINVAL,
+              "block_krylov_solve: preconditioner");
     check_patterns(pb, pats, RPF_FP64);
     check_patterns(pb, pats, prec);
     hipStream_t s = (hipStream_t)stream;
     Solver S(pb, pats, s, n_rhs, opts->method);
+    S.pc = opts->precond;
     RPF_CHECK(S.m <= 64, RPF_EINVAL, "block_krylov_solve: block width n_rhs * n_perm must be <= 64");
     const int nr = n_rhs;
     const int64_t N = S.N;

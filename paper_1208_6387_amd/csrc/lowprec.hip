@@ -688,7 +688,7 @@ __global__ __launch_bounds__(256) void k_scatter_f32_quad(int n_mult, const int*
 
 // ---------------------------------------------------------------------------- host
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
-                     int64_t ldy, int prec, hipStream_t s) {
+                     int64_t ldy, int prec, hipStream_t s, int op) {
   const bool split = (prec == RPF_BF16X3 || prec == RPF_BF16);
   // W format with ld rounded up to a multiple of 64: every 64-k chunk of a row is one 128-byte
   // cache line (unaligned rows would make each chunk touch two lines)
@@ -775,16 +775,21 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     }
 #undef RPF_GLP
     RPF_LAUNCH_CHECK();
-    void* tok = trace_begin(s, (int)prec);
+    // the tracer times the flexibility products only
+    void* tok = op == OP_FLEX ? trace_begin(s, (int)prec) : nullptr;
+    const uint16_t* Ah = op == OP_FLEX ? P->Sp_hi.p : P->S_hi.p;
+    const uint16_t* Al = op == OP_FLEX ? P->Sp_lo.p : P->S_lo.p;
+    const float* A32 = op == OP_FLEX ? P->Splus32.p : P->S32.p;
     if (split) {
       RPF_CHECK(P->ldlp == ld[p], RPF_EINVAL, "low-precision S+ layout mismatch");
+      RPF_CHECK(Ah != nullptr && Al != nullptr, RPF_EINVAL, "low-precision copy of the pattern matrix missing");
       const int tm = tile_m[p], tn = tile_n[p];
       dim3 g2((unsigned)cdiv(nb, tm), (unsigned)cdiv(cols, tn), (unsigned)nsp[p]);
 #define RPF_BF(BM_, BN_, X3)                                                                                      \
-  RPF_TIMED_LAUNCH((k_gemm_bf16<BM_, BN_, X3>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p, P->Sp_lo.p, \
+  RPF_TIMED_LAUNCH((k_gemm_bf16<BM_, BN_, X3>), g2, dim3(256), 0, s, nb, cols, (int)ld[p], Ah, Al,               \
                      ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ld[p], kch[p], slab)
 #define RPF_BIG(X3)                                                                                            \
-  RPF_TIMED_LAUNCH((k_gemm_bf16_big<X3>), g2, dim3(512), 0, s, nb, cols, (int)ld[p], P->Sp_hi.p, P->Sp_lo.p,    \
+  RPF_TIMED_LAUNCH((k_gemm_bf16_big<X3>), g2, dim3(512), 0, s, nb, cols, (int)ld[p], Ah, Al,                  \
                      ld[p], pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], yp, ldr[p], kch[p], slab)
       if (tm == 256) {
         RPF_CHECK(ld[p] % 32 == 0 && kch[p] % 32 == 0, RPF_EINVAL, "bf16 operand layout not in 32-k stages");
@@ -801,11 +806,12 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
 #undef RPF_BF
     } else {
       dim3 g2((unsigned)cdiv(nb, 64), (unsigned)cdiv(cols, 64), (unsigned)nsp[p]);
-      RPF_TIMED_LAUNCH((k_sgemm_sym<64, 64>), g2, dim3(256), 0, s, nb, cols, nb, P->Splus32.p, (int64_t)nb,
+      RPF_CHECK(A32 != nullptr, RPF_EINVAL, "FP32 copy of the pattern matrix missing");
+      RPF_TIMED_LAUNCH((k_sgemm_sym<64, 64>), g2, dim3(256), 0, s, nb, cols, nb, A32, (int64_t)nb,
                          pb->xloc32.p + off[p], ld[p], yp, ld[p], kch[p], slab);
     }
     RPF_LAUNCH_CHECK();
-    trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
+    if (tok) trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
   }
   if (pb->n_mult == 0) return;
   dim3 grid((unsigned)cdiv(pb->n_mult, 128));

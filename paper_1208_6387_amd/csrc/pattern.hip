@@ -118,7 +118,7 @@ void check_status(hipStream_t s, const int* d_status, const char* what) {
 using namespace rpf;
 
 extern "C" const char* rpf_last_error(void) { return rpf::g_last_error.c_str(); }
-extern "C" int32_t rpf_version(void) { return 100; }
+extern "C" int32_t rpf_version(void) { return 101; }
 
 extern "C" rpf_status pattern_factor(int32_t n, const int32_t* rowptr, const int32_t* colind, const double* val,
                                      int32_t n_b, const int32_t* bdofs, int32_t dpn, double ktol,
@@ -164,6 +164,7 @@ extern "C" rpf_status pattern_factor(int32_t n, const int32_t* rowptr, const int
     const int64_t nnz = rowptr[n];
     std::vector<int> first(n_i);
     std::vector<int> kbi_ptr(n_b + 1, 0), kib_ptr(n_i + 1, 0), kbi_col, kib_col, kbi_src, kib_src;
+    std::vector<int> kbb_ptr(n_b + 1, 0), kbb_col, kbb_src;
     for (int r = 0; r < n; ++r) {
       RPF_CHECK(rowptr[r + 1] >= rowptr[r], RPF_EINVAL, "pattern_factor: bad rowptr");
       const int pr = pos[r];
@@ -180,11 +181,17 @@ extern "C" rpf_status pattern_factor(int32_t n, const int32_t* rowptr, const int
         } else if (pc < n_i) {
           kbi_col.push_back(pc);
           kbi_src.push_back(e);
+        } else {
+          kbb_col.push_back(pc - n_i);
+          kbb_src.push_back(e);
         }
       }
       RPF_CHECK(diag, RPF_EINVAL, "pattern_factor: a row has no diagonal entry");
       if (pr < n_i) { first[pr] = f; kib_ptr[pr + 1] = (int)kib_col.size(); }
-      else kbi_ptr[pr - n_i + 1] = (int)kbi_col.size();
+      else {
+        kbi_ptr[pr - n_i + 1] = (int)kbi_col.size();
+        kbb_ptr[pr - n_i + 1] = (int)kbb_col.size();
+      }
     }
     const int64_t nblk = cdiv(n_i, NB);
     P->env_ii.rend.assign(nblk, 0);
@@ -230,6 +237,7 @@ extern "C" rpf_status pattern_factor(int32_t n, const int32_t* rowptr, const int
     };
     upload_csr(P->kbi_ptr, P->kbi_col, P->kbi_val, kbi_ptr, kbi_col, kbi_src);
     upload_csr(P->kib_ptr, P->kib_col, P->kib_val, kib_ptr, kib_col, kib_src);
+    upload_csr(P->kbb_ptr, P->kbb_col, P->kbb_val, kbb_ptr, kbb_col, kbb_src);
     P->d_bdofs.upload(P->bdofs.data(), n_b, s);
     if (n_i > 0) P->d_idofs.upload(P->idofs.data(), n_i, s);
 
@@ -327,6 +335,8 @@ extern "C" rpf_status pattern_condense(rpf_pattern p, int32_t prec, void* stream
     if (prec == RPF_FP32 && !(p->condensed & (1u << RPF_FP32))) {
       p->Splus32.alloc(cnt);
       hipLaunchKernelGGL(k_to_f32, dim3((unsigned)cdiv(cnt, 256)), dim3(256), 0, s, p->Splus.p, cnt, p->Splus32.p);
+      p->S32.alloc(cnt);
+      hipLaunchKernelGGL(k_to_f32, dim3((unsigned)cdiv(cnt, 256)), dim3(256), 0, s, p->S.p, cnt, p->S32.p);
       RPF_LAUNCH_CHECK();
       p->condensed |= 1u << RPF_FP32;
     }
@@ -337,6 +347,10 @@ extern "C" rpf_status pattern_condense(rpf_pattern p, int32_t prec, void* stream
       p->Sp_lo.alloc(cntp);
       hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)cdiv(cntp, 256)), dim3(256), 0, s, p->Splus.p, (int64_t)nb,
                          p->ldlp, p->Sp_hi.p, p->Sp_lo.p);
+      p->S_hi.alloc(cntp);
+      p->S_lo.alloc(cntp);
+      hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)cdiv(cntp, 256)), dim3(256), 0, s, p->S.p, (int64_t)nb,
+                         p->ldlp, p->S_hi.p, p->S_lo.p);
       RPF_LAUNCH_CHECK();
       p->condensed |= (1u << RPF_BF16X3) | (1u << RPF_BF16);
     }

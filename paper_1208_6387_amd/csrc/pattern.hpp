@@ -23,11 +23,17 @@ struct rpf_pattern_s {
   rpf::DevBuf<uint16_t> Sp_hi, Sp_lo;  // bf16 split of S+ (bit patterns), n_b rows of ldlp, zero padded
   int64_t ldlp = 0;
   uint32_t condensed = 0;      // bit per rpf_prec built
+  // the same low-precision copies of S, for the Dirichlet preconditioner of the low-precision solves
+  rpf::DevBuf<float> S32;
+  rpf::DevBuf<uint16_t> S_hi, S_lo;
 
   // K_bi (rows: boundary index, cols: interior index) and K_ib, CSR, for the
   // condensed loads g = f_b - K_bi K_ii^{-1} f_i and the interior recovery
   rpf::DevBuf<int> kbi_ptr, kbi_col, kib_ptr, kib_col;
   rpf::DevBuf<double> kbi_val, kib_val;
+  // K_bb (boundary x boundary), CSR: the local matrix of the lumped preconditioner
+  rpf::DevBuf<int> kbb_ptr, kbb_col;
+  rpf::DevBuf<double> kbb_val;
   rpf::DevBuf<int> d_bdofs, d_idofs;
 
   rpf::DevBuf<int> status;

@@ -50,6 +50,13 @@ struct rpf_problem_s {
   rpf::DevBuf<float> xloc32, yloc32;
   rpf::DevBuf<uint16_t> xhi, xlo;
 
+  // scaling of the preconditioners, (A A^T)^{-1} = C^{-1} (x) I_dpn: C couples the multipliers
+  // that share an endpoint (occurrence, local node), so C^{-1} is block diagonal over those
+  // groups; CSR over multipliers (node level)
+  rpf::DevBuf<int> d_sc_ptr, d_sc_col;
+  rpf::DevBuf<double> d_sc_val;
+  rpf::DevBuf<double> pcbuf;  // preconditioner workspace, N_lambda x m
+
   // coarse space (built for one set of pattern handles)
   std::vector<uint64_t> coarse_key;  // uids of the pattern handles the coarse space was built for
   int n_G = 0;
@@ -66,9 +73,19 @@ struct rpf_problem_s {
 namespace rpf {
 // helpers shared by the operator and the solver
 void check_patterns(rpf_problem pb, const rpf_pattern* pats, int prec);
-// Y = F X (W-format products on all patterns), optional projection
+// pattern matrix of a local product: S+ (the operator F) or S (the Dirichlet preconditioner)
+enum LocalOp { OP_FLEX = 0, OP_SCHUR = 1 };
+// Y = F X (W-format products on all patterns), optional projection; with op = OP_SCHUR the same
+// assembled product with S in place of S+
 void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
-             int64_t ldy, int prec, bool project, hipStream_t s);
+             int64_t ldy, int prec, bool project, hipStream_t s, int op = OP_FLEX);
+// Y = F~^{-1} X for the lumped (kind 1) or Dirichlet (kind 2) preconditioner, the Dirichlet
+// product in precision prec; X and Y may be the same block
+void apply_precond(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
+                   int64_t ldy, int kind, int prec, hipStream_t s);
+// Y = beta Y + alpha A X for a CSR matrix A (rows x n) and column-major X, Y (cols columns)
+void spmm_csr(hipStream_t s, int rows, int64_t cols, const int* ptr, const int* idx, const double* val,
+              const double* X, int64_t ldx, double alpha, double* Y, int64_t ldy, double beta);
 // A^(s)T gather of an interface block into the W format of pattern p
 void gather_pattern(rpf_problem pb, int p, int nbn, const double* lam, int64_t ldl, int m, double* X,
                     int64_t ldx, hipStream_t s);
@@ -90,7 +107,7 @@ void coarse_solve(rpf_problem pb, const double* c, double* y, int m, hipStream_t
 void gather_rows(rpf_problem pb, int p, const double* lam, int64_t ldl, int m, int mode, double* X64, float* Xf,
                  uint16_t* Xh, uint16_t* Xl, int64_t ldx, hipStream_t s);
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
-                     int64_t ldy, int prec, hipStream_t s);
+                     int64_t ldy, int prec, hipStream_t s, int op = OP_FLEX);
 // event tracing of the flexibility products
 bool trace_on();
 void* trace_begin(hipStream_t s, int prec);
