@@ -58,6 +58,11 @@ def main():
     ap.add_argument("--method", default=None, choices=sorted(METHODS), help="solver (default per workload)")
     ap.add_argument("--forms", default="bf16x3,fp64",
                     help="comma list of fp64, fp32, bf16x3, bf16 (first is the headline)")
+    ap.add_argument("--precond", default="none", choices=["none", "lumped", "dirichlet"],
+                    help="preconditioner of the headline solves (section 2; none = identity)")
+    ap.add_argument("--precond-extra", default="dirichlet",
+                    help="comma list of preconditioners (lumped, dirichlet) also timed for every form and reported "
+                         "under 'preconditioned' (empty: none)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-it", type=int, default=3000)
     ap.add_argument("--max-blocks", type=int, default=None, help="ORTHODIR restart length (default per workload)")
@@ -110,7 +115,9 @@ def main():
     u = torch.empty_like(f)
     torch.cuda.synchronize()
 
-    def step(prec: int):
+    PRECONDS = {"none": R.PRECOND_NONE, "lumped": R.PRECOND_LUMPED, "dirichlet": R.PRECOND_DIRICHLET}
+
+    def step(prec: int, pc: int = PRECONDS[args.precond]):
         pats = []
         for pat, v in zip(p.patterns, kvals):
             pats.append(R.pattern_factor(pat.K.indptr, pat.K.indices, v, pat.bdofs, pat.dpn,
@@ -121,7 +128,7 @@ def main():
                 R.pattern_condense(P, prec)
         res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=args.tol, max_it=args.max_it, method=method,
                                    prec=prec, inner_tol=settings["inner_tol"], max_blocks=settings["max_blocks"],
-                                   lam_out=lam, u_out=u)
+                                   lam_out=lam, u_out=u, precond=pc)
         for P in pats:
             P.free()
         return res
@@ -153,6 +160,33 @@ def main():
         results[form] = dict(ms=ms, stats=st, trace=tr)
         log(f"[bench] {form}: {ms:.2f} ms/step, iterations {st['iterations']}, sweeps {st['sweeps']}, "
             f"rel_res {st['rel_residual']:.2e}, gemm {tr['count']} launches {tr['ms']:.2f} ms")
+
+    # the same forms with a preconditioner (the timed region as above)
+    extra = {}
+    for name in [x.strip() for x in args.precond_extra.split(",") if x.strip() and x.strip() != args.precond]:
+        extra[name] = {}
+        for form in forms:
+            prec = PREC_NAMES[form]
+            for w in range(args.warmup):
+                log(f"[bench] warmup {form} + {name} {w}")
+                step(prec, PRECONDS[name])
+            torch.cuda.synchronize()
+            log(f"[bench] timing {form} + {name} preconditioner: {args.steps} steps")
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                res = step(prec, PRECONDS[name])
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            st = res.stats
+            assert st["rel_residual"] <= args.tol * 1.0000001, st
+            extra[name][form] = {"ms": round(ms, 3), "iterations": st["iterations"], "sweeps": st["sweeps"],
+                                 "rel_residual": st["rel_residual"],
+                                 "phase_ms": {q: round(st[q], 3) for q in ("ms_loads", "ms_coarse", "ms_iterate",
+                                                                           "ms_recover")}}
+            log(f"[bench] {form} + {name}: {ms:.2f} ms/step, iterations {st['iterations']}, sweeps {st['sweeps']}")
+        if "fp64" in extra[name] and len(extra[name]) > 1:
+            extra[name]["speedup_vs_fp64"] = {k: round(extra[name]["fp64"]["ms"] / v["ms"], 3)
+                                              for k, v in extra[name].items() if isinstance(v, dict) and "ms" in v}
 
     head = forms[0]
     hr = results[head]
@@ -188,6 +222,7 @@ def main():
         "dtype": "f64" if head == "fp64" else ("f32+f64" if head == "fp32" else "bf16+f64"),
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "form": head, "method": method_name,
+                   "precond": args.precond,
                    "max_blocks": settings["max_blocks"], "inner_tol": settings["inner_tol"],
                    "n_lambda": pb.n_lambda, "n_occ": p.n_occ, "n_rhs": p.n_rhs, "n_perm": p.n_perm,
                    "pattern_dofs": [pat.n for pat in p.patterns], "pattern_boundary_dofs": [pat.n_b for pat in p.patterns],
@@ -206,6 +241,8 @@ def main():
     }
     if "fp64" in results and len(results) > 1:
         out["speedup_vs_fp64"] = {k: round(results["fp64"]["ms"] / v["ms"], 3) for k, v in results.items()}
+    if extra:
+        out["preconditioned"] = extra
 
     if args.cpu:
         # the oracle computes in FP64: it is timed for the FP64 form's iteration count when measured
