@@ -273,7 +273,9 @@ def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed
     """Periodic ring of unit-square heat patterns (section 3's toy problem, cut open as a strip
     whose last right edge is glued to the first left edge).  Interface (s, s+1) has the right edge
     of s as its '+' side.  stand=True adds one stand pattern (a 1 x 1/2 rectangle) on top of
-    occurrence n_occ-1 (section 5.1.1).  dirichlet_bottom fixes the bottom edge of occurrence 0.
+    occurrence n_occ-1 (section 5.1.1).  dirichlet_bottom fixes the bottom edge of occurrence 0;
+    dirichlet_bottom="periodic" fixes the bottom-edge nodes off the interfaces of every ring
+    occurrence, which keeps the ring truly periodic.
     """
     nx, ny = pat_shape
     mesh = M.GridMesh(pat_shape, (1.0, 1.0))
@@ -297,7 +299,14 @@ def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed
         occ_gnode.append(gid)
         occ_pattern.append(1)
         n_g = n_g + W * smesh.shape[1]
-    dir_g = np.nonzero((np.arange(n_g) < W) & (np.arange(n_g) < nx + 1))[0] if dirichlet_bottom else np.zeros(0, np.int64)
+    if dirichlet_bottom == "periodic":
+        # the bottom-edge nodes of every ring occurrence off its interfaces (truly periodic)
+        gx = np.arange(W)
+        dir_g = gx[gx % nx != 0]
+    elif dirichlet_bottom:
+        dir_g = np.nonzero((np.arange(n_g) < W) & (np.arange(n_g) < nx + 1))[0]
+    else:
+        dir_g = np.zeros(0, np.int64)
     n_total = len(occ_gnode)
     rng = np.random.Generator(np.random.PCG64(seed))
     f_local = [rng.standard_normal((len(g), n_rhs)) for g in occ_gnode]
@@ -342,6 +351,41 @@ def mirror_row_heat(n_occ=2, pat_shape=(4, 4), reaction=0.1, n_rhs=1, seed=2):
                    f_local, n_rhs, 1, 1e-10, meta)
 
 
+def random_spd_ring(n_occ=5, n_if=40, n_rhs=1, n_perm=None, seed=4, shift=0.005):
+    """Academic ring of a pattern whose stiffness is a random dense symmetric positive definite
+    matrix on its interface dofs only (so its Schur complement is that matrix): the first n_if
+    dofs face the previous occurrence, the last n_if the next one, and occurrence n_occ-1 closes
+    the ring on occurrence 0.  K = M M^T / n + shift I with M i.i.d. N(0, 1); no occurrence floats
+    and there is no Dirichlet condition.  Loads i.i.d. N(0, 1) per occurrence (non-periodic).
+    Interface (s, s+1) has the last n_if dofs of s as its '+' side, so the multipliers form one
+    cyclic class per dof and Pi_k shifts the ring by k occurrences.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = 2 * n_if
+    Mr = rng.standard_normal((n, n))
+    Kd = Mr @ Mr.T / n + shift * np.eye(n)
+    Kd = 0.5 * (Kd + Kd.T)
+    K = sp.csr_matrix(Kd)
+    K.sort_indices()
+    pats = [Pattern("random-spd-pattern", 1, np.zeros((n, 2)), K, 0)]
+    occ_gnode = []
+    for s_ in range(n_occ):
+        left = s_ * n_if + np.arange(n_if)
+        right = ((s_ + 1) % n_occ) * n_if + np.arange(n_if)
+        occ_gnode.append(np.concatenate([left, right]))
+    f_local = [rng.standard_normal((n, n_rhs)) for _ in range(n_occ)]
+    rot = np.repeat(np.eye(3)[None], n_occ, axis=0)
+
+    def swap(oa, la, ob, lb):
+        # the '+' side of every interface is the right half of the lower occurrence in ring order
+        return la < n_if
+
+    meta = dict(kind="random-spd", ring=n_occ, n_if=n_if, shift=shift, seed=seed)
+    return _finish(f"random-spd-ring{n_occ}", 1, pats, [0] * n_occ, rot, occ_gnode, n_occ * n_if,
+                   np.zeros(0, np.int64), f_local, n_rhs, n_perm if n_perm is not None else n_occ, 1e-10, meta,
+                   swap_rule=swap)
+
+
 def rot_z(angle: float) -> np.ndarray:
     c, s = np.cos(angle), np.sin(angle)
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
@@ -352,7 +396,9 @@ def ring_elast(n_occ=3, pat_shape=(2, 3, 2), r_in=1.0, r_out=1.5, height=0.5, n_
     """Closed ring of n_occ identical annular-sector bricks (elasticity), occurrence s rotated by
     2 pi s / n_occ about z (section 5.2: rotations in the assembly; section 5.3: the ring of
     rotated occurrences).  pat_shape = (radial, circumferential, axial) elements; the sector spans
-    [0, 2 pi / n_occ].  The bottom face of occurrence 0 is clamped.  Interface (s, s+1) has the
+    [0, 2 pi / n_occ].  The bottom face of occurrence 0 is clamped (clamp=True), nothing
+    (False), or, with clamp="periodic", the bottom-face nodes off the interfaces of every
+    occurrence (a truly periodic structure).  Interface (s, s+1) has the
     far face of s as its '+' side; loads are i.i.d. N(0,1) nodal forces in the pattern frame.
     """
     nr_, nt, nz = pat_shape
@@ -374,6 +420,11 @@ def ring_elast(n_occ=3, pat_shape=(2, 3, 2), r_in=1.0, r_out=1.5, height=0.5, n_
     occ_gnode = [gid[s * mesh.n_nodes:(s + 1) * mesh.n_nodes] for s in range(n_occ)]
     n_g = int(gid.max()) + 1
     bottom0 = occ_gnode[0][lat[:, 2] == 0] if clamp else np.zeros(0, np.int64)
+    if clamp == "periodic":
+        # the bottom-face nodes of every occurrence that lie on no interface: the same local nodes
+        # in every occurrence, so the structure stays truly periodic under the ring shifts
+        inner_bottom = (lat[:, 2] == 0) & (lat[:, 1] > 0) & (lat[:, 1] < nt)
+        bottom0 = np.concatenate([occ_gnode[s][inner_bottom] for s in range(n_occ)])
     rng = np.random.Generator(np.random.PCG64(seed))
     f_local = [rng.standard_normal((mesh.n_nodes * 3, n_rhs)) for _ in range(n_occ)]
     far = lat[:, 1] == nt
