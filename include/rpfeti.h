@@ -220,6 +220,13 @@ typedef struct {
   int32_t precond;     /* rpf_precond: z = Q F~^{-1} r in every iteration (Table 1, lines 4 and 5.5);
                           the Dirichlet product runs in the inner precision prec.  The projector
                           keeps the identity in place of F~^{-1}. */
+  int32_t periodic;    /* 1: truly periodic structure (section 3.1, after Table 1): with several
+                          permutations, Q F of the multivector is the permuted Q F z of the nr
+                          columns of z, and the orthogonalisation applies its coefficients to the
+                          stored P blocks too, so each iteration runs one product on nr columns.
+                          The commutation of Q F (and of the preconditioner) with the permutations
+                          is checked once on a test vector: RPF_EINVAL when it fails.  Ignored
+                          for the classical method and with one permutation. */
 } rpf_solve_opts;
 
 typedef struct {

@@ -222,6 +222,17 @@ __global__ __launch_bounds__(256) void k_tblocks(int nb, int m, int c, const dou
   }
 }
 
+// x[i] = a pseudo-random value in [-0.5, 0.5) from a hash of i (a fixed test vector)
+__global__ void k_fill_hash(int64_t n, double* x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  x[i] = (double)(h >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
 // keep only the diagonal of an m x n column-major matrix (ld)
 __global__ void k_mask_diag(double* A, int m, int n, int64_t ld) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -392,7 +403,9 @@ struct Solver {
   std::vector<double> r0n;  // ||r0_c||^2 of the FP64 residual
   int iterations = 0, rank_drops = 0;
   int pc = RPF_PRECOND_NONE;  // preconditioner of z = Q F~^{-1} r
+  bool periodic = false;      // truly periodic structure: P of the multivector by permutations
   DevBuf<double> Zp;          // z before the permutations (N x nr)
+  DevBuf<double> Pz;          // Q F z (N x nr), periodic shortcut
 
   Solver(rpf_problem p, const rpf_pattern* pt, hipStream_t st, int nr_, int method_)
       : pb(p), pats(pt), s(st), nr(nr_), method(method_) {
@@ -498,6 +511,14 @@ struct Solver {
     Mo.ensure((size_t)ldW * m);
   }
 
+  // W = Q [Pi_0 z, .., Pi_{np-1} z] for the nr columns of z (N x nr), into a slot of the store
+  void permute_into(const double* z, double* W) {
+    hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np, pb->d_perm.p,
+                       pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr, z, (int64_t)nr, W, ldW);
+    RPF_LAUNCH_CHECK();
+    project(pb, W, ldW, m, s);
+  }
+
   // One inner Krylov run on F_prec: starts from residual Rs (N x nr), accumulates
   // the correction into dlam; stops when every column satisfies ||r_c||^2 <= target_c
   // (CONVERGED), when a whole block was dropped (EXHAUSTED) or after max_it iterations.
@@ -543,27 +564,28 @@ struct Solver {
       const bool direct = (np == 1);
       // orthogonalised straight from Rs
       const bool fused = pc == RPF_PRECOND_NONE && direct && nb > 0 && nb * m <= 16;
-      if (pc != RPF_PRECOND_NONE) {
-        // z = Q F~^{-1} r (Table 1), then the multivector of z, re-projected when permuted
-        if (direct) {
-          apply_precond(pb, pats, nr, Rs.p, nr, Zs, ldW, pc, prec, s);
-          project(pb, Zs, ldW, m, s);
-        } else {
+      // periodic shortcut (truly periodic structure, section 3.1): Q F of the permuted block is
+      // the permuted Q F z, so the product runs on the nr columns of z only
+      const bool per = periodic && !direct;
+      if (pc != RPF_PRECOND_NONE && direct) {
+        // z = Q F~^{-1} r (Table 1)
+        apply_precond(pb, pats, nr, Rs.p, nr, Zs, ldW, pc, prec, s);
+        project(pb, Zs, ldW, m, s);
+      } else if (!direct) {
+        // the multivector of z = Q F~^{-1} r (z = r without a preconditioner), re-projected
+        const double* z = Rs.p;
+        if (pc != RPF_PRECOND_NONE) {
           Zp.ensure((size_t)N * nr);
           apply_precond(pb, pats, nr, Rs.p, nr, Zp.p, nr, pc, prec, s);
           project(pb, Zp.p, nr, nr, s);
-          hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
-                             pb->d_perm.p, pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr,
-                             Zp.p, (int64_t)nr, Zs, ldW);
-          RPF_LAUNCH_CHECK();
-          project(pb, Zs, ldW, m, s);
+          z = Zp.p;
         }
-      } else if (!direct) {
-        hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np,
-                           pb->d_perm.p, pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr, Rs.p,
-                           (int64_t)nr, Zs, ldW);
-        RPF_LAUNCH_CHECK();
-        project(pb, Zs, ldW, m, s);
+        permute_into(z, Zs);
+        if (per) {
+          Pz.ensure((size_t)N * nr);
+          apply_F(pb, pats, nr, z, nr, Pz.p, nr, prec, true, s);
+          permute_into(Pz.p, Ps);
+        }
       } else if (!fused) {
         hipLaunchKernelGGL(k_axpby_rows, dim3(nblocks(N * nr)), dim3(256), 0, s, N, nr, 1.0, Rs.p, (int64_t)nr, 0.0,
                            Zs, ldW);
@@ -594,9 +616,11 @@ struct Solver {
         } else {
           rows_gemm(s, N, ka, m, -1.0, Zall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Zs, ldW);
         }
+        // periodic shortcut: F Z_i = P_i, so P takes the same combination of the stored P_i
+        if (per) rows_gemm(s, N, ka, m, -1.0, Pall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Ps, ldW);
       }
       // P = Q^T F Z
-      apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, true, s);
+      if (!per) apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, true, s);
       // [eta | Z^T R] = Z^T [P | R] in one pass over Z; T with T^T eta T = I on the kept directions
       {
         const size_t need = std::max((size_t)gram_chunks(N, m, 16) * m * (m + nr),
@@ -811,6 +835,46 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     // when the recursive residual reached the target but the true one did not
     const int max_sweeps = opts->max_sweeps > 0 ? opts->max_sweeps : (mixed ? 30 : 4);
     S.alloc_store(opts->max_blocks > 0 ? opts->max_blocks : std::min(opts->max_it, 2000) + 1);
+    if (opts->periodic && S.np > 1) {
+      // the shortcut holds when Q F (and the preconditioner) commute with every permutation:
+      // checked once, in FP64, on a pseudo-random vector of range Q
+      const int np = S.np;
+      DevBuf<double> x(N), a(N), pa((size_t)N * np), px((size_t)N * np), b((size_t)N * np);
+      hipLaunchKernelGGL(k_fill_hash, dim3(nblocks(N)), dim3(256), 0, s, N, x.p);
+      RPF_LAUNCH_CHECK();
+      project(pb, x.p, 1, 1, s);
+      double worst = 0.0;
+      for (int what = 0; what < (S.pc != RPF_PRECOND_NONE ? 2 : 1); ++what) {
+        auto op = [&](const double* in, double* out, int cols) {
+          if (what == 0) apply_F(pb, pats, cols, in, cols, out, cols, RPF_FP64, true, s);
+          else apply_precond(pb, pats, cols, in, cols, out, cols, S.pc, RPF_FP64, s);
+        };
+        op(x.p, a.p, 1);
+        hipLaunchKernelGGL(k_permute, dim3(nblocks(N * np)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, 1, np,
+                           pb->d_perm.p, pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr, a.p,
+                           (int64_t)1, pa.p, (int64_t)np);
+        hipLaunchKernelGGL(k_permute, dim3(nblocks(N * np)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, 1, np,
+                           pb->d_perm.p, pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr, x.p,
+                           (int64_t)1, px.p, (int64_t)np);
+        RPF_LAUNCH_CHECK();
+        project(pb, px.p, np, np, s);
+        op(px.p, b.p, np);
+        std::vector<double> ha((size_t)N * np), hb((size_t)N * np);
+        RPF_HIP(hipMemcpyAsync(ha.data(), pa.p, sizeof(double) * N * np, hipMemcpyDeviceToHost, s));
+        RPF_HIP(hipMemcpyAsync(hb.data(), b.p, sizeof(double) * N * np, hipMemcpyDeviceToHost, s));
+        RPF_HIP(hipStreamSynchronize(s));
+        double dmax = 0.0, amax = 0.0;
+        for (size_t i = 0; i < ha.size(); ++i) {
+          dmax = std::max(dmax, std::fabs(ha[i] - hb[i]));
+          amax = std::max(amax, std::fabs(ha[i]));
+        }
+        worst = std::max(worst, amax > 0.0 ? dmax / amax : 0.0);
+      }
+      RPF_CHECK(worst <= 1e-10, RPF_EINVAL,
+                "block_krylov_solve: periodic shortcut requested but the structure is not periodic under its "
+                "permutations (relative commutation defect " + std::to_string(worst) + ")");
+      S.periodic = true;
+    }
     bool converged = false;
     int sweeps = 0;
     std::vector<double> rn = S.r0n;

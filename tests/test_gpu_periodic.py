@@ -1,0 +1,126 @@
+"""Periodic shortcut of the multivector product and the academic random-SPD ring (section 3),
+on the HIP path through the C ABI, against the CPU oracle.
+
+Tolerances: displacements within 1e-8 (FP64) and 1e-6 (bf16x3 with FP64 refinement) of the
+oracle solved to 1e-12, as for the other solves.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_1208_6387_amd as R
+    R.load()
+    return R
+
+
+def _problem(name):
+    if name == "heat-ring-periodic":
+        return W.ring_heat(4, (4, 4), dirichlet_bottom="periodic", n_perm=4, n_rhs=2)
+    if name == "elast-ring-periodic-rotated":
+        return W.ring_elast(6, (2, 3, 2), clamp="periodic", n_perm=6, n_rhs=1)
+    if name == "random-spd-ring5":
+        return W.random_spd_ring(5, 40)
+    if name == "random-spd-ring9":
+        return W.random_spd_ring(9, 40)
+    raise KeyError(name)
+
+
+@pytest.fixture(scope="module", params=["heat-ring-periodic", "elast-ring-periodic-rotated", "random-spd-ring5",
+                                        "random-spd-ring9"])
+def case(request, R):
+    from paper_1208_6387_amd import structure as ST
+    p = _problem(request.param)
+    print(f"\n[periodic case {request.param}] n_lambda={p.n_lambda} n_perm={p.n_perm}", flush=True)
+    o = O.FetiOracle(p)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats, precs=(R.FP64, R.BF16X3))
+    pb = ST.create_problem(p)
+    return request.param, p, o, pats, pb
+
+
+def _err(p, res, u_o):
+    from paper_1208_6387_amd import structure as ST
+    u = ST.split_u(p, res.u)
+    return max(np.abs(a - b).max() for a, b in zip(u, u_o)) / max(np.abs(x).max() for x in u_o)
+
+
+@pytest.mark.parametrize("method", ["block_cg", "orthodir"])
+@pytest.mark.parametrize("pc", ["none", "dirichlet"])
+def test_periodic_shortcut_fp64(case, R, method, pc):
+    from paper_1208_6387_amd import structure as ST
+    name, p, o, pats, pb = case
+    meth = {"block_cg": R.BLOCK_CG, "orthodir": R.ORTHODIR}[method]
+    kind = {"none": R.PRECOND_NONE, "dirichlet": R.PRECOND_DIRICHLET}[pc]
+    f = ST.loads_to_device(p)
+    _, u_o, _ = o.solve("block", tol=1e-12)
+    out = {}
+    for per in (False, True):
+        R.trace_enable(True)
+        R.trace_read()
+        res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=1e-11, max_it=2000, method=meth, precond=kind,
+                                   periodic=per)
+        tr = R.trace_read()
+        R.trace_enable(False)
+        assert _err(p, res, u_o) < 1e-8, (per, res.stats)
+        out[per] = (res.stats["iterations"], tr["flops"])
+    # same iterations; the products now run on n_rhs columns instead of n_rhs * n_perm
+    assert abs(out[True][0] - out[False][0]) <= 1 + (method == "block_cg"), out
+    per_it = [out[k][1] / max(out[k][0], 1) for k in (False, True)]
+    assert per_it[1] < per_it[0] * (1.5 / p.n_perm + 0.2), (per_it, out)
+
+
+def test_periodic_shortcut_mixed(case, R):
+    from paper_1208_6387_amd import structure as ST
+    name, p, o, pats, pb = case
+    f = ST.loads_to_device(p)
+    res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=1e-8, max_it=2000, method=R.ORTHODIR, prec=R.BF16X3,
+                               inner_tol=1e-3, periodic=True, precond=R.PRECOND_DIRICHLET)
+    assert res.stats["rel_residual"] <= 1e-8
+    _, u_o, _ = o.solve("block", tol=1e-12)
+    assert _err(p, res, u_o) < 1e-6, res.stats
+
+
+def test_periodic_shortcut_refused_on_non_periodic_structure(R):
+    from paper_1208_6387_amd import structure as ST
+    p = W.ring_heat(4, (4, 4), dirichlet_bottom=True, n_perm=4)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats)
+    pb = ST.create_problem(p)
+    with pytest.raises(R.RpfError, match="EINVAL.*periodic"):
+        R.block_krylov_solve(pb, pats, ST.loads_to_device(p), 1, tol=1e-10, max_it=200, method=R.ORTHODIR,
+                             periodic=True)
+
+
+def test_random_spd_ring_iteration_study(R):
+    """The academic study of section 3 on the GPU: Dirichlet preconditioner, random loads; the
+    multivector of the n_occ shifts against classical CG, iteration counts as in the oracle."""
+    from paper_1208_6387_amd import structure as ST
+    saving = {}
+    for n_occ in (5, 9):
+        p = W.random_spd_ring(n_occ, 40)
+        o = O.FetiOracle(p)
+        pats = ST.factor_patterns(p)
+        ST.condense_patterns(pats)
+        pb = ST.create_problem(p)
+        f = ST.loads_to_device(p)
+        rc = R.block_krylov_solve(pb, pats, f, 1, tol=1e-10, max_it=2000, method=R.CLASSICAL,
+                                  precond=R.PRECOND_DIRICHLET)
+        rb = R.block_krylov_solve(pb, pats, f, 1, tol=1e-10, max_it=2000, method=R.ORTHODIR,
+                                  precond=R.PRECOND_DIRICHLET, periodic=True)
+        _, _, sc = o.solve("classical", tol=1e-10, precond="dirichlet")
+        _, _, sb = o.solve("block", tol=1e-10, precond="dirichlet")
+        print(f"[random-spd-ring{n_occ}] classical {rc.stats['iterations']} (oracle {sc['iterations'][0]}), "
+              f"multivector {rb.stats['iterations']} (oracle {sb['iterations']})", flush=True)
+        assert abs(rc.stats["iterations"] - sc["iterations"][0]) <= 2
+        assert abs(rb.stats["iterations"] - sb["iterations"]) <= 2
+        saving[n_occ] = 1.0 - rb.stats["iterations"] / rc.stats["iterations"]
+    assert saving[5] > 0.3 and saving[9] > saving[5], saving
