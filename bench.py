@@ -36,6 +36,12 @@ WORKLOADS = {
     "elast-12cube-4x4x4": (1, "orthodir", "3-D elasticity, 12^3-brick pattern x 64 occurrences (4x4x4), "
                                           "1 load case, 8 permutations", dict(max_blocks=0, inner_tol=1e-4)),
     "heat-row-16x16x4": (0, "orthodir", "2-D heat, 16x16 pattern x 4 (row)", dict(max_blocks=0, inner_tol=1e-4)),
+    # a truly periodic ring (the same interior bottom nodes clamped in every sector), for the periodic
+    # shortcut: run with --periodic and without
+    "ring-elast-periodic-16x12x32x8": ("ring-periodic", "orthodir", "3-D elasticity, ring of 16 rotated "
+                                       "annular sectors of 12x32x8 hex, interior bottom nodes of every "
+                                       "sector clamped, 1 load case, 16 permutations (all ring shifts)",
+                                       dict(max_blocks=0, inner_tol=1e-4)),
     "uneven-plate48-sector16-base16": (3, "orthodir", "3-D elasticity, uneven batch: 24x8x2 plates x 48 (7.5 deg "
                                                       "steps), 16x6x4 ring sectors x 16, one 16^3 base block; "
                                                       "1 load case, 8 permutations",
@@ -63,6 +69,8 @@ def main():
     ap.add_argument("--precond-extra", default="dirichlet",
                     help="comma list of preconditioners (lumped, dirichlet) also timed for every form and reported "
                          "under 'preconditioned' (empty: none)")
+    ap.add_argument("--periodic", action="store_true",
+                    help="periodic shortcut of the multivector product (truly periodic workloads only)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-it", type=int, default=3000)
     ap.add_argument("--max-blocks", type=int, default=None, help="ORTHODIR restart length (default per workload)")
@@ -104,7 +112,10 @@ def main():
         log(f"[bench] calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written per launch")
         del a, b
     log(f"[bench] generating {args.workload}")
-    p = W.config(cfg_idx)
+    if cfg_idx == "ring-periodic":
+        p = W.ring_elast(16, (12, 32, 8), r_in=1.0, r_out=1.5, height=0.5, clamp="periodic", n_perm=16, n_rhs=1)
+    else:
+        p = W.config(cfg_idx)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
 
     # ---------------- untimed: structure maps and device-resident inputs
@@ -128,7 +139,7 @@ def main():
                 R.pattern_condense(P, prec)
         res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=args.tol, max_it=args.max_it, method=method,
                                    prec=prec, inner_tol=settings["inner_tol"], max_blocks=settings["max_blocks"],
-                                   lam_out=lam, u_out=u, precond=pc)
+                                   lam_out=lam, u_out=u, precond=pc, periodic=args.periodic)
         for P in pats:
             P.free()
         return res
@@ -222,7 +233,7 @@ def main():
         "dtype": "f64" if head == "fp64" else ("f32+f64" if head == "fp32" else "bf16+f64"),
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "form": head, "method": method_name,
-                   "precond": args.precond,
+                   "precond": args.precond, "periodic": args.periodic,
                    "max_blocks": settings["max_blocks"], "inner_tol": settings["inner_tol"],
                    "n_lambda": pb.n_lambda, "n_occ": p.n_occ, "n_rhs": p.n_rhs, "n_perm": p.n_perm,
                    "pattern_dofs": [pat.n for pat in p.patterns], "pattern_boundary_dofs": [pat.n_b for pat in p.patterns],
@@ -244,7 +255,7 @@ def main():
     if extra:
         out["preconditioned"] = extra
 
-    if args.cpu:
+    if args.cpu and isinstance(cfg_idx, int):
         # the oracle computes in FP64: it is timed for the FP64 form's iteration count when measured
         it_ref = results.get("fp64", hr)["stats"]["iterations"]
         out["cpu_baseline"] = cpu_baseline(p, cfg_idx, it_ref, args.cpu_iterations, args.tol)
