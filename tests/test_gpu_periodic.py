@@ -124,3 +124,24 @@ def test_random_spd_ring_iteration_study(R):
         assert abs(rb.stats["iterations"] - sb["iterations"]) <= 2
         saving[n_occ] = 1.0 - rb.stats["iterations"] / rc.stats["iterations"]
     assert saving[5] > 0.3 and saving[9] > saving[5], saving
+
+
+@pytest.mark.parametrize("n_occ", [3, 4])
+def test_enriched_multivector(R, n_occ):
+    """The two-stand donut's enriched multivector (section 5.1.2): product permutations of the ring
+    and stand interfaces, permuted exactly on the GPU, and solved to the oracle's displacements."""
+    from paper_1208_6387_amd import structure as ST
+    p = W.ring_heat(n_occ, (6, 6), stands=(1, 0), enriched=True, n_rhs=2, dirichlet_bottom=True)
+    print(f"\n[enriched ring{n_occ}-2stands] n_lambda={p.n_lambda} n_perm={p.n_perm}", flush=True)
+    o = O.FetiOracle(p)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats)
+    pb = ST.create_problem(p)
+    Z = np.random.default_rng(3).standard_normal((p.n_lambda, 2))
+    Wg = R.feti_permute(pb, torch.from_numpy(Z).cuda()).cpu().numpy()
+    ref = o.permute(Z)
+    assert np.abs(Wg - ref).max() <= 1e-14 * np.abs(ref).max()
+    res = R.block_krylov_solve(pb, pats, ST.loads_to_device(p), p.n_rhs, tol=1e-11, max_it=2000,
+                               method=R.ORTHODIR)
+    _, u_o, st = o.solve("block", tol=1e-12)
+    assert _err(p, res, u_o) < 1e-8, res.stats

@@ -579,3 +579,45 @@ def test_periodic_shortcut_on_a_non_periodic_structure_is_wrong():
     ub, _, _, _ = O.global_solve(p)
     u = o.recover(lb, d, g)
     assert max(np.abs(x - y).max() for x, y in zip(u, ub)) > 1e-3 * max(np.abs(y).max() for y in ub)
+
+
+# ----------------------------------------------------------------------------- enriched multivector (section 5.1.2)
+
+def _paper_label(p, m):
+    """Interface label of multiplier m in the paper's numbering of the two-stand donut: ring pieces
+    1, 2, 3 are occurrences 0, 1, 2; stand 4 (on piece 2) is occurrence 3, stand 5 (on piece 1) is 4."""
+    a, b = (int(x) + 1 for x in p.mult_occ[m])
+    return f"{min(a, b)}{max(a, b)}" if {a, b} != {1, 3} else "31"
+
+
+def test_two_stand_enriched_multivector(golden_dir):
+    gold = json.load(open(os.path.join(golden_dir, "two_stand_multivector.json")))
+    p = W.ring_heat(3, (4, 4), stands=(1, 0), enriched=True)
+    assert p.n_perm == 6
+    o = O.FetiOracle(p)
+    labels = [_paper_label(p, m) for m in range(p.n_mult_nodes)]
+    code = {lab: float(i + 1) for i, lab in enumerate(gold["w"])}
+    w = np.array([[code.get(lab, 100.0 + m)] for m, lab in enumerate(labels)])
+    Wt = o.permute(w)
+    orbit = [len(set(p.perm_node[:, m])) for m in range(p.n_mult_nodes)]
+    checked = set()
+    for m, lab in enumerate(labels):
+        if lab not in code or orbit[m] != (3 if lab in ("12", "23", "31") else 2):
+            continue                     # corner links of the chains are classes of their own
+        row = gold["w"].index(lab)
+        for c in range(6):
+            assert Wt[m, c] == code[gold["w_tilde"][row][c]], (lab, c)
+        checked.add(lab)
+    assert checked == set(gold["w"])
+
+
+def test_enriched_multivector_solution():
+    """The enriched multivector (product of the ring and stand shifts) solves the same problem; with
+    four ring pieces it has 8 columns where the synchronised shifts give 4."""
+    for enriched in (False, True):
+        p = W.ring_heat(4, (6, 6), stands=(1, 0), enriched=enriched, n_rhs=2, dirichlet_bottom=True)
+        assert p.n_perm == (8 if enriched else 4)
+        o = O.FetiOracle(p)
+        ub, _, _, _ = O.global_solve(p)
+        _, u, st = o.solve("block", tol=1e-11)
+        assert max(np.abs(a - b).max() for a, b in zip(u, ub)) < 1e-9 * max(np.abs(b).max() for b in ub)

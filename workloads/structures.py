@@ -159,8 +159,14 @@ def pattern_boundaries(patterns, occ_pattern, mult_occ, mult_node):
         pat.bnodes = np.unique(np.concatenate(sel)).astype(np.int32)
 
 
-def permutation_maps(occ_pattern, mult_occ, mult_node, n_perm):
-    """Cyclic shifts within classes of equivalent multipliers (section 4.1 and 5.1 examples)."""
+def permutation_maps(occ_pattern, mult_occ, mult_node, n_perm, product=False):
+    """Cyclic shifts within classes of equivalent multipliers (section 4.1 and 5.1 examples).
+
+    product=False: Pi_k shifts every class by k.  product=True (the enriched multivector of the
+    two-stand donut, section 5.1.2): the classes are grouped by the pair of patterns they join, each
+    group gets its own shift digit, and the rows run over every combination of digits (the first
+    group, the one with the largest classes, varying fastest); n_perm None takes them all.
+    """
     n = mult_occ.shape[0]
     pa = occ_pattern[mult_occ[:, 0]]
     pb = np.where(mult_occ[:, 1] >= 0, occ_pattern[np.maximum(mult_occ[:, 1], 0)], -1)
@@ -174,17 +180,40 @@ def permutation_maps(occ_pattern, mult_occ, mult_node, n_perm):
     start = np.concatenate([[0], np.cumsum(sizes)[:-1]])
     pos = np.empty(n, np.int64)
     pos[order] = np.arange(n) - start[cls[order]]
+    if not product:
+        perm = np.empty((n_perm, n), np.int32)
+        for k in range(n_perm):
+            src_pos = (pos + k) % sizes[cls]
+            perm[k] = order[start[cls] + src_pos]
+        return perm
+    # groups of classes by the pair of patterns they join, largest classes first
+    kind_of = {}
+    for m_ in range(n):
+        kind_of.setdefault(int(cls[m_]), (int(pa[m_]), int(pb[m_])))
+    base = {}
+    for c_, kd in kind_of.items():
+        base[kd] = max(base.get(kd, 1), int(sizes[c_]))
+    kinds = sorted(base, key=lambda kd: (-base[kd], kd))
+    radix = [base[kd] for kd in kinds]
+    total = int(np.prod(radix))
+    n_perm = total if n_perm is None else min(n_perm, total)
+    kidx = np.array([kinds.index(kind_of[int(c_)]) for c_ in cls], np.int64)
     perm = np.empty((n_perm, n), np.int32)
-    for k in range(n_perm):
+    for r in range(n_perm):
+        digits, q = [], r
+        for b in radix:
+            digits.append(q % b)
+            q //= b
+        k = np.asarray(digits, np.int64)[kidx]
         src_pos = (pos + k) % sizes[cls]
-        perm[k] = order[start[cls] + src_pos]
+        perm[r] = order[start[cls] + src_pos]
     return perm
 
 
 # --------------------------------------------------------------------------- builders
 
 def _finish(name, dpn, patterns, occ_pattern, occ_rot, occ_gnode, n_gnodes, dirichlet_g,
-            f_local, n_rhs, n_perm, tol, meta, swap_rule=None):
+            f_local, n_rhs, n_perm, tol, meta, swap_rule=None, product_perm=False):
     occ_pattern = np.asarray(occ_pattern, np.int32)
     occ = np.concatenate([np.full(len(g), s) for s, g in enumerate(occ_gnode)])
     ln = np.concatenate([np.arange(len(g)) for g in occ_gnode])
@@ -193,7 +222,7 @@ def _finish(name, dpn, patterns, occ_pattern, occ_rot, occ_gnode, n_gnodes, diri
     isd[dirichlet_g] = True
     mo, mn, ms = chain_multipliers(occ, ln, gn, isd, swap_rule)
     pattern_boundaries(patterns, occ_pattern, mo, mn)
-    perm = permutation_maps(occ_pattern, mo, mn, n_perm)
+    perm = permutation_maps(occ_pattern, mo, mn, n_perm, product=product_perm)
     return Problem(name=name, dpn=dpn, patterns=patterns, occ_pattern=occ_pattern,
                    occ_rot=np.asarray(occ_rot, float), occ_gnode=[np.asarray(g, np.int64) for g in occ_gnode],
                    n_gnodes=int(n_gnodes), dirichlet_gnodes=np.asarray(dirichlet_g, np.int64),
@@ -269,11 +298,17 @@ def grid_structure(name, kind, pat_shape, pat_size, grid, n_rhs=1, n_perm=1, loa
                    f_local, n_rhs, n_perm, tol, meta)
 
 
-def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed=1, dirichlet_bottom=False):
+def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed=1, dirichlet_bottom=False,
+              stands=None, enriched=False):
     """Periodic ring of unit-square heat patterns (section 3's toy problem, cut open as a strip
     whose last right edge is glued to the first left edge).  Interface (s, s+1) has the right edge
     of s as its '+' side.  stand=True adds one stand pattern (a 1 x 1/2 rectangle) on top of
-    occurrence n_occ-1 (section 5.1.1).  dirichlet_bottom fixes the bottom edge of occurrence 0;
+    occurrence n_occ-1 (section 5.1.1).  stands: ring occurrences that each carry a stand, in the
+    order of the stand occurrences (section 5.1.2 puts two stands on ring pieces 2 and 1: stands=
+    (1, 0)); every stand has its own nodes apart from its base edge.  enriched=True builds the
+    product permutations of the enriched multivector (independent shifts of the ring interfaces
+    and of the stand interfaces; n_perm None takes all of them).  dirichlet_bottom fixes the bottom
+    edge of occurrence 0;
     dirichlet_bottom="periodic" fixes the bottom-edge nodes off the interfaces of every ring
     occurrence, which keeps the ring truly periodic.
     """
@@ -288,17 +323,21 @@ def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed
         occ_gnode.append(gx + W * mesh.lattice[:, 1])
     occ_pattern = [0] * n_occ
     n_g = W * (ny + 1)
-    if stand:
+    if stands is None:
+        stands = (n_occ - 1,) if stand else ()
+    if len(stands):
         smesh = M.GridMesh((nx, max(ny // 2, 1)), (1.0, 0.5))
         Ks = M.assemble(smesh, M.quad_laplace(*smesh.h), 1)
         pats.append(Pattern("stand-pattern", 1, smesh.coords, Ks, 1))
-        s_last = n_occ - 1
-        gx = (smesh.lattice[:, 0] + s_last * nx) % W
         iy = smesh.lattice[:, 1]
-        gid = np.where(iy == 0, gx + W * ny, n_g + gx + W * (iy - 1))
-        occ_gnode.append(gid)
-        occ_pattern.append(1)
-        n_g = n_g + W * smesh.shape[1]
+        ix = smesh.lattice[:, 0]
+        per_stand = (nx + 1) * smesh.shape[1]
+        for j, s_on in enumerate(stands):
+            gx = (ix + s_on * nx) % W
+            own = n_g + j * per_stand + ix + (nx + 1) * (iy - 1)
+            occ_gnode.append(np.where(iy == 0, gx + W * ny, own))
+            occ_pattern.append(1)
+        n_g = n_g + len(stands) * per_stand
     if dirichlet_bottom == "periodic":
         # the bottom-edge nodes of every ring occurrence off its interfaces (truly periodic)
         gx = np.arange(W)
@@ -317,10 +356,12 @@ def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed
         ring = (oa < n_occ) & (ob < n_occ)
         return ring & (la % (nx + 1) == 0) & (lb % (nx + 1) == nx)
 
-    meta = dict(kind="heat", ring=n_occ, stand=stand, grid=(n_occ,), pat_shape=pat_shape)
-    return _finish(f"ring{n_occ}{'-stand' if stand else ''}", 1, pats, occ_pattern, rot, occ_gnode,
-                   n_g, dir_g, f_local, n_rhs, n_perm if n_perm is not None else n_occ, 1e-10, meta,
-                   swap_rule=swap)
+    meta = dict(kind="heat", ring=n_occ, stand=bool(len(stands)), stands=tuple(stands), grid=(n_occ,),
+                pat_shape=pat_shape)
+    if n_perm is None and not enriched:
+        n_perm = n_occ
+    return _finish(f"ring{n_occ}{'-stand' * len(stands)}", 1, pats, occ_pattern, rot, occ_gnode,
+                   n_g, dir_g, f_local, n_rhs, n_perm, 1e-10, meta, swap_rule=swap, product_perm=enriched)
 
 
 def mirror_row_heat(n_occ=2, pat_shape=(4, 4), reaction=0.1, n_rhs=1, seed=2):
