@@ -183,6 +183,64 @@ def test_config4_operator_forms(R):
         assert (Z - FX).abs().max().item() <= tol * scale, prec
 
 
+@pytest.mark.parametrize("kind,form,tol", [("dirichlet", "fp64", 1e-12), ("dirichlet", "bf16x3", 5e-5),
+                                           ("lumped", "fp64", 1e-12)])
+@pytest.mark.parametrize("ncol", [8, 97])
+def test_config2_preconditioner(config2, R, kind, form, tol, ncol):
+    """The preconditioners at 64 occurrences against the oracle's F~^{-1}: 8 columns as in the
+    solves, 97 for the large-tile product kernels (ragged 256 x 256 bf16 tiles, 128 x 128 FP64
+    tiles) running with S in place of S+."""
+    p, o, pats, pb = config2
+    prec = R.FP64 if form == "fp64" else R.BF16X3
+    k = R.PRECOND_DIRICHLET if kind == "dirichlet" else R.PRECOND_LUMPED
+    X = np.random.default_rng(300 + ncol).standard_normal((p.n_lambda, ncol))
+    Y = R.feti_precond(pb, pats, torch.from_numpy(X).cuda(), k, prec=prec).cpu().numpy()
+    ref = o.precondition(X, kind)
+    err = np.abs(Y - ref).max() / np.abs(ref).max()
+    assert err <= tol and (form == "fp64" or err > 0.0), (kind, form, err)
+
+
+def test_config4_preconditioned(R):
+    """512 occurrences with the Dirichlet preconditioner, as bench.py times it: the operator is
+    symmetric and positive (x^T F~^{-1} x > 0 off the kernel of A^T), its bf16x3 form agrees with the
+    FP64 one, and the preconditioned mixed block-CG solution satisfies continuity, the clamped face
+    and local equilibrium on sampled occurrences."""
+    from paper_1208_6387_amd import structure as ST
+    p = W.config(4)
+    print("\n[fullsize] 512 x 20^3 bricks, Dirichlet preconditioner", flush=True)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats, (R.FP64, R.BF16X3))
+    pb = ST.create_problem(p)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    X = torch.randn(pb.n_lambda, 16, dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.randn(pb.n_lambda, 16, dtype=torch.float64, device="cuda", generator=g)
+    MX = R.feti_precond(pb, pats, X, R.PRECOND_DIRICHLET)
+    MY = R.feti_precond(pb, pats, Y, R.PRECOND_DIRICHLET)
+    a = (Y * MX).sum(0)
+    b = (X * MY).sum(0)
+    assert torch.max(torch.abs(a - b) / torch.abs(a)).item() < 1e-11
+    assert torch.min((X * MX).sum(0)).item() > 0.0
+    Z = R.feti_precond(pb, pats, X, R.PRECOND_DIRICHLET, prec=R.BF16X3)
+    assert (Z - MX).abs().max().item() <= 5e-5 * MX.abs().max().item()
+    res = R.block_krylov_solve(pb, pats, ST.loads_to_device(p), p.n_rhs, tol=1e-8, max_it=3000,
+                               method=R.BLOCK_CG, prec=R.BF16X3, inner_tol=1e-4, max_blocks=48,
+                               precond=R.PRECOND_DIRICHLET)
+    assert res.stats["rel_residual"] <= 1e-8
+    assert res.stats["iterations"] < 80, res.stats
+    lam = res.lam.cpu().numpy()
+    u = ST.split_u(p, res.u)
+    scale = max(np.abs(x).max() for x in u)
+    assert _continuity_gap(p, u) <= 1e-6 * scale
+    dsel = np.nonzero(p.mult_occ[:, 1] < 0)[0]
+    ud = _stack_u(p, u)[p.mult_occ[dsel, 0], p.mult_node[dsel, 0]]
+    assert np.abs(ud).max() <= 1e-6 * scale
+    pat = p.patterns[0]
+    rng = np.random.default_rng(1)
+    for s in rng.choice(p.n_occ, 8, replace=False):
+        res_s = pat.K @ u[s] - p.f_local[s] + _local_forces(p, lam, s, pat)
+        assert np.abs(res_s).max() <= 1e-8 * np.abs(p.f_local[s]).max(), s
+
+
 @pytest.fixture(scope="module")
 def config3(R):
     from paper_1208_6387_amd import structure as ST
