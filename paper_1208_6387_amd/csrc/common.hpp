@@ -191,9 +191,10 @@ void rows_gemm_from(hipStream_t s, int64_t N, int a, int b, double alpha, const 
 // workspace).  Returns false, doing nothing, when the block is too wide.
 // C = alpha A B (+ beta C) on the large-problem FP64 kernel (the flexibility product): column-major,
 // M and lda even, A and B 16-byte aligned, ldb a multiple of 32 with B's rows K .. ldb zero in
-// every column.  Returns false (nothing launched) when those conditions do not hold.
+// every column.  lower: only the tiles that reach the lower triangle of C are computed.  Returns
+// false (nothing launched) when those conditions do not hold.
 bool dgemm_flex(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-                const double* B, int64_t ldb, double beta, double* C, int64_t ldc);
+                const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool lower = false);
 // Z = R - X M1 (b columns) and Lam += X M2 (c columns) from one read of X (N x a); a, b, c <= 16,
 // M1 and M2 column-major with a rows.  Returns false (nothing launched) for other shapes.
 bool rows_orth_lam(hipStream_t s, int64_t N, int a, int b, int c, const double* X, int64_t ldx, const double* M1,

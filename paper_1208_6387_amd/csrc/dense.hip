@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
 template <bool BETA>
 __global__ __launch_bounds__(512) void k_dgemm_big(int M, int N, int K, double alpha, const double* __restrict__ A,
                                                    int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
-                                                   double* __restrict__ C, int64_t ldc) {
+                                                   double* __restrict__ C, int64_t ldc, int lower) {
   constexpr int BK = 32, RA = 128 + 16, SA = BK * RA, SB = 128 * BK;
   __shared__ __attribute__((aligned(1024))) double lA0[SA];
   __shared__ __attribute__((aligned(1024))) double lA1[SA];
@@ -149,6 +149,8 @@ __global__ __launch_bounds__(512) void k_dgemm_big(int M, int N, int K, double a
   int tx, ty;
   xcd_tile(gridDim.x, gridDim.y, tx, ty);
   const int m0 = tx * 128, n0 = ty * 128;
+  // lower: only tiles that reach the lower triangle (n <= m somewhere) are computed
+  if (lower && n0 > m0 + 127) return;
   const int nst = (K + BK - 1) / BK;
   // loads of a stage: wave w takes A k-rows 4w .. 4w + 3 (lane l: doubles m0 + 2l, 2l + 1) and
   // B blocks 4w .. 4w + 3 of four n-rows (lane l: n-row l / 16, chunk (l % 16) ^ (n % 16))
@@ -226,17 +228,17 @@ __global__ __launch_bounds__(512) void k_dgemm_big(int M, int N, int K, double a
 
 
 bool dgemm_flex(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-                const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
+                const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool lower) {
   if (M < 2 || N < 1 || K < 1 || (M & 1) || (lda & 1) || (ldb % 32) || K > ldb || M > INT32_MAX || N > INT32_MAX ||
       ((uintptr_t)A & 15) || ((uintptr_t)B & 15))
     return false;
   const dim3 grid((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128));
   if (beta == 0.0)
     RPF_TIMED_LAUNCH((k_dgemm_big<false>), grid, dim3(512), 0, s, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
-                     C, ldc);
+                     C, ldc, lower ? 1 : 0);
   else
     RPF_TIMED_LAUNCH((k_dgemm_big<true>), grid, dim3(512), 0, s, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
-                     C, ldc);
+                     C, ldc, lower ? 1 : 0);
   RPF_LAUNCH_CHECK();
   return true;
 }
@@ -1390,11 +1392,16 @@ Envelope Envelope::dense(int64_t n) {
 // one rank-PANEL update once the panel is done, so the trailing matrix and the boundary rows are
 // read and written once per panel instead of once per step, by GEMMs with K = PANEL (compute-bound
 // instead of memory-bound).  The result is the same factor (the updates of one column commute).
+bool gemm_nt_flex(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* X, int64_t ldx,
+                  const double* Y, int64_t ldy, double beta, double* C, int64_t ldc, bool lower, DevBuf<double>& wa,
+                  DevBuf<double>& wb);
+
 void potrf(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac, const Envelope& env, double* dinv,
            int* status) {
   constexpr int64_t PANEL = 4 * NB;
   const int64_t nblk = cdiv(n_fac, NB);
   RPF_CHECK((int64_t)env.rend.size() >= nblk, RPF_EINVAL, "potrf: envelope too short");
+  DevBuf<double> wa, wb;  // operand copies of the large rank-PANEL updates
   for (int64_t P0 = 0; P0 < n_fac; P0 += PANEL) {
     const int64_t P1 = std::min<int64_t>(P0 + PANEL, n_fac);
     int64_t pend = P1;  // rows (and columns) reached by the panel's envelope
@@ -1427,20 +1434,76 @@ void potrf(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac, cons
     if (pend > P1) {
       const int64_t K = P1 - P0;
       double* pc = A + P0 * lda;
-      dgemm(s, false, true, pend - P1, pend - P1, K, -1.0, pc + P1, lda, pc + P1, lda, 1.0, A + P1 * lda + P1, lda,
-            true);
-      if (n > n_fac)
+      if (!gemm_nt_flex(s, pend - P1, pend - P1, K, -1.0, pc + P1, lda, pc + P1, lda, 1.0, A + P1 * lda + P1, lda, true,
+                        wa, wb))
+        dgemm(s, false, true, pend - P1, pend - P1, K, -1.0, pc + P1, lda, pc + P1, lda, 1.0, A + P1 * lda + P1, lda,
+              true);
+      if (n > n_fac &&
+          !gemm_nt_flex(s, n - n_fac, pend - P1, K, -1.0, pc + n_fac, lda, pc + P1, lda, 1.0, A + P1 * lda + n_fac, lda,
+                        false, wa, wb))
         dgemm(s, false, true, n - n_fac, pend - P1, K, -1.0, pc + n_fac, lda, pc + P1, lda, 1.0, A + P1 * lda + n_fac,
               lda);
     }
   }
+  RPF_HIP(hipStreamSynchronize(s));  // the operand copies are freed on return
+}
+
+// Bt[j ldb + k] = X[j + k ldx] for j < rows, k < cols, and 0 for cols <= k < ldb: the transpose of a
+// column-major rows x cols block with zero-padded rows, through 64 x 64 LDS tiles (coalesced on
+// both sides).  Grid: (cdiv(ldb, 64), cdiv(rows, 64)).
+__global__ __launch_bounds__(256) void k_transpose_pad(int64_t rows, int64_t cols, const double* X, int64_t ldx,
+                                                       double* Bt, int64_t ldb) {
+  __shared__ double t[64][65];
+  const int64_t k0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t k = k0 + r, j = j0 + tx;
+    t[r][tx] = (k < cols && j < rows) ? X[j + k * ldx] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t j = j0 + r, k = k0 + tx;
+    if (j < rows && k < ldb) Bt[j * ldb + k] = t[tx][r];
+  }
+}
+
+// C = alpha X Y^T + beta C (X: M x K, Y: N x K, column-major) on the large-problem kernel when the
+// shape is large enough: X is used in place when its layout allows it (else copied with an even
+// leading dimension), Y^T is copied with k-contiguous rows padded to 32.  wa, wb: grow-only
+// workspaces kept by the caller across calls.  Returns false (nothing launched) for small shapes.
+bool gemm_nt_flex(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* X, int64_t ldx,
+                  const double* Y, int64_t ldy, double beta, double* C, int64_t ldc, bool lower, DevBuf<double>& wa,
+                  DevBuf<double>& wb) {
+  if (M < 1024 || (M & 1) || N < 128 || K < 64 || M > INT32_MAX || N > INT32_MAX) return false;
+  const double* Ause = X;
+  int64_t lda = ldx;
+  if ((ldx & 1) || ((uintptr_t)X & 15)) {
+    wa.ensure((size_t)M * K);
+    copy_matrix(s, X, ldx, wa.p, M, M, K);
+    Ause = wa.p;
+    lda = M;
+  }
+  const int64_t ldb = cdiv(K, 32) * 32;
+  wb.ensure((size_t)N * ldb);
+  hipLaunchKernelGGL(k_transpose_pad, dim3((unsigned)cdiv(ldb, 64), (unsigned)cdiv(N, 64)), dim3(256), 0, s, N, K, Y,
+                     ldy, wb.p, ldb);
+  RPF_LAUNCH_CHECK();
+  return dgemm_flex(s, M, N, K, alpha, Ause, lda, wb.p, ldb, beta, C, ldc, lower);
 }
 
 void schur_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac) {
   const int64_t nb = n - n_fac;
   if (nb <= 0 || n_fac <= 0) return;
-  dgemm(s, false, true, nb, nb, n_fac, -1.0, A + n_fac, lda, A + n_fac, lda, 1.0, A + n_fac * lda + n_fac, lda,
-        true);
+  const double* Lbi = A + n_fac;  // boundary rows of the factor, nb x n_fac with ld lda
+  // lower tiles only: S is symmetric and only its lower triangle is read afterwards
+  DevBuf<double> wa, wb;
+  const bool done = gemm_nt_flex(s, nb, nb, n_fac, -1.0, Lbi, lda, Lbi, lda, 1.0, A + n_fac * lda + n_fac, lda, true,
+                                 wa, wb);
+  if (done) {
+    RPF_HIP(hipStreamSynchronize(s));  // the copies are freed on return
+    return;
+  }
+  dgemm(s, false, true, nb, nb, n_fac, -1.0, Lbi, lda, Lbi, lda, 1.0, A + n_fac * lda + n_fac, lda, true);
 }
 
 // Panel triangular solve for many right-hand sides: one workgroup owns PW = 16 H columns of B and

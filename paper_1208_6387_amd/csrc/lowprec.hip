@@ -118,19 +118,42 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nbn, const int* occ_lis
       }
     }
     __syncthreads();
-    for (int e = tid; e < JW * nd; e += 256) {
-      const int jj = e / nd, t = e - jj * nd;
-      if (j0 + jj < m) {
-        const double v = tile[jj][t];
-        const int64_t o = ((int64_t)q * m + j0 + jj) * ldx + (int64_t)n0 * DPN + t;
-        if (MODE == 2) {
-          X64[o] = v;
-        } else if (MODE == 0) {
-          Xf[o] = (float)v;
-        } else {
-          const uint16_t h = bf16_bits((float)v);
-          Xh[o] = h;
-          Xl[o] = bf16_bits((float)(v - (double)bf16_val(h)));
+    if (MODE == 1 && nd % 4 == 0 && ldx % 4 == 0) {
+      // bf16 hi/lo: four consecutive dofs per thread, one 8-byte store per array (n0 DPN and ldx are
+      // multiples of 4, so every group of four starts 8-byte aligned)
+      const int nd4 = nd / 4;
+      for (int e = tid; e < JW * nd4; e += 256) {
+        const int jj = e / nd4, t = 4 * (e - jj * nd4);
+        if (j0 + jj < m) {
+          const int64_t o = ((int64_t)q * m + j0 + jj) * ldx + (int64_t)n0 * DPN + t;
+          uint16_t h[4], l[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double v = tile[jj][t + r];
+            h[r] = bf16_bits((float)v);
+            l[r] = bf16_bits((float)(v - (double)bf16_val(h[r])));
+          }
+          *reinterpret_cast<uint2*>(Xh + o) = uint2{(uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                                    (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
+          *reinterpret_cast<uint2*>(Xl + o) = uint2{(uint32_t)l[0] | ((uint32_t)l[1] << 16),
+                                                    (uint32_t)l[2] | ((uint32_t)l[3] << 16)};
+        }
+      }
+    } else {
+      for (int e = tid; e < JW * nd; e += 256) {
+        const int jj = e / nd, t = e - jj * nd;
+        if (j0 + jj < m) {
+          const double v = tile[jj][t];
+          const int64_t o = ((int64_t)q * m + j0 + jj) * ldx + (int64_t)n0 * DPN + t;
+          if (MODE == 2) {
+            X64[o] = v;
+          } else if (MODE == 0) {
+            Xf[o] = (float)v;
+          } else {
+            const uint16_t h = bf16_bits((float)v);
+            Xh[o] = h;
+            Xl[o] = bf16_bits((float)(v - (double)bf16_val(h)));
+          }
         }
       }
     }
