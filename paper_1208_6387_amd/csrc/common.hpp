@@ -237,6 +237,9 @@ void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* 
           const Envelope& env, double* B, int64_t ldb, int64_t nrhs, bool trans);
 
 // fill / copy helpers
+// Y = (L L^T)^{-1} (full, symmetric) from a dense lower Cholesky factor and its inverted diagonal blocks
+void potri_lower(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* dinv, double* Y,
+                 int64_t ldy);
 void fill(hipStream_t s, double* p, int64_t count, double v);
 void fill_matrix(hipStream_t s, double* p, int64_t rows, int64_t cols, int64_t ld, double v);
 void copy_matrix(hipStream_t s, const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,

@@ -1713,6 +1713,50 @@ void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* 
   }
 }
 
+// Y = (L L^T)^{-1} from a dense lower Cholesky factor L (n x n, ld ldl) and its inverted diagonal
+// blocks: the forward solve L X = I, then L^T Y = X, skipping what is known to be zero or not
+// needed.  X = L^{-1} is lower triangular, so block row t of the forward solve only involves the
+// columns left of its diagonal block and the diagonal block itself; Y is symmetric, so the backward
+// solve forms its lower triangle only (block row t: the columns up to its diagonal block, which need
+// only lower-triangle entries of the rows below), and the upper triangle is mirrored at the end.
+// Same arithmetic as the full solves with identity right-hand sides, about a quarter of the flops.
+void potri_lower(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* dinv, double* Y,
+                 int64_t ldy) {
+  if (n <= 0) return;
+  const int64_t nblk = cdiv(n, NB);
+  fill_matrix(s, Y, n, n, ldy, 0.0);
+  add_diag(s, Y, ldy, n, 1.0);
+  DevBuf<double> ws;
+  auto update = [&](bool ta, int jb, int64_t ncol, int64_t kdim, const double* A, const double* Bsrc, double* C) {
+    if (kdim <= 0 || ncol <= 0) return;
+    const int sp = gemm_splitk_count(jb, ncol, kdim);
+    if (sp > 1) {
+      ws.ensure((size_t)sp * jb * ncol);
+      dgemm_splitk(s, ta, false, jb, ncol, kdim, -1.0, A, ldl, Bsrc, ldy, 1.0, C, ldy, ws.p, sp);
+    } else {
+      dgemm(s, ta, false, jb, ncol, kdim, -1.0, A, ldl, Bsrc, ldy, 1.0, C, ldy);
+    }
+  };
+  // forward: X_t = inv(L_tt) (I_t - L_t,prev X_prev), nonzero in columns [0, j0 + jb)
+  for (int64_t t = 0; t < nblk; ++t) {
+    const int64_t j0 = t * NB;
+    const int jb = (int)std::min<int64_t>(NB, n - j0);
+    update(false, jb, j0, j0, L + j0, Y, Y + j0);
+    // in place: the single row tile of this product reads all of its rows before writing them
+    dgemm(s, false, false, jb, j0 + jb, jb, 1.0, dinv + t * NB * NB, NB, Y + j0, ldy, 0.0, Y + j0, ldy);
+  }
+  // backward, lower triangle: Y_t = inv(L_tt)^T (X_t - L_below,t^T Y_below) in columns [0, j0 + jb)
+  for (int64_t t = nblk - 1; t >= 0; --t) {
+    const int64_t j0 = t * NB;
+    const int jb = (int)std::min<int64_t>(NB, n - j0);
+    const int64_t r0 = j0 + jb;
+    update(true, jb, j0 + jb, n - r0, L + j0 * ldl + r0, Y + r0, Y + j0);
+    dgemm(s, true, false, jb, j0 + jb, jb, 1.0, dinv + t * NB * NB, NB, Y + j0, ldy, 0.0, Y + j0, ldy);
+  }
+  mirror_lower(s, Y, ldy, n);
+  RPF_HIP(hipStreamSynchronize(s));  // the split-K workspace is freed on return
+}
+
 // ============================================================================ elementwise helpers
 __global__ void k_fill(double* p, int64_t count, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -320,10 +320,7 @@ extern "C" rpf_status pattern_condense(rpf_pattern p, int32_t prec, void* stream
       RPF_HIP(hipMemsetAsync(p->status.p, 0, sizeof(int), s));
       potrf(s, M.p, nb, nb, nb, env, dinv.p, p->status.p);
       p->Splus.alloc((size_t)nb * nb);
-      fill(s, p->Splus.p, (int64_t)nb * nb, 0.0);
-      add_diag(s, p->Splus.p, nb, nb, 1.0);
-      trsm(s, M.p, nb, nb, dinv.p, env, p->Splus.p, nb, nb, false);
-      trsm(s, M.p, nb, nb, dinv.p, env, p->Splus.p, nb, nb, true);
+      potri_lower(s, M.p, nb, nb, dinv.p, p->Splus.p, nb);
       if (p->k > 0) dgemm(s, false, true, nb, nb, p->k, -1.0, p->Z.p, nb, p->Z.p, nb, 1.0, p->Splus.p, nb);
       hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)cdiv((int64_t)nb * nb, 256)), dim3(256), 0, s, p->Splus.p,
                          (int64_t)nb, (int64_t)nb);
