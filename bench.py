@@ -213,7 +213,7 @@ def main():
         return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic_for(args.workload, form),
                 "kernel": {"fp64": "k_dgemm_big (FP64 MFMA 16x16x4, 128x128 tiles, eight waves)", "fp32": "k_sgemm_sym (FP32 MFMA 16x16x4)",
-                           "bf16x3": "k_gemm_bf16 X3 (bf16 MFMA 16x16x32, three products)",
+                           "bf16x3": "k_gemm_bf16_big X3 (bf16 MFMA 16x16x32, 256x256 tiles, three products)",
                            "bf16": "k_gemm_bf16 (bf16 MFMA 16x16x32)"}[form],
                 "avg_launch_ms": round(gemm_ms, 4), "gflop_per_launch": round(flops / 1e9, 4),
                 "launches_per_step": tr["count"] / args.steps,
