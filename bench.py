@@ -83,8 +83,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the path shards by occurrences but no multi-GPU form is built", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the path would shard by occurrences, but no multi-GPU form exists", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
