@@ -153,3 +153,26 @@ def test_solve_preconditioned_mixed(case, R, form, method):
     scale = max(np.abs(x).max() for x in u_o)
     err = max(np.abs(a - b).max() for a, b in zip(u, u_o)) / scale
     assert err < 1e-6, (form, method, err, res.stats)
+
+
+def test_precond_error_paths(R):
+    """Bad arguments come back as RPF_EINVAL with a message, nothing is launched."""
+    from paper_1208_6387_amd import structure as ST
+    p = W.small_elast((2, 2, 2), (2, 1, 1), n_rhs=1)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats)          # FP64 only
+    pb = ST.create_problem(p)
+    X = torch.zeros((p.n_lambda, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(R.RpfError, match="EINVAL.*kind"):
+        R.feti_precond(pb, pats, X, 3)
+    with pytest.raises(R.RpfError, match="EINVAL.*not condensed"):
+        R.feti_precond(pb, pats, X, R.PRECOND_DIRICHLET, prec=R.BF16X3)
+    with pytest.raises(R.RpfError, match="EINVAL"):
+        R.feti_precond(pb, None, X, R.PRECOND_LUMPED)
+    f = ST.loads_to_device(p)
+    with pytest.raises(R.RpfError, match="EINVAL.*preconditioner"):
+        R.block_krylov_solve(pb, pats, f, 1, tol=1e-8, max_it=50, precond=5)
+    # the periodic shortcut is ignored with a single permutation
+    res = R.block_krylov_solve(pb, pats, f, 1, tol=1e-10, max_it=200, method=R.BLOCK_CG, periodic=True,
+                               precond=R.PRECOND_LUMPED)
+    assert res.stats["rel_residual"] <= 1e-10
