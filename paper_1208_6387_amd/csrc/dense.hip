@@ -1317,7 +1317,9 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* Ag, int64_t lda, int
         if (e < rem * QB) {
           const int rr = r0 + e / QB, c = e % QB;
           double acc = 0.0;
-          for (int q = 0; q <= c; ++q) acc += A[rr][k0 + q] * W[k0 + c][k0 + q];
+          // fixed trip count (W is zero above its diagonal), so the LDS reads are issued together
+#pragma unroll
+          for (int q = 0; q < QB; ++q) acc += A[rr][k0 + q] * W[k0 + c][k0 + q];
           pv[u] = acc;
         }
       }
@@ -1351,6 +1353,8 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* Ag, int64_t lda, int
     for (int e = tid; e < ib * QB * QB; e += 256) {
       const int k = e / (QB * QB), rr = (e / QB) % QB, cc = e % QB;
       double acc = 0.0;
+      // the trip count is a multiple of 16: unrolled by 4, the LDS reads of four terms are in flight
+#pragma unroll 4
       for (int q = k * QB; q < ib * QB; ++q) acc += A[ib * QB + rr][q] * W[q][k * QB + cc];
       T[k][rr][cc] = acc;
     }
