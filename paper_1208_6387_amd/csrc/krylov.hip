@@ -821,8 +821,9 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
     project(pb, S.R.p, nr, nr, s);
     S.r0n = S.colnorm2(S.R.p, nr, nr);
+    const std::vector<double> r0raw = S.r0n;  // the first convergence test sees the true norms
     for (double& v : S.r0n)
-      if (!(v > 0.0)) v = 1.0;
+      if (!(v > 0.0)) v = 1.0;  // a zero initial residual: relative to 1 (nothing to reduce)
     st.ms_coarse = tc.stop();
 
     // ------------------------------------------------------------ iterations (+ FP64 refinement)
@@ -877,7 +878,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     }
     bool converged = false;
     int sweeps = 0;
-    std::vector<double> rn = S.r0n;
+    std::vector<double> rn = r0raw;
     double rel = 1.0;
     bool fresh = true;  // S.R holds the FP64 residual of the current lambda
     for (int sw = 0; sw < max_sweeps; ++sw) {

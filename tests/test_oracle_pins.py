@@ -621,3 +621,17 @@ def test_enriched_multivector_solution():
         ub, _, _, _ = O.global_solve(p)
         _, u, st = o.solve("block", tol=1e-11)
         assert max(np.abs(a - b).max() for a, b in zip(u, ub)) < 1e-9 * max(np.abs(b).max() for b in ub)
+
+
+def test_precond_single_occurrence_is_exact():
+    """One occurrence held by Dirichlet multipliers only: F = S+ on the pattern boundary and the
+    Dirichlet preconditioner is S, so F~^{-1} F = S S+ is the orthogonal projector on range S and the
+    preconditioned solve ends in one iteration."""
+    p = W.small_elast((3, 3, 3), (1, 1, 1), n_rhs=1, seed=4)
+    o = O.FetiOracle(p)
+    I = np.eye(p.n_lambda)
+    M = o.precondition(o.F(I), "dirichlet")
+    G = o.G.toarray()                       # A Z: orthonormal columns, A a signed permutation here
+    assert np.abs(M - (I - G @ G.T)).max() < 1e-11
+    _, _, st = o.solve("block", tol=1e-12, precond="dirichlet")
+    assert st["iterations"] == 1
