@@ -171,7 +171,9 @@ void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t
 // and Y (N x b, ldy); ws must hold gram_chunks(N, a, b) * a * b doubles.
 int gram_chunks(int64_t N, int a, int b);
 // C (a x (b1 + b2), column-major ld a) = X^T [Y1 | Y2]; one pass over X when a, b1, b2 <= 16.
-// ws must hold gram_chunks(N, a, 16) * a * (b1 + b2) doubles (and what two gram calls need).
+// ws must hold gram_pair_chunks(N) * a * (b1 + b2) doubles (and what two gram calls need).
+// chunks (and partial-sum slabs of a x (b1 + b2) each) of gram_pair over N rows when a, b1, b2 <= 16
+int gram_pair_chunks(int64_t N);
 void gram_pair(hipStream_t s, int64_t N, int a, const double* X, int64_t ldx, int b1, const double* Y1,
                int64_t ldy1, int b2, const double* Y2, int64_t ldy2, double* C, double* ws);
 void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy,

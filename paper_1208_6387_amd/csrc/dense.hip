@@ -549,6 +549,13 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
   RPF_LAUNCH_CHECK();
 }
 
+// rows per chunk of gram_pair: four workgroups per CU, since one wave per SIMD does not keep enough
+// loads in flight for this memory-bound pass (the partial sums are still reduced in a fixed order)
+static int64_t gram_pair_rows(int64_t N) {
+  return cdiv(N, std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(N, 256))));
+}
+int gram_pair_chunks(int64_t N) { return (int)cdiv(N, gram_pair_rows(N)); }
+
 void gram_pair(hipStream_t s, int64_t N, int a, const double* X, int64_t ldx, int b1, const double* Y1,
                int64_t ldy1, int b2, const double* Y2, int64_t ldy2, double* C, double* ws) {
   if (a <= 0 || b1 + b2 <= 0) return;
@@ -557,9 +564,8 @@ void gram_pair(hipStream_t s, int64_t N, int a, const double* X, int64_t ldx, in
     gram(s, N, a, b2, X, ldx, Y2, ldy2, C + (int64_t)a * b1, ws);
     return;
   }
-  const int g = gram_chunks(N, a, 16);
-  const int64_t chunk = cdiv(N, g);
-  const int gz = (int)cdiv(N, chunk);
+  const int64_t chunk = gram_pair_rows(N);
+  const int gz = gram_pair_chunks(N);
   hipLaunchKernelGGL(k_gram_pair, dim3((unsigned)gz), dim3(256), 0, s, N, a, X, ldx, b1, Y1, ldy1, b2, Y2, ldy2,
                      chunk, ws);
   RPF_LAUNCH_CHECK();

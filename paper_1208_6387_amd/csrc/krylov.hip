@@ -623,7 +623,7 @@ struct Solver {
       if (!per) apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, true, s);
       // [eta | Z^T R] = Z^T [P | R] in one pass over Z; T with T^T eta T = I on the kept directions
       {
-        const size_t need = std::max((size_t)gram_chunks(N, m, 16) * m * (m + nr),
+        const size_t need = std::max((size_t)gram_pair_chunks(N) * m * (m + nr),
                                      (size_t)gram_chunks(N, m, std::max(m, nr)) * m * std::max(m, nr));
         ws.ensure(need);
         gram_pair(s, N, m, Zs, ldW, m, Ps, ldW, nr, Rs.p, nr, eta.p, ws.p);
