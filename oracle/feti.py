@@ -126,7 +126,9 @@ class FetiOracle:
     values to the pattern frame.
     """
 
-    def __init__(self, problem, patterns: list | None = None):
+    def __init__(self, problem, patterns: list | None = None, coarse: str | None = None):
+        """coarse: None for the identity in the projector, or "lumped" / "dirichlet" for that
+        preconditioner as F~^{-1} in Q and lambda_0 (section 2)."""
         pb = problem
         self.pb = pb
         self.dpn = dpn = pb.dpn
@@ -151,6 +153,8 @@ class FetiOracle:
         self.GtG = (self.G.T @ self.G).toarray()
         self._GtG_cho = None
         self._AAt = self._AAt_lu = None
+        self.coarse = coarse
+        self._MG = self._H_cho = None
 
     # -- signed Boolean assembly (eq. 2) ------------------------------------------------
     def _assembly(self, s: int) -> sp.csr_matrix:
@@ -203,11 +207,33 @@ class FetiOracle:
             self._GtG_cho = sla.cho_factor(self.GtG)
         return sla.cho_solve(self._GtG_cho, c)
 
+    def _coarse_M(self):
+        """F~^{-1} G and the Cholesky factor of G^T F~^{-1} G (section 2, projector with a
+        preconditioner), formed once."""
+        if self._MG is None:
+            Gd = self.G.toarray()
+            self._MG = self.precondition(Gd, self.coarse)
+            H = Gd.T @ self._MG
+            self._H_cho = sla.cho_factor(0.5 * (H + H.T))
+        return self._MG, self._H_cho
+
     def Q(self, X: np.ndarray) -> np.ndarray:
-        """Q X = X - G (G^T G)^{-1} G^T X (identity preconditioner; Q = Q^T)."""
+        """Q X = X - F~^{-1} G (G^T F~^{-1} G)^{-1} G^T X (section 2); with the identity in place
+        of F~^{-1} (the default) Q = I - G (G^T G)^{-1} G^T = Q^T."""
         if self.G.shape[1] == 0:
             return np.array(X, float)
-        return X - self.G @ self.coarse_solve(self.G.T @ X)
+        if self.coarse is None:
+            return X - self.G @ self.coarse_solve(self.G.T @ X)
+        MG, H = self._coarse_M()
+        return X - MG @ sla.cho_solve(H, self.G.T @ X)
+
+    def Qt(self, X: np.ndarray) -> np.ndarray:
+        """Q^T X = X - G (G^T F~^{-1} G)^{-1} (F~^{-1} G)^T X (F~^{-1} symmetric); Q itself for the
+        identity."""
+        if self.G.shape[1] == 0 or self.coarse is None:
+            return self.Q(X)
+        MG, H = self._coarse_M()
+        return X - self.G @ sla.cho_solve(H, MG.T @ X)
 
     # -- preconditioners (section 2) -------------------------------------------------------
     def assembly_gram(self) -> sp.csc_matrix:
@@ -285,15 +311,22 @@ class FetiOracle:
         return g, d, e
 
     def lambda0(self, e, lam00=None):
-        """lambda_0 = G (G^T G)^{-1} e + Q lambda_00 (Table 1, line 2)."""
-        l0 = self.G @ self.coarse_solve(e) if self.G.shape[1] else np.zeros((self.n_lambda, e.shape[1]))
+        """lambda_0 = F~^{-1} G (G^T F~^{-1} G)^{-1} e + Q lambda_00 (Table 1, line 2); F~^{-1} = I
+        by default."""
+        if not self.G.shape[1]:
+            l0 = np.zeros((self.n_lambda, e.shape[1]))
+        elif self.coarse is None:
+            l0 = self.G @ self.coarse_solve(e)
+        else:
+            MG, H = self._coarse_M()
+            l0 = MG @ sla.cho_solve(H, e)
         if lam00 is not None:
             l0 = l0 + self.Q(lam00)
         return l0
 
     def residual(self, lam, d):
         """r = Q^T (d - F lambda) (Table 1, line 3)."""
-        return self.Q(d - self.F(lam))
+        return self.Qt(d - self.F(lam))
 
     def permute(self, z: np.ndarray) -> np.ndarray:
         """Multivector [Pi_0 z, .., Pi_{np-1} z] for every column of z (section 3.1, eq. for w~).
@@ -329,7 +362,9 @@ class FetiOracle:
         record: optional list receiving lambda after every iteration (first load case).
         precond: None (identity), "lumped" or "dirichlet": z = Q F~^{-1} r (Table 1, lines 4 and
         5.5).  READING: the projector keeps the identity in place of F~^{-1} whatever the
-        preconditioner (the paper allows any of them there), so Q and lambda_0 do not change.
+        preconditioner (the paper allows any of them there) unless the oracle was built with
+        coarse=..., which puts that preconditioner in Q, Q^T and lambda_0 (then the residual and
+        the products take Q^T, the directions Q).
         """
         nr = d.shape[1]
         lam = self.lambda0(e, lam00)
@@ -337,14 +372,14 @@ class FetiOracle:
         hist = []
         for c in range(nr):
             l = lam[:, c].copy()
-            r = self.Q(d[:, c] - self.F(l))
+            r = self.Qt(d[:, c] - self.F(l))
             r0 = np.linalg.norm(r)
             z = self.Q(self.precondition(r, precond))
             w = z.copy()
             h = [1.0]
             j = 0
             while r0 > 0 and np.linalg.norm(r) > tol * r0 and j < max_it:
-                p = self.Q(self.F(w))
+                p = self.Qt(self.F(w))
                 wp = w @ p
                 alpha = (w @ r) / wp
                 l += alpha * w
@@ -386,12 +421,12 @@ class FetiOracle:
         Stopping (READING): max over load cases of ||r_c|| / ||r0_c|| <= tol.
         """
         lam = self.lambda0(e, lam00)
-        r = self.Q(d - self.F(lam))
+        r = self.Qt(d - self.F(lam))
         r0 = np.linalg.norm(r, axis=0)
         r0[r0 == 0] = 1.0
         z = self.Q(self.precondition(r, precond))
         Zb = self.Q(self.permute(z))          # READING: re-project permuted directions
-        Pz = self.Q(self.permute(self.Q(self.F(z)))) if periodic else None
+        Pz = self.Qt(self.permute(self.Qt(self.F(z)))) if periodic else None
         Ws, Ps = [], []
         W_prev = P_prev = None
         hist = [1.0]
@@ -406,7 +441,7 @@ class FetiOracle:
                     Zb = Zb - Wi @ B
                     if periodic:
                         Pz = Pz - Pi @ B
-                Pb = Pz if periodic else self.Q(self.F(Zb))
+                Pb = Pz if periodic else self.Qt(self.F(Zb))
                 eta = Zb.T @ Pb
                 eta = 0.5 * (eta + eta.T)
                 ev, V = np.linalg.eigh(eta)
@@ -432,7 +467,7 @@ class FetiOracle:
                     W = Zb + W_prev @ beta
                     P = Pz + P_prev @ beta if periodic else None
                 if P is None:
-                    P = self.Q(self.F(W))
+                    P = self.Qt(self.F(W))
                 WtP = W.T @ P
                 WtP = 0.5 * (WtP + WtP.T)
                 alpha = np.linalg.pinv(WtP) @ (W.T @ r)
@@ -446,7 +481,7 @@ class FetiOracle:
             z = self.Q(self.precondition(r, precond))
             Zb = self.Q(self.permute(z))
             if periodic:
-                Pz = self.Q(self.permute(self.Q(self.F(z))))
+                Pz = self.Qt(self.permute(self.Qt(self.F(z))))
         return lam, dict(iterations=j, history=hist, rank_drops=drops)
 
     # -- recovery -------------------------------------------------------------------------

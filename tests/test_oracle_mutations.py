@@ -163,3 +163,14 @@ def test_unscaled_preconditioner_is_caught(monkeypatch):
     monkeypatch.setattr(o, "scale", lambda X: np.asarray(X, float))
     I = np.eye(p.n_lambda)
     assert np.abs(o.precondition(o.F(I), "dirichlet") - I).max() > 0.5
+
+
+def test_projector_sides_swapped_is_caught(monkeypatch):
+    """Directions projected with Q^T instead of Q leave the admissible space G^T w = 0 when F~^{-1}
+    is in the projector."""
+    p = W.small_elast((2, 2, 2), (2, 2, 1), n_rhs=1, seed=3)
+    o = O.FetiOracle(p, coarse="dirichlet")
+    I = np.eye(p.n_lambda)
+    assert np.abs(o.G.T @ o.Q(I)).max() < 1e-13
+    monkeypatch.setattr(o, "Q", o.Qt)
+    assert np.abs(o.G.T @ o.Q(I)).max() > 1e-3

@@ -635,3 +635,33 @@ def test_precond_single_occurrence_is_exact():
     assert np.abs(M - (I - G @ G.T)).max() < 1e-11
     _, _, st = o.solve("block", tol=1e-12, precond="dirichlet")
     assert st["iterations"] == 1
+
+
+# ----------------------------------------------------------------------------- preconditioner in the projector (section 2)
+
+@pytest.mark.parametrize("case", ["elast222", "ring4"])
+@pytest.mark.parametrize("coarse", ["lumped", "dirichlet"])
+def test_projector_with_preconditioner(case, coarse):
+    """Q = I - F~^{-1} G (G^T F~^{-1} G)^{-1} G^T: a projector (Q Q = Q) onto directions with
+    G^T w = 0, Q^T its transpose, lambda_0 with G^T lambda_0 = e; with these the FETI solution is the
+    assembled one, and a consistent pair (Dirichlet preconditioner in both places) needs no more
+    iterations than the orthogonal projector."""
+    p = W.small_elast((3, 3, 3), (2, 2, 2), n_rhs=2, seed=7) if case == "elast222" else \
+        W.ring_elast(4, (1, 2, 1), n_perm=4)
+    o = O.FetiOracle(p, coarse=coarse)
+    I = np.eye(p.n_lambda)
+    Q, Qt = o.Q(I), o.Qt(I)
+    assert np.abs(o.G.T @ Q).max() < 1e-13
+    assert np.abs(Q @ Q - Q).max() < 1e-12
+    assert np.abs(Q.T - Qt).max() < 1e-12
+    assert np.abs(Q - O.FetiOracle(p).Q(I)).max() > 1e-3      # not the orthogonal projector
+    g, d, e = o.loads()
+    assert np.abs(o.G.T @ o.lambda0(e) - e).max() < 1e-12 * np.abs(e).max()
+    ub, _, _, _ = O.global_solve(p)
+    scale = max(np.abs(x).max() for x in ub)
+    for method in ("classical", "block"):
+        _, u, st = o.solve(method, tol=1e-11, precond="dirichlet")
+        assert max(np.abs(a - b).max() for a, b in zip(u, ub)) < 1e-9 * scale, (method, coarse)
+    if coarse == "dirichlet":
+        _, _, s_orth = O.FetiOracle(p).solve("block", tol=1e-11, precond="dirichlet")
+        assert st["iterations"] <= s_orth["iterations"]
