@@ -219,7 +219,7 @@ typedef struct {
                           half of the free device memory allow) */
   int32_t precond;     /* rpf_precond: z = Q F~^{-1} r in every iteration (Table 1, lines 4 and 5.5);
                           the Dirichlet product runs in the inner precision prec.  The projector
-                          keeps the identity in place of F~^{-1}. */
+                          keeps the identity in place of F~^{-1} unless coarse says otherwise. */
   int32_t periodic;    /* 1: truly periodic structure (section 3.1, after Table 1): with several
                           permutations, Q F of the multivector is the permuted Q F z of the nr
                           columns of z, and the orthogonalisation applies its coefficients to the
@@ -227,6 +227,14 @@ typedef struct {
                           The commutation of Q F (and of the preconditioner) with the permutations
                           is checked once on a test vector: RPF_EINVAL when it fails.  Ignored
                           for the classical method and with one permutation. */
+  int32_t coarse;      /* rpf_precond used as F~^{-1} in the projector and in lambda_0 (section 2:
+                          Q = I - F~^{-1} G (G^T F~^{-1} G)^{-1} G^T, lambda_0 =
+                          F~^{-1} G (G^T F~^{-1} G)^{-1} e; RPF_PRECOND_NONE: F~^{-1} = I).  With a
+                          preconditioner the residuals and the products take Q^T and the
+                          directions Q; every projection then applies F~^{-1} once, in FP64, and
+                          G^T F~^{-1} G is assembled and inverted at the first solve for the
+                          pattern handles (RPF_ENOTSPD when it is not positive definite).
+                          RPF_EINVAL together with an active periodic shortcut. */
 } rpf_solve_opts;
 
 typedef struct {

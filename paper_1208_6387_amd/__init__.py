@@ -190,14 +190,15 @@ def block_krylov_solve(pb: Problem, patterns, f_local: torch.Tensor, n_rhs: int,
                        max_it: int = 1000, method: int = ORTHODIR, prec: int = FP64, inner_tol: float = 0.0,
                        max_sweeps: int = 0, check_every: int = 1, max_blocks: int = 0, lam_out=None, u_out=None,
                        stream=None, raise_on_noconv: bool = True, precond: int = PRECOND_NONE,
-                       periodic: bool = False) -> SolveResult:
+                       periodic: bool = False, coarse: int = PRECOND_NONE) -> SolveResult:
     """Solve the interface problem and recover the displacements.  f_local: flat device float64 tensor,
-    occurrence blocks of n_p x n_rhs column-major, concatenated."""
+    occurrence blocks of n_p x n_rhs column-major, concatenated.  coarse: the preconditioner used as
+    F~^{-1} in the projector and lambda_0 (PRECOND_NONE: the identity)."""
     assert f_local.is_cuda and f_local.dtype == torch.float64 and f_local.is_contiguous()
     lam = lam_out if lam_out is not None else torch.empty((pb.n_lambda, n_rhs), dtype=torch.float64, device="cuda")
     u = u_out if u_out is not None else torch.empty_like(f_local)
     opts = _lib.SolveOpts(tol, max_it, method, prec, inner_tol, max_sweeps, check_every, max_blocks, int(precond),
-                          int(bool(periodic)))
+                          int(bool(periodic)), int(coarse))
     st = SolveStats()
     code = load().block_krylov_solve(pb.handle, _handles(patterns), n_rhs, _ptr(f_local), C.byref(opts), _ptr(lam),
                                      lam.stride(0), _ptr(u), C.byref(st), _stream(stream))

@@ -34,7 +34,8 @@ class ProblemDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_it", C.c_int32), ("method", C.c_int32), ("prec", C.c_int32),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int32), ("check_every", C.c_int32),
-                ("max_blocks", C.c_int32), ("precond", C.c_int32), ("periodic", C.c_int32)]
+                ("max_blocks", C.c_int32), ("precond", C.c_int32), ("periodic", C.c_int32),
+                ("coarse", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -1048,16 +1048,117 @@ void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s)
 // y = (G^T G)^{-1} c for n_G x m row-major blocks, with the explicit (symmetric) inverse.  Large
 // coarse spaces go through the split-K FP64 MFMA product y^T (m x n_G) = c^T Ginv; small ones
 // through the row product.
-void coarse_solve(rpf_problem pb, const double* c, double* y, int m, hipStream_t s) {
+// y = inv c for the explicit symmetric inverse of a coarse matrix (n_G x m row-major c and y)
+static void coarse_solve_with(rpf_problem pb, const double* inv, const double* c, double* y, int m, hipStream_t s) {
   const int nG = pb->n_G;
   if (nG == 0) return;
   if (nG >= 1024) {
     const int sp = gemm_splitk_count(m, nG, nG);
     pb->cws.ensure((size_t)sp * m * nG);
-    dgemm_splitk(s, false, false, m, nG, nG, 1.0, c, m, pb->Ginv.p, nG, 0.0, y, m, pb->cws.p, sp);
+    dgemm_splitk(s, false, false, m, nG, nG, 1.0, c, m, inv, nG, 0.0, y, m, pb->cws.p, sp);
   } else {
-    rows_gemm(s, nG, nG, m, 1.0, pb->Ginv.p, nG, c, 0.0, y, m, m);
+    rows_gemm(s, nG, nG, m, 1.0, inv, nG, c, 0.0, y, m, m);
   }
+}
+
+void coarse_solve(rpf_problem pb, const double* c, double* y, int m, hipStream_t s) {
+  coarse_solve_with(pb, pb->Ginv.p, c, y, m, s);
+}
+
+// E (n_G x w row-major) = columns c0 .. c0 + w - 1 of the identity
+__global__ void k_eye_slice(int nG, int c0, int w, double* E) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nG * w) return;
+  const int r = (int)(i / w), j = (int)(i % w);
+  E[i] = (r == c0 + j) ? 1.0 : 0.0;
+}
+
+// x[l * ldx + j] -= t[l * ldt + j] for N rows of m columns
+__global__ void k_sub_rows(int64_t N, int m, const double* t, int64_t ldt, double* x, int64_t ldx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * m) return;
+  const int64_t l = i / m;
+  const int j = (int)(i % m);
+  x[l * ldx + j] -= t[l * ldt + j];
+}
+
+void ensure_coarse_M(rpf_problem pb, const rpf_pattern* pats, int kind, hipStream_t s) {
+  ensure_coarse(pb, pats, s);
+  std::vector<uint64_t> key(pb->coarse_key);
+  key.push_back((uint64_t)kind);
+  if (!pb->hkey.empty() && key == pb->hkey) return;
+  pb->hkey.clear();
+  const int nG = pb->n_G;
+  if (nG == 0) {
+    pb->hkey = key;
+    return;
+  }
+  const int64_t N = pb->n_lambda;
+  constexpr int BW = 64;
+  // H (column-major, symmetric) column block by column block: G E, F~^{-1} G E, G^T F~^{-1} G E; the
+  // row-major n_G x w result is rows c0 .. c0 + w - 1 of the column-major H (H is symmetric)
+  DevBuf<double> H((size_t)nG * nG), E((size_t)nG * BW), T((size_t)N * BW), C((size_t)nG * BW);
+  for (int c0 = 0; c0 < nG; c0 += BW) {
+    const int w = std::min(BW, nG - c0);
+    hipLaunchKernelGGL(k_eye_slice, dim3((unsigned)cdiv((int64_t)nG * w, 256)), dim3(256), 0, s, nG, c0, w, E.p);
+    RPF_LAUNCH_CHECK();
+    coarse_g(pb, E.p, w, 1.0, T.p, w, 0.0, s);
+    apply_precond(pb, pats, w, T.p, w, T.p, w, kind, RPF_FP64, s);
+    coarse_gt(pb, T.p, w, w, C.p, s);
+    copy_matrix(s, C.p, w, H.p + c0, nG, w, nG);
+  }
+  mirror_lower(s, H.p, nG, nG);
+  DevBuf<double> dinv((size_t)cdiv(nG, NB) * NB * NB);
+  DevBuf<int> st(1);
+  RPF_HIP(hipMemsetAsync(st.p, 0, sizeof(int), s));
+  const Envelope env = Envelope::dense(nG);
+  potrf(s, H.p, nG, nG, nG, env, dinv.p, st.p);
+  pb->Hinv.alloc((size_t)nG * nG);
+  potri_lower(s, H.p, nG, nG, dinv.p, pb->Hinv.p, nG);
+  int hst = 0;
+  RPF_HIP(hipMemcpyAsync(&hst, st.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  RPF_HIP(hipStreamSynchronize(s));
+  RPF_CHECK(hst == 0, RPF_ENOTSPD, "coarse matrix G^T F~^{-1} G is not positive definite");
+  pb->hkey = key;
+}
+
+void project_M(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s) {
+  const int nG = pb->n_G;
+  if (nG == 0) return;
+  const int64_t N = pb->n_lambda;
+  pb->cbuf.ensure((size_t)nG * m);
+  pb->ybuf.ensure((size_t)nG * m);
+  pb->qbuf.ensure((size_t)N * m);
+  coarse_gt(pb, x, ldx, m, pb->cbuf.p, s);
+  coarse_solve_with(pb, pb->Hinv.p, pb->cbuf.p, pb->ybuf.p, m, s);
+  coarse_g(pb, pb->ybuf.p, m, 1.0, pb->qbuf.p, m, 0.0, s);
+  apply_precond(pb, pats, m, pb->qbuf.p, m, pb->qbuf.p, m, kind, RPF_FP64, s);
+  hipLaunchKernelGGL(k_sub_rows, dim3((unsigned)cdiv(N * m, 256)), dim3(256), 0, s, N, m, pb->qbuf.p, (int64_t)m, x,
+                     ldx);
+  RPF_LAUNCH_CHECK();
+}
+
+void project_Mt(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s) {
+  const int nG = pb->n_G;
+  if (nG == 0) return;
+  const int64_t N = pb->n_lambda;
+  pb->cbuf.ensure((size_t)nG * m);
+  pb->ybuf.ensure((size_t)nG * m);
+  pb->qbuf.ensure((size_t)N * m);
+  apply_precond(pb, pats, m, x, ldx, pb->qbuf.p, m, kind, RPF_FP64, s);
+  coarse_gt(pb, pb->qbuf.p, m, m, pb->cbuf.p, s);
+  coarse_solve_with(pb, pb->Hinv.p, pb->cbuf.p, pb->ybuf.p, m, s);
+  coarse_g(pb, pb->ybuf.p, m, -1.0, x, ldx, 1.0, s);
+}
+
+void lambda0_M(rpf_problem pb, const rpf_pattern* pats, int kind, const double* e, int m, double* x, int64_t ldx,
+               hipStream_t s) {
+  const int nG = pb->n_G;
+  if (nG == 0) return;
+  pb->ybuf.ensure((size_t)nG * m);
+  coarse_solve_with(pb, pb->Hinv.p, e, pb->ybuf.p, m, s);
+  coarse_g(pb, pb->ybuf.p, m, 1.0, x, ldx, 0.0, s);
+  apply_precond(pb, pats, m, x, ldx, x, ldx, kind, RPF_FP64, s);
 }
 
 void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s) { project_block(pb, x, ldx, m, s); }

@@ -404,6 +404,7 @@ struct Solver {
   int iterations = 0, rank_drops = 0;
   int pc = RPF_PRECOND_NONE;  // preconditioner of z = Q F~^{-1} r
   bool periodic = false;      // truly periodic structure: P of the multivector by permutations
+  int cq = RPF_PRECOND_NONE;  // preconditioner in the projector: Q = I - F~^{-1} G H^{-1} G^T
   DevBuf<double> Zp;          // z before the permutations (N x nr)
   DevBuf<double> Pz;          // Q F z (N x nr), periodic shortcut
 
@@ -511,12 +512,23 @@ struct Solver {
     Mo.ensure((size_t)ldW * m);
   }
 
+  // x <- Q x (directions) and x <- Q^T x (residuals and products); the two coincide unless the
+  // projector carries a preconditioner
+  void projQ(double* x, int64_t ldx, int c) {
+    if (cq != RPF_PRECOND_NONE) project_M(pb, pats, cq, x, ldx, c, s);
+    else project(pb, x, ldx, c, s);
+  }
+  void projQt(double* x, int64_t ldx, int c) {
+    if (cq != RPF_PRECOND_NONE) project_Mt(pb, pats, cq, x, ldx, c, s);
+    else project(pb, x, ldx, c, s);
+  }
+
   // W = Q [Pi_0 z, .., Pi_{np-1} z] for the nr columns of z (N x nr), into a slot of the store
   void permute_into(const double* z, double* W) {
     hipLaunchKernelGGL(k_permute, dim3(nblocks(N * m)), dim3(256), 0, s, N, pb->dpn, pb->n_mult, nr, np, pb->d_perm.p,
                        pb->d_ep_occ.p, pb->has_rot ? pb->d_rot.p : (const double*)nullptr, z, (int64_t)nr, W, ldW);
     RPF_LAUNCH_CHECK();
-    project(pb, W, ldW, m, s);
+    projQ(W, ldW, m);
   }
 
   // One inner Krylov run on F_prec: starts from residual Rs (N x nr), accumulates
@@ -536,7 +548,7 @@ struct Solver {
     // which reads the same direction block (flushed when the loop ends)
     // (not with a preconditioner: the next block is then Q F~^{-1} R, not R)
     const bool upd_gram =
-        pc == RPF_PRECOND_NONE && method != RPF_ORTHODIR && np == 1 && m <= 16 && nr <= 16 && 256 % nr == 0;
+        pc == RPF_PRECOND_NONE && cq == RPF_PRECOND_NONE && method != RPF_ORTHODIR && np == 1 && m <= 16 && nr <= 16 && 256 % nr == 0;
     bool have_gram = false, lam_pending = false;
     const double* lam_dir = nullptr;  // the direction block of the pending update
     if (upd_gram) alpha_prev.ensure((size_t)m * nr);
@@ -563,21 +575,21 @@ struct Solver {
       // permuted; with one permutation it is the residual itself and is read from Rs below
       const bool direct = (np == 1);
       // orthogonalised straight from Rs
-      const bool fused = pc == RPF_PRECOND_NONE && direct && nb > 0 && nb * m <= 16;
+      const bool fused = pc == RPF_PRECOND_NONE && cq == RPF_PRECOND_NONE && direct && nb > 0 && nb * m <= 16;
       // periodic shortcut (truly periodic structure, section 3.1): Q F of the permuted block is
       // the permuted Q F z, so the product runs on the nr columns of z only
       const bool per = periodic && !direct;
       if (pc != RPF_PRECOND_NONE && direct) {
         // z = Q F~^{-1} r (Table 1)
         apply_precond(pb, pats, nr, Rs.p, nr, Zs, ldW, pc, prec, s);
-        project(pb, Zs, ldW, m, s);
+        projQ(Zs, ldW, m);
       } else if (!direct) {
         // the multivector of z = Q F~^{-1} r (z = r without a preconditioner), re-projected
         const double* z = Rs.p;
         if (pc != RPF_PRECOND_NONE) {
           Zp.ensure((size_t)N * nr);
           apply_precond(pb, pats, nr, Rs.p, nr, Zp.p, nr, pc, prec, s);
-          project(pb, Zp.p, nr, nr, s);
+          projQ(Zp.p, nr, nr);
           z = Zp.p;
         }
         permute_into(z, Zs);
@@ -590,6 +602,8 @@ struct Solver {
         hipLaunchKernelGGL(k_axpby_rows, dim3(nblocks(N * nr)), dim3(256), 0, s, N, nr, 1.0, Rs.p, (int64_t)nr, 0.0,
                            Zs, ldW);
         RPF_LAUNCH_CHECK();
+        // the residual lies in range Q^T; the direction is its Q projection
+        if (cq != RPF_PRECOND_NONE) projQ(Zs, ldW, m);
       }
       const double* zsrc = fused ? Rs.p : Zs;
       const int64_t ldzs = fused ? (int64_t)nr : ldW;
@@ -620,7 +634,10 @@ struct Solver {
         if (per) rows_gemm(s, N, ka, m, -1.0, Pall.p + (int64_t)first * m, ldW, Mo.p, 1.0, Ps, ldW);
       }
       // P = Q^T F Z
-      if (!per) apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, true, s);
+      if (!per) {
+        apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, cq == RPF_PRECOND_NONE, s);
+        if (cq != RPF_PRECOND_NONE) projQt(Ps, ldW, m);
+      }
       // [eta | Z^T R] = Z^T [P | R] in one pass over Z; T with T^T eta T = I on the kept directions
       {
         const size_t need = std::max((size_t)gram_pair_chunks(N) * m * (m + nr),
@@ -731,6 +748,11 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     hipStream_t s = (hipStream_t)stream;
     Solver S(pb, pats, s, n_rhs, opts->method);
     S.pc = opts->precond;
+    RPF_CHECK(opts->coarse >= RPF_PRECOND_NONE && opts->coarse <= RPF_PRECOND_DIRICHLET, RPF_EINVAL,
+              "block_krylov_solve: preconditioner of the projector");
+    RPF_CHECK(!(opts->coarse != RPF_PRECOND_NONE && opts->periodic && S.np > 1), RPF_EINVAL,
+              "block_krylov_solve: the periodic shortcut needs the plain projector (coarse = RPF_PRECOND_NONE)");
+    S.cq = opts->coarse;
     RPF_CHECK(S.m <= 64, RPF_EINVAL, "block_krylov_solve: block width n_rhs * n_perm must be <= 64");
     const int nr = n_rhs;
     const int64_t N = S.N;
@@ -802,9 +824,15 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
         RPF_LAUNCH_CHECK();
         RPF_HIP(hipStreamSynchronize(s));
       }
-      // lambda_0 = G (G^T G)^{-1} e
-      coarse_solve(pb, e.p, yc.p, nr, s);
-      coarse_g(pb, yc.p, nr, 1.0, S.lam.p, nr, 0.0, s);
+      if (S.cq != RPF_PRECOND_NONE) {
+        // lambda_0 = F~^{-1} G (G^T F~^{-1} G)^{-1} e
+        ensure_coarse_M(pb, pats, S.cq, s);
+        lambda0_M(pb, pats, S.cq, e.p, nr, S.lam.p, nr, s);
+      } else {
+        // lambda_0 = G (G^T G)^{-1} e
+        coarse_solve(pb, e.p, yc.p, nr, s);
+        coarse_g(pb, yc.p, nr, 1.0, S.lam.p, nr, 0.0, s);
+      }
     } else {
       fill(s, S.lam.p, N * nr, 0.0);
     }
@@ -819,7 +847,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
     RPF_LAUNCH_CHECK();
     RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
-    project(pb, S.R.p, nr, nr, s);
+    S.projQt(S.R.p, nr, nr);
     S.r0n = S.colnorm2(S.R.p, nr, nr);
     const std::vector<double> r0raw = S.r0n;  // the first convergence test sees the true norms
     for (double& v : S.r0n)
@@ -889,7 +917,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
         hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
         RPF_LAUNCH_CHECK();
         RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
-        project(pb, S.R.p, nr, nr, s);
+        S.projQt(S.R.p, nr, nr);
         rn = S.colnorm2(S.R.p, nr, nr);
         fresh = true;
       }
@@ -917,7 +945,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
       hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
       RPF_LAUNCH_CHECK();
       RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
-      project(pb, S.R.p, nr, nr, s);
+      S.projQt(S.R.p, nr, nr);
       rn = S.colnorm2(S.R.p, nr, nr);
     }
     rel = 0.0;

@@ -68,6 +68,10 @@ struct rpf_problem_s {
   int g_km = 0;
   rpf::DevBuf<const double*> d_Zp;
   rpf::DevBuf<double> Ginv, cbuf, ybuf, cpart, cws;
+  // coarse space with a preconditioner F~^{-1} in the projector: (G^T F~^{-1} G)^{-1}, built for the
+  // pattern handles and preconditioner kind in hkey, and an N_lambda x m workspace
+  std::vector<uint64_t> hkey;
+  rpf::DevBuf<double> Hinv, qbuf;
 };
 
 namespace rpf {
@@ -101,6 +105,14 @@ void coarse_g(rpf_problem pb, const double* y, int m, double alpha, double* x, i
 void project(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
 void project_block(rpf_problem pb, double* x, int64_t ldx, int m, hipStream_t s);
 void coarse_solve(rpf_problem pb, const double* c, double* y, int m, hipStream_t s);
+// projector with the preconditioner of kind `kind` as F~^{-1} (section 2):
+// H = G^T F~^{-1} G and its inverse (after ensure_coarse); x <- Q x = x - F~^{-1} G H^{-1} G^T x;
+// x <- Q^T x = x - G H^{-1} G^T F~^{-1} x; x <- F~^{-1} G H^{-1} e (lambda_0, n_G x m e)
+void ensure_coarse_M(rpf_problem pb, const rpf_pattern* pats, int kind, hipStream_t s);
+void project_M(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s);
+void project_Mt(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s);
+void lambda0_M(rpf_problem pb, const rpf_pattern* pats, int kind, const double* e, int m, double* x, int64_t ldx,
+               hipStream_t s);
 // F X with a low-precision flexibility product (FP32 or bf16 split), FP64 in and out
 // Gather A^(s)T lam for every occurrence of pattern p into the W format (lanes over interface
 // columns; needs m >= 8 for full lanes).  mode 0: FP32 Xf, 1: bf16 hi/lo Xh/Xl, 2: FP64 X64.
