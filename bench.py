@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--precond-extra", default="dirichlet",
                     help="comma list of preconditioners (lumped, dirichlet) also timed for every form and reported "
                          "under 'preconditioned' (empty: none)")
+    ap.add_argument("--coarse", default="none", choices=["none", "lumped", "dirichlet"],
+                    help="preconditioner used as F~^{-1} inside the projector and lambda_0 of every solve "
+                         "(section 2; none = identity)")
     ap.add_argument("--periodic", action="store_true",
                     help="periodic shortcut of the multivector product (truly periodic workloads only)")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -139,7 +142,8 @@ def main():
                 R.pattern_condense(P, prec)
         res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=args.tol, max_it=args.max_it, method=method,
                                    prec=prec, inner_tol=settings["inner_tol"], max_blocks=settings["max_blocks"],
-                                   lam_out=lam, u_out=u, precond=pc, periodic=args.periodic)
+                                   lam_out=lam, u_out=u, precond=pc, periodic=args.periodic,
+                                   coarse=PRECONDS[args.coarse])
         for P in pats:
             P.free()
         return res
@@ -233,7 +237,7 @@ def main():
         "dtype": "f64" if head == "fp64" else ("f32+f64" if head == "fp32" else "bf16+f64"),
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "form": head, "method": method_name,
-                   "precond": args.precond, "periodic": args.periodic,
+                   "precond": args.precond, "coarse": args.coarse, "periodic": args.periodic,
                    "max_blocks": settings["max_blocks"], "inner_tol": settings["inner_tol"],
                    "n_lambda": pb.n_lambda, "n_occ": p.n_occ, "n_rhs": p.n_rhs, "n_perm": p.n_perm,
                    "pattern_dofs": [pat.n for pat in p.patterns], "pattern_boundary_dofs": [pat.n_b for pat in p.patterns],

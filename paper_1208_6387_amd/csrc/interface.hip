@@ -6,6 +6,7 @@
 #include "problem.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1082,6 +1083,225 @@ __global__ void k_sub_rows(int64_t N, int m, const double* t, int64_t ldt, doubl
   x[l * ldx + j] -= t[l * ldt + j];
 }
 
+// Probe column of every coarse unknown (occurrence i, mode q): colour(i) * kmax + q
+__global__ void k_probe_slice(int nG, const int* pcol, int c0, int w, double* E) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nG * w) return;
+  const int r = (int)(i / w), j = (int)(i % w);
+  E[i] = (pcol[r] - c0 == j) ? 1.0 : 0.0;
+}
+
+// dst[(q * W + c0 + j) * ldd + r] = src[(q * w + j) * nb + r]: the w columns of occurrence q from a
+// gathered block into that occurrence's W-column slab
+__global__ void k_place_cols(int nb, int nq, int w, int W, int c0, const double* src, double* dst, int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nb * nq * w) return;
+  const int r = (int)(i % nb);
+  const int64_t cj = i / nb;
+  const int j = (int)(cj % w), q = (int)(cj / w);
+  dst[((int64_t)q * W + c0 + j) * ldd + r] = src[cj * nb + r];
+}
+
+// C_q = X_q^T Y_q for every occurrence q of a pattern, X_q = X + q W ldx and Y_q = Y + q W ldy (nb x W
+// column-major), C_q (W x W, column-major) at Cs + occ[q] W^2.  Workgroup: one 32 x 32 tile of one
+// C_q, k in steps of 32 staged through LDS, 2 x 2 results per thread.
+__global__ __launch_bounds__(256) void k_occ_gram(int nb, int W, int tiles, const double* X, int64_t ldx,
+                                                  const double* Y, int64_t ldy, const int* occ, double* Cs) {
+  __shared__ double sx[32][33], sy[32][33];
+  const int64_t b = blockIdx.x;
+  const int q = (int)(b / ((int64_t)tiles * tiles));
+  const int t = (int)(b % ((int64_t)tiles * tiles));
+  const int r0 = (t % tiles) * 32, c0 = (t / tiles) * 32;
+  const double* Xq = X + (int64_t)q * W * ldx;
+  const double* Yq = Y + (int64_t)q * W * ldy;
+  const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
+  double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
+  for (int k0 = 0; k0 < nb; k0 += 32) {
+    for (int e = tid; e < 1024; e += 256) {
+      const int kk = e % 32, cc = e / 32, k = k0 + kk;
+      sx[cc][kk] = (k < nb && r0 + cc < W) ? Xq[(int64_t)(r0 + cc) * ldx + k] : 0.0;
+      sy[cc][kk] = (k < nb && c0 + cc < W) ? Yq[(int64_t)(c0 + cc) * ldy + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      const double x0 = sx[tr][kk], x1 = sx[tr + 16][kk], y0 = sy[tc][kk], y1 = sy[tc + 16][kk];
+      a00 += x0 * y0;
+      a01 += x0 * y1;
+      a10 += x1 * y0;
+      a11 += x1 * y1;
+    }
+    __syncthreads();
+  }
+  double* C = Cs + (int64_t)occ[q] * W * W;
+  const int ra = r0 + tr, rb = r0 + tr + 16, ca = c0 + tc, cb = c0 + tc + 16;
+  if (ra < W && ca < W) C[(int64_t)ca * W + ra] = a00;
+  if (ra < W && cb < W) C[(int64_t)cb * W + ra] = a01;
+  if (rb < W && ca < W) C[(int64_t)ca * W + rb] = a10;
+  if (rb < W && cb < W) C[(int64_t)cb * W + rb] = a11;
+}
+
+// H[goff[j] + a, goff[i] + b] = sum over the occurrences s that both reach of
+// C_s[colour(j) * kmax + a, colour(i) * kmax + b], C_s = X_s^T M_s X_s (W x W, column-major)
+__global__ void k_assemble_coarse(int npair, int kmax, int W, const int* pj, const int* pi, const int* pptr,
+                                  const int* ps, const int* goff, const int* kocc, const int* colour, const double* Cs,
+                                  double* H, int64_t ldh) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)npair * kmax * kmax) return;
+  const int pr = (int)(t / (kmax * kmax));
+  const int a = (int)((t / kmax) % kmax), b = (int)(t % kmax);
+  const int j = pj[pr], i = pi[pr];
+  if (a >= kocc[j] || b >= kocc[i]) return;
+  const int64_t row = (int64_t)colour[j] * kmax + a, col = (int64_t)colour[i] * kmax + b;
+  double acc = 0.0;
+  for (int e = pptr[pr]; e < pptr[pr + 1]; ++e) acc += Cs[(int64_t)ps[e] * W * W + col * W + row];
+  H[(int64_t)(goff[i] + b) * ldh + goff[j] + a] = acc;
+}
+
+// H = G^T F~^{-1} G from the responses of the patterns (section 4.5: the coarse operator as the
+// reaction of each pattern to the traces of the coarse modes that reach its boundary).  With
+// F~^{-1} = beta (sum_s A_s M_s A_s^T) beta, H = sum_s X_s^T M_s X_s with X_s = A_s^T beta G:
+// only the modes of the occurrences in occ_nbr[s] reach s.  Occurrences are coloured so that the
+// members of every occ_nbr[s] differ in colour; one probe column per (colour, mode) then carries
+// every such trace at once: X_s = A_s^T beta G E (E sums the unit vectors of a colour's modes),
+// M_s X_s is one product per pattern over all its occurrences, and C_s = X_s^T M_s X_s is read
+// back by colour.  Returns false, doing nothing, when the buffers would not fit in half of the
+// free device memory.
+static bool coarse_M_responses(rpf_problem pb, const rpf_pattern* pats, int kind, double* H, hipStream_t s) {
+  const int nG = pb->n_G, no = pb->n_occ;
+  const int64_t N = pb->n_lambda;
+  std::vector<int> kocc(no);
+  int kmax = 0;
+  for (int o = 0; o < no; ++o) {
+    kocc[o] = pats[pb->occ_pat[o]]->k;
+    kmax = std::max(kmax, kocc[o]);
+  }
+  // greedy colouring: i takes the smallest colour of no occurrence within two steps
+  std::vector<int> colour(no, 0), stamp(no + 1, -1);
+  int ncol = 0;
+  for (int i = 0; i < no; ++i) {
+    if (kocc[i] == 0) continue;
+    for (int t : pb->occ_nbr[i])
+      for (int j : pb->occ_nbr[t])
+        if (j < i && kocc[j] > 0) stamp[colour[j]] = i;
+    int c = 0;
+    while (c < ncol && stamp[c] == i) ++c;
+    colour[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  const int W = ncol * kmax;
+  // pairs (j, i) within two steps and, for each, the occurrences that both reach
+  std::vector<int> pj, pi, pptr(1, 0), ps;
+  std::vector<int> seen(no, -1);
+  for (int i = 0; i < no; ++i) {
+    if (kocc[i] == 0) continue;
+    for (int t : pb->occ_nbr[i])
+      for (int j : pb->occ_nbr[t]) {
+        if (kocc[j] == 0 || seen[j] == i) continue;
+        seen[j] = i;
+        for (int u : pb->occ_nbr[i])
+          if (std::binary_search(pb->occ_nbr[u].begin(), pb->occ_nbr[u].end(), j)) ps.push_back(u);
+        pj.push_back(j);
+        pi.push_back(i);
+        pptr.push_back((int)ps.size());
+      }
+  }
+  // memory: the scaled probes (N x W), per pattern the gathered and multiplied slabs and one
+  // gathered batch, and the C_s
+  constexpr int BW = 64;
+  const int cpb = std::max(1, BW / std::max(kmax, 1));
+  int64_t slab = 0;
+  for (int p = 0; p < pb->n_pat; ++p) {
+    const int64_t nb = pats[p]->n_b, nq = (int64_t)pb->occ_of_pat[p].size();
+    slab = std::max(slab, (cdiv(nb, 32) * 32 + nb) * nq * W + nb * nq * (int64_t)cpb * kmax);
+  }
+  const double need = 8.0 * ((double)N * W + (double)slab + (double)no * W * W + (double)nG * cpb * kmax);
+  size_t free_b = 0, total_b = 0;
+  RPF_HIP(hipMemGetInfo(&free_b, &total_b));
+  if (need > 0.5 * (double)free_b) return false;
+
+  std::vector<int> pcol(nG);
+  for (int o = 0; o < no; ++o)
+    for (int q = 0; q < kocc[o]; ++q) pcol[pb->goff[o] + q] = colour[o] * kmax + q;
+  DevBuf<int> d_pcol, d_pj, d_pi, d_pptr, d_ps, d_kocc, d_colour;
+  d_pcol.upload(pcol.data(), pcol.size(), s);
+  d_pj.upload(pj.data(), pj.size(), s);
+  d_pi.upload(pi.data(), pi.size(), s);
+  d_pptr.upload(pptr.data(), pptr.size(), s);
+  if (ps.empty()) ps.push_back(0);
+  d_ps.upload(ps.data(), ps.size(), s);
+  d_kocc.upload(kocc.data(), kocc.size(), s);
+  d_colour.upload(colour.data(), colour.size(), s);
+  // beta G E, batch by batch of whole colours
+  DevBuf<double> T((size_t)N * W), E((size_t)nG * cpb * kmax), Tb((size_t)N * cpb * kmax);
+  for (int cb = 0; cb < ncol; cb += cpb) {
+    const int w = std::min(cpb, ncol - cb) * kmax, c0 = cb * kmax;
+    hipLaunchKernelGGL(k_probe_slice, dim3((unsigned)cdiv((int64_t)nG * w, 256)), dim3(256), 0, s, nG, d_pcol.p, c0,
+                       w, E.p);
+    RPF_LAUNCH_CHECK();
+    coarse_g(pb, E.p, w, 1.0, Tb.p, w, 0.0, s);
+    scale_lam(pb, w, Tb.p, w, T.p + c0, W, s);
+  }
+  DevBuf<double> Cs((size_t)no * W * W);
+  for (int p = 0; p < pb->n_pat; ++p) {
+    const rpf_pattern P = pats[p];
+    const int nb = P->n_b;
+    const int nq = (int)pb->occ_of_pat[p].size();
+    if (nq == 0 || nb == 0) continue;
+    const int64_t cols = (int64_t)nq * W;
+    const int64_t lw = cdiv(nb, 32) * 32;
+    DevBuf<double> X((size_t)lw * cols), Y((size_t)nb * cols), Xb((size_t)nb * nq * cpb * kmax);
+    fill(s, X.p, lw * cols, 0.0);
+    for (int cb = 0; cb < ncol; cb += cpb) {
+      const int w = std::min(cpb, ncol - cb) * kmax, c0 = cb * kmax;
+      gather_pattern(pb, p, pb->pat_nbn[p], T.p + c0, W, w, Xb.p, nb, s);
+      hipLaunchKernelGGL(k_place_cols, dim3((unsigned)cdiv((int64_t)nb * nq * w, 256)), dim3(256), 0, s, nb, nq, w, W,
+                         c0, Xb.p, X.p, lw);
+      RPF_LAUNCH_CHECK();
+    }
+    if (kind == RPF_PRECOND_DIRICHLET) {
+      const bool big = nb % 2 == 0 && cdiv(nb, 128) * cdiv(cols, (int64_t)128) >= 256;
+      if (!(big && dgemm_flex(s, nb, cols, nb, 1.0, P->S.p, nb, X.p, lw, 0.0, Y.p, nb)))
+        dgemm(s, false, false, nb, cols, nb, 1.0, P->S.p, nb, X.p, lw, 0.0, Y.p, nb);
+    } else {
+      spmm_csr(s, nb, cols, P->kbb_ptr.p, P->kbb_col.p, P->kbb_val.p, X.p, lw, 1.0, Y.p, nb, 0.0);
+    }
+    const int tiles = (int)cdiv(W, 32);
+    hipLaunchKernelGGL(k_occ_gram, dim3((unsigned)((int64_t)nq * tiles * tiles)), dim3(256), 0, s, nb, W, tiles, X.p,
+                       lw, Y.p, (int64_t)nb, pb->d_occ_of_pat.p + pb->pat_occ_off[p], Cs.p);
+    RPF_LAUNCH_CHECK();
+    RPF_HIP(hipStreamSynchronize(s));  // X, Y and Xb are freed at the end of this pattern
+  }
+  fill(s, H, (int64_t)nG * nG, 0.0);
+  const int npair = (int)pj.size();
+  hipLaunchKernelGGL(k_assemble_coarse, dim3((unsigned)cdiv((int64_t)npair * kmax * kmax, 256)), dim3(256), 0, s,
+                     npair, kmax, W, d_pj.p, d_pi.p, d_pptr.p, d_ps.p, pb->d_goff.p, d_kocc.p, d_colour.p, Cs.p, H,
+                     (int64_t)nG);
+  RPF_LAUNCH_CHECK();
+  RPF_HIP(hipStreamSynchronize(s));
+  return true;
+}
+
+// H = G^T F~^{-1} G column block by column block: G E, F~^{-1} G E, G^T F~^{-1} G E with E a slice of
+// the identity (one full preconditioner application per 64 coarse unknowns)
+static void coarse_M_columns(rpf_problem pb, const rpf_pattern* pats, int kind, double* H, hipStream_t s) {
+  const int nG = pb->n_G;
+  const int64_t N = pb->n_lambda;
+  constexpr int BW = 64;
+  // the row-major n_G x w result is rows c0 .. c0 + w - 1 of the column-major H (H is symmetric)
+  DevBuf<double> E((size_t)nG * BW), T((size_t)N * BW), C((size_t)nG * BW);
+  for (int c0 = 0; c0 < nG; c0 += BW) {
+    const int w = std::min(BW, nG - c0);
+    hipLaunchKernelGGL(k_eye_slice, dim3((unsigned)cdiv((int64_t)nG * w, 256)), dim3(256), 0, s, nG, c0, w, E.p);
+    RPF_LAUNCH_CHECK();
+    coarse_g(pb, E.p, w, 1.0, T.p, w, 0.0, s);
+    apply_precond(pb, pats, w, T.p, w, T.p, w, kind, RPF_FP64, s);
+    coarse_gt(pb, T.p, w, w, C.p, s);
+    copy_matrix(s, C.p, w, H + c0, nG, w, nG);
+  }
+  RPF_HIP(hipStreamSynchronize(s));
+}
+
 void ensure_coarse_M(rpf_problem pb, const rpf_pattern* pats, int kind, hipStream_t s) {
   ensure_coarse(pb, pats, s);
   std::vector<uint64_t> key(pb->coarse_key);
@@ -1093,21 +1313,11 @@ void ensure_coarse_M(rpf_problem pb, const rpf_pattern* pats, int kind, hipStrea
     pb->hkey = key;
     return;
   }
-  const int64_t N = pb->n_lambda;
-  constexpr int BW = 64;
-  // H (column-major, symmetric) column block by column block: G E, F~^{-1} G E, G^T F~^{-1} G E; the
-  // row-major n_G x w result is rows c0 .. c0 + w - 1 of the column-major H (H is symmetric)
-  DevBuf<double> H((size_t)nG * nG), E((size_t)nG * BW), T((size_t)N * BW), C((size_t)nG * BW);
-  for (int c0 = 0; c0 < nG; c0 += BW) {
-    const int w = std::min(BW, nG - c0);
-    hipLaunchKernelGGL(k_eye_slice, dim3((unsigned)cdiv((int64_t)nG * w, 256)), dim3(256), 0, s, nG, c0, w, E.p);
-    RPF_LAUNCH_CHECK();
-    coarse_g(pb, E.p, w, 1.0, T.p, w, 0.0, s);
-    apply_precond(pb, pats, w, T.p, w, T.p, w, kind, RPF_FP64, s);
-    coarse_gt(pb, T.p, w, w, C.p, s);
-    copy_matrix(s, C.p, w, H.p + c0, nG, w, nG);
-  }
-  mirror_lower(s, H.p, nG, nG);
+  DevBuf<double> H((size_t)nG * nG);
+  // RPF_COARSE_ASSEMBLY=columns selects the column-by-column assembly (for cross-checks)
+  const char* how = std::getenv("RPF_COARSE_ASSEMBLY");
+  const bool by_columns = how && std::string(how) == "columns";
+  if (by_columns || !coarse_M_responses(pb, pats, kind, H.p, s)) coarse_M_columns(pb, pats, kind, H.p, s);
   DevBuf<double> dinv((size_t)cdiv(nG, NB) * NB * NB);
   DevBuf<int> st(1);
   RPF_HIP(hipMemsetAsync(st.p, 0, sizeof(int), s));
@@ -1344,6 +1554,21 @@ extern "C" rpf_status problem_create(const rpf_problem_desc* d, rpf_problem* out
           sc_val.push_back(v);
         }
         sc_ptr[i + 1] = (int)sc_col.size();
+      }
+      pb->occ_nbr.assign(pb->n_occ, {});
+      for (int o = 0; o < pb->n_occ; ++o) pb->occ_nbr[o].push_back(o);
+      std::vector<int> occs;
+      for (int r = 0; r < nm; ++r) {
+        occs.clear();
+        for (int i : members[r])
+          for (int e = 0; e < 2; ++e)
+            if (ep_occ[2 * i + e] >= 0) occs.push_back(ep_occ[2 * i + e]);
+        for (int a : occs)
+          for (int b : occs) pb->occ_nbr[a].push_back(b);
+      }
+      for (auto& v : pb->occ_nbr) {
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
       }
     }
     pb->pair_ptr.push_back(0);

@@ -56,6 +56,9 @@ struct rpf_problem_s {
   rpf::DevBuf<int> d_sc_ptr, d_sc_col;
   rpf::DevBuf<double> d_sc_val;
   rpf::DevBuf<double> pcbuf;  // preconditioner workspace, N_lambda x m
+  // occurrences whose boundaries meet through one of those groups (sorted, self included): the
+  // scaled trace of a coarse mode of i reaches occurrence s only when i is in occ_nbr[s]
+  std::vector<std::vector<int>> occ_nbr;
 
   // coarse space (built for one set of pattern handles)
   std::vector<uint64_t> coarse_key;  // uids of the pattern handles the coarse space was built for

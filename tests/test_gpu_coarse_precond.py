@@ -38,10 +38,17 @@ def _problem(name):
         return W.ring_elast(4, (1, 2, 1), n_rhs=2, n_perm=2)
     if name == "elast-ragged-2x3x1":
         return W.small_elast((5, 2, 3), (2, 3, 1), n_rhs=3, n_perm=1, seed=9)
+    if name == "elast-2cube-4x4x4":
+        # 64 occurrences in 27 colours: probe columns carry the modes of several occurrences
+        return W.small_elast((2, 2, 2), (4, 4, 4), n_rhs=2, n_perm=1, seed=1)
+    if name == "ring12-elast-rotated":
+        # 12 rotated occurrences in 5 colours
+        return W.ring_elast(12, (1, 2, 1), n_rhs=2, n_perm=2)
     raise KeyError(name)
 
 
-CASES = ["elast-3cube-3x2x2", "heat-3x2", "ring-elast-rotated", "elast-ragged-2x3x1"]
+CASES = ["elast-3cube-3x2x2", "heat-3x2", "ring-elast-rotated", "elast-ragged-2x3x1", "elast-2cube-4x4x4",
+         "ring12-elast-rotated"]
 
 
 @pytest.fixture(scope="module", params=CASES)
@@ -101,6 +108,27 @@ def test_solve_coarse_precond_mixed(case, R):
                                coarse=R.PRECOND_DIRICHLET)
     assert res.stats["rel_residual"] <= 1e-9
     _check(R, p, res, u_ref, O.FetiOracle(p, coarse="dirichlet"), 1e-6)
+
+
+@pytest.mark.parametrize("coarse", ["lumped", "dirichlet"])
+def test_coarse_assembly_columns_matches_responses(case, R, coarse, monkeypatch):
+    """The coarse matrix from the patterns' responses to the probed mode traces gives the same solve
+    as the column-by-column assembly (one preconditioner application per 64 coarse unknowns)."""
+    name, p, pats, pb, u_ref = case
+    from paper_1208_6387_amd import structure as ST
+    f = ST.loads_to_device(p)
+    out = {}
+    for how in ["columns", "responses"]:
+        monkeypatch.setenv("RPF_COARSE_ASSEMBLY", how)
+        # fresh structure: the coarse matrix is cached per structure and pattern handles
+        pb2 = ST.create_problem(p)
+        res = R.block_krylov_solve(pb2, pats, f, p.n_rhs, tol=1e-11, max_it=3000, method=R.BLOCK_CG,
+                                   precond=KINDS[coarse], coarse=KINDS[coarse])
+        out[how] = (res.lam.cpu().numpy(), res.stats["iterations"])
+    (la, ia), (lb, ib) = out["columns"], out["responses"]
+    # the two matrices differ by rounding only
+    assert abs(ia - ib) <= 1, (ia, ib)
+    assert np.abs(la - lb).max() <= 1e-8 * np.abs(la).max()
 
 
 def test_coarse_precond_switch_and_plain_again(R):
