@@ -1158,7 +1158,7 @@ __global__ void k_assemble_coarse(int npair, int kmax, int W, const int* pj, con
   H[(int64_t)(goff[i] + b) * ldh + goff[j] + a] = acc;
 }
 
-// H = G^T F~^{-1} G from the responses of the patterns (section 4.5: the coarse operator as the
+// H = G^T F~^{-1} G from the responses of the patterns (section 5.3: the coarse operator as the
 // reaction of each pattern to the traces of the coarse modes that reach its boundary).  With
 // F~^{-1} = beta (sum_s A_s M_s A_s^T) beta, H = sum_s X_s^T M_s X_s with X_s = A_s^T beta G:
 // only the modes of the occurrences in occ_nbr[s] reach s.  Occurrences are coloured so that the
