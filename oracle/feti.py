@@ -19,6 +19,9 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   lumped = Dirichlet without interior dofs, multiplicity scaling away from cross-points,
   spectrum of the preconditioned operator bounded below by 1, K_bb - S >= 0 ordering,
   unchanged solutions);
+* lumped or Dirichlet preconditioner inside Q, Q^T and lambda_0 (coarse=...): pinned
+  (Q Q = Q, G^T Q = 0, Q^T the transpose, G^T lambda_0 = e, solutions equal to the global
+  solve, and a swapped-sides mutation);
 * periodic shortcut of the multivector product: pinned (same iterates as the full products on
   truly periodic rings, commutation of F, Q and the preconditioner with the permutations, and a
   non-periodic negative control);
