@@ -579,17 +579,20 @@ struct Solver {
       // periodic shortcut (truly periodic structure, section 3.1): Q F of the permuted block is
       // the permuted Q F z, so the product runs on the nr columns of z only
       const bool per = periodic && !direct;
+      // with the same preconditioner in the projector, applied in FP64: Q F~^{-1} = F~^{-1} Q^T and
+      // Q^T r = r, so z = F~^{-1} r is already in range Q
+      const bool z_in_range = cq != RPF_PRECOND_NONE && pc == cq && (pc == RPF_PRECOND_LUMPED || prec == RPF_FP64);
       if (pc != RPF_PRECOND_NONE && direct) {
         // z = Q F~^{-1} r (Table 1)
         apply_precond(pb, pats, nr, Rs.p, nr, Zs, ldW, pc, prec, s);
-        projQ(Zs, ldW, m);
+        if (!z_in_range) projQ(Zs, ldW, m);
       } else if (!direct) {
         // the multivector of z = Q F~^{-1} r (z = r without a preconditioner), re-projected
         const double* z = Rs.p;
         if (pc != RPF_PRECOND_NONE) {
           Zp.ensure((size_t)N * nr);
           apply_precond(pb, pats, nr, Rs.p, nr, Zp.p, nr, pc, prec, s);
-          projQ(Zp.p, nr, nr);
+          if (!z_in_range) projQ(Zp.p, nr, nr);
           z = Zp.p;
         }
         permute_into(z, Zs);
