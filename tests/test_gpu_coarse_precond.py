@@ -42,7 +42,7 @@ def _problem(name):
         # 64 occurrences in 27 colours: probe columns carry the modes of several occurrences
         return W.small_elast((2, 2, 2), (4, 4, 4), n_rhs=2, n_perm=1, seed=1)
     if name == "ring12-elast-rotated":
-        # 12 rotated occurrences in 5 colours
+        # 12 rotated occurrences in 3 colours
         return W.ring_elast(12, (1, 2, 1), n_rhs=2, n_perm=2)
     raise KeyError(name)
 
