@@ -233,7 +233,10 @@ typedef struct {
                           preconditioner the residuals and the products take Q^T and the
                           directions Q; every projection then applies F~^{-1} once, in FP64, and
                           G^T F~^{-1} G is assembled and inverted at the first solve for the
-                          pattern handles (RPF_ENOTSPD when it is not positive definite).
+                          pattern handles (RPF_ENOTSPD when it is not positive definite or a
+                          relative pivot L_ii^2 / H_ii falls below 1e-10: with patterns that have
+                          no interior dofs, S = K_bb = K annihilates the rigid traces and
+                          G^T F~^{-1} G is singular).
                           RPF_EINVAL together with an active periodic shortcut. */
 } rpf_solve_opts;
 

@@ -1302,6 +1302,12 @@ static void coarse_M_columns(rpf_problem pb, const rpf_pattern* pats, int kind, 
   RPF_HIP(hipStreamSynchronize(s));
 }
 
+// out[i] = A[i * lda + i]
+__global__ void k_get_diag(int n, const double* A, int64_t lda, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = A[(int64_t)i * lda + i];
+}
+
 void ensure_coarse_M(rpf_problem pb, const rpf_pattern* pats, int kind, hipStream_t s) {
   ensure_coarse(pb, pats, s);
   std::vector<uint64_t> key(pb->coarse_key);
@@ -1320,15 +1326,32 @@ void ensure_coarse_M(rpf_problem pb, const rpf_pattern* pats, int kind, hipStrea
   if (by_columns || !coarse_M_responses(pb, pats, kind, H.p, s)) coarse_M_columns(pb, pats, kind, H.p, s);
   DevBuf<double> dinv((size_t)cdiv(nG, NB) * NB * NB);
   DevBuf<int> st(1);
+  // the diagonal before and after the factorisation: L_ii^2 / H_ii is the part of H_ii left to
+  // row i by the rows before it, a relative pivot
+  DevBuf<double> dg((size_t)2 * nG);
+  hipLaunchKernelGGL(k_get_diag, dim3((unsigned)cdiv(nG, 256)), dim3(256), 0, s, nG, H.p, (int64_t)nG, dg.p);
+  RPF_LAUNCH_CHECK();
   RPF_HIP(hipMemsetAsync(st.p, 0, sizeof(int), s));
   const Envelope env = Envelope::dense(nG);
   potrf(s, H.p, nG, nG, nG, env, dinv.p, st.p);
+  hipLaunchKernelGGL(k_get_diag, dim3((unsigned)cdiv(nG, 256)), dim3(256), 0, s, nG, H.p, (int64_t)nG, dg.p + nG);
+  RPF_LAUNCH_CHECK();
   pb->Hinv.alloc((size_t)nG * nG);
   potri_lower(s, H.p, nG, nG, dinv.p, pb->Hinv.p, nG);
   int hst = 0;
+  std::vector<double> hd((size_t)2 * nG);
   RPF_HIP(hipMemcpyAsync(&hst, st.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  RPF_HIP(hipMemcpyAsync(hd.data(), dg.p, sizeof(double) * 2 * nG, hipMemcpyDeviceToHost, s));
   RPF_HIP(hipStreamSynchronize(s));
   RPF_CHECK(hst == 0, RPF_ENOTSPD, "coarse matrix G^T F~^{-1} G is not positive definite");
+  // G^T F~^{-1} G is singular when the local matrices annihilate rigid traces (a pattern without
+  // interior dofs, where S = K_bb = K); rounding then leaves tiny positive pivots
+  for (int i = 0; i < nG; ++i) {
+    const double rel = hd[nG + i] * hd[nG + i] / hd[i];
+    RPF_CHECK(hd[i] > 0.0 && rel > 1e-10, RPF_ENOTSPD,
+              "coarse matrix G^T F~^{-1} G is not positive definite (relative pivot " + std::to_string(rel) +
+                  " at coarse unknown " + std::to_string(i) + ")");
+  }
   pb->hkey = key;
 }
 

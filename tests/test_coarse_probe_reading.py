@@ -133,3 +133,15 @@ def test_probe_assembly_fails_with_one_step_colouring():
     Xi = o.A[s].T @ o.scale(G[:, o.coarse_off[i]:o.coarse_off[i + 1]])
     mixed, exact = Xc.T @ (M @ Xc), Xi.T @ (M @ Xi)
     assert np.abs(mixed - exact).max() > 1e-3 * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("kind", ["lumped", "dirichlet"])
+def test_coarse_operator_singular_without_interior_dofs(kind):
+    """With no interior dofs the local matrix is K itself (S = K_bb = K): the rigid traces are in its
+    kernel and G^T F~^{-1} G is singular; one interior layer makes it definite."""
+    for pe, singular in [(1, True), (2, False)]:
+        p = W.small_elast((pe, pe + 1, pe), (1, 1, 2), n_rhs=1, seed=0)
+        o = O.FetiOracle(p, coarse=kind)
+        G = o.G.toarray()
+        w = np.linalg.eigvalsh(G.T @ o.precondition(G, kind))
+        assert (w.min() < 1e-12 * w.max()) == singular, (pe, w.min(), w.max())

@@ -163,3 +163,21 @@ def test_coarse_precond_error_paths(R):
     with pytest.raises(R.RpfError, match="EINVAL.*periodic"):
         R.block_krylov_solve(pb, pats, f, 1, tol=1e-8, max_it=50, method=R.ORTHODIR, periodic=True,
                              coarse=R.PRECOND_LUMPED)
+
+
+@pytest.mark.parametrize("coarse", ["lumped", "dirichlet"])
+def test_coarse_precond_singular_refused(R, coarse):
+    """A pattern with no interior dofs (one brick element): S = K_bb = K, whose kernel holds the
+    rigid traces, so G^T F~^{-1} G is singular (the oracle's eigenvalues, checked on the CPU) and the
+    solve is refused with RPF_ENOTSPD instead of iterating on a singular coarse problem."""
+    from paper_1208_6387_amd import structure as ST
+    p = W.small_elast((1, 2, 1), (1, 1, 2), n_rhs=1, n_perm=1, seed=0)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats)
+    pb = ST.create_problem(p)
+    f = ST.loads_to_device(p)
+    with pytest.raises(R.RpfError, match="ENOTSPD.*not positive definite"):
+        R.block_krylov_solve(pb, pats, f, 1, tol=1e-10, max_it=200, coarse=KINDS[coarse])
+    # the plain projector still solves it
+    res = R.block_krylov_solve(pb, pats, f, 1, tol=1e-10, max_it=200)
+    assert res.stats["rel_residual"] <= 1e-10

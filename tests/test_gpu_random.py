@@ -75,3 +75,45 @@ def test_random_elastic(R, gx, gy, pe, n_rhs, n_perm, seed, prec, pc):
     print(f"\n[random elastic] grid {gx}x{gy}x2 pattern {pe}x{pe + 1}x{pe} n_rhs {n_rhs} n_perm {n_perm} "
           f"seed {seed} {prec} {pc}", flush=True)
     _run(R, p, prec, "orthodir", pc)
+
+
+@settings(max_examples=10, deadline=None, database=None, derandomize=True)
+@given(elastic=st.booleans(), gx=st.integers(1, 3), gy=st.integers(1, 3), pe=st.integers(1, 2),
+       n_rhs=st.integers(1, 2), n_perm=st.integers(1, 2), seed=st.integers(0, 10_000),
+       prec=st.sampled_from(["fp64", "bf16x3"]), method=st.sampled_from(["classical", "block_cg", "orthodir"]),
+       coarse=st.sampled_from(["lumped", "dirichlet"]), same=st.booleans())
+def test_random_coarse_precond(R, elastic, gx, gy, pe, n_rhs, n_perm, seed, prec, method, coarse, same):
+    """The preconditioner in the projector on drawn structures: displacements against the oracle's
+    (unique) solution and G^T lambda = e against the oracle's G and e."""
+    from paper_1208_6387_amd import structure as ST
+    if elastic:
+        # patterns with interior dofs: without them S = K_bb = K annihilates the rigid traces and
+        # G^T F~^{-1} G is singular (the refused case of test_gpu_coarse_precond)
+        p = W.small_elast((pe + 1, pe + 1, pe + 1), (min(gx, 2), min(gy, 2), 2), n_rhs=n_rhs, n_perm=n_perm,
+                          seed=seed)
+    else:
+        p = W.small_heat((pe + 2, pe + 1), (gx, gy), n_rhs=n_rhs, n_perm=n_perm, seed=seed)
+    print(f"\n[random coarse] {p.name} n_rhs {n_rhs} n_perm {n_perm} seed {seed} {prec} {method} "
+          f"coarse {coarse} same {same}", flush=True)
+    kinds = {"lumped": R.PRECOND_LUMPED, "dirichlet": R.PRECOND_DIRICHLET}
+    pr = {"fp64": R.FP64, "bf16x3": R.BF16X3}[prec]
+    meth = {"classical": R.CLASSICAL, "block_cg": R.BLOCK_CG, "orthodir": R.ORTHODIR}[method]
+    if p.n_perm > 1 and method == "block_cg":
+        meth = R.ORTHODIR
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats, (R.FP64, pr) if pr != R.FP64 else (R.FP64,))
+    pb = ST.create_problem(p)
+    tol = 1e-11 if pr == R.FP64 else 1e-8
+    res = R.block_krylov_solve(pb, pats, ST.loads_to_device(p), p.n_rhs, tol=tol, max_it=3000, method=meth, prec=pr,
+                               inner_tol=1e-3, precond=kinds[coarse] if same else R.PRECOND_NONE,
+                               coarse=kinds[coarse])
+    assert res.stats["rel_residual"] <= tol
+    _, u_o, _ = O.FetiOracle(p).solve("block", tol=1e-12)
+    u = ST.split_u(p, res.u)
+    err = max(np.abs(a - b).max() for a, b in zip(u, u_o)) / max(np.abs(b).max() for b in u_o)
+    assert err < (1e-8 if pr == R.FP64 else 1e-6), (p.name, prec, method, coarse, same, err)
+    oc = O.FetiOracle(p, coarse=coarse)
+    _, _, e = oc.loads()
+    if oc.G.shape[1]:
+        lam = res.lam.cpu().numpy()
+        assert np.abs(oc.G.T @ lam - e).max() <= 1e-10 * max(np.abs(e).max(), 1.0)
