@@ -1371,14 +1371,15 @@ void project_M(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int
   RPF_LAUNCH_CHECK();
 }
 
-void project_Mt(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s) {
+void project_Mt(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s,
+                int prec) {
   const int nG = pb->n_G;
   if (nG == 0) return;
   const int64_t N = pb->n_lambda;
   pb->cbuf.ensure((size_t)nG * m);
   pb->ybuf.ensure((size_t)nG * m);
   pb->qbuf.ensure((size_t)N * m);
-  apply_precond(pb, pats, m, x, ldx, pb->qbuf.p, m, kind, RPF_FP64, s);
+  apply_precond(pb, pats, m, x, ldx, pb->qbuf.p, m, kind, prec, s);
   coarse_gt(pb, pb->qbuf.p, m, m, pb->cbuf.p, s);
   coarse_solve_with(pb, pb->Hinv.p, pb->cbuf.p, pb->ybuf.p, m, s);
   coarse_g(pb, pb->ybuf.p, m, -1.0, x, ldx, 1.0, s);

@@ -518,8 +518,8 @@ struct Solver {
     if (cq != RPF_PRECOND_NONE) project_M(pb, pats, cq, x, ldx, c, s);
     else project(pb, x, ldx, c, s);
   }
-  void projQt(double* x, int64_t ldx, int c) {
-    if (cq != RPF_PRECOND_NONE) project_Mt(pb, pats, cq, x, ldx, c, s);
+  void projQt(double* x, int64_t ldx, int c, int prec_m = RPF_FP64) {
+    if (cq != RPF_PRECOND_NONE) project_Mt(pb, pats, cq, x, ldx, c, s, prec_m);
     else project(pb, x, ldx, c, s);
   }
 
@@ -639,7 +639,10 @@ struct Solver {
       // P = Q^T F Z
       if (!per) {
         apply_F(pb, pats, m, Zs, ldW, Ps, ldW, prec, cq == RPF_PRECOND_NONE, s);
-        if (cq != RPF_PRECOND_NONE) projQt(Ps, ldW, m);
+        // Q^T of the product may use the inner precision's F~^{-1}: it only moves P along range G,
+        // which is orthogonal to every direction (G^T Z = 0 through the FP64 Q), and each sweep's
+        // residual is projected again in FP64
+        if (cq != RPF_PRECOND_NONE) projQt(Ps, ldW, m, cq == RPF_PRECOND_DIRICHLET ? prec : RPF_FP64);
       }
       // [eta | Z^T R] = Z^T [P | R] in one pass over Z; T with T^T eta T = I on the kept directions
       {

@@ -113,7 +113,8 @@ void coarse_solve(rpf_problem pb, const double* c, double* y, int m, hipStream_t
 // x <- Q^T x = x - G H^{-1} G^T F~^{-1} x; x <- F~^{-1} G H^{-1} e (lambda_0, n_G x m e)
 void ensure_coarse_M(rpf_problem pb, const rpf_pattern* pats, int kind, hipStream_t s);
 void project_M(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s);
-void project_Mt(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s);
+void project_Mt(rpf_problem pb, const rpf_pattern* pats, int kind, double* x, int64_t ldx, int m, hipStream_t s,
+                int prec = RPF_FP64);
 void lambda0_M(rpf_problem pb, const rpf_pattern* pats, int kind, const double* e, int m, double* x, int64_t ldx,
                hipStream_t s);
 // F X with a low-precision flexibility product (FP32 or bf16 split), FP64 in and out
