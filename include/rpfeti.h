@@ -231,8 +231,12 @@ typedef struct {
                           Q = I - F~^{-1} G (G^T F~^{-1} G)^{-1} G^T, lambda_0 =
                           F~^{-1} G (G^T F~^{-1} G)^{-1} e; RPF_PRECOND_NONE: F~^{-1} = I).  With a
                           preconditioner the residuals and the products take Q^T and the
-                          directions Q; every projection then applies F~^{-1} once, in FP64, and
-                          G^T F~^{-1} G is assembled and inverted at the first solve for the
+                          directions Q.  Each projection applies F~^{-1} once: in FP64 for the
+                          directions and the sweeps' residuals, in the inner precision for the
+                          products' Q^T (the difference lies in range G); the direction's Q is
+                          skipped when precond equals coarse and F~^{-1} runs in FP64 (then
+                          Q F~^{-1} r = F~^{-1} r).  G^T F~^{-1} G is assembled and inverted at
+                          the first solve for the
                           pattern handles (RPF_ENOTSPD when it is not positive definite or a
                           relative pivot L_ii^2 / H_ii falls below 1e-10: with patterns that have
                           no interior dofs, S = K_bb = K annihilates the rigid traces and
