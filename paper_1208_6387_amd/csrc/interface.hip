@@ -1103,42 +1103,56 @@ __global__ void k_place_cols(int nb, int nq, int w, int W, int c0, const double*
 }
 
 // C_q = X_q^T Y_q for every occurrence q of a pattern, X_q = X + q W ldx and Y_q = Y + q W ldy (nb x W
-// column-major), C_q (W x W, column-major) at Cs + occ[q] W^2.  Workgroup: one 32 x 32 tile of one
-// C_q, k in steps of 32 staged through LDS, 2 x 2 results per thread.
+// column-major), C_q (W x W, column-major) at Cs + occ[q] W^2.  Workgroup: one 64 x 64 tile of one
+// C_q, k in steps of 16 staged through LDS (k fastest, padded rows), 4 x 4 results per thread, so
+// each pair of LDS reads feeds four FMAs.
 __global__ __launch_bounds__(256) void k_occ_gram(int nb, int W, int tiles, const double* X, int64_t ldx,
                                                   const double* Y, int64_t ldy, const int* occ, double* Cs) {
-  __shared__ double sx[32][33], sy[32][33];
+  constexpr int TB = 64, KB = 16;
+  __shared__ double sx[TB][KB + 1], sy[TB][KB + 1];
   const int64_t b = blockIdx.x;
   const int q = (int)(b / ((int64_t)tiles * tiles));
   const int t = (int)(b % ((int64_t)tiles * tiles));
-  const int r0 = (t % tiles) * 32, c0 = (t / tiles) * 32;
+  const int r0 = (t % tiles) * TB, c0 = (t / tiles) * TB;
   const double* Xq = X + (int64_t)q * W * ldx;
   const double* Yq = Y + (int64_t)q * W * ldy;
   const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
-  double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
-  for (int k0 = 0; k0 < nb; k0 += 32) {
-    for (int e = tid; e < 1024; e += 256) {
-      const int kk = e % 32, cc = e / 32, k = k0 + kk;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < nb; k0 += KB) {
+#pragma unroll
+    for (int e = tid; e < TB * KB; e += 256) {
+      const int kk = e % KB, cc = e / KB, k = k0 + kk;
       sx[cc][kk] = (k < nb && r0 + cc < W) ? Xq[(int64_t)(r0 + cc) * ldx + k] : 0.0;
       sy[cc][kk] = (k < nb && c0 + cc < W) ? Yq[(int64_t)(c0 + cc) * ldy + k] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < 32; ++kk) {
-      const double x0 = sx[tr][kk], x1 = sx[tr + 16][kk], y0 = sy[tc][kk], y1 = sy[tc + 16][kk];
-      a00 += x0 * y0;
-      a01 += x0 * y1;
-      a10 += x1 * y0;
-      a11 += x1 * y1;
+#pragma unroll 4
+    for (int kk = 0; kk < KB; ++kk) {
+      double xv[4], yv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        xv[i] = sx[tr + 16 * i][kk];
+        yv[i] = sy[tc + 16 * i][kk];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += xv[i] * yv[j];
     }
     __syncthreads();
   }
   double* C = Cs + (int64_t)occ[q] * W * W;
-  const int ra = r0 + tr, rb = r0 + tr + 16, ca = c0 + tc, cb = c0 + tc + 16;
-  if (ra < W && ca < W) C[(int64_t)ca * W + ra] = a00;
-  if (ra < W && cb < W) C[(int64_t)cb * W + ra] = a01;
-  if (rb < W && ca < W) C[(int64_t)ca * W + rb] = a10;
-  if (rb < W && cb < W) C[(int64_t)cb * W + rb] = a11;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + tr + 16 * i, c = c0 + tc + 16 * j;
+      if (r < W && c < W) C[(int64_t)c * W + r] = acc[i][j];
+    }
 }
 
 // H[goff[j] + a, goff[i] + b] = sum over the occurrences s that both reach of
@@ -1266,7 +1280,7 @@ static bool coarse_M_responses(rpf_problem pb, const rpf_pattern* pats, int kind
     } else {
       spmm_csr(s, nb, cols, P->kbb_ptr.p, P->kbb_col.p, P->kbb_val.p, X.p, lw, 1.0, Y.p, nb, 0.0);
     }
-    const int tiles = (int)cdiv(W, 32);
+    const int tiles = (int)cdiv(W, 64);
     hipLaunchKernelGGL(k_occ_gram, dim3((unsigned)((int64_t)nq * tiles * tiles)), dim3(256), 0, s, nb, W, tiles, X.p,
                        lw, Y.p, (int64_t)nb, pb->d_occ_of_pat.p + pb->pat_occ_off[p], Cs.p);
     RPF_LAUNCH_CHECK();
