@@ -7,9 +7,9 @@
  * one Neumann stiffness K, so the library factors K once per pattern,
  * condenses it to the dense boundary flexibility S+ = t K+ t^T (section 2),
  * and applies the dual operator F = sum_s A^(s) S+ A^(s)T to the interface
- * vectors of every occurrence at once as one matrix product (section 4.2).
+ * vectors of every occurrence at once as one matrix product (section 3.2).
  * The interface problem (eq. 3) is solved by projected multivector CG
- * (Table 1) with full re-orthogonalisation and F-normalisation (section 4.3).
+ * (Table 1) with full re-orthogonalisation and F-normalisation (section 3.3).
  *
  * Conventions shared by every call:
  *  - Every call returns an rpf_status; on failure rpf_last_error() gives a
@@ -45,7 +45,7 @@ typedef enum {
   RPF_ENOMEM = -7       /* device allocation failed */
 } rpf_status;
 
-/* Arithmetic of the flexibility product (section 4.2 product S+ W).  FP64 is
+/* Arithmetic of the flexibility product (section 3.2 product S+ W).  FP64 is
  * the plain form.  FP32 stores S+ and W in FP32 with FP32 MFMA accumulation.
  * BF16X3 splits S+ and W into bf16 high and low parts and accumulates the
  * three leading cross products in FP32 on bf16 MFMA.  BF16 uses the high
@@ -105,8 +105,8 @@ void pattern_free(rpf_pattern p);
 
 /* ------------------------------------------------------------------ structure */
 
-/* Signed Boolean assembly and permutation structure (eq. 2; section 4.1;
- * section 5.2 for rotations).  All pointers are host pointers, copied by
+/* Signed Boolean assembly and permutation structure (eq. 2; section 3.1;
+ * section 4.2 for rotations).  All pointers are host pointers, copied by
  * problem_create.
  *
  * A multiplier (node level, dofs_per_node components each, lambda dof
@@ -150,7 +150,7 @@ void problem_free(rpf_problem pb);
 
 /* Y = F X for an m-column interface block (section 2: F = sum_s A^(s) S+ A^(s)T,
  * computed pattern by pattern as one product S+ W over all occurrences,
- * section 4.2).  patterns: host array of the factored and condensed handles,
+ * section 3.2).  patterns: host array of the factored and condensed handles,
  * indexed like the structure's patterns.  X, Y: device, N_lambda x m
  * row-major (ldx, ldy >= m), must not overlap.  prec selects the product
  * arithmetic (the pattern must have been condensed with it).  With
@@ -189,7 +189,7 @@ rpf_status feti_precond(rpf_problem pb, const rpf_pattern* patterns, int32_t m, 
  * Pi_0 = identity).  With rotated
  * occurrences each moved multiplier is turned into the frame of its new
  * place, O_t O_s^T z (O_t, O_s: rotations of the first-endpoint occurrences
- * of the target and source multipliers; section 5.2).  With
+ * of the target and source multipliers; section 4.2).  With
  * RPF_APPLY_PROJECT, W <- Q W (the re-projection of the solver; needs the
  * patterns, else patterns may be NULL).  Z: device, N_lambda x nr row-major
  * (ldz >= nr); W: device, N_lambda x (nr*n_perm) row-major
@@ -202,7 +202,7 @@ rpf_status feti_permute(rpf_problem pb, const rpf_pattern* patterns, int32_t nr,
 typedef enum {
   RPF_CLASSICAL = 0,   /* projected CG per load case (Table 1, left column; FETI-mrhs) */
   RPF_BLOCK_CG = 1,    /* multivector CG, recurrence on the previous block (Table 1, right) */
-  RPF_ORTHODIR = 2     /* multivector CG with full re-orthogonalisation (section 4.3) */
+  RPF_ORTHODIR = 2     /* multivector CG with full re-orthogonalisation (section 3.3) */
 } rpf_method;
 
 typedef struct {
@@ -267,7 +267,7 @@ rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* patterns, int32
 
 /* ------------------------------------------------------------------ tracing */
 
-/* Kernel timing of the flexibility product (section 4.2: S+ W over all the
+/* Kernel timing of the flexibility product (section 3.2: S+ W over all the
  * occurrences of a pattern), the hot kernel of every iteration.  While enabled,
  * every such product launched by feti_apply or block_krylov_solve is bracketed
  * by HIP events on its own stream.  rpf_trace_read synchronises those events,

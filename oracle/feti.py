@@ -41,7 +41,7 @@ import scipy.sparse.linalg as spla
 
 KERNEL_TAU = 1e-10      # READING: eigenvalues below tau * lambda_max(S) span the kernel
 ETA_DROP = 1e-12        # READING: eigenvalues of eta below this * (energy of the block before
-                        # orthogonalisation) are dropped (section 4.3)
+                        # orthogonalisation) are dropped (section 3.3)
 
 
 # =========================================================================== pattern level
@@ -125,7 +125,7 @@ class FetiOracle:
     projector (READING), Q = I - G (G^T G)^{-1} G^T and lambda_0 = G (G^T G)^{-1} e
     (section 2, projector and initialisation).  The solvers take the identity, lumped or
     Dirichlet preconditioner (section 2) for z = Q F~^{-1} r.  For elasticity A^(s) carries the
-    occurrence rotation O^(s) (section 5.2): A^(s)T takes global-frame interface
+    occurrence rotation O^(s) (section 4.2): A^(s)T takes global-frame interface
     values to the pattern frame.
     """
 
@@ -188,7 +188,7 @@ class FetiOracle:
 
     # -- operators ----------------------------------------------------------------------
     def F(self, X: np.ndarray) -> np.ndarray:
-        """F X = sum_s A^(s) S+ A^(s)T X (section 2; section 4.2 computes all occurrences as S+ W)."""
+        """F X = sum_s A^(s) S+ A^(s)T X (section 2; section 3.2 computes all occurrences as S+ W)."""
         X = np.asarray(X, float)
         vec = X.ndim == 1
         X2 = X[:, None] if vec else X
@@ -335,7 +335,7 @@ class FetiOracle:
         """Multivector [Pi_0 z, .., Pi_{np-1} z] for every column of z (section 3.1, eq. for w~).
 
         Columns are ordered (load case, permutation): column l*np + k = Pi_k z_l.  With rotated
-        occurrences the permuted values are carried into the frame of their new place (section 5.2):
+        occurrences the permuted values are carried into the frame of their new place (section 4.2):
         READING: the value taken from multiplier m' for multiplier m is O^(a(m)) O^(a(m'))^T z[m'],
         a(.) the occurrence of the first endpoint, so the field seen from the pattern frame is moved.
         """
@@ -360,7 +360,7 @@ class FetiOracle:
 
     # -- solvers (Table 1) ----------------------------------------------------------------
     def solve_classical(self, d, e, tol, max_it=2000, lam00=None, record=None, precond=None):
-        """Projected CG, Table 1 left column, one load case at a time (FETI-mrhs, section 4.4).
+        """Projected CG, Table 1 left column, one load case at a time (FETI-mrhs, section 3.4).
 
         record: optional list receiving lambda after every iteration (first load case).
         precond: None (identity), "lumped" or "dirichlet": z = Q F~^{-1} r (Table 1, lines 4 and
@@ -412,8 +412,8 @@ class FetiOracle:
         re-projected like the permuted direction.
 
         full_reorth=True: every new block is F-orthogonalised against all stored blocks and
-        F-normalised, W <- W eta^{-1/2}, P <- P eta^{-1/2} with eta = P^T W (section 4.3);
-        eigenvalues of eta below ETA_DROP * e are dropped (pseudo-inverse, section 4.3).
+        F-normalised, W <- W eta^{-1/2}, P <- P eta^{-1/2} with eta = P^T W (section 3.3);
+        eigenvalues of eta below ETA_DROP * e are dropped (pseudo-inverse, section 3.3).
         READING of the scale e: the largest F-energy z^T F z of a column of the block before
         the orthogonalisation (with F-orthonormal stored blocks it is |P_i^T z|^2 summed over
         the stored blocks plus the diagonal of eta), and at least the largest eigenvalue of

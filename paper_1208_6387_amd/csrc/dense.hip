@@ -4,7 +4,7 @@
 //
 // The Cholesky factors of a pattern's interior stiffness, of S + Z Z^T and of
 // the coarse matrix G^T G (section 2 of the paper) all run through potrf; the
-// flexibility product S+ W (section 4.2) and every trailing update run through
+// flexibility product S+ W (section 3.2) and every trailing update run through
 // the same MFMA GEMM.
 #include "common.hpp"
 

@@ -1,6 +1,6 @@
 // Interface level: signed Boolean assembly (eq. 2, with the occurrence
-// rotations of section 5.2), the dual operator F = sum_s A^(s) S+ A^(s)T
-// applied to all occurrences of a pattern as one product S+ W (section 4.2),
+// rotations of section 4.2), the dual operator F = sum_s A^(s) S+ A^(s)T
+// applied to all occurrences of a pattern as one product S+ W (section 3.2),
 // and the coarse projector Q = I - G (G^T G)^{-1} G^T with G = [A^(s) Z] and
 // the identity preconditioner (section 2, projector and initialisation).
 #include "problem.hpp"
@@ -1172,7 +1172,7 @@ __global__ void k_assemble_coarse(int npair, int kmax, int W, const int* pj, con
   H[(int64_t)(goff[i] + b) * ldh + goff[j] + a] = acc;
 }
 
-// H = G^T F~^{-1} G from the responses of the patterns (section 5.3: the coarse operator as the
+// H = G^T F~^{-1} G from the responses of the patterns (section 4.3: the coarse operator as the
 // reaction of each pattern to the traces of the coarse modes that reach its boundary).  With
 // F~^{-1} = beta (sum_s A_s M_s A_s^T) beta, H = sum_s X_s^T M_s X_s with X_s = A_s^T beta G:
 // only the modes of the occurrences in occ_nbr[s] reach s.  Occurrences are coloured so that the

@@ -1,7 +1,7 @@
 // Interface solver: projected multivector conjugate gradient (Table 1 of the
 // paper), with the multivector built by permuting the interface partitions of
 // the residual (section 3.1), full re-orthogonalisation and F-normalisation
-// W <- W eta^{-1/2}, P <- P eta^{-1/2} with eta = P^T W (section 4.3), and a
+// W <- W eta^{-1/2}, P <- P eta^{-1/2} with eta = P^T W (section 3.3), and a
 // pseudo-inverse (dropped eigen-directions) when eta is singular (section
 // 4.3).  Then the displacement recovery of eq. 2.
 //
@@ -19,7 +19,7 @@ namespace rpf {
 namespace {
 
 // A direction of a new block is dropped when its F-energy after the orthogonalisation is below
-// eta_drop(prec) times the block's energy before it (section 4.3: rank deficiency of eta).  The
+// eta_drop(prec) times the block's energy before it (section 3.3: rank deficiency of eta).  The
 // ratio is limited by the accuracy of the product: noise of relative size eps leaves an energy
 // fraction of about eps^2, so the low-precision forms use larger thresholds.
 constexpr double ETA_DROP = 1e-12;
@@ -37,7 +37,7 @@ inline double eta_drop(int prec) {
 // One thread per output entry (consecutive threads write consecutive entries of a row).
 // With rotated occurrences (dpn 3) the value moved from multiplier src to mult is
 // carried into the frame of its new place: O_t O_s^T z[src], O_t / O_s the rotations
-// of the first-endpoint occurrences of mult / src (section 5.2).
+// of the first-endpoint occurrences of mult / src (section 4.2).
 __global__ void k_permute(int64_t n_lambda, int dpn, int n_mult, int nr, int np, const int* perm, const int* ep_occ,
                           const double* rot, const double* z, int64_t ldz, double* Zb, int64_t ldb) {
   const int m = nr * np;
@@ -61,7 +61,7 @@ __global__ void k_permute(int64_t n_lambda, int dpn, int n_mult, int nr, int np,
   }
 }
 
-// Normalisation of a new block (section 4.3): T with T^T eta T = I on the kept directions.
+// Normalisation of a new block (section 3.3): T with T^T eta T = I on the kept directions.
 // The energy of column c before the orthogonalisation is |B_c|^2 + eta_cc (B = P_stored^T Z,
 // ka x m, ld ka; F-orthonormal stored blocks).  Diagonal form (classical CG per load case):
 // T = diag(eta_cc^{-1/2}) keeping eta_cc > tau * energy_c.  Block form: the eigen rule keeps w_i >

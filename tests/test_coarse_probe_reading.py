@@ -1,5 +1,5 @@
 """The coarse operator G^T F~^{-1} G assembled from the patterns' responses to probed traces of the
-coarse modes (section 5.3's pattern-frame assembly, in the form the library uses): occurrences that
+coarse modes (section 4.3's pattern-frame assembly, in the form the library uses): occurrences that
 meet through a scaling group are neighbours; occurrences two steps apart get different colours; one
 probe column per (colour, mode); H[j, i] is the sum over the occurrences s reached by both of
 C_s[colour(j), colour(i)], C_s = X_s^T M_s X_s with X_s = A_s^T beta G E.  Checked on the CPU

@@ -1,4 +1,4 @@
-"""Periodic shortcut of the multivector product and the academic random-SPD ring (section 3),
+"""Periodic shortcut of the multivector product and the academic random-SPD ring (sections 3.1 and 3.4.1),
 on the HIP path through the C ABI, against the CPU oracle.
 
 Tolerances: displacements within 1e-8 (FP64) and 1e-6 (bf16x3 with FP64 refinement) of the
@@ -101,7 +101,7 @@ def test_periodic_shortcut_refused_on_non_periodic_structure(R):
 
 
 def test_random_spd_ring_iteration_study(R):
-    """The academic study of section 3 on the GPU: Dirichlet preconditioner, random loads; the
+    """The academic study of section 3.4.1 on the GPU: Dirichlet preconditioner, random loads; the
     multivector of the n_occ shifts against classical CG, iteration counts as in the oracle."""
     from paper_1208_6387_amd import structure as ST
     saving = {}
@@ -128,7 +128,7 @@ def test_random_spd_ring_iteration_study(R):
 
 @pytest.mark.parametrize("n_occ", [3, 4])
 def test_enriched_multivector(R, n_occ):
-    """The two-stand donut's enriched multivector (section 5.1.2): product permutations of the ring
+    """The two-stand donut's enriched multivector (section 4.1.2): product permutations of the ring
     and stand interfaces, permuted exactly on the GPU, and solved to the oracle's displacements."""
     from paper_1208_6387_amd import structure as ST
     p = W.ring_heat(n_occ, (6, 6), stands=(1, 0), enriched=True, n_rhs=2, dirichlet_bottom=True)

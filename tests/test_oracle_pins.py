@@ -213,7 +213,7 @@ def test_stand_interface_replicated(golden_dir):
 
 
 def test_ring_coarse_G_structure(golden_dir):
-    """Section 5.3: block structure and signs of G on a three-occurrence ring."""
+    """Section 4.3: block structure and signs of G on a three-occurrence ring."""
     gold = json.load(open(os.path.join(golden_dir, "ring_coarse_G.json")))
     p = W.ring_heat(3, (2, 2), n_perm=3, dirichlet_bottom=False)
     o = O.FetiOracle(p)
@@ -267,7 +267,7 @@ def test_periodic_ring_commutation():
 
 
 def test_rotated_ring_permutation_carries_frames():
-    """Sections 3.1 and 5.2: on a periodic ring of rotated elastic sectors F commutes with the
+    """Sections 3.1 and 4.2: on a periodic ring of rotated elastic sectors F commutes with the
     permutations only when each moved multiplier is turned into the frame of its new place
     (O_t O_s^T); moving the components as they are does not commute."""
     p = W.ring_elast(4, (1, 2, 1), n_perm=4, clamp=False)
@@ -287,7 +287,7 @@ def test_rotated_ring_permutation_carries_frames():
 
 
 def test_rotated_ring_brute_force():
-    """Section 5.2 assembly with rotated occurrences: FETI on a clamped ring of three sectors
+    """Section 4.2 assembly with rotated occurrences: FETI on a clamped ring of three sectors
     reproduces the directly assembled global solution and its interface forces."""
     p = W.ring_elast(3, (2, 3, 2), n_rhs=2)
     o = O.FetiOracle(p)
@@ -301,7 +301,7 @@ def test_rotated_ring_brute_force():
 
 def test_uneven_three_patterns_brute_force():
     """Three patterns of uneven size (plates, ring sectors, a base block) joined by algebraic glue
-    with rotated frames (sections 2 and 5.2): FETI reproduces the directly assembled global solution
+    with rotated frames (sections 2 and 4.2): FETI reproduces the directly assembled global solution
     and its interface forces, G^T lambda = e holds, and every floating occurrence is in equilibrium
     against its rigid modes."""
     p = W.uneven_three(plate=(6, 8, 2), sector=(2, 6, 4), base=6, n_sectors=4, plates_per_sector=1, n_perm=4,
@@ -387,7 +387,7 @@ def test_classical_converges_within_rank():
 
 
 def test_block_not_slower_than_classical():
-    """Sections 3.1 and 6: the multivector method needs no more iterations (soft check)."""
+    """Sections 3.1 and 5: the multivector method needs no more iterations (soft check)."""
     p = W.config(0)
     o = O.FetiOracle(p)
     _, _, sc = o.solve("classical")
@@ -492,7 +492,7 @@ def test_precond_solutions_match_brute_force():
             assert its * 3 < s_id["iterations"], (kind, method, its)
 
 
-# ----------------------------------------------------------------------------- academic study (section 3 tests)
+# ----------------------------------------------------------------------------- academic study (section 3.4.1)
 
 @pytest.mark.parametrize("n_occ", [5, 9])
 def test_random_spd_ring_solution(n_occ):
@@ -581,7 +581,7 @@ def test_periodic_shortcut_on_a_non_periodic_structure_is_wrong():
     assert max(np.abs(x - y).max() for x, y in zip(u, ub)) > 1e-3 * max(np.abs(y).max() for y in ub)
 
 
-# ----------------------------------------------------------------------------- enriched multivector (section 5.1.2)
+# ----------------------------------------------------------------------------- enriched multivector (section 4.1.2)
 
 def _paper_label(p, m):
     """Interface label of multiplier m in the paper's numbering of the two-stand donut: ring pieces

@@ -5,8 +5,8 @@ Neumann stiffness matrix K of a pattern and its nodal loads.  It holds none of
 the method's own arithmetic (no condensation, no interface operator, no
 solver); both the CPU oracle and the GPU library receive what it builds.
 
-Elements (the paper's test problems are thermal and elastic, section 4.1 and
-section 5.2; its matrices came from an external mesher and are not available):
+Elements (the paper's test problems are thermal and elastic, section 3.4 and
+section 4.2; its matrices came from an external mesher and are not available):
 
 * Q1 bilinear quadrilateral for the scalar heat equation, conductivity k,
   integrated with 2x2 Gauss points.  On a square it is the classical

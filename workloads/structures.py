@@ -3,12 +3,12 @@
 A ``Problem`` is the statement of the method's input (the dual split of
 section 2, eq. 2): for every pattern its Neumann stiffness K (CSR) and the set
 of boundary nodes, for every occurrence the pattern it instantiates, its
-rotation O (pattern frame -> global frame, section 5.2) and its loads f, and
+rotation O (pattern frame -> global frame, section 4.2) and its loads f, and
 the signed Boolean assembly A as a list of multipliers, each joining one node of
 one occurrence (sign +1) to one node of another (sign -1), or, for a Dirichlet
-condition imposed by a multiplier (Total FETI reading of section 5.1.3), to a
+condition imposed by a multiplier (Total FETI reading of section 4.1.3), to a
 single node.  It also carries the permutation maps used to build multivectors
-(section 4.1): index structure, not arithmetic.
+(section 3.1): index structure, not arithmetic.
 
 Readings taken here (the paper does not define them for 3-D grids):
 
@@ -160,10 +160,10 @@ def pattern_boundaries(patterns, occ_pattern, mult_occ, mult_node):
 
 
 def permutation_maps(occ_pattern, mult_occ, mult_node, n_perm, product=False):
-    """Cyclic shifts within classes of equivalent multipliers (section 4.1 and 5.1 examples).
+    """Cyclic shifts within classes of equivalent multipliers (section 3.1 and 4.1 examples).
 
     product=False: Pi_k shifts every class by k.  product=True (the enriched multivector of the
-    two-stand donut, section 5.1.2): the classes are grouped by the pair of patterns they join, each
+    two-stand donut, section 4.1.2): the classes are grouped by the pair of patterns they join, each
     group gets its own shift digit, and the rows run over every combination of digits (the first
     group, the one with the largest classes, varying fastest); n_perm None takes them all.
     """
@@ -303,8 +303,8 @@ def ring_heat(n_occ=3, pat_shape=(4, 4), stand=False, n_rhs=1, n_perm=None, seed
     """Periodic ring of unit-square heat patterns (section 3's toy problem, cut open as a strip
     whose last right edge is glued to the first left edge).  Interface (s, s+1) has the right edge
     of s as its '+' side.  stand=True adds one stand pattern (a 1 x 1/2 rectangle) on top of
-    occurrence n_occ-1 (section 5.1.1).  stands: ring occurrences that each carry a stand, in the
-    order of the stand occurrences (section 5.1.2 puts two stands on ring pieces 2 and 1: stands=
+    occurrence n_occ-1 (section 4.1.1).  stands: ring occurrences that each carry a stand, in the
+    order of the stand occurrences (section 4.1.2 puts two stands on ring pieces 2 and 1: stands=
     (1, 0)); every stand has its own nodes apart from its base edge.  enriched=True builds the
     product permutations of the enriched multivector (independent shifts of the ring interfaces
     and of the stand interfaces; n_perm None takes all of them).  dirichlet_bottom fixes the bottom
@@ -435,7 +435,7 @@ def rot_z(angle: float) -> np.ndarray:
 def ring_elast(n_occ=3, pat_shape=(2, 3, 2), r_in=1.0, r_out=1.5, height=0.5, n_rhs=1, n_perm=None, seed=3,
                tol=1e-8, clamp=True):
     """Closed ring of n_occ identical annular-sector bricks (elasticity), occurrence s rotated by
-    2 pi s / n_occ about z (section 5.2: rotations in the assembly; section 5.3: the ring of
+    2 pi s / n_occ about z (section 4.2: rotations in the assembly; section 4.3: the ring of
     rotated occurrences).  pat_shape = (radial, circumferential, axial) elements; the sector spans
     [0, 2 pi / n_occ].  The bottom face of occurrence 0 is clamped (clamp=True), nothing
     (False), or, with clamp="periodic", the bottom-face nodes off the interfaces of every
