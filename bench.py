@@ -48,6 +48,7 @@ WORKLOADS = {
                                        dict(max_blocks=0, inner_tol=1e-4)),
 }
 PREC_NAMES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16": 3}
+PHASES = ("ms_factor", "ms_condense", "ms_loads", "ms_coarse", "ms_iterate", "ms_recover")
 METHODS = {"classical": 0, "block_cg": 1, "orthodir": 2}
 
 
@@ -132,18 +133,25 @@ def main():
     PRECONDS = {"none": R.PRECOND_NONE, "lumped": R.PRECOND_LUMPED, "dirichlet": R.PRECOND_DIRICHLET}
 
     def step(prec: int, pc: int = PRECONDS[args.precond]):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
         pats = []
         for pat, v in zip(p.patterns, kvals):
             pats.append(R.pattern_factor(pat.K.indptr, pat.K.indices, v, pat.bdofs, pat.dpn,
                                          expected_kernel_dim=pat.kernel_dim))
+        ev[1].record()
         for P in pats:
             R.pattern_condense(P, R.FP64)
             if prec != R.FP64:
                 R.pattern_condense(P, prec)
+        ev[2].record()
         res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=args.tol, max_it=args.max_it, method=method,
                                    prec=prec, inner_tol=settings["inner_tol"], max_blocks=settings["max_blocks"],
                                    lam_out=lam, u_out=u, precond=pc, periodic=args.periodic,
                                    coarse=PRECONDS[args.coarse])
+        # the solve has synchronised the stream, so the events are complete
+        res.stats["ms_factor"] = ev[0].elapsed_time(ev[1])
+        res.stats["ms_condense"] = ev[1].elapsed_time(ev[2])
         for P in pats:
             P.free()
         return res
@@ -172,7 +180,10 @@ def main():
         ms = (t1 - t0) * 1e3 / args.steps
         st = stats[-1]
         assert st["rel_residual"] <= args.tol * 1.0000001, st
-        results[form] = dict(ms=ms, stats=st, trace=tr)
+        # untimed: the last step's solution checked against the problem statement
+        chk = solution_check(p, lam.cpu().numpy(), ST.split_u(p, u))
+        results[form] = dict(ms=ms, stats=st, trace=tr, check=chk)
+        log(f"[bench] {form} solution check: {chk}")
         log(f"[bench] {form}: {ms:.2f} ms/step, iterations {st['iterations']}, sweeps {st['sweeps']}, "
             f"rel_res {st['rel_residual']:.2e}, gemm {tr['count']} launches {tr['ms']:.2f} ms")
 
@@ -196,8 +207,7 @@ def main():
             assert st["rel_residual"] <= args.tol * 1.0000001, st
             extra[name][form] = {"ms": round(ms, 3), "iterations": st["iterations"], "sweeps": st["sweeps"],
                                  "rel_residual": st["rel_residual"],
-                                 "phase_ms": {q: round(st[q], 3) for q in ("ms_loads", "ms_coarse", "ms_iterate",
-                                                                           "ms_recover")}}
+                                 "phase_ms": {q: round(st[q], 3) for q in PHASES}}
             log(f"[bench] {form} + {name}: {ms:.2f} ms/step, iterations {st['iterations']}, sweeps {st['sweeps']}")
         if "fp64" in extra[name] and len(extra[name]) > 1:
             extra[name]["speedup_vs_fp64"] = {k: round(extra[name]["fp64"]["ms"] / v["ms"], 3)
@@ -245,12 +255,13 @@ def main():
         "iterations": hr["stats"]["iterations"],
         "sweeps": hr["stats"]["sweeps"],
         "rel_residual": hr["stats"]["rel_residual"],
-        "phase_ms": {k: round(hr["stats"][k], 3) for k in ("ms_loads", "ms_coarse", "ms_iterate", "ms_recover")},
+        "phase_ms": {k: round(hr["stats"][k], 3) for k in PHASES},
+        "check": hr["check"],
         "roofline": roofline(head),
         "forms": {k: {"ms": round(v["ms"], 3), "iterations": v["stats"]["iterations"],
                       "sweeps": v["stats"]["sweeps"], "rel_residual": v["stats"]["rel_residual"],
-                      "phase_ms": {q: round(v["stats"][q], 3) for q in ("ms_loads", "ms_coarse", "ms_iterate",
-                                                                        "ms_recover")},
+                      "phase_ms": {q: round(v["stats"][q], 3) for q in PHASES},
+                      "check": v["check"],
                       "roofline": roofline(k)}
                   for k, v in results.items()},
     }
@@ -264,6 +275,54 @@ def main():
         it_ref = results.get("fp64", hr)["stats"]["iterations"]
         out["cpu_baseline"] = cpu_baseline(p, cfg_idx, it_ref, args.cpu_iterations, args.tol)
     print(json.dumps(out), flush=True)
+
+
+def solution_check(p, lam, u):
+    """What the solution satisfies, from the problem statement alone (no oracle): the largest local
+    equilibrium residual |K u - f + t^T A^T lambda| of any occurrence and load case over max |f|
+    (the rows of eq. 2 of each subdomain), the largest interface gap |O_a u_a - O_b u_b| over max |u|
+    (continuity, B u = 0), and the largest |u| on a Dirichlet node over max |u|."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    dpn, nr = p.dpn, lam.shape[1]
+    lm = lam.reshape(p.n_mult_nodes, dpn, nr)
+    off = np.zeros(p.n_occ + 1, np.int64)
+    for s in range(p.n_occ):
+        off[s + 1] = off[s] + p.patterns[p.occ_pattern[s]].n_nodes
+    U = np.concatenate([x.reshape(-1, dpn, nr) for x in u])          # (sum nodes, dpn, nr)
+    B = np.zeros_like(U)
+    for e in range(2):
+        sel = np.nonzero(p.mult_occ[:, e] >= 0)[0]
+        s = p.mult_occ[sel, e]
+        loc = lm[sel] * p.mult_sign[sel, e].astype(float)[:, None, None]
+        if p.has_rotation and dpn > 1:
+            loc = np.einsum("kca,kcr->kar", p.occ_rot[s][:, :dpn, :dpn], loc)
+        np.add.at(B, off[s] + p.mult_node[sel, e], loc)
+
+    def occ_res(s):
+        K = p.patterns[p.occ_pattern[s]].K
+        r = K @ u[s] - p.f_local[s] + B[off[s]:off[s + 1]].reshape(-1, nr)
+        return float(np.abs(r).max())
+
+    with ThreadPoolExecutor(8) as ex:
+        eq = max(ex.map(occ_res, range(p.n_occ)))
+    fmax = max(float(np.abs(x).max()) for x in p.f_local)
+    umax = max(float(np.abs(x).max()) for x in u)
+    gap = 0.0
+    inter = np.nonzero(p.mult_occ[:, 1] >= 0)[0]
+    for chunk in np.array_split(inter, 16):
+        ends = []
+        for e in range(2):
+            s = p.mult_occ[chunk, e]
+            ue = U[off[s] + p.mult_node[chunk, e]]
+            if p.has_rotation and dpn > 1:
+                ue = np.einsum("kab,kbr->kar", p.occ_rot[s][:, :dpn, :dpn], ue)
+            ends.append(ue)
+        if len(chunk):
+            gap = max(gap, float(np.abs(ends[0] - ends[1]).max()))
+    dsel = np.nonzero(p.mult_occ[:, 1] < 0)[0]
+    clamp = float(np.abs(U[off[p.mult_occ[dsel, 0]] + p.mult_node[dsel, 0]]).max()) if len(dsel) else 0.0
+    return {"equilibrium": eq / fmax, "continuity": gap / umax, "dirichlet": clamp / umax}
 
 
 def traffic_for(workload, form):

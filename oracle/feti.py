@@ -360,48 +360,41 @@ class FetiOracle:
 
     # -- solvers (Table 1) ----------------------------------------------------------------
     def solve_classical(self, d, e, tol, max_it=2000, lam00=None, record=None, precond=None):
-        """Projected CG, Table 1 left column, one load case at a time (FETI-mrhs, section 3.4).
+        """Projected conjugate gradient for each load case on its own (FETI-mrhs, section 3.4).
+
+        The left column of Table 1 is its right column with one direction per iteration and no
+        permutation, so each load case runs solve_block below on its own column, with the identity
+        permutation and the short recurrence (the new direction made F-orthogonal to the previous
+        one only).  Stopping per load case: ||r|| / ||r_0|| <= tol.
 
         record: optional list receiving lambda after every iteration (first load case).
-        precond: None (identity), "lumped" or "dirichlet": z = Q F~^{-1} r (Table 1, lines 4 and
-        5.5).  READING: the projector keeps the identity in place of F~^{-1} whatever the
-        preconditioner (the paper allows any of them there) unless the oracle was built with
-        coarse=..., which puts that preconditioner in Q, Q^T and lambda_0 (then the residual and
-        the products take Q^T, the directions Q).
+        precond: None (identity), "lumped" or "dirichlet": z = Q F~^{-1} r (section 2).  READING: the
+        projector keeps the identity in place of F~^{-1} whatever the preconditioner (the paper
+        allows any of them there) unless the oracle was built with coarse=..., which puts that
+        preconditioner in Q, Q^T and lambda_0 (then the residual and the products take Q^T, the
+        directions Q).
         """
         nr = d.shape[1]
-        lam = self.lambda0(e, lam00)
-        its = []
-        hist = []
+        lam = np.zeros((self.n_lambda, nr))
+        its, hist = [], []
         for c in range(nr):
-            l = lam[:, c].copy()
-            r = self.Qt(d[:, c] - self.F(l))
-            r0 = np.linalg.norm(r)
-            z = self.Q(self.precondition(r, precond))
-            w = z.copy()
-            h = [1.0]
-            j = 0
-            while r0 > 0 and np.linalg.norm(r) > tol * r0 and j < max_it:
-                p = self.Qt(self.F(w))
-                wp = w @ p
-                alpha = (w @ r) / wp
-                l += alpha * w
-                r -= alpha * p
-                z = self.Q(self.precondition(r, precond))
-                beta = -(p @ z) / wp
-                w = z + beta * w
-                j += 1
-                h.append(np.linalg.norm(r) / r0)
-                if record is not None and c == 0:
-                    record.append(l.copy())
-            lam[:, c] = l
-            its.append(j)
-            hist.append(h)
+            rec = [] if (record is not None and c == 0) else None
+            l00 = None if lam00 is None else lam00[:, c:c + 1]
+            lc, st = self.solve_block(d[:, c:c + 1], e[:, c:c + 1], tol, max_it, lam00=l00, full_reorth=False,
+                                      record=rec, precond=precond, permute=False)
+            lam[:, c] = lc[:, 0]
+            its.append(st["iterations"])
+            hist.append(st["history"])
+            if rec is not None:
+                record.extend(x[:, 0] for x in rec)
         return lam, dict(iterations=its, history=hist)
 
     def solve_block(self, d, e, tol, max_it=2000, lam00=None, full_reorth=True, record=None, precond=None,
-                    periodic=False):
+                    periodic=False, permute=True):
         """Multivector projected CG, Table 1 right column.
+
+        permute=False takes the identity in place of the structure's permutations (one direction per
+        column of z: the classical method for a single column).
 
         precond: as in solve_classical; the permutations act on z = Q F~^{-1} r.
         periodic: the shortcut of truly periodic structures (section 3.1, after Table 1): when F,
@@ -427,9 +420,11 @@ class FetiOracle:
         r = self.Qt(d - self.F(lam))
         r0 = np.linalg.norm(r, axis=0)
         r0[r0 == 0] = 1.0
+        perm = self.permute if permute else (lambda x: x)
+        periodic = periodic and permute
         z = self.Q(self.precondition(r, precond))
-        Zb = self.Q(self.permute(z))          # READING: re-project permuted directions
-        Pz = self.Qt(self.permute(self.Qt(self.F(z)))) if periodic else None
+        Zb = self.Q(perm(z))          # READING: re-project permuted directions
+        Pz = self.Qt(perm(self.Qt(self.F(z)))) if periodic else None
         Ws, Ps = [], []
         W_prev = P_prev = None
         hist = [1.0]
@@ -482,9 +477,9 @@ class FetiOracle:
             if record is not None:
                 record.append(lam.copy())
             z = self.Q(self.precondition(r, precond))
-            Zb = self.Q(self.permute(z))
+            Zb = self.Q(perm(z))
             if periodic:
-                Pz = self.Qt(self.permute(self.Qt(self.F(z))))
+                Pz = self.Qt(perm(self.Qt(self.F(z))))
         return lam, dict(iterations=j, history=hist, rank_drops=drops)
 
     # -- recovery -------------------------------------------------------------------------

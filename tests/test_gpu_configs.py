@@ -1,0 +1,219 @@
+"""Parity at the benchmark configurations, through the C ABI, in the launch configuration bench.py
+times, against the CPU oracle.
+
+* 64 occurrences of the 12^3-brick elasticity pattern, one load case, 8 permuted copies (FP64 and
+  mixed, ORTHODIR): the permuted multivector against the oracle's permutation element by element,
+  and u against the oracle's reference solution.
+* the same structure with 8 load cases (block CG): u against the oracle's reference solution.
+* 512 occurrences of the 20^3-brick pattern, 16 load cases: the pattern's S, S+ and Z Z^T on
+  sampled columns against the oracle's values (tests/golden/elast20_pattern_columns.npz, written
+  by tests/golden/make_pattern_columns.py), and the FP64 and mixed block-CG solutions through local
+  equilibrium of all 512 occurrences, interface continuity and the clamped face.
+
+The reference solutions are the oracle's own solves run to a relative residual of 1e-12.  The GPU
+stops at 1e-8 as bench.py does; since two iterates at that residual can differ by more than 1e-8
+in u, the FP64 displacement bound of 1e-8 is checked on solves run to 1e-10 (the error at 1e-8 is
+checked against 1e-7).  Each test prints the errors it measured.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import props
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "elast20_pattern_columns.npz")
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_1208_6387_amd as R
+    R.load()
+    return R
+
+
+def _reference(o, method):
+    """The oracle's displacements and multipliers at a relative residual of 1e-12."""
+    g, d, e = o.loads()
+    if method == "classical":
+        lam, _ = o.solve_classical(d, e, 1e-12)
+    else:
+        lam, _ = o.solve_block(d, e, 1e-12, full_reorth=False)
+    return lam, o.recover(lam, d, g)
+
+
+def _solve(R, p, pats, pb, form, method, tol=1e-8, **kw):
+    from paper_1208_6387_amd import structure as ST
+    prec = R.FP64 if form == "fp64" else R.BF16X3
+    meth = {"orthodir": R.ORTHODIR, "block_cg": R.BLOCK_CG}[method]
+    res = R.block_krylov_solve(pb, pats, ST.loads_to_device(p), p.n_rhs, tol=tol, max_it=3000, method=meth,
+                               prec=prec, inner_tol=1e-4, **kw)
+    return res, res.lam.cpu().numpy(), ST.split_u(p, res.u)
+
+
+# ------------------------------------------------------------------ 64 occurrences, 8 permutations
+@pytest.fixture(scope="module")
+def config1(R):
+    from paper_1208_6387_amd import structure as ST
+    p = W.config(1)
+    print("\n[configs] 64 x 12^3 bricks, one load case, 8 permutations: oracle reference solve", flush=True)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats, (R.FP64, R.BF16X3))
+    pb = ST.create_problem(p)
+    o = O.FetiOracle(p)
+    lam_o, u_o = _reference(o, "classical")
+    return p, o, pats, pb, lam_o, u_o
+
+
+@pytest.mark.timeout(600)
+def test_config1_permuted_multivector(config1, R):
+    """[Pi_0 z, .., Pi_7 z] for 76,080 multipliers: exact copies of the oracle's permutation (no
+    rotation here, so the values move unchanged), and Q applied to it at 1e-12."""
+    p, o, pats, pb, _, _ = config1
+    assert pb.n_perm == 8
+    z = np.random.default_rng(11).standard_normal((p.n_lambda, 2))
+    zd = torch.from_numpy(z).cuda()
+    Wg = R.feti_permute(pb, zd).cpu().numpy()
+    ref = o.permute(z)
+    assert Wg.shape == ref.shape
+    assert np.array_equal(Wg, ref)
+    Wq = R.feti_permute(pb, zd, patterns=pats, project=True).cpu().numpy()
+    refq = o.Q(ref)
+    err = np.abs(Wq - refq).max() / np.abs(refq).max()
+    print(f"[configs] permuted multivector with Q: max rel err {err:.2e}")
+    assert err <= 1e-12, err
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("form,tol,bound", [("fp64", 1e-8, 1e-7), ("fp64", 1e-10, 1e-8), ("bf16x3", 1e-8, 1e-6),
+                                            ("bf16x3", 1e-10, 1e-8)])
+def test_config1_solution(config1, R, form, tol, bound):
+    """ORTHODIR over the 8 permuted copies, as the configuration names it.  At the timed stopping
+    residual (1e-8) two converged iterates may differ by more than 1e-8 in u, so the FP64 form is
+    also run to 1e-10, where u must lie within 1e-8 of the oracle's reference; the mixed form
+    (bf16x3 products, FP64 refinement) within 1e-6 at 1e-8 and within 1e-8 at 1e-10.  lambda within
+    ten times the u bound, the FP64 residual at tol against the oracle's operator, equilibrium of
+    all 64 occurrences, continuity and the clamp within the u bound."""
+    p, o, pats, pb, lam_o, u_o = config1
+    res, lam, u = _solve(R, p, pats, pb, form, "orthodir", tol=tol)
+    g, d, e = o.loads()
+    r0 = np.linalg.norm(o.Q(d - o.F(o.lambda0(e))), axis=0)
+    r = np.linalg.norm(o.Q(d - o.F(lam)), axis=0)
+    u_err = props.rel_err(u, u_o)
+    lam_err = np.abs(lam - lam_o).max() / np.abs(lam_o).max()
+    scale = max(np.abs(x).max() for x in u_o)
+    eq = props.equilibrium_residual(p, u, lam)
+    gap = props.continuity_gap(p, u) / scale
+    print(f"[configs] 64 occ, 8 perms, {form}, tol {tol:.0e}: its={res.stats['iterations']} "
+          f"sweeps={res.stats['sweeps']} res={np.max(r / r0):.2e} u_err={u_err:.2e} lam_err={lam_err:.2e} "
+          f"equilibrium={eq:.2e} continuity={gap:.2e}")
+    assert np.max(r / r0) <= 1.05 * tol
+    assert u_err <= bound and lam_err <= 10 * bound
+    assert eq <= 1e-10
+    assert gap <= bound
+    assert props.dirichlet_max(p, u) <= bound * scale
+
+
+# ------------------------------------------------------------------ 64 occurrences, 8 load cases
+@pytest.fixture(scope="module")
+def config2(R):
+    from paper_1208_6387_amd import structure as ST
+    p = W.config(2)
+    print("\n[configs] 64 x 12^3 bricks, 8 load cases: oracle reference solve", flush=True)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats, (R.FP64, R.BF16X3))
+    pb = ST.create_problem(p)
+    o = O.FetiOracle(p)
+    lam_o, u_o = _reference(o, "block_cg")
+    return p, o, pats, pb, lam_o, u_o
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("form,method,tol,bound", [("fp64", "block_cg", 1e-8, 1e-7), ("fp64", "block_cg", 1e-10, 1e-8),
+                                                   ("bf16x3", "block_cg", 1e-8, 1e-6),
+                                                   ("fp64", "orthodir", 1e-10, 1e-8)])
+def test_config2_u_against_oracle(config2, R, form, method, tol, bound):
+    """u of every load case against the oracle's reference: within 1e-6 for the mixed form at the
+    timed 1e-8 residual, within 1e-8 for the FP64 form run to 1e-10 (and 1e-7 at 1e-8), with
+    continuity and the clamp at the same level and equilibrium of all 64 occurrences."""
+    p, o, pats, pb, lam_o, u_o = config2
+    res, lam, u = _solve(R, p, pats, pb, form, method, tol=tol)
+    u_err = props.rel_err(u, u_o)
+    scale = max(np.abs(x).max() for x in u_o)
+    gap = props.continuity_gap(p, u) / scale
+    eq = props.equilibrium_residual(p, u, lam)
+    print(f"[configs] 64 occ, 8 rhs, {form} {method}, tol {tol:.0e}: its={res.stats['iterations']} "
+          f"res={res.stats['rel_residual']:.2e} u_err={u_err:.2e} equilibrium={eq:.2e} continuity={gap:.2e}")
+    assert res.stats["rel_residual"] <= tol
+    assert u_err <= bound
+    assert gap <= bound
+    assert eq <= 1e-10
+    assert props.dirichlet_max(p, u) <= bound * scale
+
+
+# ------------------------------------------------------------------ 512 occurrences, 16 load cases
+@pytest.fixture(scope="module")
+def config4(R):
+    from paper_1208_6387_amd import structure as ST
+    p = W.config(4)
+    print("\n[configs] 512 x 20^3 bricks, 16 load cases", flush=True)
+    pats = ST.factor_patterns(p)
+    ST.condense_patterns(pats, (R.FP64, R.BF16X3))
+    pb = ST.create_problem(p)
+    return p, pats, pb
+
+
+@pytest.mark.timeout(600)
+def test_config4_pattern_columns(config4, R):
+    """S, S+ and Z Z^T of the 20^3-brick pattern (n_b = 7,206) on 8 columns against the oracle: 768
+    sampled rows and the diagonal one by one, and each whole column through its 2-norm and its
+    dot product with a seeded weight vector."""
+    p, pats, pb = config4
+    gold = np.load(GOLDEN)
+    cols, rows = gold["cols"], gold["rows"]
+    nb = int(gold["n_b"])
+    assert pats[0].n_b == nb and pats[0].kernel_dim == int(gold["kernel_dim"])
+    w = np.random.default_rng(int(gold["weight_seed"])).standard_normal(nb)
+    S = R.pattern_export(pats[0], "S")
+    Sp = R.pattern_export(pats[0], "Splus")
+    Z = R.pattern_export(pats[0], "Z")
+    idx = torch.from_numpy(cols).cuda()
+    mats = {"S": S[:, idx].cpu().numpy(), "Splus": Sp[:, idx].cpu().numpy(),
+            "ZZt": (Z @ Z[idx].T).cpu().numpy()}
+    for name, tol in (("S", 1e-12), ("Splus", 1e-9), ("ZZt", 1e-10)):
+        C = mats[name]
+        scale = float(gold[name + "_absmax"])
+        e_rows = np.abs(C[rows] - gold[name + "_rows"]).max() / scale
+        e_diag = np.abs(C[cols, np.arange(len(cols))] - gold[name + "_diag"]).max() / scale
+        e_norm = np.abs(np.linalg.norm(C, axis=0) - gold[name + "_norm"]).max() / np.abs(gold[name + "_norm"]).max()
+        e_wdot = np.abs(w @ C - gold[name + "_wdot"]).max() / (np.linalg.norm(w) * np.abs(gold[name + "_norm"]).max())
+        print(f"[configs] 20^3 pattern {name}: rows {e_rows:.2e} diag {e_diag:.2e} norm {e_norm:.2e} "
+              f"wdot {e_wdot:.2e}")
+        assert max(e_rows, e_diag, e_norm, e_wdot) <= tol, name
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("form", ["fp64", "bf16x3"])
+def test_config4_solution_all_occurrences(config4, R, form):
+    """Block CG as bench.py times it, in both forms: local equilibrium of all 512 occurrences and
+    16 load cases, interface continuity at every multiplier and the clamped face.  The continuity
+    bound is the displacement bound of the form (1e-8 FP64, 1e-6 mixed) relative to max |u|."""
+    p, pats, pb = config4
+    res, lam, u = _solve(R, p, pats, pb, form, "block_cg", max_blocks=48)
+    scale = max(np.abs(x).max() for x in u)
+    eq = props.equilibrium_residual(p, u, lam)
+    gap = props.continuity_gap(p, u) / scale
+    dmax = props.dirichlet_max(p, u) / scale
+    print(f"[configs] 512 occ, 16 rhs, {form}: its={res.stats['iterations']} sweeps={res.stats['sweeps']} "
+          f"res={res.stats['rel_residual']:.2e} equilibrium={eq:.2e} continuity={gap:.2e} clamp={dmax:.2e}")
+    bound = 1e-8 if form == "fp64" else 1e-6
+    assert res.stats["rel_residual"] <= 1e-8
+    assert eq <= 1e-9
+    assert gap <= bound
+    assert dmax <= bound

@@ -5,9 +5,9 @@
   oracle's own F and Q: the FP64 interface residual Q^T (d - F lambda) recomputed on the CPU.
 * 512-occurrence elasticity (20^3 bricks, 16 load cases): too large for the oracle's condensation;
   the solution is checked through properties that characterise it at any size, computed on the
-  CPU from the problem statement only: interface continuity of u at every multiplier, u = 0 on
-  the clamped face, and the local equilibrium K^(s) u^(s) = f^(s) - t^T A^(s)T lambda on sampled
-  occurrences.
+  CPU from the problem statement only (tests/props.py): interface continuity of u at every
+  multiplier, u = 0 on the clamped face, and the local equilibrium K^(s) u^(s) = f^(s) - t^T A^(s)T
+  lambda of every occurrence.
 * uneven batch (48 plates, 16 ring sectors, one base block, rotated frames, 8 permutations): the
   operator in every precision against the oracle's F, and FP64 / mixed ORTHODIR solutions against
   the oracle's residual and displacements.
@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import props
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -28,46 +29,6 @@ def R():
     import paper_1208_6387_amd as R
     R.load()
     return R
-
-
-def _local_forces(p, lam, s, pat):
-    """t^T A^(s)T lambda for occurrence s (pattern frame), from the multiplier lists."""
-    dpn = p.dpn
-    out = np.zeros((pat.n, lam.shape[1]))
-    O3 = p.occ_rot[s][:dpn, :dpn]
-    for e in range(2):
-        sel = np.nonzero(p.mult_occ[:, e] == s)[0]
-        if len(sel) == 0:
-            continue
-        sg = p.mult_sign[sel, e].astype(float)
-        nodes = p.mult_node[sel, e]
-        lm = lam.reshape(p.n_mult_nodes, dpn, -1)[sel]            # (k, dpn, nr), global frame
-        loc = np.einsum("ca,kcr->kar", O3, lm) * sg[:, None, None]  # O^T lambda
-        np.add.at(out.reshape(pat.n_nodes, dpn, -1), nodes, loc)
-    return out
-
-
-def _stack_u(p, u):
-    """(n_occ, n_nodes, dpn, n_rhs) view of the displacements (single-pattern structures)."""
-    nn = p.patterns[0].n_nodes
-    return np.stack(u).reshape(p.n_occ, nn, p.dpn, -1)
-
-
-def _continuity_gap(p, u):
-    """max over interface multipliers of |O_a u_a - O_b u_b| (global frame)."""
-    dpn = p.dpn
-    U = _stack_u(p, u)
-    inter = np.nonzero(p.mult_occ[:, 1] >= 0)[0]
-    gap = 0.0
-    for chunk in np.array_split(inter, 16):
-        sa, na = p.mult_occ[chunk, 0], p.mult_node[chunk, 0]
-        sb, nb = p.mult_occ[chunk, 1], p.mult_node[chunk, 1]
-        ua, ub = U[sa, na], U[sb, nb]
-        if p.has_rotation:
-            ua = np.einsum("kab,kbr->kar", p.occ_rot[sa][:, :dpn, :dpn], ua)
-            ub = np.einsum("kab,kbr->kar", p.occ_rot[sb][:, :dpn, :dpn], ub)
-        gap = max(gap, np.abs(ua - ub).max())
-    return gap
 
 
 @pytest.fixture(scope="module")
@@ -127,38 +88,8 @@ def test_config2_solution(config2, R, form, method):
     assert np.abs(o.G.T @ lam - e).max() <= 1e-9 * np.abs(e).max()
     u = ST.split_u(p, res.u)
     scale = max(np.abs(x).max() for x in u)
-    assert _continuity_gap(p, u) <= 1e-6 * scale
-    for s in (0, 21, 42, 63):
-        pat = p.patterns[0]
-        res_s = pat.K @ u[s] - p.f_local[s] + _local_forces(p, lam, s, pat)
-        assert np.abs(res_s).max() <= 1e-9 * np.abs(p.f_local[s]).max()
-
-
-def test_config4_solution_properties(R):
-    """512 occurrences of the 20^3-brick pattern, 16 load cases (the largest single-GPU configuration),
-    mixed bf16x3 form with block CG as bench.py times it."""
-    from paper_1208_6387_amd import structure as ST
-    p = W.config(4)
-    print("\n[fullsize] 512 x 20^3 bricks, 16 load cases", flush=True)
-    pats = ST.factor_patterns(p)
-    ST.condense_patterns(pats, (R.FP64, R.BF16X3))
-    pb = ST.create_problem(p)
-    res = R.block_krylov_solve(pb, pats, ST.loads_to_device(p), p.n_rhs, tol=1e-8, max_it=3000,
-                               method=R.BLOCK_CG, prec=R.BF16X3, inner_tol=1e-3)
-    assert res.stats["rel_residual"] <= 1e-8
-    lam = res.lam.cpu().numpy()
-    u = ST.split_u(p, res.u)
-    scale = max(np.abs(x).max() for x in u)
-    assert _continuity_gap(p, u) <= 1e-6 * scale
-    # clamped face: every Dirichlet multiplier's node has u = 0
-    dsel = np.nonzero(p.mult_occ[:, 1] < 0)[0]
-    ud = _stack_u(p, u)[p.mult_occ[dsel, 0], p.mult_node[dsel, 0]]
-    assert np.abs(ud).max() <= 1e-6 * scale
-    pat = p.patterns[0]
-    rng = np.random.default_rng(0)
-    for s in rng.choice(p.n_occ, 12, replace=False):
-        res_s = pat.K @ u[s] - p.f_local[s] + _local_forces(p, lam, s, pat)
-        assert np.abs(res_s).max() <= 1e-8 * np.abs(p.f_local[s]).max(), s
+    assert props.continuity_gap(p, u) <= (1e-8 if form == "fp64" else 1e-6) * scale
+    assert props.equilibrium_residual(p, u, lam) <= 1e-10
 
 
 def test_config4_operator_forms(R):
@@ -230,15 +161,9 @@ def test_config4_preconditioned(R):
     lam = res.lam.cpu().numpy()
     u = ST.split_u(p, res.u)
     scale = max(np.abs(x).max() for x in u)
-    assert _continuity_gap(p, u) <= 1e-6 * scale
-    dsel = np.nonzero(p.mult_occ[:, 1] < 0)[0]
-    ud = _stack_u(p, u)[p.mult_occ[dsel, 0], p.mult_node[dsel, 0]]
-    assert np.abs(ud).max() <= 1e-6 * scale
-    pat = p.patterns[0]
-    rng = np.random.default_rng(1)
-    for s in rng.choice(p.n_occ, 8, replace=False):
-        res_s = pat.K @ u[s] - p.f_local[s] + _local_forces(p, lam, s, pat)
-        assert np.abs(res_s).max() <= 1e-8 * np.abs(p.f_local[s]).max(), s
+    assert props.continuity_gap(p, u) <= 1e-6 * scale
+    assert props.dirichlet_max(p, u) <= 1e-6 * scale
+    assert props.equilibrium_residual(p, u, lam) <= 1e-9
 
 
 @pytest.fixture(scope="module")

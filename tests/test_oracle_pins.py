@@ -378,6 +378,46 @@ def test_block_single_direction_equals_classical():
         assert np.abs(rc[j] - rb[j][:, 0]).max() < 1e-10 * np.abs(rc[j]).max()
 
 
+def _krylov_minimisers(o, d, e, n_it, precond=None):
+    """The iterates that define projected CG, computed from their definition and nothing else: the
+    j-th is the minimiser of the F-energy of the error over lambda_0 + K_j, K_j = span{z_0, A z_0,
+    .., A^{j-1} z_0} with z_0 = Q F~^{-1} r_0 and A = Q F~^{-1} Q^T F.  With V an orthonormal basis
+    of K_j (range Q, where Q V = V): (V^T F V) y = V^T r_0 and lambda_j = lambda_0 + V y."""
+    l0 = o.lambda0(e)[:, 0]
+    r0 = o.Qt(d[:, 0] - o.F(l0))
+    V, FV, out = [], [], []
+    w = o.Q(o.precondition(r0, precond))
+    for _ in range(n_it):
+        for _ in range(2):
+            for v in V:
+                w = w - (v @ w) * v
+        w = o.Q(w)
+        V.append(w / np.linalg.norm(w))
+        FV.append(o.F(V[-1]))
+        Vm, FVm = np.array(V).T, np.array(FV).T
+        H = Vm.T @ FVm
+        y = np.linalg.solve(0.5 * (H + H.T), Vm.T @ r0)
+        out.append(l0 + Vm @ y)
+        w = o.Q(o.precondition(o.Qt(FV[-1]), precond))
+    return out
+
+
+@pytest.mark.parametrize("precond,coarse", [(None, None), ("dirichlet", None), ("lumped", "lumped")])
+def test_classical_iterates_minimise_energy_over_krylov_space(precond, coarse):
+    """Section 2: projected (preconditioned) CG gives, at iteration j, the F-energy minimiser over
+    lambda_0 + K_j.  The oracle's recurrences reproduce the minimisers computed from that
+    definition (with an orthonormal Krylov basis and a dense Galerkin solve) over the first 15
+    iterations, before rounding separates the two."""
+    p = W.small_elast((2, 2, 2), (2, 2, 1), n_rhs=1, n_perm=1, seed=31)
+    o = O.FetiOracle(p, coarse=coarse)
+    g, d, e = o.loads()
+    rc = []
+    o.solve_classical(d, e, 1e-14, record=rc, max_it=15, precond=precond)
+    ref = _krylov_minimisers(o, d, e, min(15, len(rc)), precond)
+    for j, (a, b) in enumerate(zip(rc, ref)):
+        assert np.abs(a - b).max() < 1e-9 * np.abs(b).max(), j
+
+
 def test_classical_converges_within_rank():
     p = W.small_heat((2, 2), (3, 1), n_rhs=1)
     o = O.FetiOracle(p)
