@@ -160,6 +160,24 @@ void problem_free(rpf_problem pb);
 rpf_status feti_apply(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X, int64_t ldx,
                       double* Y, int64_t ldy, int32_t prec, uint32_t flags, void* stream);
 
+/* Y = F X in FP64 without allocating device memory, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, layouts and results as feti_apply with
+ * prec = RPF_FP64 and flags = 0, on the same kernels.  The W-format workspace
+ * (gathered blocks, product results and split-K slabs) lives in a fixed device
+ * array of RPF_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library is
+ * loaded on that GPU and held until the process ends; its address is looked up
+ * on the first call on each device (the current device).  Every call on a GPU
+ * shares that array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Each call overwrites
+ * every workspace entry it reads, so nothing carries over between calls.
+ * Errors: RPF_EINVAL for prec != RPF_FP64, any flag, bad blocks, patterns not
+ * condensed, or a block whose workspace exceeds the limit (the message gives
+ * the bytes needed; fewer columns per call fit).  Asynchronous. */
+#define RPF_NOALLOC_SCRATCH_BYTES (128ll << 20)
+rpf_status feti_apply_noalloc(rpf_problem pb, const rpf_pattern* patterns, int32_t m, const double* X, int64_t ldx,
+                              double* Y, int64_t ldy, int32_t prec, uint32_t flags, void* stream);
+
 /* Preconditioners of the interface problem (section 2).  F~^{-1} =
  * sum_s beta A^(s) M A^(s)T beta, with M the pattern's Schur complement S
  * (Dirichlet) or its boundary block K_bb (lumped), over the whole pattern

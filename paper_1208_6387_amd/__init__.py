@@ -19,7 +19,7 @@ from ._lib import (APPLY_PROJECT, BF16, BF16X3, BLOCK_CG, CLASSICAL, FP32, FP64,
                    PRECOND_LUMPED, PRECOND_NONE, RpfError, SolveStats, check, load)
 
 __all__ = ["Pattern", "Problem", "pattern_factor", "pattern_condense", "pattern_export", "problem_create",
-           "feti_apply", "feti_precond", "feti_permute", "block_krylov_solve", "dgemm", "dposv", "dsyev_small",
+           "feti_apply", "feti_apply_noalloc", "feti_precond", "feti_permute", "block_krylov_solve", "dgemm", "dposv", "dsyev_small",
            "load", "RpfError", "FP64", "FP32", "BF16X3", "BF16", "CLASSICAL", "BLOCK_CG", "ORTHODIR",
            "PRECOND_NONE", "PRECOND_LUMPED", "PRECOND_DIRICHLET", "APPLY_PROJECT"]
 
@@ -146,6 +146,17 @@ def feti_apply(pb: Problem, patterns, X: torch.Tensor, prec: int = FP64, project
     check(load().feti_apply(pb.handle, _handles(patterns), m, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), prec,
                             APPLY_PROJECT if project else 0, _stream(stream)))
     return Y
+
+
+def feti_apply_noalloc(pb: Problem, patterns, X: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """Y = F X in FP64 with the library's fixed per-GPU workspace (no device allocation); out must be
+    given.  Calls overlapping on one GPU share that workspace and race."""
+    assert X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[0] == pb.n_lambda
+    assert X.stride(1) == 1 and out.stride(1) == 1 and out.shape == X.shape
+    m = X.shape[1]
+    check(load().feti_apply_noalloc(pb.handle, _handles(patterns), m, _ptr(X), X.stride(0), _ptr(out),
+                                    out.stride(0), FP64, 0, _stream(stream)))
+    return out
 
 
 def feti_precond(pb: Problem, patterns, X: torch.Tensor, kind: int, prec: int = FP64, project: bool = False,

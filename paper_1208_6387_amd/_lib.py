@@ -14,11 +14,12 @@ FP64, FP32, BF16X3, BF16 = 0, 1, 2, 3
 CLASSICAL, BLOCK_CG, ORTHODIR = 0, 1, 2
 PRECOND_NONE, PRECOND_LUMPED, PRECOND_DIRICHLET = 0, 1, 2
 APPLY_PROJECT = 1
+NOALLOC_SCRATCH_BYTES = 128 << 20   # RPF_NOALLOC_SCRATCH_BYTES
 
 # every symbol the header declares
 EXPORTS = ["rpf_last_error", "rpf_version", "pattern_factor", "pattern_condense", "pattern_info", "pattern_export",
            "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "problem_n_perm", "feti_apply",
-           "feti_precond", "feti_permute",
+           "feti_apply_noalloc", "feti_precond", "feti_permute",
            "block_krylov_solve",
            "rpf_dgemm", "rpf_dposv", "rpf_dsyev_small", "rpf_trace_enable", "rpf_trace_read"]
 
@@ -72,6 +73,7 @@ def load() -> C.CDLL:
         "problem_free": (None, [vp]),
         "problem_n_perm": (i32, [vp]),
         "feti_apply": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, C.c_uint32, vp]),
+        "feti_apply_noalloc": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, C.c_uint32, vp]),
         "feti_precond": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, i32, C.c_uint32, vp]),
         "feti_permute": (i32, [vp, vp, i32, vp, i64, vp, i64, C.c_uint32, vp]),
         "block_krylov_solve": (i32, [vp, vp, i32, vp, C.POINTER(SolveOpts), vp, i64, vp, C.POINTER(SolveStats), vp]),

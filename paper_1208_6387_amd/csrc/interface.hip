@@ -716,6 +716,62 @@ void scatter_all(rpf_problem pb, const YLoc& yl, int m, double* Y, int64_t ldy, 
   RPF_LAUNCH_CHECK();
 }
 
+F64Plan plan_F64(rpf_problem pb, const rpf_pattern* pats, int m) {
+  // W-format workspace: one slab per pattern (times the K splits for the results).  When the
+  // 128 x 128 tiles alone fill the chip, the product runs on the large-problem kernel, whose W
+  // blocks have their leading dimension padded to a multiple of 32 with zero rows.
+  F64Plan pl{};
+  for (int p = 0; p < pb->n_pat; ++p) {
+    const int nb = pats[p]->n_b;
+    const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
+    // split K while the output tiles alone cannot give ~4 workgroups per CU, keeping >= 256 per split
+    const int64_t tiles = std::max<int64_t>(1, gemm_tiles(nb, cols));
+    int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, nb / 256));
+    sp = std::min(sp, 8);
+    pl.nsp[p] = splits_used(nb, sp);
+    pl.alloc_sp[p] = sp;
+    pl.big[p] = pl.nsp[p] == 1 && nb % 2 == 0 && cdiv(nb, 128) * cdiv(cols, (int64_t)128) >= 256;
+    pl.ldw[p] = pl.big[p] ? cdiv(nb, 32) * 32 : nb;
+    pl.off[p + 1] = pl.off[p] + pl.ldw[p] * cols;
+    pl.yoff[p + 1] = pl.yoff[p] + (int64_t)nb * cols * sp;
+  }
+  pl.xneed = std::max<int64_t>(pl.off[pb->n_pat], 1);
+  pl.yneed = std::max<int64_t>(pl.yoff[pb->n_pat], 1);
+  return pl;
+}
+
+YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, const double* X, int64_t ldx,
+             double* xw, double* yw, hipStream_t s, int op, bool trace) {
+  YLoc yl{};
+  for (int p = 0; p < pb->n_pat; ++p) {
+    const int nb = pats[p]->n_b;
+    const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
+    double* xp = xw + pl.off[p];
+    double* yp = yw + pl.yoff[p];
+    const int64_t lw = pl.ldw[p];
+    if (lw > nb) {
+      const int64_t npad = (lw - nb) * cols;
+      hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, xp, lw, nb, cols);
+      RPF_LAUNCH_CHECK();
+    }
+    gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, lw, s);
+    // the tracer times the flexibility products only
+    void* tok = (trace && op == OP_FLEX) ? trace_begin(s, RPF_FP64) : nullptr;
+    const double* Mp = op == OP_FLEX ? pats[p]->Splus.p : pats[p]->S.p;
+    if (pl.nsp[p] > 1) {
+      dgemm_partials(s, nb, cols, nb, Mp, nb, xp, lw, yp, pl.alloc_sp[p]);
+    } else if (!(pl.big[p] && dgemm_flex(s, nb, cols, nb, 1.0, Mp, nb, xp, lw, 0.0, yp, nb))) {
+      dgemm(s, false, false, nb, cols, nb, 1.0, Mp, nb, xp, lw, 0.0, yp, nb);
+    }
+    if (tok) trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
+    yl.base[p] = yp;
+    yl.ld[p] = nb;
+    yl.slab[p] = (int64_t)nb * cols;
+    yl.nsplit[p] = pl.nsp[p];
+  }
+  return yl;
+}
+
 void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y, int64_t ldy,
              int prec, bool project, hipStream_t s, int op) {
   if (prec != RPF_FP64) {
@@ -726,54 +782,10 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     }
     return;
   }
-  // W-format workspace: one slab per pattern (times the K splits for the results).  When the
-  // 128 x 128 tiles alone fill the chip, the product runs on the large-problem kernel, whose W
-  // blocks have their leading dimension padded to a multiple of 32 with zero rows.
-  std::vector<int64_t> off(pb->n_pat + 1, 0), yoff(pb->n_pat + 1, 0), ldw(pb->n_pat);
-  std::vector<int> nsp(pb->n_pat, 1);
-  std::vector<char> big(pb->n_pat, 0);
-  for (int p = 0; p < pb->n_pat; ++p) {
-    const int nb = pats[p]->n_b;
-    const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
-    // split K while the output tiles alone cannot give ~4 workgroups per CU, keeping >= 256 per split
-    const int64_t tiles = std::max<int64_t>(1, gemm_tiles(nb, cols));
-    int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, nb / 256));
-    sp = std::min(sp, 8);
-    nsp[p] = splits_used(nb, sp);
-    big[p] = nsp[p] == 1 && nb % 2 == 0 && cdiv(nb, 128) * cdiv(cols, (int64_t)128) >= 256;
-    ldw[p] = big[p] ? cdiv(nb, 32) * 32 : nb;
-    off[p + 1] = off[p] + ldw[p] * cols;
-    yoff[p + 1] = yoff[p] + (int64_t)nb * cols * sp;
-  }
-  pb->xloc.ensure(std::max<int64_t>(off[pb->n_pat], 1));
-  pb->yloc.ensure(std::max<int64_t>(yoff[pb->n_pat], 1));
-  YLoc yl{};
-  for (int p = 0; p < pb->n_pat; ++p) {
-    const int nb = pats[p]->n_b;
-    const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
-    double* xp = pb->xloc.p + off[p];
-    double* yp = pb->yloc.p + yoff[p];
-    const int64_t lw = ldw[p];
-    if (lw > nb) {
-      const int64_t npad = (lw - nb) * cols;
-      hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, xp, lw, nb, cols);
-      RPF_LAUNCH_CHECK();
-    }
-    gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, lw, s);
-    // the tracer times the flexibility products only
-    void* tok = op == OP_FLEX ? trace_begin(s, RPF_FP64) : nullptr;
-    const double* Mp = op == OP_FLEX ? pats[p]->Splus.p : pats[p]->S.p;
-    if (nsp[p] > 1) {
-      dgemm_partials(s, nb, cols, nb, Mp, nb, xp, lw, yp, (int)((yoff[p + 1] - yoff[p]) / ((int64_t)nb * cols)));
-    } else if (!(big[p] && dgemm_flex(s, nb, cols, nb, 1.0, Mp, nb, xp, lw, 0.0, yp, nb))) {
-      dgemm(s, false, false, nb, cols, nb, 1.0, Mp, nb, xp, lw, 0.0, yp, nb);
-    }
-    if (tok) trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
-    yl.base[p] = yp;
-    yl.ld[p] = nb;
-    yl.slab[p] = (int64_t)nb * cols;
-    yl.nsplit[p] = nsp[p];
-  }
+  const F64Plan pl = plan_F64(pb, pats, m);
+  pb->xloc.ensure(pl.xneed);
+  pb->yloc.ensure(pl.yneed);
+  const YLoc yl = run_F64(pb, pats, pl, m, X, ldx, pb->xloc.p, pb->yloc.p, s, op, true);
   pb->last_yl = yl;
   pb->last_x = op == OP_FLEX ? X : nullptr;
   pb->last_ldx = ldx;

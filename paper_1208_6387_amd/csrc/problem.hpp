@@ -82,6 +82,20 @@ namespace rpf {
 void check_patterns(rpf_problem pb, const rpf_pattern* pats, int prec);
 // pattern matrix of a local product: S+ (the operator F) or S (the Dirichlet preconditioner)
 enum LocalOp { OP_FLEX = 0, OP_SCHUR = 1 };
+// Workspace plan of the FP64 operator for an m-column block: per pattern the offsets of its W
+// block (leading dimension ldw, padded to 32 rows for the large-problem kernel) and of its result
+// slabs (alloc_sp split-K slabs of n_b x cols, nsp of them written), and the doubles needed.
+struct F64Plan {
+  int64_t off[MAXP + 1], yoff[MAXP + 1], ldw[MAXP];
+  int nsp[MAXP], alloc_sp[MAXP];
+  char big[MAXP];
+  int64_t xneed, yneed;
+};
+F64Plan plan_F64(rpf_problem pb, const rpf_pattern* pats, int m);
+// Gather and FP64 product of every pattern into the workspaces xw (plan.xneed doubles) and yw
+// (plan.yneed doubles); returns the result slabs for scatter_all.  No allocation.
+YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, const double* X, int64_t ldx,
+             double* xw, double* yw, hipStream_t s, int op, bool trace);
 // Y = F X (W-format products on all patterns), optional projection; with op = OP_SCHUR the same
 // assembled product with S in place of S+
 void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
