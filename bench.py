@@ -81,6 +81,14 @@ def main():
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     ap.add_argument("--cpu-iterations", type=int, default=10)
+    ap.add_argument("--graph-batch", type=int, default=4,
+                    help="iterations per captured HIP graph in the extra captured run of the headline form "
+                         "(block CG and classical; 0: no captured run)")
+    ap.add_argument("--extra-methods", default="orthodir",
+                    help="comma list of solvers also timed for the headline form (reported under 'methods')")
+    ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of each extra run (captured, methods, "
+                    "preconditioned), at most --steps")
+    ap.add_argument("--no-schedules", action="store_true", help="ignore the tuned product schedules")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain elementwise copy of MIB MiB (read + write) three times, the reference "
                          "kernel that scales HBM traffic counters")
@@ -124,6 +132,7 @@ def main():
 
     # ---------------- untimed: structure maps and device-resident inputs
     pb = ST.create_problem(p)
+    n_sched = 0 if args.no_schedules else ST.install_schedules(pb, p)
     kvals = [torch.from_numpy(np.ascontiguousarray(pat.K.data)).cuda() for pat in p.patterns]
     f = ST.loads_to_device(p)
     lam = torch.empty((pb.n_lambda, p.n_rhs), dtype=torch.float64, device="cuda")
@@ -132,7 +141,7 @@ def main():
 
     PRECONDS = {"none": R.PRECOND_NONE, "lumped": R.PRECOND_LUMPED, "dirichlet": R.PRECOND_DIRICHLET}
 
-    def step(prec: int, pc: int = PRECONDS[args.precond]):
+    def step(prec: int, pc: int = PRECONDS[args.precond], gb: int = 0, meth: int = method):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record()
         pats = []
@@ -145,10 +154,10 @@ def main():
             if prec != R.FP64:
                 R.pattern_condense(P, prec)
         ev[2].record()
-        res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=args.tol, max_it=args.max_it, method=method,
+        res = R.block_krylov_solve(pb, pats, f, p.n_rhs, tol=args.tol, max_it=args.max_it, method=meth,
                                    prec=prec, inner_tol=settings["inner_tol"], max_blocks=settings["max_blocks"],
                                    lam_out=lam, u_out=u, precond=pc, periodic=args.periodic,
-                                   coarse=PRECONDS[args.coarse])
+                                   coarse=PRECONDS[args.coarse], graph_batch=gb)
         # the solve has synchronised the stream, so the events are complete
         res.stats["ms_factor"] = ev[0].elapsed_time(ev[1])
         res.stats["ms_condense"] = ev[1].elapsed_time(ev[2])
@@ -187,22 +196,56 @@ def main():
         log(f"[bench] {form}: {ms:.2f} ms/step, iterations {st['iterations']}, sweeps {st['sweeps']}, "
             f"rel_res {st['rel_residual']:.2e}, gemm {tr['count']} launches {tr['ms']:.2f} ms")
 
+    xsteps = max(1, min(args.steps, args.extra_steps))
+
+    def timed(label, fn):
+        for w in range(min(args.warmup, 1)):
+            log(f"[bench] warmup {label} {w}")
+            fn()
+        torch.cuda.synchronize()
+        log(f"[bench] timing {label}: {xsteps} steps")
+        t0 = time.perf_counter()
+        for k in range(xsteps):
+            res = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / xsteps
+        st = res.stats
+        assert st["rel_residual"] <= args.tol * 1.0000001, st
+        log(f"[bench] {label}: {ms:.2f} ms/step, iterations {st['iterations']}, sweeps {st['sweeps']}")
+        return {"ms": round(ms, 3), "iterations": st["iterations"], "sweeps": st["sweeps"],
+                "rel_residual": st["rel_residual"], "graph_replays": st["graph_replays"],
+                "phase_ms": {q: round(st[q], 3) for q in PHASES}}
+
+    # the headline form with captured iteration batches (untraced: the event tracer times single
+    # kernels and is off inside graphs), and with the other solvers
+    hprec = PREC_NAMES[forms[0]]
+    captured = None
+    if args.graph_batch > 0 and method_name != "orthodir":
+        captured = timed(f"{forms[0]} captured (batches of {args.graph_batch})",
+                         lambda: step(hprec, gb=args.graph_batch))
+        captured["graph_batch"] = args.graph_batch
+        uncaptured = timed(f"{forms[0]} uncaptured, untraced", lambda: step(hprec))
+        captured["uncaptured_ms"] = uncaptured["ms"]
+    methods = {}
+    for mname in [x.strip() for x in args.extra_methods.split(",") if x.strip() and x.strip() != method_name]:
+        methods[mname] = timed(f"{forms[0]} {mname}", lambda: step(hprec, meth=METHODS[mname]))
+
     # the same forms with a preconditioner (the timed region as above)
     extra = {}
     for name in [x.strip() for x in args.precond_extra.split(",") if x.strip() and x.strip() != args.precond]:
         extra[name] = {}
         for form in forms:
             prec = PREC_NAMES[form]
-            for w in range(args.warmup):
+            for w in range(min(args.warmup, 1)):
                 log(f"[bench] warmup {form} + {name} {w}")
                 step(prec, PRECONDS[name])
             torch.cuda.synchronize()
-            log(f"[bench] timing {form} + {name} preconditioner: {args.steps} steps")
+            log(f"[bench] timing {form} + {name} preconditioner: {xsteps} steps")
             t0 = time.perf_counter()
-            for k in range(args.steps):
+            for k in range(xsteps):
                 res = step(prec, PRECONDS[name])
             torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            ms = (time.perf_counter() - t0) * 1e3 / xsteps
             st = res.stats
             assert st["rel_residual"] <= args.tol * 1.0000001, st
             extra[name][form] = {"ms": round(ms, 3), "iterations": st["iterations"], "sweeps": st["sweeps"],
@@ -250,6 +293,7 @@ def main():
                    "precond": args.precond, "coarse": args.coarse, "periodic": args.periodic,
                    "max_blocks": settings["max_blocks"], "inner_tol": settings["inner_tol"],
                    "n_lambda": pb.n_lambda, "n_occ": p.n_occ, "n_rhs": p.n_rhs, "n_perm": p.n_perm,
+                   "tuned_schedules": n_sched,
                    "pattern_dofs": [pat.n for pat in p.patterns], "pattern_boundary_dofs": [pat.n_b for pat in p.patterns],
                    "tol": args.tol},
         "iterations": hr["stats"]["iterations"],
@@ -269,6 +313,10 @@ def main():
         out["speedup_vs_fp64"] = {k: round(results["fp64"]["ms"] / v["ms"], 3) for k, v in results.items()}
     if extra:
         out["preconditioned"] = extra
+    if captured:
+        out["captured"] = captured
+    if methods:
+        out["methods"] = methods
 
     if args.cpu and isinstance(cfg_idx, int):
         # the oracle computes in FP64: it is timed for the FP64 form's iteration count when measured

@@ -144,6 +144,35 @@ int64_t problem_n_lambda(rpf_problem pb);
 int32_t problem_n_perm(rpf_problem pb);  /* permutations of the structure (1: none) */
 void problem_free(rpf_problem pb);
 
+/* Schedules of the flexibility products (section 3.2: the product S+ W over
+ * all occurrences of a pattern, here over all patterns at once).  A schedule
+ * for block width m and arithmetic prec names the workgroup tile: 0 = the
+ * built-in size rule (default); 64 or 128 = every pattern's product in one
+ * grouped persistent launch of that tile, each pattern's K split into pieces so
+ * that its tiles times pieces reach about `work` items (at most 8 pieces of at
+ * least 256); 256 = the large-tile kernel of a single-pattern structure.
+ * Schedules change the summation order of the products, so results differ in
+ * the last bits between schedules, never in accuracy.  FP32 takes tile 0 only.
+ * problem_set_schedule installs one (tile 0 removes it).  Errors: RPF_EINVAL. */
+rpf_status problem_set_schedule(rpf_problem pb, int32_t m, int32_t prec, int32_t tile, int32_t work);
+
+typedef struct {
+  int32_t tile;
+  int32_t work;
+  double ms;       /* mean time of one operator application Y = F X (gather, products, scatter) */
+  int32_t chosen;  /* 1 for the installed (fastest) candidate */
+} rpf_schedule_entry;
+
+/* Autotuner: time every candidate schedule (tile 0; tiles 64 and 128 with work
+ * 256 .. 4096; tile 256 where it applies) on this structure for an m-column
+ * block in arithmetic prec, `reps` applications each after one warm-up, on
+ * `stream`, with a deterministic test block; install the fastest.  out
+ * (host, max_out entries, may be NULL) receives every candidate with its time;
+ * *n_out the candidate count.  Allocates two N_lambda x m blocks for the
+ * duration of the call and blocks the host.  Errors: RPF_EINVAL. */
+rpf_status problem_tune(rpf_problem pb, const rpf_pattern* patterns, int32_t m, int32_t prec, int32_t reps,
+                        rpf_schedule_entry* out, int32_t max_out, int32_t* n_out, void* stream);
+
 /* ------------------------------------------------------------------ operator */
 
 #define RPF_APPLY_PROJECT 1u  /* return Q^T F X instead of F X (Q: coarse projector, F~ = I) */
@@ -260,6 +289,12 @@ typedef struct {
                           no interior dofs, S = K_bb = K annihilates the rigid traces and
                           G^T F~^{-1} G is singular).
                           RPF_EINVAL together with an active periodic shortcut. */
+  int32_t graph_batch; /* block CG and classical: from the third iteration of each sweep on, record
+                          graph_batch iterations (rounded down to even; 0 or 1: off) once into a HIP
+                          graph on a capture stream of the library and replay it on `stream`, with
+                          one convergence check per replay (so a converged run may do up to
+                          2 * graph_batch extra, still valid, iterations).  Same results as the
+                          uncaptured run.  Ignored for ORTHODIR and while tracing is enabled. */
 } rpf_solve_opts;
 
 typedef struct {
@@ -269,6 +304,7 @@ typedef struct {
   int32_t converged;
   double rel_residual; /* final max_c ||r_c|| / ||r0_c||, recomputed in FP64 */
   double ms_loads, ms_coarse, ms_iterate, ms_recover;
+  int32_t graph_replays; /* replays of captured iteration batches */
 } rpf_solve_stats;
 
 /* Solve the interface problem (eq. 3) for n_rhs load cases and recover the

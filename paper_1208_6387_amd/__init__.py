@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (APPLY_PROJECT, BF16, BF16X3, BLOCK_CG, CLASSICAL, FP32, FP64, ORTHODIR, PRECOND_DIRICHLET,
                    PRECOND_LUMPED, PRECOND_NONE, RpfError, SolveStats, check, load)
 
-__all__ = ["Pattern", "Problem", "pattern_factor", "pattern_condense", "pattern_export", "problem_create",
+__all__ = ["Pattern", "Problem", "pattern_factor", "pattern_condense", "pattern_export", "problem_create", "problem_set_schedule", "problem_tune",
            "feti_apply", "feti_apply_noalloc", "feti_precond", "feti_permute", "block_krylov_solve", "dgemm", "dposv", "dsyev_small",
            "load", "RpfError", "FP64", "FP32", "BF16X3", "BF16", "CLASSICAL", "BLOCK_CG", "ORTHODIR",
            "PRECOND_NONE", "PRECOND_LUMPED", "PRECOND_DIRICHLET", "APPLY_PROJECT"]
@@ -131,6 +131,22 @@ def problem_create(dofs_per_node: int, pat_n_nodes, pat_bnodes, occ_pattern, occ
     return Problem(h)
 
 
+def problem_set_schedule(pb: Problem, m: int, prec: int, tile: int, work: int = 1024) -> None:
+    """Install the schedule of the flexibility products for block width m and arithmetic prec
+    (tile 0: the size rule; 64 / 128: one grouped launch; 256: the single-pattern large tile)."""
+    check(load().problem_set_schedule(pb.handle, m, prec, tile, work))
+
+
+def problem_tune(pb: Problem, patterns, m: int, prec: int = FP64, reps: int = 5, stream=None) -> list:
+    """Time every candidate schedule for an m-column block, install the fastest, return them all as
+    dicts (tile, work, ms, chosen)."""
+    arr = (_lib.ScheduleEntry * 64)()
+    n = C.c_int32()
+    check(load().problem_tune(pb.handle, _handles(patterns), m, prec, reps, arr, 64, C.byref(n), _stream(stream)))
+    return [{"tile": arr[i].tile, "work": arr[i].work, "ms": arr[i].ms, "chosen": bool(arr[i].chosen)}
+            for i in range(min(n.value, 64))]
+
+
 def _handles(patterns):
     arr = (C.c_void_p * len(patterns))(*[p.handle for p in patterns])
     return arr
@@ -201,15 +217,16 @@ def block_krylov_solve(pb: Problem, patterns, f_local: torch.Tensor, n_rhs: int,
                        max_it: int = 1000, method: int = ORTHODIR, prec: int = FP64, inner_tol: float = 0.0,
                        max_sweeps: int = 0, check_every: int = 1, max_blocks: int = 0, lam_out=None, u_out=None,
                        stream=None, raise_on_noconv: bool = True, precond: int = PRECOND_NONE,
-                       periodic: bool = False, coarse: int = PRECOND_NONE) -> SolveResult:
+                       periodic: bool = False, coarse: int = PRECOND_NONE, graph_batch: int = 0) -> SolveResult:
     """Solve the interface problem and recover the displacements.  f_local: flat device float64 tensor,
     occurrence blocks of n_p x n_rhs column-major, concatenated.  coarse: the preconditioner used as
-    F~^{-1} in the projector and lambda_0 (PRECOND_NONE: the identity)."""
+    F~^{-1} in the projector and lambda_0 (PRECOND_NONE: the identity).  graph_batch: iterations per
+    captured HIP graph (block CG and classical; 0: no capture)."""
     assert f_local.is_cuda and f_local.dtype == torch.float64 and f_local.is_contiguous()
     lam = lam_out if lam_out is not None else torch.empty((pb.n_lambda, n_rhs), dtype=torch.float64, device="cuda")
     u = u_out if u_out is not None else torch.empty_like(f_local)
     opts = _lib.SolveOpts(tol, max_it, method, prec, inner_tol, max_sweeps, check_every, max_blocks, int(precond),
-                          int(bool(periodic)), int(coarse))
+                          int(bool(periodic)), int(coarse), int(graph_batch))
     st = SolveStats()
     code = load().block_krylov_solve(pb.handle, _handles(patterns), n_rhs, _ptr(f_local), C.byref(opts), _ptr(lam),
                                      lam.stride(0), _ptr(u), C.byref(st), _stream(stream))

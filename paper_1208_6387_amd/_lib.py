@@ -18,7 +18,7 @@ NOALLOC_SCRATCH_BYTES = 128 << 20   # RPF_NOALLOC_SCRATCH_BYTES
 
 # every symbol the header declares
 EXPORTS = ["rpf_last_error", "rpf_version", "pattern_factor", "pattern_condense", "pattern_info", "pattern_export",
-           "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "problem_n_perm", "feti_apply",
+           "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "problem_n_perm", "problem_set_schedule", "problem_tune", "feti_apply",
            "feti_apply_noalloc", "feti_precond", "feti_permute",
            "block_krylov_solve",
            "rpf_dgemm", "rpf_dposv", "rpf_dsyev_small", "rpf_trace_enable", "rpf_trace_read"]
@@ -36,13 +36,18 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_it", C.c_int32), ("method", C.c_int32), ("prec", C.c_int32),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int32), ("check_every", C.c_int32),
                 ("max_blocks", C.c_int32), ("precond", C.c_int32), ("periodic", C.c_int32),
-                ("coarse", C.c_int32)]
+                ("coarse", C.c_int32), ("graph_batch", C.c_int32)]
+
+
+class ScheduleEntry(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("work", C.c_int32), ("ms", C.c_double), ("chosen", C.c_int32)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("sweeps", C.c_int32), ("rank_drops", C.c_int32),
                 ("converged", C.c_int32), ("rel_residual", C.c_double), ("ms_loads", C.c_double),
-                ("ms_coarse", C.c_double), ("ms_iterate", C.c_double), ("ms_recover", C.c_double)]
+                ("ms_coarse", C.c_double), ("ms_iterate", C.c_double), ("ms_recover", C.c_double),
+                ("graph_replays", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,6 +77,8 @@ def load() -> C.CDLL:
         "problem_n_lambda": (i64, [vp]),
         "problem_free": (None, [vp]),
         "problem_n_perm": (i32, [vp]),
+        "problem_set_schedule": (i32, [vp, i32, i32, i32, i32]),
+        "problem_tune": (i32, [vp, vp, i32, i32, i32, C.POINTER(ScheduleEntry), i32, C.POINTER(i32), vp]),
         "feti_apply": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, C.c_uint32, vp]),
         "feti_apply_noalloc": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, C.c_uint32, vp]),
         "feti_precond": (i32, [vp, vp, i32, vp, i64, vp, i64, i32, i32, C.c_uint32, vp]),

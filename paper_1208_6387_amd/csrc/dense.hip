@@ -7,6 +7,7 @@
 // flexibility product S+ W (section 3.2) and every trailing update run through
 // the same MFMA GEMM.
 #include "common.hpp"
+#include "problem.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -21,11 +22,14 @@ namespace rpf {
 // of one item store 16 consecutive doubles of a column of C (coalesced).
 // Operand tiles are staged through LDS (k-major); the next K tile is loaded
 // into registers while the current one is consumed.
+// One output tile (tx, ty) of K split z, called with the same tile by every thread of the
+// workgroup (consecutive tiles of the grouped kernel reuse the LDS: the barrier that opens each k
+// stage orders a tile's stores after the previous tile's reads).
 template <int BM, int BN, int WGM, int WGN, bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
-                                               const double* A, int64_t lda, const double* B,
-                                               int64_t ldb, double beta, double* C, int64_t ldc,
-                                               int lower, int64_t kchunk, double* part) {
+__device__ __forceinline__ void dgemm_tile(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                                           int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                                           int64_t ldc, int lower, int64_t kchunk, double* part, int tx, int ty,
+                                           int z) {
   constexpr int BK = 16, PAD = 2;
   constexpr int WTM = BM / WGM, WTN = BN / WGN, TM = WTM / 16, TN = WTN / 16;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
@@ -34,11 +38,9 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
   __shared__ double sB[BK][BN + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
-  int tx, ty;
-  xcd_tile(gridDim.x, gridDim.y, tx, ty);
   const int64_t m0 = (int64_t)tx * BM, n0 = (int64_t)ty * BN;
   if (lower && n0 >= m0 + BM) return;  // tile strictly above the diagonal
-  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kbeg = (int64_t)z * kchunk;
   const int64_t kend = K < kbeg + kchunk ? K : kbeg + kchunk;
 
   v4d acc[TM][TN];
@@ -115,13 +117,39 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
         if (m < M && n < N && (!lower || m >= n)) {
           const double v = alpha * acc[i][j][r];
           if (part) {
-            part[((int64_t)blockIdx.z * N + n) * M + m] = v;
+            part[((int64_t)z * N + n) * M + m] = v;
           } else {
             double* c = C + n * ldc + m;
             *c = (beta == 0.0) ? v : v + beta * *c;
           }
         }
       }
+}
+
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
+                                               const double* A, int64_t lda, const double* B,
+                                               int64_t ldb, double beta, double* C, int64_t ldc,
+                                               int lower, int64_t kchunk, double* part) {
+  int tx, ty;
+  xcd_tile(gridDim.x, gridDim.y, tx, ty);
+  dgemm_tile<BM, BN, WGM, WGN, TA, TB>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, lower, kchunk, part, tx, ty,
+                                       blockIdx.z);
+}
+
+// Every pattern's FP64 flexibility product in one persistent launch (see k_gemm_bf16_group):
+// C_p = A_p B_p into split-K slabs part_p (M x N each, column-major).
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_dgemm_group(const DGroup g) {
+  for (int t = blockIdx.x; t < g.start[g.n]; t += gridDim.x) {
+    int p = 0;
+    while (t >= g.start[p + 1]) ++p;
+    const int l = t - g.start[p];
+    const int per_z = g.tm[p] * g.tn[p];
+    const int z = l / per_z, r = l - z * per_z;
+    dgemm_tile<BM, BN, 2, 2, false, false>(g.M[p], g.N[p], g.K[p], 1.0, g.A[p], g.lda[p], g.B[p], g.ldb[p], 0.0,
+                                           nullptr, 0, 0, g.kchunk[p], g.part[p], r % g.tm[p], r / g.tm[p], z);
+  }
 }
 
 // FP64 C = alpha A B (+ beta C), column-major; A: M x K with lda, B: K x N with ldb, its k-contiguous
@@ -344,6 +372,31 @@ void dgemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
   if (M <= 0 || N <= 0) return;
   if (K <= 0 && beta == 1.0) return;  // nothing to add; K = 0 otherwise scales C by beta
   launch_gemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, lower, 1, nullptr);
+}
+
+// resident workgroups of a kernel on the whole device (occupancy times compute units), cached
+template <typename Kern>
+static int resident_blocks(Kern k, int threads) {
+  int per_cu = 0, dev = 0;
+  RPF_HIP(hipGetDevice(&dev));
+  RPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0));
+  hipDeviceProp_t prop;
+  RPF_HIP(hipGetDeviceProperties(&prop, dev));
+  return std::max(1, per_cu) * std::max(1, prop.multiProcessorCount);
+}
+
+void dgemm_group(hipStream_t s, int tile, const DGroup& g) {
+  const int total = g.start[g.n];
+  if (total == 0) return;
+  if (tile == 128) {
+    static const int cap = resident_blocks(k_dgemm_group<128, 128>, 256);
+    RPF_TIMED_LAUNCH((k_dgemm_group<128, 128>), dim3((unsigned)std::min(total, cap)), dim3(256), 0, s, g);
+  } else {
+    RPF_CHECK(tile == 64, RPF_EINVAL, "dgemm_group: tile must be 64 or 128");
+    static const int cap = resident_blocks(k_dgemm_group<64, 64>, 256);
+    RPF_TIMED_LAUNCH((k_dgemm_group<64, 64>), dim3((unsigned)std::min(total, cap)), dim3(256), 0, s, g);
+  }
+  RPF_LAUNCH_CHECK();
 }
 
 int gemm_tiles(int64_t M, int64_t N) {

@@ -716,24 +716,53 @@ void scatter_all(rpf_problem pb, const YLoc& yl, int m, double* Y, int64_t ldy, 
   RPF_LAUNCH_CHECK();
 }
 
-F64Plan plan_F64(rpf_problem pb, const rpf_pattern* pats, int m) {
+Schedule schedule_for(rpf_problem pb, int m, int prec) {
+  const auto it = pb->sched.find({m, prec});
+  return it == pb->sched.end() ? Schedule{0, 1024} : it->second;
+}
+
+int64_t group_kchunk(int64_t nb_rows, int64_t K, int64_t cols, int tile, int work, int align) {
+  const int64_t tiles = std::max<int64_t>(1, cdiv(nb_rows, tile) * cdiv(cols, (int64_t)tile));
+  int64_t sp = std::max<int64_t>(1, work / tiles);
+  sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 256));
+  sp = std::min<int64_t>(sp, 8);
+  return cdiv(cdiv(K, sp), (int64_t)align) * align;
+}
+
+F64Plan plan_F64(rpf_problem pb, const rpf_pattern* pats, int m, const Schedule& sc) {
   // W-format workspace: one slab per pattern (times the K splits for the results).  When the
-  // 128 x 128 tiles alone fill the chip, the product runs on the large-problem kernel, whose W
-  // blocks have their leading dimension padded to a multiple of 32 with zero rows.
+  // 128 x 128 tiles alone fill the chip (or the schedule asks for it), a pattern's product runs on
+  // the large-problem kernel, whose W blocks have their leading dimension padded to a multiple of
+  // 32 with zero rows.  A grouped schedule puts every pattern's product in one launch.
   F64Plan pl{};
+  pl.tile = (sc.tile == 64 || sc.tile == 128) ? sc.tile : 0;
   for (int p = 0; p < pb->n_pat; ++p) {
     const int nb = pats[p]->n_b;
     const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
-    // split K while the output tiles alone cannot give ~4 workgroups per CU, keeping >= 256 per split
-    const int64_t tiles = std::max<int64_t>(1, gemm_tiles(nb, cols));
-    int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, nb / 256));
-    sp = std::min(sp, 8);
-    pl.nsp[p] = splits_used(nb, sp);
-    pl.alloc_sp[p] = sp;
-    pl.big[p] = pl.nsp[p] == 1 && nb % 2 == 0 && cdiv(nb, 128) * cdiv(cols, (int64_t)128) >= 256;
-    pl.ldw[p] = pl.big[p] ? cdiv(nb, 32) * 32 : nb;
+    if (pl.tile) {
+      pl.kchunk[p] = group_kchunk(nb, nb, cols, pl.tile, sc.work, 16);
+      pl.nsp[p] = pl.alloc_sp[p] = (int)cdiv(nb, pl.kchunk[p]);
+      pl.big[p] = 0;
+      pl.ldw[p] = nb;
+    } else {
+      // split K while the output tiles alone cannot give ~4 workgroups per CU, keeping >= 256 per split
+      const int64_t tiles = std::max<int64_t>(1, gemm_tiles(nb, cols));
+      int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, nb / 256));
+      sp = std::min(sp, 8);
+      pl.nsp[p] = splits_used(nb, sp);
+      pl.alloc_sp[p] = sp;
+      if (sc.tile == 256 && nb % 2 == 0) {
+        // the schedule asks for the large-problem kernel whatever the tile count
+        pl.nsp[p] = pl.alloc_sp[p] = 1;
+        pl.big[p] = 1;
+      } else {
+        pl.big[p] = pl.nsp[p] == 1 && nb % 2 == 0 && cdiv(nb, 128) * cdiv(cols, (int64_t)128) >= 256;
+      }
+      pl.ldw[p] = pl.big[p] ? cdiv(nb, 32) * 32 : nb;
+      pl.kchunk[p] = 0;
+    }
     pl.off[p + 1] = pl.off[p] + pl.ldw[p] * cols;
-    pl.yoff[p + 1] = pl.yoff[p] + (int64_t)nb * cols * sp;
+    pl.yoff[p + 1] = pl.yoff[p] + (int64_t)nb * cols * pl.alloc_sp[p];
   }
   pl.xneed = std::max<int64_t>(pl.off[pb->n_pat], 1);
   pl.yneed = std::max<int64_t>(pl.yoff[pb->n_pat], 1);
@@ -743,6 +772,8 @@ F64Plan plan_F64(rpf_problem pb, const rpf_pattern* pats, int m) {
 YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, const double* X, int64_t ldx,
              double* xw, double* yw, hipStream_t s, int op, bool trace) {
   YLoc yl{};
+  DGroup g{};
+  double gflops = 0.0;
   for (int p = 0; p < pb->n_pat; ++p) {
     const int nb = pats[p]->n_b;
     const int64_t cols = (int64_t)pb->occ_of_pat[p].size() * m;
@@ -755,19 +786,42 @@ YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, 
       RPF_LAUNCH_CHECK();
     }
     gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, lw, s);
+    const double* Mp = op == OP_FLEX ? pats[p]->Splus.p : pats[p]->S.p;
+    yl.base[p] = yp;
+    yl.ld[p] = nb;
+    yl.slab[p] = (int64_t)nb * cols;
+    yl.nsplit[p] = pl.nsp[p];
+    if (pl.tile) {
+      if (cols == 0) continue;
+      const int q = g.n++;
+      g.M[q] = nb;
+      g.N[q] = (int)cols;
+      g.K[q] = nb;
+      g.kchunk[q] = (int)pl.kchunk[p];
+      g.tm[q] = (int)cdiv(nb, pl.tile);
+      g.tn[q] = (int)cdiv(cols, (int64_t)pl.tile);
+      g.A[q] = Mp;
+      g.lda[q] = nb;
+      g.B[q] = xp;
+      g.ldb[q] = lw;
+      g.part[q] = yp;
+      g.start[q + 1] = g.start[q] + g.tm[q] * g.tn[q] * pl.nsp[p];
+      gflops += 2.0 * nb * (double)nb * (double)cols;
+      continue;
+    }
     // the tracer times the flexibility products only
     void* tok = (trace && op == OP_FLEX) ? trace_begin(s, RPF_FP64) : nullptr;
-    const double* Mp = op == OP_FLEX ? pats[p]->Splus.p : pats[p]->S.p;
     if (pl.nsp[p] > 1) {
       dgemm_partials(s, nb, cols, nb, Mp, nb, xp, lw, yp, pl.alloc_sp[p]);
     } else if (!(pl.big[p] && dgemm_flex(s, nb, cols, nb, 1.0, Mp, nb, xp, lw, 0.0, yp, nb))) {
       dgemm(s, false, false, nb, cols, nb, 1.0, Mp, nb, xp, lw, 0.0, yp, nb);
     }
     if (tok) trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
-    yl.base[p] = yp;
-    yl.ld[p] = nb;
-    yl.slab[p] = (int64_t)nb * cols;
-    yl.nsplit[p] = pl.nsp[p];
+  }
+  if (pl.tile && g.n > 0) {
+    void* tok = (trace && op == OP_FLEX) ? trace_begin(s, RPF_FP64) : nullptr;
+    dgemm_group(s, pl.tile, g);
+    if (tok) trace_end(tok, s, gflops);
   }
   return yl;
 }
@@ -782,7 +836,7 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
     }
     return;
   }
-  const F64Plan pl = plan_F64(pb, pats, m);
+  const F64Plan pl = plan_F64(pb, pats, m, schedule_for(pb, m, RPF_FP64));
   pb->xloc.ensure(pl.xneed);
   pb->yloc.ensure(pl.yneed);
   const YLoc yl = run_F64(pb, pats, pl, m, X, ldx, pb->xloc.p, pb->yloc.p, s, op, true);

@@ -459,6 +459,28 @@ struct Solver {
                            hipMemcpyDeviceToHost, s));
     RPF_HIP(hipEventRecord(nev[slot], s));
   }
+  // norms held in device slot dslot, copied to host slot hslot
+  void post_norms_from(const double* X, int dslot, int hslot, bool have_sq) {
+    if (!have_sq) gram(X, nr, nr, X, nr, nr, nrm2[dslot].p);
+    RPF_HIP(hipMemcpyAsync(hnorm + (size_t)hslot * slot_len(), nrm2[dslot].p, sizeof(double) * slot_len(),
+                           hipMemcpyDeviceToHost, s));
+    RPF_HIP(hipEventRecord(nev[hslot], s));
+  }
+  // captured batches of iterations (block CG and classical)
+  int graph_batch = 0;        // iterations per captured batch (0: no capture)
+  hipStream_t cs = nullptr;   // capture stream (default priority)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int gprec = -1;             // inner precision the graph was captured for
+  bool graph_sq = false;      // the captured last iteration leaves the squared norms in slot 0
+  int graph_replays = 0;
+  void release_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    gprec = -1;
+  }
   enum Check { GOING = 0, CONVERGED = 1, EXHAUSTED = 2 };
   Check read_norms(int slot, const std::vector<double>& target) {
     RPF_HIP(hipEventSynchronize(nev[slot]));
@@ -473,6 +495,8 @@ struct Solver {
     return h[(size_t)nr * nr] != 0.0 ? EXHAUSTED : GOING;
   }
   ~Solver() {
+    release_graph();
+    if (cs) (void)hipStreamDestroy(cs);
     if (hnorm) (void)hipHostFree(hnorm);
     for (auto& e : nev)
       if (e) (void)hipEventDestroy(e);
@@ -552,7 +576,9 @@ struct Solver {
     bool have_gram = false, lam_pending = false;
     const double* lam_dir = nullptr;  // the direction block of the pending update
     if (upd_gram) alpha_prev.ensure((size_t)m * nr);
-    for (int it = 0; it < max_it; ++it) {
+    // One iteration (it): everything up to the residual update.  check: the residual update also
+    // leaves the squared column norms in nrm_out (returns true), else the caller forms them.
+    auto step = [&](int it, bool check, double* nrm_out) -> bool {
       // ORTHODIR: orthogonalise against every stored block (restart when the store is full);
       // block CG / classical: against the previous block only, two alternating slots
       int slot, first, nb;
@@ -673,8 +699,6 @@ struct Solver {
       if (diag_only) hipLaunchKernelGGL(k_mask_diag, dim3(nblocks((int64_t)m * nr)), dim3(256), 0, s, gam.p, m, nr, (int64_t)m);
       hipLaunchKernelGGL(k_tblocks, dim3(1), dim3(256), 0, s, 1, m, nr, Tj, 0, gam.p, alpha.p);
       RPF_LAUNCH_CHECK();
-      const bool check = (it + 1) % check_every == 0 || it + 1 == max_it;
-      const int slot_n = nchk & 1;
       // the residual update also returns the squared column norms (into the check slot)
       sqpart.ensure((size_t)cdiv(N, 256) * nr);
       bool have_sq = false;
@@ -682,22 +706,75 @@ struct Solver {
       if (upd_gram) {
         gpart.ensure((size_t)(cdiv(N, 256) + 256) * m * nr);
         sqpart.ensure((size_t)(cdiv(N, 256) + 256) * nr);
-        // lambda += Z_j alpha_j is deferred to the next step (or the flush below)
-        RPF_HIP(hipMemcpyAsync(alpha_prev.p, alpha.p, sizeof(double) * m * nr, hipMemcpyDeviceToDevice, s));
+        // lambda += Z_j alpha_j is deferred to the next step (or the flush below); the copy is a
+        // kernel, so that a captured iteration holds kernels only
+        copy_matrix(s, alpha.p, m, alpha_prev.p, m, m, nr);
         lam_pending = true;
         lam_dir = Zs;
         have_gram = rows_update_gram(s, N, m, nr, alpha.p, Ps, ldW, -1.0, 1.0, Rs.p, nr, sqpart.p,
-                                     check ? nrm2[slot_n].p : nullptr, nr + 1, gpart.p, Cb.p);
+                                     check ? nrm_out : nullptr, nr + 1, gpart.p, Cb.p);
         RPF_CHECK(have_gram, RPF_EINVAL, "block step: residual update shape");
         have_sq = check;
       } else {
         have_sq = check && rows_gemm2_sq(s, N, m, nr, alpha.p, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0,
-                                         Rs.p, nr, sqpart.p, nrm2[slot_n].p, nr + 1);
+                                         Rs.p, nr, sqpart.p, nrm_out, nr + 1);
         if (!have_sq)
           rows_gemm2(s, N, m, nr, alpha.p, 0, 1.0, Zs, ldW, 1.0, dlam.p, nr, -1.0, Ps, ldW, 1.0, Rs.p, nr);
       }
       ++nst;
       ++iterations;
+      return have_sq;
+    };
+    // Captured batches (block CG and classical, whose two alternating slots make the launches of
+    // iterations it and it + 2 identical from it = 2 on): gb iterations are recorded once into a
+    // graph on a capture stream and replayed on s, one convergence check per replay (its norms in
+    // device slot 0, copied to the lagged host slot after the replay).
+    const int gb = (method != RPF_ORTHODIR && graph_batch >= 2 && !trace_on()) ? graph_batch & ~1 : 0;
+    if (gb && gexec && gprec != prec) release_graph();
+    int it = 0;
+    while (it < max_it) {
+      if (gb && it >= 2 && it % 2 == 0 && it + gb <= max_it) {
+        if (!gexec) {
+          if (!cs) RPF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+          const hipStream_t s0 = s;
+          RPF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+          s = cs;
+          try {
+            for (int k = 0; k < gb; ++k) graph_sq = step(it + k, k == gb - 1, nrm2[0].p);
+          } catch (...) {
+            s = s0;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          s = s0;
+          RPF_HIP(hipStreamEndCapture(cs, &graph));
+          RPF_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+          gprec = prec;
+          // the capture ran the host side of these iterations; the replays below run the device side
+          nst -= gb;
+          iterations -= gb;
+        }
+        RPF_HIP(hipGraphLaunch(gexec, s));
+        ++graph_replays;
+        nst += gb;
+        iterations += gb;
+        it += gb;
+        const int slot_n = nchk & 1;
+        post_norms_from(Rs.p, 0, slot_n, graph_sq);
+        if (pending >= 0 && (conv = read_norms(pending, target)) != GOING) {
+          pending = -1;
+          break;
+        }
+        pending = slot_n;
+        ++nchk;
+        continue;
+      }
+      const bool check = (it + 1) % check_every == 0 || it + 1 == max_it;
+      const int slot_n = nchk & 1;
+      const bool have_sq = step(it, check, nrm2[slot_n].p);
+      ++it;
       if (check) {
         post_norms(Rs.p, slot_n, have_sq);
         // the previous check is read now, while this iteration is already queued; when it
@@ -710,6 +787,8 @@ struct Solver {
         ++nchk;
       }
     }
+    // replays overwrote the local product buffers behind the host's record of the last product
+    if (graph_replays) ++pb->fp64_gen;
     if (lam_pending) {
       rows_gemm(s, N, m, nr, 1.0, lam_dir, ldW, alpha_prev.p, 1.0, dlam.p, nr, 0);
       lam_pending = false;
@@ -754,6 +833,8 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     hipStream_t s = (hipStream_t)stream;
     Solver S(pb, pats, s, n_rhs, opts->method);
     S.pc = opts->precond;
+    RPF_CHECK(opts->graph_batch >= 0, RPF_EINVAL, "block_krylov_solve: graph_batch < 0");
+    S.graph_batch = opts->graph_batch;
     RPF_CHECK(opts->coarse >= RPF_PRECOND_NONE && opts->coarse <= RPF_PRECOND_DIRICHLET, RPF_EINVAL,
               "block_krylov_solve: preconditioner of the projector");
     RPF_CHECK(!(opts->coarse != RPF_PRECOND_NONE && opts->periodic && S.np > 1), RPF_EINVAL,
@@ -961,6 +1042,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     st.iterations = S.iterations;
     st.sweeps = std::max(sweeps, 1);
     st.rank_drops = S.rank_drops;
+    st.graph_replays = S.graph_replays;
     st.rel_residual = rel;
 
     // ------------------------------------------------------------ recovery (eq. 2)

@@ -287,14 +287,18 @@ __global__ __launch_bounds__(256) void k_sgemm_sym(int M, int N, int Kfull, cons
 // Same product with both operands split into bf16 hi + lo; 16x16x32 MFMA, BK = 32.
 // LDS holds rows of 32 k-values (64 bytes, padded) so a lane reads its 8
 // consecutive k of one row as one 16-byte access.
+// One output tile (tx, ty) of K split z; every thread of the workgroup calls it with the same
+// tile (the grouped kernel below runs several tiles one after another through the same LDS: the
+// barrier that opens each k stage keeps a tile's stores behind the previous tile's reads).
 template <int BM, int BN, bool X3>
-__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* Ah, const uint16_t* Al,
-                                                   int64_t lda, const uint16_t* Bh, const uint16_t* Bl, int64_t ldb,
-                                                   float* C, int64_t ldc, int kchunk, int64_t slab) {
+__device__ __forceinline__ void gemm_bf16_tile(int M, int N, int K, const uint16_t* Ah, const uint16_t* Al,
+                                               int64_t lda, const uint16_t* Bh, const uint16_t* Bl, int64_t ldb,
+                                               float* C, int64_t ldc, int kchunk, int64_t slab, int tx, int ty,
+                                               int z) {
   constexpr int BK = 64, RS = BK + 8;  // row stride in bf16 elements (144 bytes)
-  const int kbeg = blockIdx.z * kchunk;
+  const int kbeg = z * kchunk;
   const int kend = min(K, kbeg + kchunk);
-  C += (int64_t)blockIdx.z * slab;
+  C += (int64_t)z * slab;
   constexpr int WTM = BM / 2, WTN = BN / 2, TM = WTM / 16, TN = WTN / 16;
   constexpr int NA = BM * BK / 8 / 256, NB = BN * BK / 8 / 256;  // 16-byte chunks per thread
   static_assert(NA >= 1 && NB >= 1, "tile too small");
@@ -304,8 +308,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   __shared__ __attribute__((aligned(16))) uint16_t sBl[BN * RS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
-  int tx, ty;
-  xcd_tile(gridDim.x, gridDim.y, tx, ty);
   const int m0 = tx * BM, n0 = ty * BN;
   f32x4 acc[TM][TN];
 #pragma unroll
@@ -423,6 +425,32 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
         const int n = n0 + wn * WTN + j * 16 + 4 * (lane >> 4) + r;
         if (m < M && n < N) C[(int64_t)n * ldc + m] = acc[i][j][r];
       }
+}
+
+template <int BM, int BN, bool X3>
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* Ah, const uint16_t* Al,
+                                                   int64_t lda, const uint16_t* Bh, const uint16_t* Bl, int64_t ldb,
+                                                   float* C, int64_t ldc, int kchunk, int64_t slab) {
+  int tx, ty;
+  xcd_tile(gridDim.x, gridDim.y, tx, ty);
+  gemm_bf16_tile<BM, BN, X3>(M, N, K, Ah, Al, lda, Bh, Bl, ldb, C, ldc, kchunk, slab, tx, ty, blockIdx.z);
+}
+
+// Every pattern's product in one persistent launch: the workgroups walk the group's tile list
+// (pattern by pattern in the order the host gave, split by split, then column tile by column
+// tile), tile t, t + gridDim.x, ..., so a launch sized to the resident workgroups covers patterns
+// of any size without a tail launch per pattern.
+template <int BM, int BN, bool X3>
+__global__ __launch_bounds__(256) void k_gemm_bf16_group(const BfGroup g) {
+  for (int t = blockIdx.x; t < g.start[g.n]; t += gridDim.x) {
+    int p = 0;
+    while (t >= g.start[p + 1]) ++p;
+    const int l = t - g.start[p];
+    const int per_z = g.tm[p] * g.tn[p];
+    const int z = l / per_z, r = l - z * per_z;
+    gemm_bf16_tile<BM, BN, X3>(g.M[p], g.N[p], g.K[p], g.Ah[p], g.Al[p], g.lda[p], g.Bh[p], g.Bl[p], g.ldb[p],
+                               g.C[p], g.ldc[p], g.kchunk[p], g.slab[p], r % g.tm[p], r / g.tm[p], z);
+  }
 }
 
 // ---------------------------------------------------------------------------- bf16 MFMA GEMM, 256 x 256 tiles
@@ -709,6 +737,35 @@ __global__ __launch_bounds__(256) void k_scatter_f32_quad(int n_mult, const int*
   }
 }
 
+// ---------------------------------------------------------------------------- grouped launch
+template <typename Kern>
+static int resident_blocks_lp(Kern k, int threads) {
+  int per_cu = 0, dev = 0;
+  RPF_HIP(hipGetDevice(&dev));
+  RPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0));
+  hipDeviceProp_t prop;
+  RPF_HIP(hipGetDeviceProperties(&prop, dev));
+  return std::max(1, per_cu) * std::max(1, prop.multiProcessorCount);
+}
+
+void gemm_bf16_group(hipStream_t s, int tile, bool x3, const BfGroup& g) {
+  const int total = g.start[g.n];
+  if (total == 0) return;
+#define RPF_GRP(T, X)                                                                                   \
+  {                                                                                                     \
+    static const int cap = resident_blocks_lp(k_gemm_bf16_group<T, T, X>, 256);                         \
+    RPF_TIMED_LAUNCH((k_gemm_bf16_group<T, T, X>), dim3((unsigned)std::min(total, cap)), dim3(256), 0, s, g); \
+  }
+  RPF_CHECK(tile == 64 || tile == 128, RPF_EINVAL, "gemm_bf16_group: tile must be 64 or 128");
+  if (tile == 128) {
+    if (x3) RPF_GRP(128, true) else RPF_GRP(128, false)
+  } else {
+    if (x3) RPF_GRP(64, true) else RPF_GRP(64, false)
+  }
+#undef RPF_GRP
+  RPF_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------------------- host
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
                      int64_t ldy, int prec, hipStream_t s, int op) {
@@ -720,6 +777,10 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
   // ~4 workgroups per CU; the scatter sums the split slabs
   std::vector<int64_t> yoff(pb->n_pat + 1, 0), ldr(pb->n_pat, 0);
   std::vector<int> nsp(pb->n_pat, 1), kch(pb->n_pat, 0), tile_m(pb->n_pat, 64), tile_n(pb->n_pat, 64);
+  // a grouped schedule (bf16 forms only) runs every pattern's product in one persistent launch of
+  // its tile, each pattern's K split set by the schedule's work target
+  const Schedule sc = schedule_for(pb, m, prec);
+  const int gtile = (split && (sc.tile == 64 || sc.tile == 128)) ? sc.tile : 0;
   for (int p = 0; p < pb->n_pat; ++p) {
     const int nb = pats[p]->n_b;
     ld[p] = cdiv(nb, 64) * 64;
@@ -727,9 +788,11 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     off[p + 1] = off[p] + ld[p] * cols;
     // bf16 workgroup tile: 256 x 256 when those tiles alone fill the chip (about one per CU), else
     // 128 x 128 (64 x 64 per wave) when both sides allow it, else 64 x 64
-    const int tm = (split && cdiv(nb, 256) * cdiv(cols, (int64_t)256) >= 240) ? 256
-                   : (split && nb >= 128 && cols >= 128)                       ? 128
-                                                                               : 64;
+    int tm = (split && cdiv(nb, 256) * cdiv(cols, (int64_t)256) >= 240) ? 256
+             : (split && nb >= 128 && cols >= 128)                       ? 128
+                                                                         : 64;
+    if (gtile) tm = gtile;
+    else if (split && sc.tile == 256) tm = 256;
     const int tn = tm;
     tile_m[p] = tm;
     tile_n[p] = tn;
@@ -737,6 +800,7 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     int sp = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), std::max<int64_t>(1, ld[p] / 256));
     sp = tm == 256 ? 1 : std::min(sp, 8);
     kch[p] = (int)(cdiv(cdiv(ld[p], sp), 64) * 64);
+    if (gtile) kch[p] = (int)group_kchunk(nb, ld[p], cols, gtile, sc.work, 64);
     nsp[p] = (int)cdiv(ld[p], kch[p]);
     // the 256 x 256 kernel's row-major result: n_b rows of ldr[p] (a multiple of 16 floats)
     ldr[p] = cdiv(cols, (int64_t)16) * 16;
@@ -751,6 +815,8 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     pb->xloc32.ensure(tot);
   }
   YLoc32 yl{};
+  BfGroup grp{};
+  double gflops = 0.0;
   for (int p = 0; p < pb->n_pat; ++p) {
     const rpf_pattern P = pats[p];
     const int nb = P->n_b, nq = (int)pb->occ_of_pat[p].size(), nbn = pb->pat_nbn[p];
@@ -798,11 +864,35 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     }
 #undef RPF_GLP
     RPF_LAUNCH_CHECK();
-    // the tracer times the flexibility products only
-    void* tok = op == OP_FLEX ? trace_begin(s, (int)prec) : nullptr;
     const uint16_t* Ah = op == OP_FLEX ? P->Sp_hi.p : P->S_hi.p;
     const uint16_t* Al = op == OP_FLEX ? P->Sp_lo.p : P->S_lo.p;
     const float* A32 = op == OP_FLEX ? P->Splus32.p : P->S32.p;
+    if (gtile) {
+      // queued for the one grouped launch after the loop
+      RPF_CHECK(P->ldlp == ld[p], RPF_EINVAL, "low-precision S+ layout mismatch");
+      RPF_CHECK(Ah != nullptr && Al != nullptr, RPF_EINVAL, "low-precision copy of the pattern matrix missing");
+      const int q = grp.n++;
+      grp.M[q] = nb;
+      grp.N[q] = cols;
+      grp.K[q] = (int)ld[p];
+      grp.kchunk[q] = kch[p];
+      grp.tm[q] = (int)cdiv(nb, gtile);
+      grp.tn[q] = (int)cdiv(cols, gtile);
+      grp.Ah[q] = Ah;
+      grp.Al[q] = Al;
+      grp.lda[q] = ld[p];
+      grp.Bh[q] = pb->xhi.p + off[p];
+      grp.Bl[q] = pb->xlo.p + off[p];
+      grp.ldb[q] = ld[p];
+      grp.C[q] = yp;
+      grp.ldc[q] = ld[p];
+      grp.slab[q] = slab;
+      grp.start[q + 1] = grp.start[q] + grp.tm[q] * grp.tn[q] * nsp[p];
+      gflops += 2.0 * nb * (double)nb * (double)cols;
+      continue;
+    }
+    // the tracer times the flexibility products only
+    void* tok = op == OP_FLEX ? trace_begin(s, (int)prec) : nullptr;
     if (split) {
       RPF_CHECK(P->ldlp == ld[p], RPF_EINVAL, "low-precision S+ layout mismatch");
       RPF_CHECK(Ah != nullptr && Al != nullptr, RPF_EINVAL, "low-precision copy of the pattern matrix missing");
@@ -835,6 +925,11 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     }
     RPF_LAUNCH_CHECK();
     if (tok) trace_end(tok, s, 2.0 * nb * (double)nb * (double)cols);
+  }
+  if (grp.n > 0) {
+    void* tok = op == OP_FLEX ? trace_begin(s, (int)prec) : nullptr;
+    gemm_bf16_group(s, gtile, prec == RPF_BF16X3, grp);
+    if (tok) trace_end(tok, s, gflops);
   }
   if (pb->n_mult == 0) return;
   dim3 grid((unsigned)cdiv(pb->n_mult, 128));

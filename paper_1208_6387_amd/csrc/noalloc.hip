@@ -45,7 +45,7 @@ extern "C" rpf_status feti_apply_noalloc(rpf_problem pb, const rpf_pattern* patt
               "feti_apply_noalloc: no flags are accepted (the coarse projector allocates its space)");
     check_patterns(pb, patterns, RPF_FP64);
     if (pb->n_lambda == 0) return;
-    const F64Plan pl = plan_F64(pb, patterns, m);
+    const F64Plan pl = plan_F64(pb, patterns, m, schedule_for(pb, m, RPF_FP64));
     const int64_t xn = cdiv(pl.xneed, 32) * 32;  // keeps the result slabs 256-byte aligned
     const int64_t need = xn + pl.yneed;
     RPF_CHECK(need <= SCRATCH_DOUBLES, RPF_EINVAL,

@@ -118,7 +118,7 @@ void check_status(hipStream_t s, const int* d_status, const char* what) {
 using namespace rpf;
 
 extern "C" const char* rpf_last_error(void) { return rpf::g_last_error.c_str(); }
-extern "C" int32_t rpf_version(void) { return 102; }
+extern "C" int32_t rpf_version(void) { return 200; }
 
 extern "C" rpf_status pattern_factor(int32_t n, const int32_t* rowptr, const int32_t* colind, const double* val,
                                      int32_t n_b, const int32_t* bdofs, int32_t dpn, double ktol,

@@ -4,6 +4,8 @@
 
 #include "pattern.hpp"
 
+#include <map>
+
 namespace rpf {
 constexpr int MAXP = 8;   // patterns per structure
 constexpr int KMAX = 8;   // kernel dimension per pattern (coarse kernels)
@@ -15,6 +17,38 @@ struct YLoc {
   int64_t ld[MAXP];
   int64_t slab[MAXP];
   int nsplit[MAXP];
+};
+// Every pattern's flexibility product in one persistent launch: per pattern its operands and
+// shape, its tile grid (tm x tn tiles of the kernel's size, K split into pieces of kchunk) and the
+// index of its first tile in the group's tile list (start[n] = all tiles).
+struct BfGroup {
+  int n;
+  int start[MAXP + 1];
+  int M[MAXP], N[MAXP], K[MAXP], kchunk[MAXP], tm[MAXP], tn[MAXP];
+  const uint16_t* Ah[MAXP];
+  const uint16_t* Al[MAXP];
+  const uint16_t* Bh[MAXP];
+  const uint16_t* Bl[MAXP];
+  int64_t lda[MAXP], ldb[MAXP], ldc[MAXP], slab[MAXP];
+  float* C[MAXP];
+};
+struct DGroup {
+  int n;
+  int start[MAXP + 1];
+  int M[MAXP], N[MAXP], K[MAXP], kchunk[MAXP], tm[MAXP], tn[MAXP];
+  const double* A[MAXP];
+  const double* B[MAXP];
+  int64_t lda[MAXP], ldb[MAXP];
+  double* part[MAXP];  // split-K result slabs, M x N column-major each
+};
+
+// Schedule of the flexibility products of a structure for one block width and arithmetic: the
+// workgroup tile (64 or 128 in a grouped persistent launch; 256 for the single-pattern large-tile
+// kernels, 0 for the size rule) and the target count of work items (tiles times K splits) that
+// sets each pattern's K split.
+struct Schedule {
+  int tile = 0;
+  int work = 1024;
 };
 }  // namespace rpf
 
@@ -75,6 +109,10 @@ struct rpf_problem_s {
   // pattern handles and preconditioner kind in hkey, and an N_lambda x m workspace
   std::vector<uint64_t> hkey;
   rpf::DevBuf<double> Hinv, qbuf;
+
+  // schedules of the flexibility products installed by problem_tune / problem_set_schedule, per
+  // (block width m, arithmetic); absent: the size rule
+  std::map<std::pair<int, int>, rpf::Schedule> sched;
 };
 
 namespace rpf {
@@ -86,12 +124,21 @@ enum LocalOp { OP_FLEX = 0, OP_SCHUR = 1 };
 // block (leading dimension ldw, padded to 32 rows for the large-problem kernel) and of its result
 // slabs (alloc_sp split-K slabs of n_b x cols, nsp of them written), and the doubles needed.
 struct F64Plan {
-  int64_t off[MAXP + 1], yoff[MAXP + 1], ldw[MAXP];
+  int64_t off[MAXP + 1], yoff[MAXP + 1], ldw[MAXP], kchunk[MAXP];
   int nsp[MAXP], alloc_sp[MAXP];
   char big[MAXP];
+  int tile;  // 64 or 128: every pattern in one grouped launch of that tile; 0: per-pattern launches
   int64_t xneed, yneed;
 };
-F64Plan plan_F64(rpf_problem pb, const rpf_pattern* pats, int m);
+// the schedule installed for (m, prec), or the size rule (tile 0)
+Schedule schedule_for(rpf_problem pb, int m, int prec);
+F64Plan plan_F64(rpf_problem pb, const rpf_pattern* pats, int m, const Schedule& sc);
+// grouped persistent launches of the flexibility products (tile 64 or 128)
+void dgemm_group(hipStream_t s, int tile, const DGroup& g);
+void gemm_bf16_group(hipStream_t s, int tile, bool x3, const BfGroup& g);
+// K split of one pattern in a grouped launch: the tiles of the pattern times the split reach about
+// `work` items, each piece at least 256 deep, at most 8 pieces; a multiple of `align`
+int64_t group_kchunk(int64_t nb_rows, int64_t K, int64_t cols, int tile, int work, int align);
 // Gather and FP64 product of every pattern into the workspaces xw (plan.xneed doubles) and yw
 // (plan.yneed doubles); returns the result slabs for scatter_all.  No allocation.
 YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, const double* X, int64_t ldx,

@@ -11,7 +11,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import FP64, Pattern, Problem, pattern_condense, pattern_factor, problem_create
+from . import FP64, Pattern, Problem, pattern_condense, pattern_factor, problem_create, problem_set_schedule
 
 
 def factor_patterns(desc, check_kernel: bool = True, stream=None):
@@ -53,3 +53,20 @@ def split_u(desc, u: torch.Tensor):
         out.append(blk)
         o += n * desc.n_rhs
     return out
+
+
+def install_schedules(pb: Problem, desc, table: dict | None = None) -> int:
+    """Install the tuned product schedules recorded for this structure (schedules.json, written by
+    python -m paper_1208_6387_amd.tune); returns how many were installed."""
+    from .tune import FORMS, load_table, signature
+    table = load_table() if table is None else table
+    n_occ = list(np.bincount(desc.occ_pattern, minlength=len(desc.patterns)))
+    n_b = [p.n_b for p in desc.patterns]
+    done = 0
+    for m in sorted({desc.n_rhs * desc.n_perm, desc.n_rhs}):
+        for form, prec in FORMS.items():
+            rec = table.get(signature(n_b, n_occ, m, form))
+            if rec:
+                problem_set_schedule(pb, m, prec, int(rec["tile"]), int(rec["work"]))
+                done += 1
+    return done
