@@ -28,6 +28,10 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
 * classical and block solvers, recovery: pinned against a brute-force global
   solve assembled from the global node numbering, and the closed-form 1-D
   solution of the heat row;
+* non-Boolean (mortar) assembly of non-matching meshes: pinned (the coupling weights
+  reproduce linear fields, B u = 0 for every linear field cut into the occurrences, the
+  solution equals the dense saddle-point solve of the constrained problem and the exact
+  linear solution of the flux problem, and matching meshes give the Boolean result);
 * iteration counts against the paper's tables: parity unpinned (the paper's
   matrices are not reproduced); its academic study (random dense SPD pattern,
   five and nine repetitions, Dirichlet preconditioner) is checked qualitatively.
@@ -161,12 +165,34 @@ class FetiOracle:
 
     # -- signed Boolean assembly (eq. 2) ------------------------------------------------
     def _assembly(self, s: int) -> sp.csr_matrix:
-        """A^(s): N_lambda x n_b(s); (A v)[l] = sign * O^(s) v[node] at every endpoint on s."""
+        """A^(s): N_lambda x n_b(s); (A v)[l] = sign * O^(s) v[node] at every endpoint on s.
+
+        A non-Boolean structure (mortar coupling of non-matching meshes, section 5) gives each
+        side of a multiplier several local nodes with real weights: (A v)[l] = sum_k w_k O^(s)
+        v[node_k] over the entries of the side on s."""
         pb, dpn = self.pb, self.dpn
         p = pb.occ_pattern[s]
         nb = self.pats[p].n_b
         O = pb.occ_rot[s][:dpn, :dpn] if dpn > 1 else np.ones((1, 1))
         rows, cols, vals = [], [], []
+        if getattr(pb, "entry_ptr", None) is not None:
+            ptr, node, wgt = pb.entry_ptr, pb.entry_node, pb.entry_weight
+            for e in range(2):
+                sel = np.nonzero(pb.mult_occ[:, e] == s)[0]
+                for m_ in sel:
+                    for k in range(ptr[2 * m_ + e], ptr[2 * m_ + e + 1]):
+                        bp = self.bpos[p][node[k]]
+                        assert bp >= 0
+                        for c in range(dpn):
+                            for c2 in range(dpn):
+                                if O[c, c2] != 0.0:
+                                    rows.append([m_ * dpn + c])
+                                    cols.append([bp * dpn + c2])
+                                    vals.append([wgt[k] * O[c, c2]])
+            if not rows:
+                return sp.csr_matrix((self.n_lambda, nb))
+            return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                 shape=(self.n_lambda, nb))
         for e in range(2):
             sel = np.nonzero(pb.mult_occ[:, e] == s)[0]
             if len(sel) == 0:
@@ -528,6 +554,8 @@ def global_solve(problem):
     Returns u per occurrence (pattern frame) and the global vector.
     """
     pb = problem
+    if getattr(pb, "meta", {}).get("mortar"):
+        raise ValueError("global_solve: the occurrences of a mortar structure share no mesh; use constrained_solve")
     dpn = pb.dpn
     n = pb.n_gnodes * dpn
     rows, cols, vals = [], [], []
@@ -561,6 +589,34 @@ def global_solve(problem):
         gd = (pb.occ_gnode[s][:, None] * dpn + np.arange(dpn)[None, :]).ravel()
         u.append(R.T @ ug[gd])
     return u, ug, K, f
+
+
+def constrained_solve(problem, oracle: FetiOracle | None = None):
+    """The constrained global problem behind eq. 2, solved directly: minimise the energy
+    sum_s (u_s^T K_s u_s / 2 - f_s^T u_s) subject to B u = 0, B = [.. A^(s) t^(s) ..], by the dense
+    saddle-point system [K B^T; B 0] [u; lambda] = [f; 0] (K block diagonal, floating blocks
+    included).  For structures without a global mesh (non-matching, mortar-coupled occurrences)
+    this is the brute-force reference; on conforming meshes it equals global_solve.  Tiny sizes only.
+    Returns u per occurrence (pattern frame) and lambda."""
+    pb = problem
+    o = FetiOracle(pb) if oracle is None else oracle
+    ns = [pb.patterns[p].n for p in pb.occ_pattern]
+    off = np.concatenate([[0], np.cumsum(ns)])
+    n = int(off[-1])
+    nl = pb.n_lambda
+    Kd = np.zeros((n + nl, n + nl))
+    rhs = np.zeros((n + nl, pb.n_rhs))
+    for s in range(pb.n_occ):
+        pat = pb.patterns[pb.occ_pattern[s]]
+        P = o.pats[pb.occ_pattern[s]]
+        Kd[off[s]:off[s + 1], off[s]:off[s + 1]] = pat.K.toarray()
+        Bs = np.zeros((nl, ns[s]))
+        Bs[:, P.b] = o.A[s].toarray()
+        Kd[n:, off[s]:off[s + 1]] = Bs
+        Kd[off[s]:off[s + 1], n:] = Bs.T
+        rhs[off[s]:off[s + 1]] = pb.f_local[s]
+    x = np.linalg.solve(Kd, rhs)
+    return [x[off[s]:off[s + 1]] for s in range(pb.n_occ)], x[n:]
 
 
 def multipliers_from_displacements(oracle: FetiOracle, u):

@@ -80,6 +80,13 @@ class Problem:
     perm_node: np.ndarray         # (n_perm, N_mn) int32: (Pi_k z)[mn] = z[perm_node[k, mn]]
     tol: float = 1e-8
     meta: dict = field(default_factory=dict)
+    # non-Boolean assembly (section 5: mortar coupling of non-matching meshes): side e of
+    # multiplier i couples the local nodes entry_node[k] of occurrence mult_occ[i, e] with weights
+    # entry_weight[k], k in [entry_ptr[2i+e], entry_ptr[2i+e+1]); None: the signed Boolean
+    # assembly given by mult_node and mult_sign
+    entry_ptr: Optional[np.ndarray] = None
+    entry_node: Optional[np.ndarray] = None
+    entry_weight: Optional[np.ndarray] = None
 
     @property
     def n_occ(self) -> int:
@@ -108,6 +115,19 @@ class Problem:
 
     def n_dirichlet_mult(self) -> int:
         return int((self.mult_occ[:, 1] < 0).sum())
+
+    @property
+    def weighted(self) -> bool:
+        return self.entry_ptr is not None
+
+    def entries(self):
+        """(entry_ptr, entry_node, entry_weight) of the assembly; for a Boolean structure, the one
+        node and the sign of each side."""
+        if self.weighted:
+            return self.entry_ptr, self.entry_node, self.entry_weight
+        has = (self.mult_occ >= 0).ravel()
+        ptr = np.concatenate([[0], np.cumsum(has)]).astype(np.int32)
+        return ptr, self.mult_node.ravel()[has].astype(np.int32), self.mult_sign.ravel()[has].astype(float)
 
 
 # --------------------------------------------------------------------------- multipliers
@@ -573,6 +593,164 @@ def uneven_three(plate=(24, 8, 2), sector=(6, 16, 4), base=16, n_sectors=16, pla
 
 
 # --------------------------------------------------------------------------- named configurations
+
+# --------------------------------------------------------------------------- non-matching meshes
+
+def mortar_weights_1d(xs: np.ndarray, xm: np.ndarray) -> np.ndarray:
+    """Coupling weights of two non-matching piecewise-linear meshes of one segment, by the mortar
+    method with dual Lagrange multipliers (Wohlmuth's biorthogonal basis).
+
+    The multipliers live on the non-mortar side (nodes xs); row i of the result W gives
+    u_s(x_i) = sum_l W[i, l] u_m(xm_l), W = D^{-1} M with D_ii = int phi_i (phi: the non-mortar hat
+    functions) and M_il = int psi_i chi_l, where psi_i = 2 phi_i - phi_j on each non-mortar element
+    [x_i, x_j] (the dual basis: int psi_i phi_k = delta_ik D_kk) and chi_l are the mortar-side hats.
+    The products are integrated exactly (two Gauss points per piece between consecutive breakpoints
+    of both meshes).  Rows sum to one and linear functions are reproduced exactly.
+    """
+    xs = np.asarray(xs, float)
+    xm = np.asarray(xm, float)
+    ns, nm = len(xs), len(xm)
+    D = np.zeros(ns)
+    Mw = np.zeros((ns, nm))
+    br = np.unique(np.concatenate([xs, xm]))
+    g = np.array([-1.0, 1.0]) / np.sqrt(3.0)
+
+    def hats(x, nodes):
+        # values of every hat function of a 1-D mesh at the points x
+        v = np.zeros((len(x), len(nodes)))
+        e = np.clip(np.searchsorted(nodes, x, side="right") - 1, 0, len(nodes) - 2)
+        t_ = (x - nodes[e]) / (nodes[e + 1] - nodes[e])
+        v[np.arange(len(x)), e] = 1.0 - t_
+        v[np.arange(len(x)), e + 1] = t_
+        return v, e
+
+    for a, b in zip(br[:-1], br[1:]):
+        x = 0.5 * (a + b) + 0.5 * (b - a) * g
+        w = np.full(2, 0.5 * (b - a))
+        phi, e = hats(x, xs)
+        chi, _ = hats(x, xm)
+        # dual basis on the non-mortar element holding each point
+        psi = np.zeros_like(phi)
+        for q in range(len(x)):
+            i, j = e[q], e[q] + 1
+            psi[q, i] = 2.0 * phi[q, i] - phi[q, j]
+            psi[q, j] = 2.0 * phi[q, j] - phi[q, i]
+        D += w @ phi
+        Mw += (psi * w[:, None]).T @ chi
+    return Mw / D[:, None]
+
+
+def mortar_row(kind="heat", shapes=((8, 8), (6, 6)), n_occ=4, n_rhs=1, load="normal", seed=61, n_perm=None,
+               tol=1e-10):
+    """A row of unit boxes meshed alternately by two patterns whose shared faces do not match:
+    occurrence s is [s, s+1] x [0, 1]^(d-1) with pattern s % 2.  kind 'heat' (2-D quads, one dof
+    per node) or 'elast' (3-D bricks, E = 1, nu = 0.3, three dofs per node).  The interface between
+    s and s+1 carries one multiplier (per dof of a node) for each node of the x = 0 face of s+1 (the
+    non-mortar side), coupled to the x = 1 face of s by mortar_weights_1d (in 3-D the tensor
+    product of the weights along y and z, exact for these structured faces): the non-Boolean
+    assembly of section 5.  u = 0 on the x = 0 face of occurrence 0 (Total FETI Dirichlet
+    multipliers).  load: 'normal' (i.i.d. N(0,1) nodal loads) or, for heat, 'flux' (no source, unit
+    outward flux on the right edge of the last occurrence: the exact solution is u = x, which the
+    mortar coupling reproduces).
+    """
+    pats, meshes = [], []
+    dim = len(shapes[0])
+    for k, shp in enumerate(shapes):
+        mesh = M.GridMesh(shp, (1.0,) * dim)
+        if kind == "heat":
+            assert dim == 2
+            dpn, kdim = 1, 1
+            K = M.assemble(mesh, M.quad_laplace(*mesh.h), 1)
+        else:
+            assert dim == 3
+            dpn, kdim = 3, 6
+            K = M.assemble(mesh, M.hex_elasticity(*mesh.h), 3)
+        pats.append(Pattern(f"mortar-{kind}-pattern{k}", dpn, mesh.coords, K, kdim))
+        meshes.append(mesh)
+    occ_pattern = np.array([s % len(shapes) for s in range(n_occ)], np.int32)
+
+    def face(s, side):
+        # nodes of the x = side face of occurrence s, ordered by (z, y), and the 1-D coordinates
+        m = meshes[occ_pattern[s]]
+        nodes = m.face_nodes(0, side)
+        c = m.coords[nodes]
+        order = np.lexsort(tuple(c[:, d] for d in range(1, dim)))
+        axes = [np.unique(c[:, d]) for d in range(1, dim)]
+        return nodes[order], axes
+
+    def face_weights(ys_axes, ym_axes):
+        Wt = np.ones((1, 1))
+        for a_s, a_m in zip(ys_axes, ym_axes):    # y fastest, z slowest
+            Wt = np.kron(mortar_weights_1d(a_s, a_m), Wt)
+        return Wt
+
+    mo, mn, ms, ptr, en, ew = [], [], [], [0], [], []
+    for s in range(n_occ - 1):
+        sn, ax_s = face(s + 1, 0)   # non-mortar: x = 0 face of s + 1
+        mnodes, ax_m = face(s, 1)   # mortar: x = 1 face of s
+        Wt = face_weights(ax_s, ax_m)
+        for i in range(len(sn)):
+            nz = np.nonzero(np.abs(Wt[i]) > 1e-14)[0]
+            ref = nz[np.argmax(np.abs(Wt[i, nz]))]
+            mo.append((s + 1, s))
+            mn.append((sn[i], mnodes[ref]))
+            ms.append((1, -1))
+            en.append(sn[i])
+            ew.append(1.0)
+            ptr.append(len(en))
+            en.extend(mnodes[nz])
+            ew.extend(-Wt[i, nz])
+            ptr.append(len(en))
+    dn, _ = face(0, 0)
+    for n_ in dn:
+        mo.append((0, -1))
+        mn.append((n_, -1))
+        ms.append((1, 0))
+        en.append(n_)
+        ew.append(1.0)
+        ptr.append(len(en))
+        ptr.append(len(en))
+    mo = np.asarray(mo, np.int32)
+    mn = np.asarray(mn, np.int32)
+    ms = np.asarray(ms, np.int8)
+    ptr = np.asarray(ptr, np.int32)
+    en = np.asarray(en, np.int32)
+    ew = np.asarray(ew, float)
+    # pattern boundary: every local node that any assembly entry names
+    occ_of_entry = np.repeat(mo.ravel(), np.diff(ptr))
+    for p, pat in enumerate(pats):
+        sel = (occ_of_entry >= 0) & (occ_pattern[np.maximum(occ_of_entry, 0)] == p)
+        pat.bnodes = np.unique(en[sel]).astype(np.int32)
+    perm = permutation_maps(occ_pattern, mo, mn, n_occ if n_perm is None else n_perm)
+    # no global mesh: every occurrence keeps its own nodes (the meshes do not match)
+    occ_gnode, off = [], 0
+    for s in range(n_occ):
+        nn = meshes[occ_pattern[s]].n_nodes
+        occ_gnode.append(off + np.arange(nn))
+        off += nn
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f_local = []
+    for s in range(n_occ):
+        m = meshes[occ_pattern[s]]
+        if load == "normal":
+            draws = rng.standard_normal((n_rhs, m.n_nodes, dpn))
+            f_local.append(np.ascontiguousarray(draws.reshape(n_rhs, -1).T))
+        elif load == "flux" and kind == "heat":
+            f = np.zeros((m.n_nodes, n_rhs))
+            if s == n_occ - 1:
+                nodes, (y,) = face(s, 1)
+                h = np.diff(y)
+                f[nodes, :] = (np.concatenate([h, [0.0]]) / 2 + np.concatenate([[0.0], h]) / 2)[:, None]
+            f_local.append(f)
+        else:
+            raise ValueError(load)
+    rot = np.repeat(np.eye(3)[None], n_occ, axis=0)
+    meta = dict(kind=kind, mortar=True, shapes=tuple(map(tuple, shapes)), grid=(n_occ,), load=load)
+    return Problem(name=f"mortar-{kind}-row{n_occ}", dpn=dpn, patterns=pats, occ_pattern=occ_pattern,
+                   occ_rot=rot, occ_gnode=occ_gnode, n_gnodes=off, dirichlet_gnodes=np.zeros(0, np.int64),
+                   mult_occ=mo, mult_node=mn, mult_sign=ms, n_rhs=n_rhs, f_local=f_local, perm_node=perm, tol=tol,
+                   meta=meta, entry_ptr=ptr, entry_node=en, entry_weight=ew)
+
 
 def config(i: int, small: bool = False) -> Problem:
     """The five benchmark configurations, 0-based (seed 12086387 + i).
