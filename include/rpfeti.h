@@ -137,6 +137,19 @@ typedef struct {
   const int8_t* mult_sign;       /* [2*n_mult], +1 or -1 */
   int32_t n_perm;
   const int32_t* perm_node;      /* [n_perm*n_mult] or NULL */
+  /* Non-Boolean assembly (section 5: operators from a mortar coupling of non-matching meshes), or
+   * all NULL for the signed Boolean one given by mult_node and mult_sign.  Side e of multiplier i
+   * couples the entries k = entry_ptr[2i+e] .. entry_ptr[2i+e+1]-1: local node entry_node[k] of
+   * occurrence mult_occ[2i+e] with weight entry_weight[k] (the sign included), so that
+   * (A^(s) v)[(i, c)] = sum_k entry_weight[k] (O^(s) v[entry_node[k]])[c].  A side has entries
+   * exactly when it has an occurrence; every entry node must be a boundary node of its pattern.
+   * mult_node and mult_sign stay required: they name one reference node per side, used to
+   * validate the structure (the rotation of a permuted multiplier is that of its first side's
+   * occurrence, as for the Boolean assembly).  A weighted structure takes no preconditioner
+   * (RPF_EINVAL): its multiplicity scaling is defined for the Boolean assembly only. */
+  const int32_t* entry_ptr;      /* [2*n_mult+1] or NULL */
+  const int32_t* entry_node;     /* [entry_ptr[2*n_mult]] */
+  const double* entry_weight;    /* [entry_ptr[2*n_mult]] */
 } rpf_problem_desc;
 
 rpf_status problem_create(const rpf_problem_desc* desc, rpf_problem* out);

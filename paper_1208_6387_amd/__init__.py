@@ -107,9 +107,11 @@ def pattern_export(p: Pattern, what: str, stream=None) -> torch.Tensor:
 
 
 def problem_create(dofs_per_node: int, pat_n_nodes, pat_bnodes, occ_pattern, occ_rot, mult_occ, mult_node,
-                   mult_sign, perm_node=None) -> Problem:
+                   mult_sign, perm_node=None, entries=None) -> Problem:
     """Structure from host arrays: pat_bnodes is a list of per-pattern sorted boundary node arrays,
-    mult_* are (n_mult, 2) arrays, occ_rot an (n_occ, 3, 3) array or None, perm_node (n_perm, n_mult)."""
+    mult_* are (n_mult, 2) arrays, occ_rot an (n_occ, 3, 3) array or None, perm_node (n_perm, n_mult).
+    entries: None (signed Boolean assembly) or (entry_ptr, entry_node, entry_weight) of a
+    non-Boolean one."""
     lib = load()
     nn = _host(pat_n_nodes, np.int32)
     ptr = _host(np.concatenate([[0], np.cumsum([len(b) for b in pat_bnodes])]), np.int32)
@@ -123,9 +125,14 @@ def problem_create(dofs_per_node: int, pat_n_nodes, pat_bnodes, occ_pattern, occ
         pn = _host(perm_node, np.int32)
         n_perm = pn.shape[0]
         pn = pn.reshape(-1)
+    if entries is not None:
+        eptr, enode, ew = (_host(entries[0], np.int32), _host(entries[1], np.int32), _host(entries[2], np.float64))
     d = _lib.ProblemDesc(dofs_per_node, len(nn), nn.ctypes.data, ptr.ctypes.data, bn.ctypes.data, len(op),
                          op.ctypes.data, None if rot is None else rot.ctypes.data, len(mo) // 2, mo.ctypes.data,
-                         mn.ctypes.data, ms.ctypes.data, n_perm, None if pn is None else pn.ctypes.data)
+                         mn.ctypes.data, ms.ctypes.data, n_perm, None if pn is None else pn.ctypes.data,
+                         None if entries is None else eptr.ctypes.data,
+                         None if entries is None else enode.ctypes.data,
+                         None if entries is None else ew.ctypes.data)
     h = C.c_void_p()
     check(lib.problem_create(C.byref(d), C.byref(h)))
     return Problem(h)

@@ -29,7 +29,8 @@ class ProblemDesc(C.Structure):
                 ("pat_bnode_ptr", C.c_void_p), ("pat_bnodes", C.c_void_p), ("n_occ", C.c_int32),
                 ("occ_pattern", C.c_void_p), ("occ_rot", C.c_void_p), ("n_mult", C.c_int32),
                 ("mult_occ", C.c_void_p), ("mult_node", C.c_void_p), ("mult_sign", C.c_void_p),
-                ("n_perm", C.c_int32), ("perm_node", C.c_void_p)]
+                ("n_perm", C.c_int32), ("perm_node", C.c_void_p), ("entry_ptr", C.c_void_p),
+                ("entry_node", C.c_void_p), ("entry_weight", C.c_void_p)]
 
 
 class SolveOpts(C.Structure):

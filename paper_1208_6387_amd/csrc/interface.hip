@@ -6,6 +6,7 @@
 #include "problem.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <map>
 #include <memory>
@@ -677,6 +678,11 @@ void gather_pattern(rpf_problem pb, int p, int nbn, const double* lam, int64_t l
                     int64_t ldx, hipStream_t s) {
   const int nq = (int)pb->occ_of_pat[p].size();
   if (nq == 0 || nbn == 0) return;
+  if (pb->weighted) {
+    RPF_CHECK(nbn == pb->pat_nbn[p], RPF_EINVAL, "gather: partial boundary with a non-Boolean assembly");
+    wgather(pb, p, lam, ldl, m, 2, X, nullptr, nullptr, nullptr, ldx, s);
+    return;
+  }
   if (m >= 8 && nbn == pb->pat_nbn[p]) {
     gather_rows(pb, p, lam, ldl, m, 2, X, nullptr, nullptr, nullptr, ldx, s);
     return;
@@ -702,6 +708,18 @@ void gather_pattern(rpf_problem pb, int p, int nbn, const double* lam, int64_t l
 
 void scatter_all(rpf_problem pb, const YLoc& yl, int m, double* Y, int64_t ldy, double beta, hipStream_t s) {
   if (pb->n_mult == 0) return;
+  if (pb->weighted) {
+    RPF_CHECK(beta == 0.0, RPF_EINVAL, "scatter: beta with a non-Boolean assembly");
+    WLoc<double> w{};
+    for (int p = 0; p < pb->n_pat; ++p) {
+      w.base[p] = yl.base[p];
+      w.ld[p] = yl.ld[p];
+      w.slab[p] = yl.slab[p];
+      w.nsplit[p] = yl.nsplit[p];
+    }
+    wscatter(pb, w, m, Y, ldy, s);
+    return;
+  }
   dim3 grid((unsigned)cdiv(pb->n_mult, 128));
   const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
 #define RPF_SCATTER(D)                                                                                        \
@@ -892,6 +910,8 @@ void scale_lam(rpf_problem pb, int m, const double* X, int64_t ldx, double* Y, i
 void apply_precond(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
                    int64_t ldy, int kind, int prec, hipStream_t s) {
   if (pb->n_mult == 0) return;
+  RPF_CHECK(!pb->weighted, RPF_EINVAL,
+            "preconditioner: the multiplicity scaling (A A^T)^{-1} is defined for the signed Boolean assembly only");
   const int64_t N = pb->n_lambda;
   pb->pcbuf.ensure((size_t)N * m);
   double* T = pb->pcbuf.p;
@@ -951,6 +971,13 @@ void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
   pb->d_kp.upload(kp.data(), kp.size(), s);
   DevBuf<double> GtG((size_t)nG * nG);
   fill(s, GtG.p, (int64_t)nG * nG, 0.0);
+  int km = 0;
+  for (int p = 0; p < pb->n_pat; ++p) km = std::max(km, kp[p]);
+  pb->g_km = km <= 1 ? 1 : km <= 3 ? 3 : km <= 6 ? 6 : KMAX;
+  if (pb->weighted) {
+    // the rows of G first, then G^T G from them
+    wcoarse_setup(pb, GtG.p, nG, s);
+  } else {
 #define RPF_GTG(D)                                                                                               \
   do {                                                                                                           \
     hipLaunchKernelGGL(k_gtg_diag<D>, dim3(pb->n_occ), dim3(256), 0, s, pb->d_occ_pat.p, pb->d_slot_off.p,       \
@@ -968,6 +995,7 @@ void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
   }
 #undef RPF_GTG
   RPF_LAUNCH_CHECK();
+  }
   // explicit inverse of the coarse matrix: projections then cost one small GEMM
   const Envelope env = Envelope::dense(nG);
   DevBuf<double> dinv((size_t)cdiv(nG, NB) * NB * NB);
@@ -986,11 +1014,8 @@ void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
     pb->coarse_key.clear();
     throw Error(RPF_ENOTSPD, "coarse matrix G^T G is singular (the structure has no Dirichlet condition?)");
   }
-  // rows of G per multiplier for the projections (x -= G y)
-  int km = 0;
-  for (int p = 0; p < pb->n_pat; ++p) km = std::max(km, kp[p]);
-  pb->g_km = km <= 1 ? 1 : km <= 3 ? 3 : km <= 6 ? 6 : KMAX;
-  if (pb->n_mult > 0) {
+  // rows of G per multiplier for the projections (x -= G y; built above for a weighted assembly)
+  if (pb->n_mult > 0 && !pb->weighted) {
     const int64_t tot = (int64_t)pb->n_mult * 2 * pb->dpn * pb->g_km;
     pb->d_grow.ensure((size_t)tot);
     pb->d_ep_goff.ensure((size_t)2 * pb->n_mult);
@@ -1009,6 +1034,10 @@ void ensure_coarse(rpf_problem pb, const rpf_pattern* pats, hipStream_t s) {
 }
 
 void coarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, hipStream_t s) {
+  if (pb->weighted) {
+    wcoarse_gt(pb, x, ldx, m, c, s);
+    return;
+  }
   // slices per occurrence: about 1024 workgroups in all, at least 256 dofs per slice; with lanes
   // over columns also at most ~8 nodes per lane group, so that the dependent loads of many
   // nodes are in flight at once
@@ -1575,12 +1604,76 @@ extern "C" rpf_status problem_create(const rpf_problem_desc* d, rpf_problem* out
         l2m_bn[fillp[slot]] = ep_bn[2 * i + e];
         l2m_code[fillp[slot]++] = (i << 1) | (ep_sign[2 * i + e] < 0 ? 1 : 0);
       }
+    // non-Boolean assembly: the entries of every multiplier side and their transposes
+    if (d->entry_ptr != nullptr) {
+      RPF_CHECK(d->entry_node != nullptr && d->entry_weight != nullptr, RPF_EINVAL,
+                "problem_create: entry_ptr without entry_node / entry_weight");
+      pb->weighted = true;
+      const int32_t* ep = d->entry_ptr;
+      RPF_CHECK(ep[0] == 0, RPF_EINVAL, "problem_create: entry_ptr[0] must be 0");
+      std::vector<int> wm_bn((size_t)ep[2 * (size_t)nm]);
+      std::vector<int> wl_cnt(nslot + 1, 0), wo_cnt(no + 1, 0);
+      for (int i = 0; i < nm; ++i)
+        for (int e = 0; e < 2; ++e) {
+          const int k0 = ep[2 * i + e], k1 = ep[2 * i + e + 1];
+          RPF_CHECK(k1 >= k0, RPF_EINVAL, "problem_create: entry_ptr not increasing");
+          const int s = ep_occ[2 * i + e];
+          RPF_CHECK(s >= 0 ? k1 > k0 : k1 == k0, RPF_EINVAL,
+                    "problem_create: a side has entries exactly when it has an occurrence");
+          if (s < 0) continue;
+          const int p = pb->occ_pat[s];
+          wo_cnt[s + 1]++;
+          for (int k = k0; k < k1; ++k) {
+            const int node = d->entry_node[k];
+            RPF_CHECK(node >= 0 && node < d->pat_n_nodes[p] && bpos[p][node] >= 0, RPF_EINVAL,
+                      "problem_create: entry node is not a boundary node of its pattern");
+            RPF_CHECK(std::isfinite(d->entry_weight[k]), RPF_EINVAL, "problem_create: entry weight not finite");
+            wm_bn[k] = bpos[p][node];
+            wl_cnt[pb->slot_off[s] + wm_bn[k] + 1]++;
+          }
+        }
+      std::vector<int> wl_ptr(nslot + 1, 0), wo_ptr(no + 1, 0);
+      for (int i = 0; i < nslot; ++i) wl_ptr[i + 1] = wl_ptr[i] + wl_cnt[i + 1];
+      for (int o = 0; o < no; ++o) wo_ptr[o + 1] = wo_ptr[o] + wo_cnt[o + 1];
+      std::vector<int> wl_mult(wl_ptr[nslot]), wo_me(wo_ptr[no]);
+      std::vector<double> wl_w(wl_ptr[nslot]);
+      std::vector<int> fl(wl_ptr.begin(), wl_ptr.end() - 1), fo(wo_ptr.begin(), wo_ptr.end() - 1);
+      for (int i = 0; i < nm; ++i)
+        for (int e = 0; e < 2; ++e) {
+          const int s = ep_occ[2 * i + e];
+          if (s < 0) continue;
+          wo_me[fo[s]++] = 2 * i + e;
+          for (int k = ep[2 * i + e]; k < ep[2 * i + e + 1]; ++k) {
+            const int sl = pb->slot_off[s] + wm_bn[k];
+            wl_mult[fl[sl]] = i;
+            wl_w[fl[sl]++] = d->entry_weight[k];
+          }
+        }
+      hipStream_t s0w = nullptr;
+      pb->d_wm_ptr.upload(ep, 2 * (size_t)nm + 1, s0w);
+      if (!wm_bn.empty()) {
+        pb->d_wm_bn.upload(wm_bn.data(), wm_bn.size(), s0w);
+        pb->d_wm_w.upload(d->entry_weight, wm_bn.size(), s0w);
+      }
+      pb->d_wl_ptr.upload(wl_ptr.data(), wl_ptr.size(), s0w);
+      if (!wl_mult.empty()) {
+        pb->d_wl_mult.upload(wl_mult.data(), wl_mult.size(), s0w);
+        pb->d_wl_w.upload(wl_w.data(), wl_w.size(), s0w);
+      }
+      pb->d_wo_ptr.upload(wo_ptr.data(), wo_ptr.size(), s0w);
+      if (!wo_me.empty()) pb->d_wo_me.upload(wo_me.data(), wo_me.size(), s0w);
+      RPF_HIP(hipStreamSynchronize(s0w));
+    }
     // scaling of the preconditioners: C = A A^T at node level (A^(s) A^(s)T of two multipliers
     // on the same endpoint is sign sign O O^T = sign sign I), block diagonal over the groups of
     // multipliers joined through shared endpoints; C^{-1} is formed group by group
     std::vector<int> sc_ptr(nm + 1, 0), sc_col;
     std::vector<double> sc_val;
-    {
+    if (pb->weighted) {
+      // the preconditioners (and so their scaling) are defined for the Boolean assembly only
+      pb->occ_nbr.assign(pb->n_occ, {});
+      for (int o = 0; o < pb->n_occ; ++o) pb->occ_nbr[o].push_back(o);
+    } else {
       std::vector<int> uf(nm);
       for (int i = 0; i < nm; ++i) uf[i] = i;
       auto find = [&](int x) {

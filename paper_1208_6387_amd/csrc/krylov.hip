@@ -826,6 +826,9 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     RPF_CHECK(opts->tol > 0 && opts->max_it >= 1, RPF_EINVAL, "block_krylov_solve: tol / max_it");
     const int prec = opts->prec;
     RPF_CHECK(prec >= RPF_FP64 && prec <= RPF_BF16, RPF_EINVAL, "block_krylov_solve: precision");
+    RPF_CHECK(!(pb->weighted && (opts->precond != RPF_PRECOND_NONE || opts->coarse != RPF_PRECOND_NONE)), RPF_EINVAL,
+              "block_krylov_solve: a non-Boolean assembly takes no preconditioner (the multiplicity scaling is "
+              "defined for the signed Boolean assembly)");
     RPF_CHECK(opts->precond >= RPF_PRECOND_NONE && opts->precond <= RPF_PRECOND_DIRICHLET, RPF_EINVAL,
               "block_krylov_solve: preconditioner");
     check_patterns(pb, pats, RPF_FP64);

@@ -793,6 +793,7 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
                                                                          : 64;
     if (gtile) tm = gtile;
     else if (split && sc.tile == 256) tm = 256;
+    if (tm == 256 && pb->weighted) tm = 128;  // the non-Boolean scatter reads column-major results
     const int tn = tm;
     tile_m[p] = tm;
     tile_n[p] = tn;
@@ -844,7 +845,9 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
         hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, pb->xhi.p + off[p],
                            pb->xlo.p + off[p], ld[p], nb, cols);
       }
-      if (m >= 8) {
+      if (pb->weighted) {
+        wgather(pb, p, X, ldx, m, 1, nullptr, nullptr, pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], s);
+      } else if (m >= 8) {
         gather_rows(pb, p, X, ldx, m, 1, nullptr, nullptr, pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], s);
       } else {
         switch (pb->dpn) {
@@ -853,6 +856,8 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
           default: RPF_GLP(3, 1);
         }
       }
+    } else if (pb->weighted) {
+      wgather(pb, p, X, ldx, m, 0, nullptr, pb->xloc32.p + off[p], nullptr, nullptr, ld[p], s);
     } else if (m >= 8) {
       gather_rows(pb, p, X, ldx, m, 0, nullptr, pb->xloc32.p + off[p], nullptr, nullptr, ld[p], s);
     } else {
@@ -932,6 +937,18 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
     if (tok) trace_end(tok, s, gflops);
   }
   if (pb->n_mult == 0) return;
+  if (pb->weighted) {
+    WLoc<float> w{};
+    for (int p = 0; p < pb->n_pat; ++p) {
+      RPF_CHECK(!yl.rowmajor[p] || pb->occ_of_pat[p].empty(), RPF_EINVAL, "non-Boolean scatter: row-major result");
+      w.base[p] = yl.base[p];
+      w.ld[p] = yl.ld[p];
+      w.slab[p] = yl.slab[p];
+      w.nsplit[p] = yl.nsplit[p];
+    }
+    wscatter(pb, w, m, Y, ldy, s);
+    return;
+  }
   dim3 grid((unsigned)cdiv(pb->n_mult, 128));
   const double* rot = pb->has_rot ? pb->d_rot.p : nullptr;
   bool all_rm = true;

@@ -42,6 +42,16 @@ struct DGroup {
   double* part[MAXP];  // split-K result slabs, M x N column-major each
 };
 
+// Local results of a product for the non-Boolean scatter: column-major per pattern, nsplit
+// partial slabs `slab` apart (FP64 or FP32).
+template <typename T>
+struct WLoc {
+  const T* base[MAXP];
+  int64_t ld[MAXP];
+  int64_t slab[MAXP];
+  int nsplit[MAXP];
+};
+
 // Schedule of the flexibility products of a structure for one block width and arithmetic: the
 // workgroup tile (64 or 128 in a grouped persistent launch; 256 for the single-pattern large-tile
 // kernels, 0 for the size rule) and the target count of work items (tiles times K splits) that
@@ -109,6 +119,13 @@ struct rpf_problem_s {
   // pattern handles and preconditioner kind in hkey, and an N_lambda x m workspace
   std::vector<uint64_t> hkey;
   rpf::DevBuf<double> Hinv, qbuf;
+
+  // non-Boolean assembly (weights per side of a multiplier): per slot the (multiplier, weight)
+  // entries (gather), per multiplier side the (boundary node, weight) entries (scatter, rows of G),
+  // per occurrence the multiplier sides that touch it (G^T x, G^T G)
+  bool weighted = false;
+  rpf::DevBuf<int> d_wl_ptr, d_wl_mult, d_wm_ptr, d_wm_bn, d_wo_ptr, d_wo_me;
+  rpf::DevBuf<double> d_wl_w, d_wm_w;
 
   // schedules of the flexibility products installed by problem_tune / problem_set_schedule, per
   // (block width m, arithmetic); absent: the size rule
@@ -185,6 +202,14 @@ void gather_rows(rpf_problem pb, int p, const double* lam, int64_t ldl, int m, i
                  uint16_t* Xh, uint16_t* Xl, int64_t ldx, hipStream_t s);
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
                      int64_t ldy, int prec, hipStream_t s, int op = OP_FLEX);
+// non-Boolean assembly: gather (mode 2 FP64, 0 FP32, 1 bf16 split), scatter from column-major
+// local results, rows of G with G^T G, and G^T x
+void wgather(rpf_problem pb, int p, const double* lam, int64_t ldl, int m, int mode, double* X64, float* Xf,
+             uint16_t* Xh, uint16_t* Xl, int64_t ldx, hipStream_t s);
+template <typename T>
+void wscatter(rpf_problem pb, const WLoc<T>& yl, int m, double* Y, int64_t ldy, hipStream_t s);
+void wcoarse_setup(rpf_problem pb, double* GtG, int64_t ldg, hipStream_t s);
+void wcoarse_gt(rpf_problem pb, const double* x, int64_t ldx, int m, double* c, hipStream_t s);
 // event tracing of the flexibility products
 bool trace_on();
 void* trace_begin(hipStream_t s, int prec);

@@ -30,11 +30,15 @@ def condense_patterns(patterns, precs=(FP64,), stream=None):
             pattern_condense(p, prec, stream=stream)
 
 
-def create_problem(desc) -> Problem:
+def create_problem(desc, weighted: bool | None = None) -> Problem:
+    """weighted: pass the assembly as weighted entries (None: when the description has them; True
+    also describes a Boolean assembly through its one-node, signed entries)."""
     rot = desc.occ_rot if desc.has_rotation else None
+    use_w = getattr(desc, "entry_ptr", None) is not None if weighted is None else weighted
     return problem_create(desc.dpn, [p.n_nodes for p in desc.patterns], [p.bnodes for p in desc.patterns],
                           desc.occ_pattern, rot, desc.mult_occ, desc.mult_node, desc.mult_sign,
-                          desc.perm_node if desc.perm_node.shape[0] > 1 else None)
+                          desc.perm_node if desc.perm_node.shape[0] > 1 else None,
+                          entries=desc.entries() if use_w else None)
 
 
 def loads_to_device(desc) -> torch.Tensor:
