@@ -132,7 +132,7 @@ def main():
 
     # ---------------- untimed: structure maps and device-resident inputs
     pb = ST.create_problem(p)
-    n_sched = 0 if args.no_schedules else ST.install_schedules(pb, p)
+    sched = {} if args.no_schedules else ST.install_schedules(pb, p)
     kvals = [torch.from_numpy(np.ascontiguousarray(pat.K.data)).cuda() for pat in p.patterns]
     f = ST.loads_to_device(p)
     lam = torch.empty((pb.n_lambda, p.n_rhs), dtype=torch.float64, device="cuda")
@@ -259,6 +259,19 @@ def main():
     head = forms[0]
     hr = results[head]
 
+    def kernel_label(form):
+        tiles = sorted({t for (m, f), (t, w) in sched.items() if f == form and t > 0})
+        if tiles and form in ("fp64", "bf16x3"):
+            t = tiles[-1]
+            return (f"k_dgemm_group<{t}, {t}> (FP64 MFMA 16x16x4, one grouped launch over all patterns)"
+                    if form == "fp64" else
+                    f"k_gemm_bf16_group<{t}, {t}, X3> (bf16 MFMA 16x16x32, one grouped launch over all patterns, "
+                    f"three products)")
+        return {"fp64": "k_dgemm_big (FP64 MFMA 16x16x4, 128x128 tiles, eight waves)",
+                "fp32": "k_sgemm_sym (FP32 MFMA 16x16x4)",
+                "bf16x3": "k_gemm_bf16_big X3 (bf16 MFMA 16x16x32, 256x256 tiles, three products)",
+                "bf16": "k_gemm_bf16 (bf16 MFMA 16x16x32)"}[form]
+
     def roofline(form):
         tr = results[form]["trace"]
         n = max(tr["count"], 1)
@@ -269,9 +282,7 @@ def main():
         peak = PEAKS_TFLOPS[dt]
         return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic_for(args.workload, form),
-                "kernel": {"fp64": "k_dgemm_big (FP64 MFMA 16x16x4, 128x128 tiles, eight waves)", "fp32": "k_sgemm_sym (FP32 MFMA 16x16x4)",
-                           "bf16x3": "k_gemm_bf16_big X3 (bf16 MFMA 16x16x32, 256x256 tiles, three products)",
-                           "bf16": "k_gemm_bf16 (bf16 MFMA 16x16x32)"}[form],
+                "kernel": kernel_label(form),
                 "avg_launch_ms": round(gemm_ms, 4), "gflop_per_launch": round(flops / 1e9, 4),
                 "launches_per_step": tr["count"] / args.steps,
                 "share_of_step": round(tr["ms"] / args.steps / results[form]["ms"], 4)}
@@ -293,7 +304,7 @@ def main():
                    "precond": args.precond, "coarse": args.coarse, "periodic": args.periodic,
                    "max_blocks": settings["max_blocks"], "inner_tol": settings["inner_tol"],
                    "n_lambda": pb.n_lambda, "n_occ": p.n_occ, "n_rhs": p.n_rhs, "n_perm": p.n_perm,
-                   "tuned_schedules": n_sched,
+                   "tuned_schedules": {f"{f}|m={m}": list(v) for (m, f), v in sorted(sched.items())},
                    "pattern_dofs": [pat.n for pat in p.patterns], "pattern_boundary_dofs": [pat.n_b for pat in p.patterns],
                    "tol": args.tol},
         "iterations": hr["stats"]["iterations"],

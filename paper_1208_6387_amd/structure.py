@@ -59,18 +59,19 @@ def split_u(desc, u: torch.Tensor):
     return out
 
 
-def install_schedules(pb: Problem, desc, table: dict | None = None) -> int:
+def install_schedules(pb: Problem, desc, table: dict | None = None) -> dict:
     """Install the tuned product schedules recorded for this structure (schedules.json, written by
-    python -m paper_1208_6387_amd.tune); returns how many were installed."""
+    python -m paper_1208_6387_amd.tune); returns {(block size, form): (tile, work)} of those installed
+    (tile 0: one launch per pattern, else the grouped launch over all patterns with that tile)."""
     from .tune import FORMS, load_table, signature
     table = load_table() if table is None else table
     n_occ = list(np.bincount(desc.occ_pattern, minlength=len(desc.patterns)))
     n_b = [p.n_b for p in desc.patterns]
-    done = 0
+    done = {}
     for m in sorted({desc.n_rhs * desc.n_perm, desc.n_rhs}):
         for form, prec in FORMS.items():
             rec = table.get(signature(n_b, n_occ, m, form))
             if rec:
                 problem_set_schedule(pb, m, prec, int(rec["tile"]), int(rec["work"]))
-                done += 1
+                done[(m, form)] = (int(rec["tile"]), int(rec["work"]))
     return done
