@@ -235,8 +235,13 @@ void potrf(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac, cons
 void schur_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fac);
 
 // B <- L^{-1} B (trans = false) or L^{-T} B (trans = true), L = leading n x n of a factor.
+// upper: the strict upper triangle of L's envelope holds L^T (mirror_envelope has run on it), so the
+// transposed solve reads the rows of L^T as contiguous columns.
 void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* dinv,
-          const Envelope& env, double* B, int64_t ldb, int64_t nrhs, bool trans);
+          const Envelope& env, double* B, int64_t ldb, int64_t nrhs, bool trans, bool upper = false);
+// A[c, r] = A[r, c] for every entry r > c of the envelope of the leading n x n factor (column block
+// t: rows up to env.rend[t]); the lower triangle is left as it is.
+void mirror_envelope(hipStream_t s, double* A, int64_t lda, int64_t n, const Envelope& env);
 
 // fill / copy helpers
 // Y = (L L^T)^{-1} (full, symmetric) from a dense lower Cholesky factor and its inverted diagonal blocks

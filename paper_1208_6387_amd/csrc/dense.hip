@@ -1579,8 +1579,10 @@ void schur_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t n_fa
 // the loads of a wave's next group are in flight while the MFMAs of the current one run, and the
 // four partial products are summed in LDS.  The band operands come from L2 (every workgroup reads
 // the same band of L; its own panel of X was written by itself one block earlier); the band's L2
-// traffic is one read per PW right-hand sides.
-template <bool FWD, int H>
+// traffic is one read per PW right-hand sides.  UP (backward only): the band of L^T is read from the
+// mirrored upper triangle, L^T[row][k] = A[row + k ldl], sixteen consecutive rows per load like the
+// forward solve, instead of sixteen columns of L 8 bytes each.
+template <bool FWD, int H, bool UP = false>
 __global__ __launch_bounds__(256) void k_trsm_panel(const double* L, int64_t ldl, int64_t n, const double* dinv,
                                                     const int64_t* lo, const int64_t* hi, double* B, int64_t ldb,
                                                     int64_t nrhs) {
@@ -1622,7 +1624,7 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const double* L, int64_t ldl
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t row = j0 + 16 * q + li;
-          a[4 * q + u] = (kok && row < j0 + jb) ? (FWD ? L[row + k * ldl] : L[k + row * ldl]) : 0.0;
+          a[4 * q + u] = (kok && row < j0 + jb) ? ((FWD || UP) ? L[row + k * ldl] : L[k + row * ldl]) : 0.0;
         }
       }
     };
@@ -1688,7 +1690,7 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const double* L, int64_t ldl
 }
 
 void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* dinv, const Envelope& env,
-          double* B, int64_t ldb, int64_t nrhs, bool trans) {
+          double* B, int64_t ldb, int64_t nrhs, bool trans, bool upper) {
   if (n <= 0 || nrhs <= 0) return;
   const int64_t nblk = cdiv(n, NB);
   bool dense = true;
@@ -1702,12 +1704,17 @@ void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* 
     }
     DevBuf<int64_t> db;
     db.upload(bounds.data(), bounds.size(), s);
-    // backward: 32 columns per workgroup (half the band traffic: 15 ms instead of 21 ms at 8192
-    // columns); forward: 16 (13 ms against 14: its band rows are contiguous, and twice as many
-    // workgroups keep two per CU)
+    // 16 columns per workgroup, two workgroups per CU, where the band of L (or of the mirrored L^T)
+    // is read sixteen rows at a time: 12.7 ms each way at 8192 columns of the 20^3 pattern (32
+    // columns, one workgroup per CU: 14 ms forward, 14.3 ms backward).  Without the mirror the
+    // backward reads columns of L, and 32 columns per workgroup halve that less efficient band
+    // traffic (15.5 ms; 21 ms at 16).
     if (!trans)
       hipLaunchKernelGGL((k_trsm_panel<true, 1>), dim3((unsigned)cdiv(nrhs, 16)), dim3(256), 0, s, L, ldl, n, dinv,
                          db.p, db.p + nblk, B, ldb, nrhs);
+    else if (upper)
+      hipLaunchKernelGGL((k_trsm_panel<false, 1, true>), dim3((unsigned)cdiv(nrhs, 16)), dim3(256), 0, s, L, ldl, n,
+                         dinv, db.p, db.p + nblk, B, ldb, nrhs);
     else
       hipLaunchKernelGGL((k_trsm_panel<false, 2>), dim3((unsigned)cdiv(nrhs, 32)), dim3(256), 0, s, L, ldl, n, dinv,
                          db.p, db.p + nblk, B, ldb, nrhs);
@@ -1870,6 +1877,43 @@ void copy_matrix(hipStream_t s, const double* src, int64_t lds, double* dst, int
   hipLaunchKernelGGL(k_copy_matrix, dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s, src, lds, dst, ldd,
                      rows, cols);
   RPF_LAUNCH_CHECK();
+}
+
+// One 64 x 64 tile of column block t (blockIdx.y), rows r0 = t 64 + 64 blockIdx.x up to rend[t]: read
+// down the columns, written along the rows (both coalesced, through LDS); only entries below the
+// diagonal are copied, so the lower triangle is untouched.
+__global__ __launch_bounds__(256) void k_mirror_env(double* A, int64_t lda, int64_t n, const int64_t* rend) {
+  __shared__ double t[64][65];
+  const int64_t j0 = (int64_t)blockIdx.y * 64;
+  const int64_t r0 = j0 + (int64_t)blockIdx.x * 64;
+  const int64_t re = min(rend[blockIdx.y], n);
+  if (r0 >= re) return;
+  const int jb = (int)min<int64_t>(64, n - j0);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int c = ty; c < jb; c += 4) {
+    const int64_t r = r0 + tx;
+    t[c][tx] = r < re ? A[r + (j0 + c) * lda] : 0.0;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i;
+    const int c = tx;
+    if (r < re && c < jb && r > j0 + c) A[(j0 + c) + r * lda] = t[c][i];
+  }
+}
+
+void mirror_envelope(hipStream_t s, double* A, int64_t lda, int64_t n, const Envelope& env) {
+  if (n <= 0) return;
+  const int64_t nblk = cdiv(n, NB);
+  RPF_CHECK((int64_t)env.rend.size() >= nblk, RPF_EINVAL, "mirror_envelope: envelope too short");
+  std::vector<int64_t> re(env.rend.begin(), env.rend.begin() + nblk);
+  int64_t tiles = 1;
+  for (int64_t t = 0; t < nblk; ++t) tiles = std::max<int64_t>(tiles, cdiv(std::min(re[t], n) - t * NB, NB));
+  DevBuf<int64_t> d;
+  d.upload(re.data(), re.size(), s);
+  hipLaunchKernelGGL(k_mirror_env, dim3((unsigned)tiles, (unsigned)nblk), dim3(256), 0, s, A, lda, n, d.p);
+  RPF_LAUNCH_CHECK();
+  RPF_HIP(hipStreamSynchronize(s));  // the bounds buffer is freed on return
 }
 
 void mirror_lower(hipStream_t s, double* A, int64_t lda, int64_t n) {

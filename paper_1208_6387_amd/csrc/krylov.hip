@@ -873,7 +873,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
       if (P->n_i > 0) {
         // Y2 = K_ii^{-1} f_i ; g = f_b - K_bi Y2
         trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Y2[p].p, P->n_i, cols, false);
-        trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Y2[p].p, P->n_i, cols, true);
+        trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Y2[p].p, P->n_i, cols, true, P->L_upper);
         hipLaunchKernelGGL(k_spmm, dim3(spmm_blocks(P->n_b, cols)), dim3(256), 0, s, P->n_b, cols,
                            P->kbi_ptr.p, P->kbi_col.p, P->kbi_val.p, Y2[p].p, (int64_t)P->n_i, -1.0, G[p].p,
                            (int64_t)P->n_b, 1.0);
@@ -1094,7 +1094,7 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
                            P->kib_col.p, P->kib_val.p, Ub.p, (int64_t)P->n_b, 1.0, Ti.p, (int64_t)P->n_i, 0.0);
         RPF_LAUNCH_CHECK();
         trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Ti.p, P->n_i, cols, false);
-        trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Ti.p, P->n_i, cols, true);
+        trsm(s, P->L.p, P->ld, P->n_i, P->dinv_ii.p, P->env_ii, Ti.p, P->n_i, cols, true, P->L_upper);
         hipLaunchKernelGGL(k_axpby, dim3(nblocks((int64_t)P->n_i * cols)), dim3(256), 0, s, (int64_t)P->n_i * cols, 1.0,
                            Y2[p].p, -1.0, Ti.p);
         RPF_LAUNCH_CHECK();

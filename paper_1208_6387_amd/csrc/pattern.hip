@@ -245,6 +245,9 @@ extern "C" rpf_status pattern_factor(int32_t n, const int32_t* rowptr, const int
       P->dinv_ii.alloc((size_t)nblk * NB * NB);
       potrf(s, P->L.p, P->ld, n, n_i, P->env_ii, P->dinv_ii.p, P->status.p);
       schur_update(s, P->L.p, P->ld, n, n_i);
+      // L_ii^T in the (otherwise unused) upper triangle: the backward solves read it row-contiguous
+      mirror_envelope(s, P->L.p, P->ld, n_i, P->env_ii);
+      P->L_upper = true;
     }
     P->S.alloc((size_t)n_b * n_b);
     copy_matrix(s, P->L.p + (int64_t)n_i * P->ld + n_i, P->ld, P->S.p, n_b, n_b, n_b);

@@ -15,6 +15,7 @@ struct rpf_pattern_s {
   int64_t ld = 0;
   rpf::DevBuf<double> dinv_ii;  // inverses of the NB x NB diagonal blocks of L_ii
   rpf::Envelope env_ii;
+  bool L_upper = false;         // the upper triangle of L_ii's envelope holds L_ii^T
 
   rpf::DevBuf<double> S;       // n_b x n_b, full, ld n_b
   rpf::DevBuf<double> Z;       // n_b x k orthonormal kernel basis, ld n_b
