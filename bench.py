@@ -217,10 +217,10 @@ def main():
                 "phase_ms": {q: round(st[q], 3) for q in PHASES}}
 
     # the headline form with captured iteration batches (untraced: the event tracer times single
-    # kernels and is off inside graphs), and with the other solvers
+    # kernels and is off inside graphs), and with the other solvers, uncaptured and captured
     hprec = PREC_NAMES[forms[0]]
     captured = None
-    if args.graph_batch > 0 and method_name != "orthodir":
+    if args.graph_batch > 0:
         captured = timed(f"{forms[0]} captured (batches of {args.graph_batch})",
                          lambda: step(hprec, gb=args.graph_batch))
         captured["graph_batch"] = args.graph_batch
@@ -229,6 +229,9 @@ def main():
     methods = {}
     for mname in [x.strip() for x in args.extra_methods.split(",") if x.strip() and x.strip() != method_name]:
         methods[mname] = timed(f"{forms[0]} {mname}", lambda: step(hprec, meth=METHODS[mname]))
+        if args.graph_batch > 0:
+            methods[mname]["captured"] = timed(f"{forms[0]} {mname} captured (batches of {args.graph_batch})",
+                                               lambda: step(hprec, gb=args.graph_batch, meth=METHODS[mname]))
 
     # the same forms with a preconditioner (the timed region as above)
     extra = {}

@@ -302,12 +302,18 @@ typedef struct {
                           no interior dofs, S = K_bb = K annihilates the rigid traces and
                           G^T F~^{-1} G is singular).
                           RPF_EINVAL together with an active periodic shortcut. */
-  int32_t graph_batch; /* block CG and classical: from the third iteration of each sweep on, record
-                          graph_batch iterations (rounded down to even; 0 or 1: off) once into a HIP
-                          graph on a capture stream of the library and replay it on `stream`, with
+  int32_t graph_batch; /* 0 or 1: off.  Otherwise batches of iterations are recorded once into HIP
+                          graphs on a capture stream of the library and replayed on `stream`, with
                           one convergence check per replay (so a converged run may do up to
-                          2 * graph_batch extra, still valid, iterations).  Same results as the
-                          uncaptured run.  Ignored for ORTHODIR and while tracing is enabled. */
+                          2 * graph_batch extra, still valid, iterations).  Block CG and classical:
+                          from the third iteration of each sweep on, one graph of graph_batch
+                          iterations (rounded down to even).  ORTHODIR: one graph per starting
+                          place 0, graph_batch, 2 graph_batch, ... of the restart cycle
+                          (max_blocks stored blocks), each captured the first time the cycle
+                          reaches it after the first iteration of the sweep; a batch that would
+                          cross a restart runs uncaptured, and
+                          nothing is captured when the cycle is not shorter than max_it.  Same
+                          results as the uncaptured run.  Ignored while tracing is enabled. */
 } rpf_solve_opts;
 
 typedef struct {

@@ -228,7 +228,7 @@ def block_krylov_solve(pb: Problem, patterns, f_local: torch.Tensor, n_rhs: int,
     """Solve the interface problem and recover the displacements.  f_local: flat device float64 tensor,
     occurrence blocks of n_p x n_rhs column-major, concatenated.  coarse: the preconditioner used as
     F~^{-1} in the projector and lambda_0 (PRECOND_NONE: the identity).  graph_batch: iterations per
-    captured HIP graph (block CG and classical; 0: no capture)."""
+    captured HIP graph (0: no capture; ORTHODIR: one graph per place in its restart cycle of max_blocks)."""
     assert f_local.is_cuda and f_local.dtype == torch.float64 and f_local.is_contiguous()
     lam = lam_out if lam_out is not None else torch.empty((pb.n_lambda, n_rhs), dtype=torch.float64, device="cuda")
     u = u_out if u_out is not None else torch.empty_like(f_local)

@@ -1728,7 +1728,20 @@ void trsm(hipStream_t s, const double* L, int64_t ldl, int64_t n, const double* 
     // (one product with a long inner dimension, split over K when its output tiles alone cannot
     // fill the chip), then X_t = inv(L_tt) B_t; B is read once per block instead of rewritten for
     // every trailing update.
+    // the split-K workspace is sized once for the largest block: growing it inside the loop would
+    // free and reallocate it (a device-wide synchronisation) at every larger block
     DevBuf<double> ws;
+    {
+      size_t most = 0;
+      for (int64_t t = 0; t < nblk; ++t) {
+        const int64_t j0 = t * NB;
+        const int jb = (int)std::min<int64_t>(NB, n - j0);
+        const int64_t kdim = trans ? n - j0 - jb : j0;
+        const int sp = kdim > 0 ? gemm_splitk_count(jb, nrhs, kdim) : 1;
+        if (sp > 1) most = std::max(most, (size_t)sp * jb * nrhs);
+      }
+      ws.ensure(most);
+    }
     auto update = [&](bool ta, int jb, int64_t kdim, const double* A, const double* Bsrc, double* C) {
       if (kdim <= 0) return;
       const int sp = gemm_splitk_count(jb, nrhs, kdim);
@@ -1796,7 +1809,22 @@ void potri_lower(hipStream_t s, const double* L, int64_t ldl, int64_t n, const d
   const int64_t nblk = cdiv(n, NB);
   fill_matrix(s, Y, n, n, ldy, 0.0);
   add_diag(s, Y, ldy, n, 1.0);
+  // the split-K workspace is sized once for the largest block (see trsm)
   DevBuf<double> ws;
+  {
+    size_t most = 0;
+    for (int64_t t = 0; t < nblk; ++t) {
+      const int64_t j0 = t * NB;
+      const int jb = (int)std::min<int64_t>(NB, n - j0);
+      const int64_t fw[2][2] = {{j0, j0}, {j0 + jb, n - j0 - jb}};  // (ncol, kdim) forward, backward
+      for (const auto& d : fw) {
+        if (d[0] <= 0 || d[1] <= 0) continue;
+        const int sp = gemm_splitk_count(jb, d[0], d[1]);
+        if (sp > 1) most = std::max(most, (size_t)sp * jb * d[0]);
+      }
+    }
+    ws.ensure(most);
+  }
   auto update = [&](bool ta, int jb, int64_t ncol, int64_t kdim, const double* A, const double* Bsrc, double* C) {
     if (kdim <= 0 || ncol <= 0) return;
     const int sp = gemm_splitk_count(jb, ncol, kdim);

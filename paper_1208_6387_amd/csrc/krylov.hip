@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
 #include <cmath>
 
 namespace rpf {
@@ -466,20 +467,42 @@ struct Solver {
                            hipMemcpyDeviceToHost, s));
     RPF_HIP(hipEventRecord(nev[hslot], s));
   }
-  // captured batches of iterations (block CG and classical)
+  // captured batches of iterations: one graph for block CG and classical, one per starting place
+  // in the restart cycle for ORTHODIR (keyed by that place)
+  struct Captured {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool sq = false;  // the captured last iteration leaves the squared norms in slot 0
+  };
   int graph_batch = 0;        // iterations per captured batch (0: no capture)
   hipStream_t cs = nullptr;   // capture stream (default priority)
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  int gprec = -1;             // inner precision the graph was captured for
-  bool graph_sq = false;      // the captured last iteration leaves the squared norms in slot 0
+  std::map<int, Captured> graphs;
+  int gprec = -1;             // inner precision the graphs were captured for
   int graph_replays = 0;
   void release_graph() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    gexec = nullptr;
-    graph = nullptr;
+    for (auto& kv : graphs) {
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+      if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    graphs.clear();
     gprec = -1;
+  }
+  // Nothing may be allocated while a stream is captured (hipMalloc fails there), and no workspace
+  // may be reallocated while captured graphs refer to it: every buffer an iteration grows on demand
+  // is sized once, before the first capture.  The gram workspace covers every Gram an iteration or
+  // a sweep forms (ORTHODIR: up to max_blocks - 1 stored blocks against the new one).
+  void presize_step_buffers(bool upd_gram) {
+    size_t most = (size_t)gram_pair_chunks(N) * m * (m + nr);
+    const int w = std::max(m, nr);
+    most = std::max(most, (size_t)gram_chunks(N, m, w) * m * w);
+    most = std::max(most, (size_t)gram_chunks(N, nr, nr) * nr * nr);
+    const int top = method == RPF_ORTHODIR ? max_blocks - 1 : 1;
+    for (int nb = 1; nb <= top; ++nb) most = std::max(most, (size_t)gram_chunks(N, nb * m, m) * nb * m * m);
+    ws.ensure(most);
+    sqpart.ensure((size_t)(cdiv(N, 256) + 256) * nr);
+    if (upd_gram) gpart.ensure((size_t)(cdiv(N, 256) + 256) * m * nr);
+    if (np > 1 && pc != RPF_PRECOND_NONE) Zp.ensure((size_t)N * nr);
+    if (np > 1 && periodic) Pz.ensure((size_t)N * nr);
   }
   enum Check { GOING = 0, CONVERGED = 1, EXHAUSTED = 2 };
   Check read_norms(int slot, const std::vector<double>& target) {
@@ -725,44 +748,78 @@ struct Solver {
       ++iterations;
       return have_sq;
     };
-    // Captured batches (block CG and classical, whose two alternating slots make the launches of
-    // iterations it and it + 2 identical from it = 2 on): gb iterations are recorded once into a
-    // graph on a capture stream and replayed on s, one convergence check per replay (its norms in
-    // device slot 0, copied to the lagged host slot after the replay).
-    const int gb = (method != RPF_ORTHODIR && graph_batch >= 2 && !trace_on()) ? graph_batch & ~1 : 0;
-    if (gb && gexec && gprec != prec) release_graph();
+    // Captured batches: gb iterations are recorded once into a graph on a capture stream and
+    // replayed on s, one convergence check per replay (its norms in device slot 0, copied to the
+    // lagged host slot after the replay).  Block CG and classical: the two alternating slots make
+    // the launches of iterations it and it + 2 identical from it = 2 on, so one graph (gb even)
+    // serves every batch.  ORTHODIR: an iteration's launches depend on its place in the restart
+    // cycle (how many blocks are stored), so a batch starting at place 0, gb, 2 gb, ... is captured
+    // the first time the cycle gets there (after the sweep's first iteration) and replayed at that
+    // place in every later cycle; a batch that would reach a restart runs uncaptured.
+    // (ORTHODIR only when a restart cycle fits in the iterations left: otherwise no place of the
+    // cycle comes round twice and every graph would be recorded for one replay)
+    const bool od = method == RPF_ORTHODIR;
+    const int gb = (graph_batch >= 2 && !trace_on() && (!od || max_blocks < max_it))
+                       ? (od ? graph_batch : graph_batch & ~1) : 0;
+    if (gb && !graphs.empty() && gprec != prec) release_graph();
+    if (gb) presize_step_buffers(upd_gram);
+    // place in the ORTHODIR cycle of the next iteration (after its restart test), and whether the
+    // gb iterations from there fit before the next restart
+    auto od_place = [&](bool& fits) {
+      int pos = nst;
+      if (pos == max_blocks || (prec != RPF_FP64 && (int64_t)(pos + 1) * m > N)) pos = 0;
+      fits = pos % gb == 0 && pos + gb <= max_blocks && (prec == RPF_FP64 || (int64_t)(pos + gb) * m <= N);
+      return pos;
+    };
     int it = 0;
     while (it < max_it) {
-      if (gb && it >= 2 && it % 2 == 0 && it + gb <= max_it) {
-        if (!gexec) {
+      bool cap = false;
+      int key = 0;
+      if (gb && it + gb <= max_it) {
+        // the first iteration of a sweep always runs uncaptured: it also sizes what the kernels it
+        // calls (the preconditioner's, for one) allocate on first use
+        if (od) {
+          key = od_place(cap);
+          cap = cap && it > 0;
+        } else {
+          cap = it >= 2 && it % 2 == 0;
+        }
+      }
+      if (cap) {
+        Captured& g = graphs[key];
+        if (!g.exec) {
           if (!cs) RPF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
           const hipStream_t s0 = s;
           RPF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
           s = cs;
           try {
-            for (int k = 0; k < gb; ++k) graph_sq = step(it + k, k == gb - 1, nrm2[0].p);
+            for (int k = 0; k < gb; ++k) g.sq = step(it + k, k == gb - 1, nrm2[0].p);
           } catch (...) {
             s = s0;
-            hipGraph_t g = nullptr;
-            (void)hipStreamEndCapture(cs, &g);
-            if (g) (void)hipGraphDestroy(g);
+            hipGraph_t gg = nullptr;
+            (void)hipStreamEndCapture(cs, &gg);
+            if (gg) (void)hipGraphDestroy(gg);
+            graphs.erase(key);
             throw;
           }
           s = s0;
-          RPF_HIP(hipStreamEndCapture(cs, &graph));
-          RPF_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+          RPF_HIP(hipStreamEndCapture(cs, &g.graph));
+          RPF_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
           gprec = prec;
-          // the capture ran the host side of these iterations; the replays below run the device side
+          // the capture ran the host side of these iterations (an ORTHODIR restart included); the
+          // replay below runs the device side
           nst -= gb;
           iterations -= gb;
+        } else if (od && nst != key) {
+          nst = key;  // the restart that the replayed batch starts with
         }
-        RPF_HIP(hipGraphLaunch(gexec, s));
+        RPF_HIP(hipGraphLaunch(g.exec, s));
         ++graph_replays;
         nst += gb;
         iterations += gb;
         it += gb;
         const int slot_n = nchk & 1;
-        post_norms_from(Rs.p, 0, slot_n, graph_sq);
+        post_norms_from(Rs.p, 0, slot_n, g.sq);
         if (pending >= 0 && (conv = read_norms(pending, target)) != GOING) {
           pending = -1;
           break;
