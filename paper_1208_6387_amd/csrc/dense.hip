@@ -495,20 +495,56 @@ __global__ __launch_bounds__(256) void k_gram_pair(int64_t N, int a, const doubl
   const int i = lane & 15, j = lane & 15;
   const bool iok = i < a, j1 = j < b1, j2 = j < b2;
   v4d acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t r0 = r_beg + 4 * wave; r0 < r_end; r0 += 64) {
-    double xa[4], y1[4], y2[4];
+  if (b1 > 0 && b2 > 0 && r_end > r_beg) {
+    // loads at clamped (always valid) rows and columns, masked afterwards, and the next group's
+    // loads issued before this group's MFMAs: no load behind a branch, two groups in flight
+    const int ic = min(i, a - 1), jc1 = min(j, b1 - 1), jc2 = min(j, b2 - 1);
+    double xa[4], y1[4], y2[4], nx[4], n1[4], n2[4];
+    auto load = [&](int64_t r0, double* x, double* p1, double* p2) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t row = r0 + 16 * u + (lane >> 4);
-      const bool rok = row < r_end;
-      xa[u] = (rok && iok) ? X[row * ldx + i] : 0.0;
-      y1[u] = (rok && j1) ? Y1[row * ldy1 + j] : 0.0;
-      y2[u] = (rok && j2) ? Y2[row * ldy2 + j] : 0.0;
+      for (int u = 0; u < 4; ++u) {
+        const int64_t row = min(r0 + 16 * u + (lane >> 4), r_end - 1);
+        x[u] = X[row * ldx + ic];
+        p1[u] = Y1[row * ldy1 + jc1];
+        p2[u] = Y2[row * ldy2 + jc2];
+      }
+    };
+    auto mma = [&](int64_t r0, const double* x, const double* p1, const double* p2) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool rok = r0 + 16 * u + (lane >> 4) < r_end;
+        const double xv = (rok && iok) ? x[u] : 0.0;
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, (rok && j1) ? p1[u] : 0.0, acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, (rok && j2) ? p2[u] : 0.0, acc2, 0, 0, 0);
+      }
+    };
+    // two register sets in turn (no copies): the loads of one group are in flight while the
+    // MFMAs of the other run; a prefetch past the last group reads the clamped last row
+    int64_t r0 = r_beg + 4 * wave;
+    load(r0, xa, y1, y2);
+    for (; r0 < r_end; r0 += 128) {
+      load(r0 + 64, nx, n1, n2);
+      mma(r0, xa, y1, y2);
+      if (r0 + 64 >= r_end) break;
+      load(r0 + 128, xa, y1, y2);
+      mma(r0 + 64, nx, n1, n2);
     }
+  } else {
+    for (int64_t r0 = r_beg + 4 * wave; r0 < r_end; r0 += 64) {
+      double xa[4], y1[4], y2[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], y1[u], acc1, 0, 0, 0);
-      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], y2[u], acc2, 0, 0, 0);
+      for (int u = 0; u < 4; ++u) {
+        const int64_t row = r0 + 16 * u + (lane >> 4);
+        const bool rok = row < r_end;
+        xa[u] = (rok && iok) ? X[row * ldx + i] : 0.0;
+        y1[u] = (rok && j1) ? Y1[row * ldy1 + j] : 0.0;
+        y2[u] = (rok && j2) ? Y2[row * ldy2 + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], y1[u], acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], y2[u], acc2, 0, 0, 0);
+      }
     }
   }
 #pragma unroll
@@ -927,12 +963,17 @@ __global__ __launch_bounds__(256) void k_rows_update_gram(int64_t N, int a, int 
   double myq = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * 256;
   const int rows = (int)min<int64_t>(256, N - r0);
+  // whole tile of 16 columns: Y's old values are loaded together with X (one memory latency
+  // instead of two in a row)
+  const bool pre = rows == 256 && a == 16 && b == 16 && beta != 0.0;
+  double zv[16];
   if (rows == 256 && a == 16) {
     double t[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int e = tid + u * 256;
       t[u] = X[(r0 + (e >> 4)) * ldx + (e & 15)];
+      if (pre) zv[u] = Y[(r0 + (e >> 4)) * ldy + (e & 15)];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -961,8 +1002,7 @@ __global__ __launch_bounds__(256) void k_rows_update_gram(int64_t N, int a, int 
   }
   __syncthreads();
   if (rows == 256 && b == 16) {
-    double zv[16];
-    if (beta != 0.0) {
+    if (beta != 0.0 && !pre) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int e = tid + u * 256;
@@ -1044,6 +1084,52 @@ __global__ __launch_bounds__(256) void k_rows_orth_lam(int64_t N, int a, int b, 
   }
   const int64_t r0 = (int64_t)blockIdx.x * 256;
   const int rows = (int)min<int64_t>(256, N - r0);
+  if (rows == 256 && a == 16 && b == 16 && c == 16) {
+    // whole tile, 16 columns everywhere: the loads of X, R and Lam are all issued before anything
+    // waits (one memory latency per workgroup instead of three in a row)
+    double t[16], rv[16], lv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t row = r0 + ((tid + u * 256) >> 4);
+      const int col = (tid + u * 256) & 15;
+      t[u] = X[row * ldx + col];
+      rv[u] = R[row * ldr + col];
+      lv[u] = Lam[row * ldl + col];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      xs[e >> 4][e & 15] = t[u];
+    }
+    __syncthreads();
+    double acc1[16], acc2[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc1[j] = acc2[j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const double xv = xs[tid][i];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        acc1[j] += xv * sm1[i][j];
+        acc2[j] += xv * sm2[i][j];
+      }
+    }
+    __syncthreads();  // xs is reused for the first product
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      xs[tid][j] = acc1[j];
+      ys[tid][j] = acc2[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 256;
+      const int64_t row = r0 + (e >> 4);
+      Z[row * ldz + (e & 15)] = rv[u] - xs[e >> 4][e & 15];
+      Lam[row * ldl + (e & 15)] = lv[u] + ys[e >> 4][e & 15];
+    }
+    return;
+  }
   if (rows == 256 && a == 16) {
     double t[16];
 #pragma unroll
@@ -1308,12 +1394,24 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* Ag, int64_t lda, int
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) bad = 0;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e & (NB - 1), c = e >> 6;
-    double v = (r == c) ? 1.0 : 0.0;
-    if (r < jb && c < jb && c <= r) v = Ag[(int64_t)c * lda + r];
-    A[r][c] = v;
-    W[r][c] = 0.0;
+  {
+    // all sixteen loads of a thread at clamped (always valid) addresses, issued together and
+    // waited for once; values outside the lower jb x jb triangle are replaced afterwards (a load
+    // behind a branch would cost one global-memory round trip each)
+    double v[NB * NB / 256];
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = tid + 256 * u;
+      const int r = min(e & (NB - 1), jb - 1), c = min(e >> 6, jb - 1);
+      v[u] = Ag[(int64_t)c * lda + r];
+    }
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e & (NB - 1), c = e >> 6;
+      A[r][c] = (r < jb && c < jb && c <= r) ? v[u] : ((r == c) ? 1.0 : 0.0);
+      W[r][c] = 0.0;
+    }
   }
   __syncthreads();
   for (int kb = 0; kb < NB / QB; ++kb) {

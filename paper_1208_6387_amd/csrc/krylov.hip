@@ -78,10 +78,25 @@ __global__ __launch_bounds__(64) void k_eta_chol(int m, const double* eta, int d
                                                  double* state) {
   __shared__ double epre[64];
   __shared__ double Ls[MM][MM + 1];
+  __shared__ double es[MM * MM];
   __shared__ double rdiag[MM];
   __shared__ double emax_s, trace_s;
   __shared__ int bad_s;
   const int t = threadIdx.x;
+  // eta staged in LDS, and B read, by loads at clamped (always valid) addresses whose values are
+  // masked afterwards: no load sits behind a branch, so each group is issued together and waited
+  // for once instead of one global-memory round trip at a time
+  {
+    constexpr int EU = (MM * MM + 63) / 64;
+    double ev[EU];
+    const int mm = m * m;
+#pragma unroll
+    for (int u = 0; u < EU; ++u) ev[u] = eta[min(t + 64 * u, mm - 1)];
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+      if (t + 64 * u < MM * MM) es[t + 64 * u] = (t + 64 * u < mm) ? ev[u] : 0.0;
+  }
+  __syncthreads();
   {
     // squared column norms of B: every column's loads of a 64-row chunk are issued together
     double part[MM];
@@ -89,24 +104,28 @@ __global__ __launch_bounds__(64) void k_eta_chol(int m, const double* eta, int d
     for (int c = 0; c < MM; ++c) part[c] = 0.0;
     for (int i0 = 0; i0 < ka; i0 += 64) {
       const int i = i0 + t;
+      const int ic = min(i, ka - 1);
+      double bv[MM];
+#pragma unroll
+      for (int c = 0; c < MM; ++c) bv[c] = B[(int64_t)min(c, m - 1) * ka + ic];
 #pragma unroll
       for (int c = 0; c < MM; ++c) {
-        const double b = (c < m && i < ka) ? B[(int64_t)c * ka + i] : 0.0;
+        const double b = (c < m && i < ka) ? bv[c] : 0.0;
         part[c] += b * b;
       }
     }
     // lane t holds eta_tt; every reduction below is a butterfly across the wave (no serial loops
     // of dependent loads on one lane)
-    const double dg = t < m ? eta[t * m + t] : 0.0;
+    const double dg = t < m ? es[t * m + t] : 0.0;
+    // all MM butterflies in straight-line code (columns past m are zeros), so they interleave
     double mine = 0.0;
 #pragma unroll
     for (int c = 0; c < MM; ++c) {
-      if (c < m) {
-        double acc = part[c];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        acc += __shfl(dg, c, 64);
-        if (t == c) mine = acc;
-      }
+      double acc = part[c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      acc += __shfl(dg, c, 64);
+      if (t == c) mine = acc;
     }
     if (t < m) epre[t] = mine;
     double me = mine, tr = fmax(dg, 0.0);
@@ -124,14 +143,14 @@ __global__ __launch_bounds__(64) void k_eta_chol(int m, const double* eta, int d
   if (diag_only) {
     bool keep = false;
     if (t < m) {
-      const double wi = eta[t * m + t];
+      const double wi = es[t * m + t];
       keep = wi > 0.0 && wi > tau * epre[t];
       if (!keep) atomicAdd(drops, 1);
     }
     const bool any = __any(keep);
     for (int i = t; i < m * m; i += 64) {
       const int r = i % m, c = i / m;
-      const double wc = eta[c * m + c];
+      const double wc = es[c * m + c];
       T[i] = (r == c && wc > 0.0 && wc > tau * epre[c]) ? 1.0 / sqrt(wc) : 0.0;
     }
     if (t == 0) {
@@ -146,30 +165,36 @@ __global__ __launch_bounds__(64) void k_eta_chol(int m, const double* eta, int d
   // Cholesky, lane t owns row t
   double a[MM];
 #pragma unroll
-  for (int c = 0; c < MM; ++c) a[c] = (t < m && c < m && c <= t) ? 0.5 * (eta[c * m + t] + eta[t * m + c]) : 0.0;
+  for (int c = 0; c < MM; ++c) a[c] = (t < m && c < m && c <= t) ? 0.5 * (es[c * m + t] + es[t * m + c]) : 0.0;
+  // (fully unrolled with compile-time indices into a[]: a loop left with a runtime bound would index
+  // the register array dynamically; the column of L is read from LDS in one independent batch)
 #pragma unroll
   for (int j = 0; j < MM; ++j) {
-    if (j >= m) break;
-    if (t == j) {
-      double d = a[j];
-      if (!(d > 0.0)) {
-        bad_s = 1;
-        d = 1.0;
+    if (j < m) {
+      if (t == j) {
+        double d = a[j];
+        if (!(d > 0.0)) {
+          bad_s = 1;
+          d = 1.0;
+        }
+        a[j] = sqrt(d);
+        rdiag[j] = 1.0 / a[j];
       }
-      a[j] = sqrt(d);
-      rdiag[j] = 1.0 / a[j];
-    }
-    __syncthreads();
-    if (t > j && t < m) {
-      a[j] *= rdiag[j];
-      Ls[t][j] = a[j];
-    }
-    __syncthreads();
-    if (t > j && t < m) {
-      const double ltj = a[j];
+      __syncthreads();
+      if (t > j && t < m) {
+        a[j] *= rdiag[j];
+        Ls[t][j] = a[j];
+      }
+      __syncthreads();
+      double lc[MM];
 #pragma unroll
-      for (int c = j + 1; c < MM; ++c)
-        if (c <= t) a[c] -= ltj * Ls[c][j];
+      for (int c = j + 1; c < MM; ++c) lc[c] = Ls[c][j];
+      if (t > j && t < m) {
+        const double ltj = a[j];
+#pragma unroll
+        for (int c = j + 1; c < MM; ++c)
+          if (c <= t) a[c] -= ltj * lc[c];
+      }
     }
   }
   __syncthreads();
