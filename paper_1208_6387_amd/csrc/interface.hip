@@ -220,9 +220,28 @@ __global__ __launch_bounds__(256) void k_coarse_gt_rows(const int* occ_pat, cons
   const int nper = (nbn + nsplit - 1) / nsplit;
   const int n_beg = sp * nper, n_end = min(nbn, n_beg + nper);
   const double* Z = Zp[p];
-  for (int i = threadIdx.x; i < max(n_end - n_beg, 0) * DPN * KMAX; i += 256) {
-    const int r = i % KMAX, dof = i / KMAX;  // dof within the slice
-    zl[i] = r < k ? Z[r * nd + (int64_t)n_beg * DPN + dof] : 0.0;
+  {
+    // all of a thread's mode-row loads at clamped (always valid) addresses, issued together and
+    // waited for once; entries past the kernel are zeros (a load behind a branch would cost one
+    // round trip each)
+    constexpr int PER = (GT_MAX_NODES * DPN * KMAX + 255) / 256;
+    const int nent = max(n_end - n_beg, 0) * DPN * KMAX;
+    if (k > 0 && nent > 0) {
+      double v[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int i = min((int)threadIdx.x + 256 * u, nent - 1);
+        const int r = min(i % KMAX, k - 1), dof = i / KMAX;  // dof within the slice
+        v[u] = Z[r * nd + (int64_t)n_beg * DPN + dof];
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + 256 * u;
+        if (i < nent) zl[i] = (i % KMAX < k) ? v[u] : 0.0;
+      }
+    } else {
+      for (int i = threadIdx.x; i < nent; i += 256) zl[i] = 0.0;
+    }
   }
   __syncthreads();
   const int tid = threadIdx.x, g = tid / JW, jl = tid % JW;

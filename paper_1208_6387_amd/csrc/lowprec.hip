@@ -84,7 +84,10 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nbn, const int* occ_lis
                                                      const double* lam, int64_t ldl, int m, double* X64, float* Xf,
                                                      uint16_t* Xh, uint16_t* Xl, int64_t ldx) {
   constexpr int NG = 256 / JW, NBK = 64;
+  constexpr int NPG = NBK / NG;  // nodes per lane group
+  constexpr int UM = 2;          // incidences per node fetched in the batch (faces 1, edges 2, corners 3)
   __shared__ double tile[JW][NBK * DPN + 1];
+  __shared__ int sptr[NBK + 1];
   const int q = blockIdx.y, s = occ_list[q];
   const int n0 = blockIdx.x * NBK;
   const int nn = min(NBK, nbn - n0);
@@ -93,28 +96,72 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nbn, const int* occ_lis
   double O[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) O[i] = rot ? rot[9 * s + i] : ((i % 4 == 0) ? 1.0 : 0.0);
+  if (tid <= nn) sptr[tid] = l2m_ptr[base_slot + tid];
+  __syncthreads();
+  // the block's incidences are one contiguous run [eb, ee) of the slot lists: every code and
+  // multiplier-row load below goes to a clamped index inside it (always valid: a node's own last
+  // incidence, so a surplus load re-reads a row already being read) and is masked afterwards, so a
+  // group's codes, then all their rows, are each one batch of loads in flight
+  const int eb = sptr[0], ee = sptr[nn];
   const int nd = nn * DPN;
   for (int j0 = 0; j0 < m; j0 += JW) {
     const int j = j0 + jl;
     const bool jok = j < m;
-    for (int b = g; b < nn; b += NG) {
-      const int e0 = l2m_ptr[base_slot + b], e1 = l2m_ptr[base_slot + b + 1];
-      double xg[DPN];
+    const int jc = min(j, m - 1);
+    double xg[NPG][DPN];
 #pragma unroll
-      for (int c = 0; c < DPN; ++c) xg[c] = 0.0;
-      for (int e = e0; e < e1; ++e) {
-        const int code = l2m_code[e];
-        const double sg = (code & 1) ? -1.0 : 1.0;
-        const int64_t mult = code >> 1;
-        if (jok) {
+    for (int i = 0; i < NPG; ++i)
 #pragma unroll
-          for (int c = 0; c < DPN; ++c) xg[c] += sg * lam[(mult * DPN + c) * ldl + j];
+      for (int c = 0; c < DPN; ++c) xg[i][c] = 0.0;
+    if (ee > eb) {
+      int e0[NPG], e1[NPG], code[NPG][UM];
+#pragma unroll
+      for (int i = 0; i < NPG; ++i) {
+        const int b = g + NG * i;
+        e0[i] = b < nn ? sptr[b] : 0;
+        e1[i] = b < nn ? sptr[b + 1] : 0;
+#pragma unroll
+        for (int u = 0; u < UM; ++u) code[i][u] = l2m_code[e1[i] > e0[i] ? min(e0[i] + u, e1[i] - 1) : eb];
+      }
+      double v[NPG][UM][DPN];
+#pragma unroll
+      for (int i = 0; i < NPG; ++i)
+#pragma unroll
+        for (int u = 0; u < UM; ++u)
+#pragma unroll
+          for (int c = 0; c < DPN; ++c) v[i][u][c] = lam[((int64_t)(code[i][u] >> 1) * DPN + c) * ldl + jc];
+#pragma unroll
+      for (int i = 0; i < NPG; ++i) {
+#pragma unroll
+        for (int u = 0; u < UM; ++u) {
+          if (jok && e0[i] + u < e1[i]) {
+            const double sg = (code[i][u] & 1) ? -1.0 : 1.0;
+#pragma unroll
+            for (int c = 0; c < DPN; ++c) xg[i][c] += sg * v[i][u][c];
+          }
+        }
+        // nodes with more incidences than the batch takes (none in the brick structures)
+        for (int e = e0[i] + UM; e < e1[i]; ++e) {
+          const int cd = l2m_code[e];
+          const double sg = (cd & 1) ? -1.0 : 1.0;
+          const int64_t mult = cd >> 1;
+          if (jok) {
+#pragma unroll
+            for (int c = 0; c < DPN; ++c) xg[i][c] += sg * lam[(mult * DPN + c) * ldl + j];
+          }
         }
       }
+    }
 #pragma unroll
-      for (int c2 = 0; c2 < DPN; ++c2) {
-        const double v = (DPN == 3) ? O[c2] * xg[0] + O[3 + c2] * xg[1 % DPN] + O[6 + c2] * xg[2 % DPN] : xg[c2];
-        tile[jl][b * DPN + c2] = v;
+    for (int i = 0; i < NPG; ++i) {
+      const int b = g + NG * i;
+      if (b < nn) {
+#pragma unroll
+        for (int c2 = 0; c2 < DPN; ++c2) {
+          const double vv = (DPN == 3) ? O[c2] * xg[i][0] + O[3 + c2] * xg[i][1 % DPN] + O[6 + c2] * xg[i][2 % DPN]
+                                       : xg[i][c2];
+          tile[jl][b * DPN + c2] = vv;
+        }
       }
     }
     __syncthreads();
