@@ -344,19 +344,40 @@ __global__ void k_spmm(int rows, int64_t cols, const int* ptr, const int* idx, c
 #pragma unroll
   for (int j = 0; j < SPMM_CB; ++j) s[j] = 0.0;
   const double* Xc = X + c0 * ldx;
-  for (int e = ptr[row]; e < ptr[row + 1]; ++e) {
-    const int64_t k = idx[e];
-    const double v = val[e];
+  const int p0 = ptr[row], p1 = ptr[row + 1];
+  // four entries at a time: their indices and values, then all their gathers from X, each one
+  // batch of loads at clamped (always valid) positions, masked afterwards (entries in their order,
+  // as a plain walk would add them)
+  constexpr int EU = 4;
+  for (int e0 = p0; e0 < p1; e0 += EU) {
+    int64_t k[EU];
+    double v[EU];
 #pragma unroll
-    for (int j = 0; j < SPMM_CB; ++j)
-      if (j < cn) s[j] += v * Xc[j * ldx + k];
+    for (int u = 0; u < EU; ++u) {
+      const int e = min(e0 + u, p1 - 1);
+      k[u] = idx[e];
+      v[u] = val[e];
+    }
+    double xv[EU][SPMM_CB];
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+#pragma unroll
+      for (int j = 0; j < SPMM_CB; ++j) xv[u][j] = Xc[(int64_t)min(j, cn - 1) * ldx + k[u]];
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+      if (e0 + u < p1) {
+#pragma unroll
+        for (int j = 0; j < SPMM_CB; ++j) s[j] += v[u] * xv[u][j];
+      }
+  }
+  double yo[SPMM_CB];
+  if (beta != 0.0) {
+#pragma unroll
+    for (int j = 0; j < SPMM_CB; ++j) yo[j] = Y[(c0 + min(j, cn - 1)) * ldy + row];
   }
 #pragma unroll
-  for (int j = 0; j < SPMM_CB; ++j) {
-    if (j >= cn) break;
-    double* y = Y + (c0 + j) * ldy + row;
-    *y = (beta == 0.0) ? alpha * s[j] : beta * *y + alpha * s[j];
-  }
+  for (int j = 0; j < SPMM_CB; ++j)
+    if (j < cn) Y[(c0 + j) * ldy + row] = (beta == 0.0) ? alpha * s[j] : beta * yo[j] + alpha * s[j];
 }
 inline unsigned spmm_blocks(int rows, int64_t cols) {
   return (unsigned)cdiv(std::max<int64_t>((int64_t)rows * ((cols + SPMM_CB - 1) / SPMM_CB), 1), 256);
