@@ -263,7 +263,8 @@ def main():
     hr = results[head]
 
     def kernel_label(form):
-        tiles = sorted({t for (m, f), (t, w) in sched.items() if f == form and t > 0})
+        # tile 64 or 128: the grouped launch over all patterns; 256 (or 0): one launch per pattern
+        tiles = sorted({t for (m, f), (t, w) in sched.items() if f == form and t in (64, 128)})
         if tiles and form in ("fp64", "bf16x3"):
             t = tiles[-1]
             return (f"k_dgemm_group<{t}, {t}> (FP64 MFMA 16x16x4, one grouped launch over all patterns)"
