@@ -340,7 +340,7 @@ class FetiOracle:
         return g, d, e
 
     def lambda0(self, e, lam00=None):
-        """lambda_0 = F~^{-1} G (G^T F~^{-1} G)^{-1} e + Q lambda_00 (Table 1, line 2); F~^{-1} = I
+        """lambda_0 = F~^{-1} G (G^T F~^{-1} G)^{-1} e + Q lambda_00 (Table 1, initialisation); F~^{-1} = I
         by default."""
         if not self.G.shape[1]:
             l0 = np.zeros((self.n_lambda, e.shape[1]))
@@ -354,7 +354,7 @@ class FetiOracle:
         return l0
 
     def residual(self, lam, d):
-        """r = Q^T (d - F lambda) (Table 1, line 3)."""
+        """r = Q^T (d - F lambda) (Table 1, initial residual)."""
         return self.Qt(d - self.F(lam))
 
     def permute(self, z: np.ndarray) -> np.ndarray:
