@@ -277,7 +277,7 @@ typedef struct {
   int32_t check_every; /* read the convergence flag every k iterations (0: 1) */
   int32_t max_blocks;  /* ORTHODIR: stored (W, P) blocks before a restart (0: as many as max_it and
                           half of the free device memory allow) */
-  int32_t precond;     /* rpf_precond: z = Q F~^{-1} r in every iteration (Table 1, lines 4 and 5.5);
+  int32_t precond;     /* rpf_precond: z = Q F~^{-1} r in every iteration (Table 1: initial and updated search directions);
                           the Dirichlet product runs in the inner precision prec.  The projector
                           keeps the identity in place of F~^{-1} unless coarse says otherwise. */
   int32_t periodic;    /* 1: truly periodic structure (section 3.1, after Table 1): with several
@@ -364,6 +364,21 @@ rpf_status rpf_dgemm(int32_t ta, int32_t tb, int64_t M, int64_t N, int64_t K, do
 rpf_status rpf_dposv(int64_t n, double* A, int64_t lda, int64_t nrhs, double* B, int64_t ldb, void* stream);
 /* Symmetric eigen-decomposition of batch m x m matrices (m <= 64), ascending. */
 rpf_status rpf_dsyev_small(int32_t m, int32_t batch, const double* A, double* V, double* w, void* stream);
+/* Row-block products of the multivector solver (section 3.3: F-orthogonalisation of a new block
+ * against every stored block, and the block updates of Table 1).  X (N x a) and Y (N x b) are
+ * row-major device blocks with leading dimensions ldx >= a and ldy >= b.
+ * rpf_rows_gemm: Y <- beta Y + alpha X M.  M (a x b, device) is row-major with row stride
+ * mrow >= b, or column-major with leading dimension a when mrow = 0.  Y must not overlap X or M;
+ * with beta = 0 the old Y is not read.  Asynchronous on stream.
+ * rpf_gram: C <- X^T Y, C (a x b, device) column-major with leading dimension a.  The partial
+ * sums over row chunks are added in a fixed order.  Allocates its workspace and blocks the host
+ * until the result is written.
+ * Both: RPF_EINVAL for negative sizes (rpf_rows_gemm: a < 1) or leading dimensions below the
+ * widths; nothing is done when N or b is 0, or (rpf_gram) a is 0: C is then left untouched. */
+rpf_status rpf_rows_gemm(int64_t N, int32_t a, int32_t b, double alpha, const double* X, int64_t ldx,
+                         const double* M, int64_t mrow, double beta, double* Y, int64_t ldy, void* stream);
+rpf_status rpf_gram(int64_t N, int32_t a, int32_t b, const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                    double* C, void* stream);
 
 #ifdef __cplusplus
 }

@@ -281,6 +281,37 @@ def dsyev_small(A: torch.Tensor, stream=None):
     return w, V.transpose(1, 2)
 
 
+def _rows(t: torch.Tensor):
+    """(rows, cols, leading dimension) of a row-major FP64 device block."""
+    assert t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
+def rows_gemm(X: torch.Tensor, M: torch.Tensor, Y: torch.Tensor, alpha=1.0, beta=0.0, stream=None) -> torch.Tensor:
+    """Y <- beta Y + alpha X M for row-major blocks X (N x a), Y (N x b); M (a x b) row-major or, when
+    its transpose is contiguous, column-major."""
+    N, a, ldx = _rows(X)
+    N2, b, ldy = _rows(Y)
+    assert N2 == N and tuple(M.shape) == (a, b) and M.is_cuda and M.dtype == torch.float64
+    if M.stride(1) == 1 and M.stride(0) >= b:
+        mrow = M.stride(0)
+    else:
+        assert M.stride(0) == 1 and M.stride(1) == a, "M must be row-major or column-major with ld a"
+        mrow = 0
+    check(load().rpf_rows_gemm(N, a, b, alpha, _ptr(X), ldx, _ptr(M), mrow, beta, _ptr(Y), ldy, _stream(stream)))
+    return Y
+
+
+def gram(X: torch.Tensor, Y: torch.Tensor, stream=None) -> torch.Tensor:
+    """X^T Y (a x b) for row-major blocks X (N x a), Y (N x b)."""
+    N, a, ldx = _rows(X)
+    N2, b, ldy = _rows(Y)
+    assert N2 == N
+    C_out = torch.zeros((b, a), dtype=torch.float64, device="cuda")
+    check(load().rpf_gram(N, a, b, _ptr(X), ldx, _ptr(Y), ldy, _ptr(C_out), _stream(stream)))
+    return C_out.T
+
+
 def trace_enable(on: bool = True) -> None:
     """Bracket every flexibility product S+ W with HIP events (see rpf_trace_read)."""
     check(load().rpf_trace_enable(1 if on else 0))

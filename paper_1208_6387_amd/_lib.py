@@ -21,7 +21,8 @@ EXPORTS = ["rpf_last_error", "rpf_version", "pattern_factor", "pattern_condense"
            "pattern_free", "problem_create", "problem_n_lambda", "problem_free", "problem_n_perm", "problem_set_schedule", "problem_tune", "feti_apply",
            "feti_apply_noalloc", "feti_precond", "feti_permute",
            "block_krylov_solve",
-           "rpf_dgemm", "rpf_dposv", "rpf_dsyev_small", "rpf_trace_enable", "rpf_trace_read"]
+           "rpf_dgemm", "rpf_dposv", "rpf_dsyev_small", "rpf_rows_gemm", "rpf_gram", "rpf_trace_enable",
+           "rpf_trace_read"]
 
 
 class ProblemDesc(C.Structure):
@@ -88,6 +89,8 @@ def load() -> C.CDLL:
         "rpf_dgemm": (i32, [i32, i32, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64, vp]),
         "rpf_dposv": (i32, [i64, vp, i64, i64, vp, i64, vp]),
         "rpf_dsyev_small": (i32, [i32, i32, vp, vp, vp, vp]),
+        "rpf_rows_gemm": (i32, [i64, i32, i32, f64, vp, i64, vp, i64, f64, vp, i64, vp]),
+        "rpf_gram": (i32, [i64, i32, i32, vp, i64, vp, i64, vp, vp]),
         "rpf_trace_enable": (i32, [i32]),
         "rpf_trace_read": (i32, [i32, C.POINTER(i64), C.POINTER(f64), C.POINTER(f64)]),
     }

@@ -286,19 +286,36 @@ __global__ __launch_bounds__(256) void k_splitk_reduce_thread(int64_t M, int64_t
   *c = (beta == 0.0) ? s : s + beta * *c;
 }
 
+// Sum of the split partial slabs: a workgroup covers 16 consecutive outputs (lane & 15, so each
+// slab row read is 128 contiguous bytes) and its 16 thread rows take every 16th slab, eight loads
+// in flight at clamped (always valid) slabs; the 16 row sums are then added in LDS in a fixed
+// order.  C = sum (+ beta C), M x N column-major with leading dimension ldc.
 __global__ __launch_bounds__(256) void k_splitk_reduce(int64_t M, int64_t N, int splits, const double* part,
                                                        double beta, double* C, int64_t ldc) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + wave;
+  __shared__ double red[16][17];
+  const int tx = threadIdx.x & 15, tz = threadIdx.x >> 4;
   const int64_t MN = M * N;
-  if (idx >= MN) return;
-  double s = 0.0;
-  for (int z = lane; z < splits; z += 64) s += part[(int64_t)z * MN + idx];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) {
+  const int64_t idx = (int64_t)blockIdx.x * 16 + tx;
+  const int64_t ic = min(idx, MN - 1);
+  double sum = 0.0;
+  constexpr int U = 8;
+  for (int z0 = tz; z0 < splits; z0 += 16 * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = part[(int64_t)min(z0 + 16 * u, splits - 1) * MN + ic];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (z0 + 16 * u < splits) sum += v[u];
+  }
+  red[tz][tx] = sum;
+  __syncthreads();
+  if (tz == 0 && idx < MN) {
+    double t = 0.0;
+#pragma unroll
+    for (int z = 0; z < 16; ++z) t += red[z][tx];
     const int64_t m = idx % M, n = idx / M;
     double* c = C + n * ldc + m;
-    *c = (beta == 0.0) ? s : s + beta * *c;
+    *c = (beta == 0.0) ? t : t + beta * *c;
   }
 }
 
@@ -438,7 +455,7 @@ void dgemm_splitk(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t
     hipLaunchKernelGGL(k_splitk_reduce_thread, dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s, M, N, gz, ws, beta,
                        C, ldc);
   else
-    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 4)), dim3(256), 0, s, M, N, gz, ws, beta, C,
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv(M * N, 16)), dim3(256), 0, s, M, N, gz, ws, beta, C,
                        ldc);
   RPF_LAUNCH_CHECK();
 }
@@ -561,57 +578,121 @@ __global__ __launch_bounds__(256) void k_gram_pair(int64_t N, int a, const doubl
   if (ci < a && cj < b2) pc[(int64_t)(b1 + cj) * a + ci] = red[0][1][t] + red[1][1][t] + red[2][1][t] + red[3][1][t];
 }
 
-// Wide form (X with many columns, e.g. all stored search directions): a workgroup
-// covers 16 column tiles of X (4 per wave) against one 16-column tile of Y over
-// a chunk of rows; each Y fragment is loaded once and feeds 4 MFMAs, so Y is
-// re-read cdiv(a, 256) times instead of cdiv(a, 16).  No cross-wave reduction:
-// every wave owns its tiles.
+// Wide form (X with many columns, e.g. all stored search directions).  The a columns are split
+// into ga groups of at most 32 column tiles, spread evenly; a workgroup covers one group against
+// one 16-column tile of Y over a chunk of rows.  Its four waves are WT tile slices (TW tiles each)
+// times 4/WT row slices: few tiles are split over rows instead of leaving waves idle, and each Y
+// fragment feeds TW MFMAs.  The row slices' sums are added in LDS before the partial is written.
+// With more than 4 tiles (a > 64), TW is 5 to 8.
+struct WideShape {
+  int ga, wt, tw;
+};
+static WideShape wide_shape(int a) {
+  const int ta = (a + 15) / 16;
+  const int ga = (ta + 31) / 32;
+  const int tg = (ta + ga - 1) / ga;
+  const int wt = tg <= 8 ? 1 : (tg <= 16 ? 2 : 4);
+  return {ga, wt, (tg + wt - 1) / wt};
+}
+
+template <int TW>
 __global__ __launch_bounds__(256) void k_gram_wide(int64_t N, int a, int b, const double* X, int64_t ldx,
-                                                   const double* Y, int64_t ldy, int64_t chunk, double* part) {
+                                                   const double* Y, int64_t ldy, int64_t chunk, int ga, int wt,
+                                                   double* part) {
+  __shared__ double red[4][256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ta = (a + 15) / 16, ga = (ta + 15) / 16;
+  const int wr_n = 4 / wt, wslice = wave % wt, wrow = wave / wt;
   const int grp = blockIdx.x % ga, tj = blockIdx.x / ga;
+  const int ta = (a + 15) / 16, tg = (ta + ga - 1) / ga;
+  const int tbase = grp * tg + wslice * TW;
+  const int tend = min(ta, (grp + 1) * tg);
   const int j = tj * 16 + (lane & 15);
   const bool jok = j < b;
-  const int tbase = grp * 16 + wave * 4;
   const int64_t r_beg = (int64_t)blockIdx.y * chunk;
   const int64_t r_end = min(N, r_beg + chunk);
-  v4d acc[4];
+  v4d acc[TW];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int64_t r0 = r_beg; r0 < r_end; r0 += 8) {
-    double yb[2], xa[2][4];
+  for (int t = 0; t < TW; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  if (r_end > r_beg) {
+    // loads at clamped (always valid) rows and columns, masked before the MFMAs, and the next
+    // group of 8 rows loaded while this group's MFMAs run (two register sets in turn)
+    const int jc = min(j, b - 1);
+    int ic[TW];
+    bool iok[TW];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int64_t row = r0 + 4 * u + (lane >> 4);
-      const bool rok = row < r_end;
-      yb[u] = (rok && jok) ? Y[row * ldy + j] : 0.0;
+    for (int t = 0; t < TW; ++t) {
+      const int i = (tbase + t) * 16 + (lane & 15);
+      ic[t] = min(i, a - 1);
+      iok[t] = tbase + t < tend && i < a;
+    }
+    double yb[2], xa[2][TW], ny[2], nx[2][TW];
+    auto load = [&](int64_t r0, double* y, double (*x)[TW]) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int i = (tbase + t) * 16 + (lane & 15);
-        xa[u][t] = (rok && i < a) ? X[row * ldx + i] : 0.0;
+      for (int u = 0; u < 2; ++u) {
+        const int64_t row = min(r0 + 4 * u + (lane >> 4), r_end - 1);
+        y[u] = Y[row * ldy + jc];
+#pragma unroll
+        for (int t = 0; t < TW; ++t) x[u][t] = X[row * ldx + ic[t]];
+      }
+    };
+    auto mma = [&](int64_t r0, const double* y, const double (*x)[TW]) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool rok = r0 + 4 * u + (lane >> 4) < r_end;
+        const double yv = (rok && jok) ? y[u] : 0.0;
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((rok && iok[t]) ? x[u][t] : 0.0, yv, acc[t], 0, 0, 0);
+      }
+    };
+    // this wave's row slice: groups of 8 rows r_beg + 8 (wrow + wr_n q), q = 0, 1, ...
+    const int64_t step = 8 * (int64_t)wr_n;
+    int64_t r0 = r_beg + 8 * wrow;
+    if (r0 < r_end) {
+      load(r0, yb, xa);
+      for (; r0 < r_end; r0 += 2 * step) {
+        load(r0 + step, ny, nx);
+        mma(r0, yb, xa);
+        if (r0 + step >= r_end) break;
+        load(r0 + 2 * step, yb, xa);
+        mma(r0 + step, ny, nx);
       }
     }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][t], yb[u], acc[t], 0, 0, 0);
   }
+  double* pc = part + (int64_t)blockIdx.y * a * b;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TW; ++t) {
+    if (wr_n > 1) {
+      __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ci = (tbase + t) * 16 + (lane >> 4) + 4 * r, cj = tj * 16 + (lane & 15);
-      if (ci < a && cj < b) part[((int64_t)blockIdx.y * b + cj) * a + ci] = acc[t][r];
+      for (int r = 0; r < 4; ++r) red[wave][64 * r + lane] = acc[t][r];
+      __syncthreads();
+      if (wrow == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double v = red[wave][64 * r + lane];
+          for (int q = 1; q < wr_n; ++q) v += red[wave + wt * q][64 * r + lane];
+          acc[t][r] = v;
+        }
+      }
     }
+    if (wrow == 0 && tbase + t < tend) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ci = (tbase + t) * 16 + (lane >> 4) + 4 * r, cj = tj * 16 + (lane & 15);
+        if (ci < a && cj < b) pc[(int64_t)cj * a + ci] = acc[t][r];
+      }
+    }
+  }
 }
 
 static bool gram_is_wide(int a) { return a > 64; }
 
 int gram_chunks(int64_t N, int a, int b) {
-  // about one to two workgroups per CU in total, at least 256 rows per chunk
-  const int64_t tiles = gram_is_wide(a) ? cdiv(cdiv(a, 16), 16) * cdiv(b, 16) : cdiv(a, 16) * cdiv(b, 16);
-  int64_t g = cdiv(gram_is_wide(a) ? 512 : 256, tiles);
+  // about one to two workgroups per CU in total for the narrow form and about four for the wide
+  // one, at least 256 rows per chunk
+  const int64_t tiles = gram_is_wide(a) ? (int64_t)wide_shape(a).ga * cdiv(b, 16) : cdiv(a, 16) * cdiv(b, 16);
+  int64_t g = cdiv(gram_is_wide(a) ? 1024 : 256, tiles);
   g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(N, 256)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
 }
@@ -624,16 +705,25 @@ void gram(hipStream_t s, int64_t N, int a, int b, const double* X, int64_t ldx, 
   const int gz = (int)cdiv(N, chunk);
   RPF_CHECK(gz <= 65535, RPF_EINVAL, "gram: too many chunks");
   if (gram_is_wide(a)) {
-    const int64_t groups = cdiv(cdiv(a, 16), 16) * cdiv(b, 16);
-    hipLaunchKernelGGL(k_gram_wide, dim3((unsigned)groups, (unsigned)gz), dim3(256), 0, s, N, a, b, X, ldx, Y, ldy,
-                       chunk, ws);
+    const WideShape w = wide_shape(a);
+    const dim3 grid((unsigned)(w.ga * cdiv(b, 16)), (unsigned)gz);
+    switch (w.tw) {
+#define RPF_WIDE(TW)                                                                                         \
+  case TW:                                                                                                   \
+    hipLaunchKernelGGL(k_gram_wide<TW>, grid, dim3(256), 0, s, N, a, b, X, ldx, Y, ldy, chunk, w.ga, w.wt, ws); \
+    break;
+      RPF_WIDE(5) RPF_WIDE(6) RPF_WIDE(7) RPF_WIDE(8)
+#undef RPF_WIDE
+      default:
+        RPF_CHECK(false, RPF_EINVAL, "gram: unexpected wide shape");
+    }
   } else {
     const int64_t tiles = cdiv(a, 16) * cdiv(b, 16);
     hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)tiles, (unsigned)gz), dim3(256), 0, s, N, a, b, X, ldx, Y,
                        ldy, chunk, ws);
   }
   RPF_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * b, 4)), dim3(256), 0, s, (int64_t)a,
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * b, 16)), dim3(256), 0, s, (int64_t)a,
                      (int64_t)b, gz, ws, 0.0, C, (int64_t)a);
   RPF_LAUNCH_CHECK();
 }
@@ -658,7 +748,7 @@ void gram_pair(hipStream_t s, int64_t N, int a, const double* X, int64_t ldx, in
   hipLaunchKernelGGL(k_gram_pair, dim3((unsigned)gz), dim3(256), 0, s, N, a, X, ldx, b1, Y1, ldy1, b2, Y2, ldy2,
                      chunk, ws);
   RPF_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * (b1 + b2), 4)), dim3(256), 0, s, (int64_t)a,
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)cdiv((int64_t)a * (b1 + b2), 16)), dim3(256), 0, s, (int64_t)a,
                      (int64_t)(b1 + b2), gz, ws, 0.0, C, (int64_t)a);
   RPF_LAUNCH_CHECK();
 }
@@ -681,25 +771,42 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, doub
   const int64_t row = row0 + r;
   for (int j0 = 0; j0 < b; j0 += 16) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // each 32-column chunk of X (and of M) is loaded into registers at clamped (always valid)
+    // positions one chunk ahead, while the current chunk is multiplied from LDS: no load waits
+    // behind a branch, and one chunk's loads are in flight during the other's FMAs
+    double xr[8], mv[2];
+    auto load = [&](int i0) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int idx = tid + 256 * e;
+        const int ii = idx & 31, rr = idx >> 5;
+        const int64_t gr = min(row0 + rr, N - 1);
+        xr[e] = X[gr * ldx + min(i0 + ii, a - 1)];
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int idx = tid + 256 * e;
+        const int ic = min(i0 + (idx & 31), a - 1), jc = min(j0 + (idx >> 5), b - 1);
+        mv[e] = mrow > 0 ? Mm[(int64_t)ic * mrow + jc] : Mm[(int64_t)ic + (int64_t)a * jc];
+      }
+    };
+    load(0);
     for (int i0 = 0; i0 < a; i0 += 32) {
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int idx = tid + 256 * e;
         const int ii = idx & 31, rr = idx >> 5;
-        const int64_t gr = row0 + rr;
-        sx[rr][ii] = (gr < N && i0 + ii < a) ? X[gr * ldx + i0 + ii] : 0.0;
+        sx[rr][ii] = (row0 + rr < N && i0 + ii < a) ? xr[e] : 0.0;
       }
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int idx = tid + 256 * e;
         const int ii = idx & 31, jj = idx >> 5;
-        sm[ii][jj] = (i0 + ii < a && j0 + jj < b)
-                         ? (mrow > 0 ? Mm[(int64_t)(i0 + ii) * mrow + (j0 + jj)]
-                                     : Mm[(int64_t)(i0 + ii) + (int64_t)a * (j0 + jj)])
-                         : 0.0;
+        sm[ii][jj] = (i0 + ii < a && j0 + jj < b) ? mv[e] : 0.0;
       }
       __syncthreads();
+      load(i0 + 32);
 #pragma unroll 8
       for (int ii = 0; ii < 32; ++ii) {
         const double xv = sx[r][ii];
@@ -708,15 +815,110 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t N, int a, int b, doub
       }
     }
     if (row < N) {
+      // the old values of the four outputs are read together (clamped to a valid column)
+      double yo[4] = {0.0, 0.0, 0.0, 0.0};
+      if (beta != 0.0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) yo[u] = Y[row * ldy + min(j0 + 4 * q + u, b - 1)];
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + 4 * q + u;
-        if (j < b) {
-          double* y = Y + row * ldy + j;
-          *y = (beta == 0.0) ? alpha * acc[u] : beta * *y + alpha * acc[u];
-        }
+        if (j < b) Y[row * ldy + j] = (beta == 0.0) ? alpha * acc[u] : beta * yo[u] + alpha * acc[u];
       }
     }
+  }
+}
+
+// Same product for many rows, a long inner dimension and at most 16 columns of M (e.g. the
+// orthogonalisation against all stored blocks), on FP64 MFMA 16x16x4 with X rows as the M
+// dimension.  A workgroup owns 64 rows and walks X in 32-column chunks.  A chunk is loaded with
+// whole 128-byte lines per row (16 lanes of 16 bytes per row, four rows per load instruction; the
+// MFMA operand layout, 4 lanes per row, would split every line over two instructions, which
+// measured a fifth slower) into registers one chunk ahead, at clamped (always valid) positions, and
+// stored masked into one of two LDS buffers with the matching 32 rows of M; wave w then multiplies
+// rows 16 w .. 16 w + 15 from LDS, two accumulators in turn.  VEC: 16-byte loads (a and ldx even,
+// X aligned).
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_rows_mfma(int64_t N, int a, int b, double alpha, const double* X,
+                                                   int64_t ldx, const double* Mm, int64_t mrow, double beta, double* Y,
+                                                   int64_t ldy) {
+  __shared__ double sx[2][64][34];
+  __shared__ double sm[2][32][16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  // chunk staging: piece p = tid + 256 i is row p >> 4, columns k0 + 2 (p & 15) + {0, 1}; M entry
+  // e = tid + 256 i is row k0 + (e >> 4), column e & 15
+  double2 xr[4];
+  double mr[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = tid + 256 * i, r = p >> 4, sg = p & 15;
+      const double* xrow = X + min(row0 + r, N - 1) * ldx;
+      if (VEC) {
+        xr[i] = *reinterpret_cast<const double2*>(xrow + min(k0 + 2 * sg, a - 2));
+      } else {
+        xr[i].x = xrow[min(k0 + 2 * sg, a - 1)];
+        xr[i].y = xrow[min(k0 + 2 * sg + 1, a - 1)];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = tid + 256 * i, kk = e >> 4, j = e & 15;
+      const int kc = min(k0 + kk, a - 1), jc = min(j, b - 1);
+      mr[i] = mrow > 0 ? Mm[(int64_t)kc * mrow + jc] : Mm[(int64_t)kc + (int64_t)a * jc];
+    }
+  };
+  auto sstore = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = tid + 256 * i, r = p >> 4, sg = p & 15;
+      const int c = k0 + 2 * sg;
+      double2 v;
+      v.x = c < a ? xr[i].x : 0.0;
+      v.y = c + 1 < a ? xr[i].y : 0.0;
+      *reinterpret_cast<double2*>(&sx[buf][r][2 * sg]) = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = tid + 256 * i, kk = e >> 4, j = e & 15;
+      sm[buf][kk][j] = k0 + kk < a ? mr[i] : 0.0;
+    }
+  };
+  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};  // even and odd k-steps
+  gload(0);
+  sstore(0, 0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < a; k0 += 32) {
+    // the next chunk's loads are in flight while this chunk is multiplied; they go into the other
+    // buffer, whose last readers all passed the barrier that ended the previous chunk
+    gload(k0 + 32);
+#pragma unroll
+    for (int st = 0; st < 8; st += 2) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(sx[buf][16 * wave + m][4 * st + q], sm[buf][4 * st + q][m], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(sx[buf][16 * wave + m][4 * st + 4 + q], sm[buf][4 * st + 4 + q][m], acc1,
+                                                  0, 0, 0);
+    }
+    sstore(buf ^ 1, k0 + 32);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // lane holds rows 16 w + q + 4 r, column m; the old values are read together first
+  const bool jok = m < b;
+  const int jc = min(m, b - 1);
+  double yo[4];
+  if (beta != 0.0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) yo[r] = Y[min(row0 + 16 * wave + q + 4 * r, N - 1) * ldy + jc];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = row0 + 16 * wave + q + 4 * r;
+    const double v = acc0[r] + acc1[r];
+    if (jok && row < N) Y[row * ldy + m] = (beta == 0.0) ? alpha * v : beta * yo[r] + alpha * v;
   }
 }
 
@@ -735,18 +937,19 @@ __global__ __launch_bounds__(256) void k_rows_gemm_wave(int64_t N, int a, int b,
     double acc[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    // the 16 M entries of a step are loaded at clamped (always valid) columns and masked, so they
+    // are one batch in flight instead of one load behind each column test
     for (int i = lane; i < a; i += 64) {
       const double xv = x[i];
-      if (mrow > 0) {
-        const double* mr = Mm + (int64_t)i * mrow + j0;
+      double mv[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (u < nj) acc[u] += xv * mr[u];
-      } else {
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (u < nj) acc[u] += xv * Mm[(int64_t)i + (int64_t)a * (j0 + u)];
+      for (int u = 0; u < 16; ++u) {
+        const int uc = min(u, nj - 1);
+        mv[u] = mrow > 0 ? Mm[(int64_t)i * mrow + j0 + uc] : Mm[(int64_t)i + (int64_t)a * (j0 + uc)];
       }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u < nj) acc[u] += xv * mv[u];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u)
@@ -781,9 +984,20 @@ struct RowsPairs {
 __global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, const double* Mm, int64_t mrow,
                                                     RowsPairs pr, int vec) {
   __shared__ double sm[64 * 16];
-  for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-    const int i = e >> 4, j = e & 15;
-    sm[e] = (i < a && j < b) ? (mrow > 0 ? Mm[(int64_t)i * mrow + j] : Mm[i + (int64_t)a * j]) : 0.0;
+  {
+    // staged from clamped (always valid) positions and masked, so the four loads are in flight together
+    double mv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int ic = min(e >> 4, a - 1), jc = min(e & 15, b - 1);
+      mv[q] = mrow > 0 ? Mm[(int64_t)ic * mrow + jc] : Mm[ic + (int64_t)a * jc];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      sm[e] = ((e >> 4) < a && (e & 15) < b) ? mv[q] : 0.0;
+    }
   }
   __syncthreads();
   const RowsPair& P = pr.p[blockIdx.y];
@@ -804,7 +1018,9 @@ __global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, con
       }
     } else {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) xv[u] = (i0 + u < a) ? x[i0 + u] : 0.0;
+      for (int u = 0; u < 8; ++u) xv[u] = x[min(i0 + u, a - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = (i0 + u < a) ? xv[u] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -816,6 +1032,11 @@ __global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, con
   double* y = P.Y + row * P.ldy;
   const double* z = P.Z ? P.Z + row * P.ldz : y;
   if (vec && (b & 1) == 0) {
+    double2 zt[8];
+    if (P.beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < 16; j += 2) zt[j / 2] = *reinterpret_cast<const double2*>(z + min(j, b - 2));
+    }
 #pragma unroll
     for (int j = 0; j < 16; j += 2) {
       if (j < b) {
@@ -824,17 +1045,21 @@ __global__ __launch_bounds__(256) void k_rows_small(int64_t N, int a, int b, con
           o.x = P.alpha * acc[j];
           o.y = P.alpha * acc[j + 1];
         } else {
-          const double2 t = *reinterpret_cast<const double2*>(z + j);
-          o.x = P.beta * t.x + P.alpha * acc[j];
-          o.y = P.beta * t.y + P.alpha * acc[j + 1];
+          o.x = P.beta * zt[j / 2].x + P.alpha * acc[j];
+          o.y = P.beta * zt[j / 2].y + P.alpha * acc[j + 1];
         }
         *reinterpret_cast<double2*>(y + j) = o;
       }
     }
   } else {
+    double zv[16];
+    if (P.beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) zv[j] = z[min(j, b - 1)];
+    }
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-      if (j < b) y[j] = (P.beta == 0.0) ? P.alpha * acc[j] : P.beta * z[j] + P.alpha * acc[j];
+      if (j < b) y[j] = (P.beta == 0.0) ? P.alpha * acc[j] : P.beta * zv[j] + P.alpha * acc[j];
   }
 }
 
@@ -1368,6 +1593,14 @@ void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const doubl
     // few row blocks: a wavefront per row keeps the whole chip busy on the inner dimension
     hipLaunchKernelGGL(k_rows_gemm_wave, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, mrow,
                        beta, Y, ldy);
+  } else if (b <= 16 && a >= 2) {
+    const bool vec = (a % 2) == 0 && (ldx % 2) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0;
+    if (vec)
+      hipLaunchKernelGGL(k_rows_mfma<true>, dim3((unsigned)cdiv(N, 64)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm,
+                         mrow, beta, Y, ldy);
+    else
+      hipLaunchKernelGGL(k_rows_mfma<false>, dim3((unsigned)cdiv(N, 64)), dim3(256), 0, s, N, a, b, alpha, X, ldx,
+                         Mm, mrow, beta, Y, ldy);
   } else {
     hipLaunchKernelGGL(k_rows_gemm, dim3((unsigned)cdiv(N, 64)), dim3(256), 0, s, N, a, b, alpha, X, ldx, Mm, mrow,
                        beta, Y, ldy);

@@ -258,26 +258,37 @@ __global__ __launch_bounds__(256) void k_coarse_gt_rows(const int* occ_pat, cons
 #pragma unroll
     for (int r = 0; r < KMAX; ++r) acc[r] = 0.0;
     constexpr int U = 4;
-    for (int e0 = e_beg + g; e0 < e_end; e0 += NG * U) {
+    // a batch's incidence codes are loaded at clamped (always valid) entries one batch ahead, and
+    // the multiplier rows they name at a clamped column, all in flight together: one round trip per
+    // batch instead of one per load behind a test
+    if (e_beg + g < e_end) {
+      const int elast = e_end - 1, jc = min(j, m - 1);
       int code[U], bnu[U];
+      auto load_codes = [&](int e0, int* cd, int* bn) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * NG;
-        const bool ok = e < e_end;
-        code[u] = ok ? l2m_code[e] : 0;
-        bnu[u] = ok ? l2m_bn[e] : -1;
-      }
+        for (int u = 0; u < U; ++u) {
+          const int e = min(e0 + u * NG, elast);
+          cd[u] = l2m_code[e];
+          bn[u] = l2m_bn[e];
+        }
+      };
+      load_codes(e_beg + g, code, bnu);
+      for (int e0 = e_beg + g; e0 < e_end; e0 += NG * U) {
       double xv[U][DPN];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t mult = code[u] >> 1;
 #pragma unroll
-        for (int c = 0; c < DPN; ++c) xv[u][c] = (bnu[u] >= 0 && jok) ? x[(mult * DPN + c) * ldx + j] : 0.0;
+        for (int c = 0; c < DPN; ++c) xv[u][c] = x[(mult * DPN + c) * ldx + jc];
       }
+      int ncode[U], nbnu[U];
+      load_codes(e0 + NG * U, ncode, nbnu);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (bnu[u] < 0) continue;
-        const double sg = (code[u] & 1) ? -1.0 : 1.0;
+        // entries past the end (clamped loads) and columns past m count with weight 0; no branch,
+        // so the compiler keeps every load of the batch ahead of the first use
+        const bool ok = jok && e0 + u * NG < e_end;
+        const double sg = ok ? ((code[u] & 1) ? -1.0 : 1.0) : 0.0;
         double xl[DPN];
         if (DPN == 3) {
 #pragma unroll
@@ -292,6 +303,12 @@ __global__ __launch_bounds__(256) void k_coarse_gt_rows(const int* occ_pat, cons
         for (int c = 0; c < DPN; ++c)
 #pragma unroll
           for (int r = 0; r < KMAX; ++r) acc[r] += zr[c * KMAX + r] * xl[c];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        code[u] = ncode[u];
+        bnu[u] = nbnu[u];
+      }
       }
     }
 #pragma unroll

@@ -413,6 +413,30 @@ extern "C" rpf_status rpf_dposv(int64_t n, double* A, int64_t lda, int64_t nrhs,
   });
 }
 
+extern "C" rpf_status rpf_rows_gemm(int64_t N, int32_t a, int32_t b, double alpha, const double* X, int64_t ldx,
+                                    const double* M, int64_t mrow, double beta, double* Y, int64_t ldy,
+                                    void* stream) {
+  return guarded([&] {
+    RPF_CHECK(N >= 0 && a >= 1 && b >= 0, RPF_EINVAL, "rpf_rows_gemm: bad size");
+    RPF_CHECK(ldx >= a && ldy >= b && (mrow == 0 || mrow >= b), RPF_EINVAL, "rpf_rows_gemm: leading dimension");
+    if (N == 0 || b == 0) return;
+    rows_gemm((hipStream_t)stream, N, a, b, alpha, X, ldx, M, beta, Y, ldy, mrow);
+  });
+}
+
+extern "C" rpf_status rpf_gram(int64_t N, int32_t a, int32_t b, const double* X, int64_t ldx, const double* Y,
+                               int64_t ldy, double* C, void* stream) {
+  return guarded([&] {
+    RPF_CHECK(N >= 0 && a >= 0 && b >= 0, RPF_EINVAL, "rpf_gram: negative size");
+    RPF_CHECK(ldx >= a && ldy >= b, RPF_EINVAL, "rpf_gram: leading dimension");
+    if (N == 0 || a == 0 || b == 0) return;
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<double> ws((size_t)gram_chunks(N, a, b) * a * b);
+    gram(s, N, a, b, X, ldx, Y, ldy, C, ws.p);
+    RPF_HIP(hipStreamSynchronize(s));
+  });
+}
+
 extern "C" rpf_status rpf_dsyev_small(int32_t m, int32_t batch, const double* A, double* V, double* w,
                                       void* stream) {
   return guarded([&] {

@@ -72,8 +72,11 @@ def test_periodic_shortcut_fp64(case, R, method, pc):
         R.trace_enable(False)
         assert _err(p, res, u_o) < 1e-8, (per, res.stats)
         out[per] = (res.stats["iterations"], tr["flops"])
-    # same iterations; the products now run on n_rhs columns instead of n_rhs * n_perm
-    assert abs(out[True][0] - out[False][0]) <= 1 + (method == "block_cg"), out
+    # the same iterates in exact arithmetic (section 3.1), so about the same count: the two paths
+    # round differently, and block CG's short recurrence lets that move the last iterations near
+    # the stopping residual by a few; the products now run on n_rhs columns instead of
+    # n_rhs * n_perm
+    assert abs(out[True][0] - out[False][0]) <= 1 + 2 * (method == "block_cg"), out
     per_it = [out[k][1] / max(out[k][0], 1) for k in (False, True)]
     assert per_it[1] < per_it[0] * (1.5 / p.n_perm + 0.2), (per_it, out)
 
