@@ -1617,6 +1617,14 @@ void rows_gemm(hipStream_t s, int64_t N, int a, int b, double alpha, const doubl
 // W_ik = -W_ii sum_{j=k}^{i-1} L_ij W_jk.  A single right-looking wavefront needs either ~20k
 // unrolled instructions (more than the instruction cache holds) or 64 dependent steps over LDS;
 // this form has 4 short serial steps.  Rows and columns beyond jb are padded with the identity.
+// Value of v in lane src of the wavefront, src uniform (here a compile-time constant once the
+// loops are unrolled): two v_readlane into scalar registers, no LDS round trip as a shuffle takes.
+__device__ inline double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 __global__ __launch_bounds__(256) void k_potrf_diag(double* Ag, int64_t lda, int jb, double* dinv, int* status,
                                                     int blk) {
   static_assert(NB == 64, "k_potrf_diag assumes 64 x 64 blocks");
@@ -1659,7 +1667,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* Ag, int64_t lda, int
       bool badw = false;
 #pragma unroll
       for (int j = 0; j < QB; ++j) {
-        double d = __shfl(a[j], j, 64);
+        double d = lane_value(a[j], j);
         if (!(d > 0.0)) {
           badw = true;
           d = 1.0;
@@ -1670,7 +1678,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* Ag, int64_t lda, int
         if (r > j) a[j] *= rd[j];
 #pragma unroll
         for (int c = j + 1; c < QB; ++c) {
-          const double lcj = __shfl(a[j], c, 64);  // row c's entry in column j
+          const double lcj = lane_value(a[j], c);  // row c's entry in column j
           if (r >= c) a[c] -= a[j] * lcj;
         }
       }
@@ -1687,7 +1695,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* Ag, int64_t lda, int
       for (int k = 0; k < QB; ++k) {
         x[k] *= rd[k];
 #pragma unroll
-        for (int i = k + 1; i < QB; ++i) x[i] -= __shfl(a[k], i, 64) * x[k];  // l_ik from row i's lane
+        for (int i = k + 1; i < QB; ++i) x[i] -= lane_value(a[k], i) * x[k];  // l_ik from row i's lane
       }
       if (lane < QB) {
 #pragma unroll
