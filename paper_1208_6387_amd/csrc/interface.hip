@@ -823,8 +823,22 @@ F64Plan plan_F64(rpf_problem pb, const rpf_pattern* pats, int m, const Schedule&
   return pl;
 }
 
+__global__ void k_rsub_cols(int rows, int64_t cols, const double* g, int64_t ldg, double* x, int64_t ldx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  const int64_t r = i % rows, c = i / rows;
+  x[c * ldx + r] = g[c * ldg + r] - x[c * ldx + r];
+}
+
+void rsub_cols(hipStream_t s, int rows, int64_t cols, const double* g, int64_t ldg, double* x, int64_t ldx) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(k_rsub_cols, dim3((unsigned)cdiv((int64_t)rows * cols, 256)), dim3(256), 0, s, rows, cols, g, ldg,
+                     x, ldx);
+  RPF_LAUNCH_CHECK();
+}
+
 YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, const double* X, int64_t ldx,
-             double* xw, double* yw, hipStream_t s, int op, bool trace) {
+             double* xw, double* yw, hipStream_t s, int op, bool trace, const double* const* gsub) {
   YLoc yl{};
   DGroup g{};
   double gflops = 0.0;
@@ -840,6 +854,7 @@ YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, 
       RPF_LAUNCH_CHECK();
     }
     gather_pattern(pb, p, pb->pat_nbn[p], X, ldx, m, xp, lw, s);
+    if (gsub) rsub_cols(s, nb, cols, gsub[p], nb, xp, lw);
     const double* Mp = op == OP_FLEX ? pats[p]->Splus.p : pats[p]->S.p;
     yl.base[p] = yp;
     yl.ld[p] = nb;
@@ -881,9 +896,9 @@ YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, 
 }
 
 void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y, int64_t ldy,
-             int prec, bool project, hipStream_t s, int op) {
+             int prec, bool project, hipStream_t s, int op, const double* const* gsub) {
   if (prec != RPF_FP64) {
-    apply_F_lowprec(pb, pats, m, X, ldx, Y, ldy, prec, s, op);
+    apply_F_lowprec(pb, pats, m, X, ldx, Y, ldy, prec, s, op, gsub);
     if (project) {
       ensure_coarse(pb, pats, s);
       project_block(pb, Y, ldy, m, s);
@@ -893,11 +908,12 @@ void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, in
   const F64Plan pl = plan_F64(pb, pats, m, schedule_for(pb, m, RPF_FP64));
   pb->xloc.ensure(pl.xneed);
   pb->yloc.ensure(pl.yneed);
-  const YLoc yl = run_F64(pb, pats, pl, m, X, ldx, pb->xloc.p, pb->yloc.p, s, op, true);
+  const YLoc yl = run_F64(pb, pats, pl, m, X, ldx, pb->xloc.p, pb->yloc.p, s, op, true, gsub);
   pb->last_yl = yl;
   pb->last_x = op == OP_FLEX ? X : nullptr;
   pb->last_ldx = ldx;
   pb->last_m = m;
+  pb->last_gsub = gsub != nullptr;
   ++pb->fp64_gen;
   scatter_all(pb, yl, m, Y, ldy, 0.0, s);
   if (project) {

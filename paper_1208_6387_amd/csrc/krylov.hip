@@ -272,21 +272,13 @@ __global__ void k_axpby(int64_t count, double a, const double* x, double b, doub
   if (i < count) y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
 }
 
-// out = a - sum_z b[z slab + .] (nsplit slabs of partial sums)
-__global__ void k_sub_slabs(int64_t count, const double* a, const double* b, int64_t slab, int nsplit, double* out) {
+// out = sum_z b[z slab + .] (nsplit slabs of partial sums)
+__global__ void k_sum_slabs(int64_t count, const double* b, int64_t slab, int nsplit, double* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  double v = a[i];
-  for (int z = 0; z < nsplit; ++z) v -= b[z * slab + i];
+  double v = 0.0;
+  for (int z = 0; z < nsplit; ++z) v += b[z * slab + i];
   out[i] = v;
-}
-
-// dst[c ldd + r] = src[c lds + r] for r < rows, 0 for rows <= r < ldd (column-major, cols columns)
-__global__ void k_copy_pad(int rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ldd * cols) return;
-  const int64_t r = i % ldd, c = i / ldd;
-  dst[i] = r < rows ? src[c * lds + r] : 0.0;
 }
 
 // strided rows: y[l*ldy + j] = a x[l*ldx + j] + b y[l*ldy + j]
@@ -441,7 +433,7 @@ struct Solver {
   // Krylov store: for every stored block j the raw directions Z_j and P_j = Q^T F Z_j (N x m each,
   // slot j of the row-major N x ldW arrays) and the normalisation T_j (m x m); the F-orthonormal
   // block is W_j = Z_j T_j with F W_j = P_j T_j, never formed explicitly.
-  DevBuf<double> lam, d, R, Rs, tmp, Zall, Pall, Tall, dlam;
+  DevBuf<double> lam, R, Rs, tmp, Zall, Pall, Tall, dlam;
   int64_t ldW = 0;
   int max_blocks = 0;
   // small matrices
@@ -574,7 +566,6 @@ struct Solver {
   void alloc(int64_t ld_lam_unused) {
     (void)ld_lam_unused;
     lam.ensure((size_t)N * nr);
-    d.ensure((size_t)N * nr);
     R.ensure((size_t)N * nr);
     Rs.ensure((size_t)N * nr);
     dlam.ensure((size_t)N * nr);
@@ -951,18 +942,13 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     const int64_t N = S.N;
     S.alloc(ld_lambda);
 
-    // ------------------------------------------------------------ loads: g, d, e
+    // ------------------------------------------------------------ loads: g and e (d is never formed)
     Timer tl(s);
     std::vector<int64_t> foff(pb->n_occ + 1, 0);
     for (int o = 0; o < pb->n_occ; ++o) foff[o + 1] = foff[o] + (int64_t)pats[pb->occ_pat[o]]->n * nr;
     DevBuf<int64_t> d_foff;
     d_foff.upload(foff.data(), foff.size(), s);
     std::vector<DevBuf<double>> Y2(pb->n_pat), G(pb->n_pat);
-    std::vector<int64_t> off(pb->n_pat + 1, 0);
-    for (int p = 0; p < pb->n_pat; ++p)
-      off[p + 1] = off[p] + (int64_t)pats[p]->n_b * (int64_t)pb->occ_of_pat[p].size() * nr;
-    DevBuf<double> Yg(std::max<int64_t>(off[pb->n_pat], 1));
-    YLoc yl{};
     for (int p = 0; p < pb->n_pat; ++p) {
       const rpf_pattern P = pats[p];
       const int nq = (int)pb->occ_of_pat[p].size();
@@ -982,22 +968,11 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
                            (int64_t)P->n_b, 1.0);
         RPF_LAUNCH_CHECK();
       }
-      double* yp = Yg.p + off[p];
-      // the large-problem FP64 kernel reads its right operand with a zero-padded leading dimension
-      const int64_t lw = cdiv(P->n_b, 32) * 32;
-      bool done = false;
-      if (P->n_b % 2 == 0 && cdiv(P->n_b, 128) * cdiv(cols, (int64_t)128) >= 256) {
-        pb->xloc.ensure(lw * cols);
-        hipLaunchKernelGGL(k_copy_pad, dim3(nblocks(lw * cols)), dim3(256), 0, s, P->n_b, cols, G[p].p,
-                           (int64_t)P->n_b, pb->xloc.p, lw);
-        RPF_LAUNCH_CHECK();
-        done = dgemm_flex(s, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, pb->xloc.p, lw, 0.0, yp, P->n_b);
-      }
-      if (!done) dgemm(s, false, false, P->n_b, cols, P->n_b, 1.0, P->Splus.p, P->n_b, G[p].p, P->n_b, 0.0, yp, P->n_b);
-      yl.base[p] = yp;
-      yl.ld[p] = P->n_b;
     }
-    scatter_all(pb, yl, nr, S.d.p, nr, 0.0, s);  // d = sum A S+ g
+    // d = sum_s A^(s) S+ g^(s) is never formed: every residual d - F lambda is the single product
+    // sum_s A^(s) S+ (g^(s) - A^(s)T lambda) (apply_F with the offsets g)
+    std::vector<const double*> gp(pb->n_pat);
+    for (int p = 0; p < pb->n_pat; ++p) gp[p] = G[p].p;
     st.ms_loads = tl.stop();
 
     // ------------------------------------------------------------ coarse problem, lambda_0, r_0
@@ -1030,15 +1005,13 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
       fill(s, S.lam.p, N * nr, 0.0);
     }
     // r_0 = Q^T (d - F lambda_0).  Here and at every later residual, S.tmp keeps the unprojected
-    // d - F lambda of the current lambda: the recovery reuses it.  A mixed solve forms r_0 with the
-    // low-precision product: it only seeds the first sweep, whose inner solve stops at inner_tol,
-    // far above that product's error; every residual after a sweep (and so every convergence
-    // decision) is FP64.
+    // d - F lambda of the current lambda, one product on g - A^T lambda: the recovery reuses it.  A
+    // mixed solve forms r_0 with the low-precision product: it only seeds the first sweep, whose
+    // inner solve stops at inner_tol, far above that product's error; every residual after a sweep
+    // (and so every convergence decision) is FP64.
     const bool lp_r0 = prec != RPF_FP64;
-    apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, lp_r0 ? prec : RPF_FP64, false, s);
+    apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, lp_r0 ? prec : RPF_FP64, false, s, OP_FLEX, gp.data());
     uint64_t res_gen = lp_r0 ? ~(uint64_t)0 : pb->fp64_gen;  // the FP64 product behind S.tmp, if any
-    hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
-    RPF_LAUNCH_CHECK();
     RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
     S.projQt(S.R.p, nr, nr);
     S.r0n = S.colnorm2(S.R.p, nr, nr);
@@ -1105,10 +1078,8 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     for (int sw = 0; sw < max_sweeps; ++sw) {
       if (!fresh) {
         // FP64 residual of the current lambda
-        apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+        apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s, OP_FLEX, gp.data());
         res_gen = pb->fp64_gen;
-        hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
-        RPF_LAUNCH_CHECK();
         RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
         S.projQt(S.R.p, nr, nr);
         rn = S.colnorm2(S.R.p, nr, nr);
@@ -1133,10 +1104,8 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
     }
     // final FP64 residual check (recomputed unless the loop ended on a fresh one)
     if (!fresh) {
-      apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s);
+      apply_F(pb, pats, nr, S.lam.p, nr, S.tmp.p, nr, RPF_FP64, false, s, OP_FLEX, gp.data());
       res_gen = pb->fp64_gen;
-      hipLaunchKernelGGL(k_axpby, dim3(nblocks(N * nr)), dim3(256), 0, s, N * nr, 1.0, S.d.p, -1.0, S.tmp.p);
-      RPF_LAUNCH_CHECK();
       RPF_HIP(hipMemcpyAsync(S.R.p, S.tmp.p, sizeof(double) * N * nr, hipMemcpyDeviceToDevice, s));
       S.projQt(S.R.p, nr, nr);
       rn = S.colnorm2(S.R.p, nr, nr);
@@ -1163,19 +1132,20 @@ extern "C" rpf_status block_krylov_solve(rpf_problem pb, const rpf_pattern* pats
       RPF_LAUNCH_CHECK();
       coarse_solve(pb, ca.p, aa.p, nr, s);
     }
-    // S+ A^T lambda of the final lambda is still in the problem's local product buffer when the
-    // last FP64 product was that of the final residual (no other FP64 product since)
-    const bool reuse = pb->fp64_gen == res_gen && pb->last_x == S.lam.p && pb->last_m == nr && pb->last_ldx == nr;
+    // S+ (g - A^T lambda) of the final lambda is still in the problem's local product buffer when
+    // the last FP64 product was that of the final residual (no other FP64 product since)
+    const bool reuse = pb->fp64_gen == res_gen && pb->last_gsub && pb->last_x == S.lam.p && pb->last_m == nr &&
+                       pb->last_ldx == nr;
     for (int p = 0; p < pb->n_pat; ++p) {
       const rpf_pattern P = pats[p];
       const int nq = (int)pb->occ_of_pat[p].size();
       const int64_t cols = (int64_t)nq * nr;
       const int* occ = pb->d_occ_of_pat.p + pb->pat_occ_off[p];
       DevBuf<double> Ub((size_t)P->n_b * cols);
-      // u_b = S+ (g - A^T lambda) + Z alpha_s = S+ g - S+ A^T lambda + Z alpha_s
+      // u_b = S+ (g - A^T lambda) + Z alpha_s
       if (reuse) {
-        hipLaunchKernelGGL(k_sub_slabs, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, (int64_t)P->n_b * cols,
-                           Yg.p + off[p], pb->last_yl.base[p], pb->last_yl.slab[p], pb->last_yl.nsplit[p], Ub.p);
+        hipLaunchKernelGGL(k_sum_slabs, dim3(nblocks((int64_t)P->n_b * cols)), dim3(256), 0, s, (int64_t)P->n_b * cols,
+                           pb->last_yl.base[p], pb->last_yl.slab[p], pb->last_yl.nsplit[p], Ub.p);
         RPF_LAUNCH_CHECK();
       } else {
         DevBuf<double> X((size_t)P->n_b * cols);

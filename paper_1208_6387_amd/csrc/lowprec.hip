@@ -814,8 +814,25 @@ void gemm_bf16_group(hipStream_t s, int tile, bool x3, const BfGroup& g) {
 }
 
 // ---------------------------------------------------------------------------- host
+// W format from an FP64 column-major block (rows x cols, ld ldxin): mode 1 bf16 hi/lo, 0 FP32
+__global__ void k_to_w(int rows, int64_t cols, const double* X, int64_t ldxin, int mode, float* Xf, uint16_t* Xh,
+                       uint16_t* Xl, int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  const int64_t r = i % rows, c = i / rows;
+  const double v = X[c * ldxin + r];
+  const int64_t o = c * ld + r;
+  if (mode == 1) {
+    const uint16_t h = bf16_bits((float)v);
+    Xh[o] = h;
+    Xl[o] = bf16_bits((float)(v - (double)bf16_val(h)));
+  } else {
+    Xf[o] = (float)v;
+  }
+}
+
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
-                     int64_t ldy, int prec, hipStream_t s, int op) {
+                     int64_t ldy, int prec, hipStream_t s, int op, const double* const* gsub) {
   const bool split = (prec == RPF_BF16X3 || prec == RPF_BF16);
   // W format with ld rounded up to a multiple of 64: every 64-k chunk of a row is one 128-byte
   // cache line (unaligned rows would make each chunk touch two lines)
@@ -885,13 +902,22 @@ void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const doubl
   hipLaunchKernelGGL((k_gather_lp<D, MODE>), grid, dim3(128), 0, s, nbn, occ, pb->d_slot_off.p, pb->d_l2m_ptr.p, \
                      pb->d_l2m_code.p, rot, X, ldx, m, pb->xloc32.p + off[p], pb->xhi.p + off[p],                 \
                      pb->xlo.p + off[p], ld[p])
-    if (split) {
-      // the padded rows between n_b and ld must hold zeros for the 16-byte loads
-      if (ld[p] != nb) {
-        const int64_t npad = (ld[p] - nb) * (int64_t)cols;
-        hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, pb->xhi.p + off[p],
-                           pb->xlo.p + off[p], ld[p], nb, cols);
-      }
+    // the padded rows between n_b and ld must hold zeros for the 16-byte loads
+    if (split && ld[p] != nb) {
+      const int64_t npad = (ld[p] - nb) * (int64_t)cols;
+      hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, pb->xhi.p + off[p],
+                         pb->xlo.p + off[p], ld[p], nb, cols);
+    }
+    if (gsub) {
+      // g - A^T X: gathered in FP64 (any assembly and block width), the difference taken there and
+      // rounded once into the W format, as a gathered column is
+      pb->xloc.ensure((size_t)nb * cols);
+      gather_pattern(pb, p, nbn, X, ldx, m, pb->xloc.p, nb, s);
+      rsub_cols(s, nb, cols, gsub[p], nb, pb->xloc.p, nb);
+      hipLaunchKernelGGL(k_to_w, dim3((unsigned)cdiv((int64_t)nb * cols, 256)), dim3(256), 0, s, nb, (int64_t)cols,
+                         pb->xloc.p, (int64_t)nb, split ? 1 : 0, split ? nullptr : pb->xloc32.p + off[p],
+                         split ? pb->xhi.p + off[p] : nullptr, split ? pb->xlo.p + off[p] : nullptr, ld[p]);
+    } else if (split) {
       if (pb->weighted) {
         wgather(pb, p, X, ldx, m, 1, nullptr, nullptr, pb->xhi.p + off[p], pb->xlo.p + off[p], ld[p], s);
       } else if (m >= 8) {

@@ -90,6 +90,7 @@ struct rpf_problem_s {
   const double* last_x = nullptr;
   int64_t last_ldx = 0;
   int last_m = 0;
+  bool last_gsub = false;  // the last FP64 product's input was g - A^T X (apply_F's gsub)
   uint64_t fp64_gen = 0;
   rpf::DevBuf<float> xloc32, yloc32;
   rpf::DevBuf<uint16_t> xhi, xlo;
@@ -158,12 +159,18 @@ void gemm_bf16_group(hipStream_t s, int tile, bool x3, const BfGroup& g);
 int64_t group_kchunk(int64_t nb_rows, int64_t K, int64_t cols, int tile, int work, int align);
 // Gather and FP64 product of every pattern into the workspaces xw (plan.xneed doubles) and yw
 // (plan.yneed doubles); returns the result slabs for scatter_all.  No allocation.
+// gsub: optional per-pattern blocks g_p (n_b x occurrences * m, column-major, ld n_b); the
+// product input of pattern p is then g_p - A^(s)T X instead of A^(s)T X.
 YLoc run_F64(rpf_problem pb, const rpf_pattern* pats, const F64Plan& pl, int m, const double* X, int64_t ldx,
-             double* xw, double* yw, hipStream_t s, int op, bool trace);
+             double* xw, double* yw, hipStream_t s, int op, bool trace, const double* const* gsub = nullptr);
 // Y = F X (W-format products on all patterns), optional projection; with op = OP_SCHUR the same
-// assembled product with S in place of S+
+// assembled product with S in place of S+.  With gsub (see run_F64), Y = sum_s A^(s) S+ (g - A^(s)T X),
+// which is d - F X for the condensed loads g (eq. 3 with d = sum_s A^(s) S+ g) without forming d.
 void apply_F(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
-             int64_t ldy, int prec, bool project, hipStream_t s, int op = OP_FLEX);
+             int64_t ldy, int prec, bool project, hipStream_t s, int op = OP_FLEX,
+             const double* const* gsub = nullptr);
+// x[c ldx + r] = g[c ldg + r] - x[c ldx + r] for r < rows (column-major, cols columns)
+void rsub_cols(hipStream_t s, int rows, int64_t cols, const double* g, int64_t ldg, double* x, int64_t ldx);
 // Y = F~^{-1} X for the lumped (kind 1) or Dirichlet (kind 2) preconditioner, the Dirichlet
 // product in precision prec; X and Y may be the same block
 void apply_precond(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
@@ -201,7 +208,7 @@ void lambda0_M(rpf_problem pb, const rpf_pattern* pats, int kind, const double* 
 void gather_rows(rpf_problem pb, int p, const double* lam, int64_t ldl, int m, int mode, double* X64, float* Xf,
                  uint16_t* Xh, uint16_t* Xl, int64_t ldx, hipStream_t s);
 void apply_F_lowprec(rpf_problem pb, const rpf_pattern* pats, int m, const double* X, int64_t ldx, double* Y,
-                     int64_t ldy, int prec, hipStream_t s, int op = OP_FLEX);
+                     int64_t ldy, int prec, hipStream_t s, int op = OP_FLEX, const double* const* gsub = nullptr);
 // non-Boolean assembly: gather (mode 2 FP64, 0 FP32, 1 bf16 split), scatter from column-major
 // local results, rows of G with G^T G, and G^T x
 void wgather(rpf_problem pb, int p, const double* lam, int64_t ldl, int m, int mode, double* X64, float* Xf,
