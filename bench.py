@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-it", type=int, default=3000)
     ap.add_argument("--max-blocks", type=int, default=None, help="ORTHODIR restart length (default per workload)")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="relative residual reduction of each low-precision sweep (default per workload)")
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     ap.add_argument("--cpu-iterations", type=int, default=10)
@@ -113,6 +115,8 @@ def main():
         method_name = args.method
     if args.max_blocks is not None:
         settings = dict(settings, max_blocks=args.max_blocks)
+    if args.inner_tol is not None:
+        settings = dict(settings, inner_tol=args.inner_tol)
     method = METHODS[method_name]
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 8
